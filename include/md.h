@@ -1,0 +1,242 @@
+/*
+ * md.h - C ABI of the MI355X (gfx950) short-range molecular-dynamics core.
+ *
+ * The operations follow the statement of the problem in "JAX, M.D.: A
+ * Framework for Differentiable Physics" (arXiv:1912.04232):
+ *   - a periodic space with a nearest-image displacement and a shift
+ *     (Sec. 3.2.1 "Spaces"),
+ *   - a pair energy U = 1/2 sum_{i != j} u(r_ij) and forces F = -grad U
+ *     (Sec. 3.2.2 "Interactions", Sec. 3.3.2 "Energy Functions"),
+ *   - a cell list and a neighbor list with a halo ("skin") that is rebuilt
+ *     when particles have moved too far (Sec. 3.2.3 "Spatial Partitioning",
+ *     Sec. 3.1 "Benchmarks"),
+ *   - constant-energy (NVE) dynamics and FIRE descent, each an init/update
+ *     pair (Sec. 3.3.1 "Dynamics and Simulations").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is DEVICE memory owned by the caller.  The library
+ *    never frees or reallocates caller memory.  Scratch memory (second
+ *    position buffer, cell list, reduction partials) belongs to the md_ctx
+ *    and is allocated only by md_ctx_create / md_ctx_reserve.
+ *  - Positions are torus coordinates: pos[i*dim + k] is a uint32 fraction of
+ *    the box edge, x = pos * L_k / 2^32, so the box is [0, L_x) x [0, L_y)
+ *    (x [0, L_z)).  The nearest-image displacement along k is the signed
+ *    32-bit wrap of pos_ik - pos_jk times L_k / 2^32, exact in integers.
+ *    md_positions_from_float / md_positions_to_float convert.
+ *  - Velocities and forces are float, row-major [N][dim].  Per-particle
+ *    energies and virials are double [N].  Masses are 1.
+ *  - dim is 2 or 3.  Boxes are orthorhombic with origin 0.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Calls enqueue work and return without waiting, except md_flags_read
+ *    and md_ctx_* which synchronise as documented.
+ *  - Errors the host can see are returned at once and nothing is enqueued:
+ *    NULL pointers, dim not in {2,3}, N < 0, sizes above what md_ctx_reserve
+ *    provided (MD_ERR_CAPACITY), r_list >= L_k/2 (MD_ERR_BOX).  Conditions
+ *    found on the device are written to nl->flags (see MD_FLAG_*) and read
+ *    by the caller when it chooses.  Nothing is printed; no C++ exception
+ *    crosses this interface.
+ *  - One md_ctx per stream: two calls that share a ctx must not overlap.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,            /* NULL pointer, bad dim, bad size or parameter */
+    MD_ERR_BOX = -2,            /* r_list >= L/2 in some dimension (nearest image ambiguous) */
+    MD_ERR_CAPACITY = -3,       /* N or cell count above the reserved scratch size */
+    MD_ERR_HIP = -4,            /* a HIP runtime call failed */
+    MD_ERR_NOT_CONVERGED = -5,  /* reported by helpers that poll convergence */
+    MD_ERR_NONFINITE = -6,      /* reported by helpers that poll the non-finite flag */
+} md_status;
+
+/* Periodic orthorhombic box [0,L_0) x [0,L_1) (x [0,L_2)) (Sec. 3.2.1). */
+typedef struct {
+    int32_t dim;   /* 2 or 3 */
+    float L[3];    /* edge lengths; L[2] ignored when dim == 2 */
+} md_box;
+
+enum { MD_LJ = 0, MD_SOFT_SPHERE = 1 };
+
+/*
+ * Pair potential with S species (Sec. 3.3.2; species matrices as in App. A).
+ *   MD_LJ          u = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] for r < r_cut,
+ *                  minus u(r_cut) when shift != 0; 0 beyond r_cut.
+ *   MD_SOFT_SPHERE u = eps_ab/alpha (1 - r/sigma_ab)^alpha for r < sigma_ab, else 0.
+ * sigma and epsilon are S x S row-major (entry a*S+b), symmetric, S <= 8.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t n_species;
+    float sigma[64];
+    float epsilon[64];
+    float alpha;      /* soft-sphere exponent, >= 1 (2 = harmonic) */
+    float r_cut;      /* Lennard-Jones cutoff distance (absolute) */
+    int32_t shift;    /* Lennard-Jones energy shift on/off */
+    int32_t reserved;
+} md_potential;
+
+/* Device flag words in md_nlist.flags (int32 each). */
+enum {
+    MD_FLAG_OVERFLOW = 0,   /* a row needed more than `capacity` entries; the list is invalid */
+    MD_FLAG_MAXCOUNT = 1,   /* largest row length seen by any build (the capacity needed) */
+    MD_FLAG_NONFINITE = 2,  /* a non-finite force was produced */
+    MD_FLAG_REBUILDS = 3,   /* number of builds performed (incremented by every build) */
+    MD_FLAG_PENDING0 = 4,   /* rebuild-pending words used in rotation by verlet_step/fire_step */
+    MD_FLAG_PENDING1 = 5,
+    MD_FLAG_PENDING2 = 6,
+    MD_FLAG_STEPS = 7,      /* steps completed by the last verlet_step / fire_step call */
+    MD_NFLAGS = 8
+};
+
+/*
+ * Neighbor list (Sec. 3.2.3) in ELL layout: row i holds the indices j of all
+ * particles with |d(r_i, r_j)| < r_list, j != i (both directions, "full"
+ * list).  Entry k of row i is idx[k*N + i]; count[i] is the row length.
+ * Rows list neighbor cells in a fixed stencil order and, inside a cell,
+ * increasing j, so a build is deterministic.  r_list = cutoff + skin; the
+ * list stays valid while every particle has moved less than skin/2 from
+ * pos_ref, the positions at the last build (Sec. 3.1: rebuilt when particles
+ * have moved farther than the halo allows).
+ */
+typedef struct {
+    int32_t N;
+    int32_t capacity;    /* entries per row */
+    float r_list;        /* list radius */
+    float skin;          /* r_list - cutoff; rebuild when a particle moved > skin/2 */
+    int32_t *idx;        /* [capacity][N] */
+    int32_t *count;      /* [N] */
+    uint32_t *pos_ref;   /* [N][dim] positions at the last build */
+    int32_t *flags;      /* [MD_NFLAGS] */
+} md_nlist;
+
+typedef struct md_ctx md_ctx;
+
+/* Create a context on HIP device `device` (makes it current). */
+md_status md_ctx_create(int device, md_ctx **out);
+/* Synchronise the device and free the context's scratch. */
+md_status md_ctx_destroy(md_ctx *ctx);
+/*
+ * Reserve scratch for up to N particles in `dim` dimensions and up to
+ * max_cells cells.  This is the only call that allocates; it synchronises
+ * the device when it has to grow.  Every other call returns MD_ERR_CAPACITY
+ * when it would need more than was reserved.
+ */
+md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells);
+/* Number of cells the cell list uses for this box and list radius (host only). */
+int32_t md_cell_count(const md_box *box, float r_list);
+
+/* x (float [N][dim], any real value) -> torus coordinates pos (nearest 2^-32 L, wrapped). */
+md_status md_positions_from_float(const md_box *box, const float *x, uint32_t *pos, int32_t N, void *stream);
+/* pos -> x = pos * L / 2^32 rounded to float. */
+md_status md_positions_to_float(const md_box *box, const uint32_t *pos, float *x, int32_t N, void *stream);
+
+/*
+ * Build the neighbor list of `pos` (Sec. 3.2.3): counting-sort cell binning
+ * with cells of edge >= r_list (27 or 9 stencil cells; a dimension with fewer
+ * than 3 cells is scanned whole), then one candidate scan per particle.  The
+ * predicate is r2 < r_list^2 with r2 evaluated in IEEE double as
+ * d_0*d_0 + d_1*d_1 (+ d_2*d_2), d_k = (double)wrap32(pos_ik - pos_jk) *
+ * (L_k / 2^32): a single-precision filter decides pairs far from the
+ * boundary and the double expression decides the rest.  Copies pos to
+ * nl->pos_ref, raises MD_FLAG_OVERFLOW when a row does not fit and updates
+ * MD_FLAG_MAXCOUNT / MD_FLAG_REBUILDS.  nl->N must equal N.
+ */
+md_status nl_build(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream);
+
+/*
+ * Forces, and optionally per-particle energies and virials (Sec. 3.2.2):
+ *   force[i]  = sum_j f(r_ij)/r_ij * d(r_i, r_j)         (float, [N][dim])
+ *   energy[i] = 1/2 sum_j u(r_ij)                        (double [N] or NULL)
+ *   virial[i] = 1/2 sum_j r_ij f(r_ij),  f = -du/dr      (double [N] or NULL)
+ * over the neighbor list when nl != NULL (its pairs beyond the cutoff add
+ * nothing), or over all N(N-1) ordered pairs when nl == NULL (dense).
+ * Pair arithmetic is single precision; energy and virial sums are double.
+ * species may be NULL when pot->n_species == 1.  force may be NULL.
+ */
+md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos,
+                            const int32_t *species, int32_t N, const md_nlist *nl, float *force,
+                            double *energy, double *virial, void *stream);
+
+/*
+ * n_steps of velocity-Verlet NVE (Sec. 3.3.1), unit masses:
+ *   v += dt/2 F;  r = shift(r, dt v);  F = F(r);  v += dt/2 F.
+ * On entry `force` must hold F(pos) (pair_energy_force) and nl must be a
+ * valid list for pos (nl_build).  Before each force evaluation the list is
+ * rebuilt on the device when some particle has moved more than nl->skin/2
+ * since the last build; no host synchronisation happens.  On return pos,
+ * vel and force hold the state after n_steps.  If a rebuild overflows, the
+ * remaining steps do nothing, MD_FLAG_OVERFLOW stays set, MD_FLAG_STEPS
+ * counts the steps that were done, and the state is partial: the caller
+ * re-runs from its own copy of the input with a larger capacity.
+ */
+md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                      float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt,
+                      int32_t n_steps, void *stream);
+
+/* FIRE parameters (Bitzek et al. 2006, cited in Sec. 3.3.1). */
+typedef struct {
+    float dt_start, dt_max, f_inc, f_dec, alpha_start, f_alpha;
+    int32_t n_min;
+    int32_t reserved;
+} md_fire_params;
+
+/* FIRE scalars, kept in DEVICE memory by the caller (one struct). */
+typedef struct {
+    double dt;        /* current time step */
+    double alpha;     /* current mixing factor */
+    double fmax;      /* max_i |F_i| after the last step */
+    double power;     /* P = F . v of the last step */
+    int64_t steps;    /* steps taken since fire_init */
+    int32_t n_pos;    /* steps since P was last <= 0 */
+    int32_t converged;/* 1 once max_i |F_i| < f_tol */
+} md_fire_state;
+
+/*
+ * FIRE descent init (Sec. 3.3.1, App. A "fire_descent"): vel = 0,
+ * force = F(pos) over nl, st = {dt_start, alpha_start, n_pos 0}, fmax and
+ * converged from the initial forces against f_tol.
+ */
+md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos,
+                    float *vel, float *force, const int32_t *species, int32_t N, md_nlist *nl,
+                    const md_fire_params *fp, md_fire_state *st, double f_tol, void *stream);
+/*
+ * Up to n_steps FIRE steps (unit masses), each:
+ *   r = shift(r, dt v + dt^2/2 F); F' = F(r); v += dt/2 (F + F'); F = F';
+ *   stop once max_i |F_i| < f_tol;  P = F.v;  v = (1-a) v + a |v| F/|F|;
+ *   P > 0: n_pos++, and when n_pos > n_min: dt = min(dt f_inc, dt_max), a *= f_alpha
+ *   else : dt *= f_dec, v = 0, a = alpha_start, n_pos = 0.
+ * Steps after convergence do nothing, so the call can be enqueued in fixed
+ * chunks; st->converged / st->steps tell the caller where it stopped.  The
+ * neighbor list is rebuilt on the device as in verlet_step.  Global sums are
+ * double and summed in a fixed order.
+ */
+md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                    float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
+                    md_fire_state *st, int32_t n_steps, double f_tol, void *stream);
+
+/* out[0] = sum of x[0..n) in double, summed in a fixed order (deterministic). out is device memory. */
+md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
+/* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */
+md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t dim, double *out, void *stream);
+
+/* Copy nl->flags to host `out` (MD_NFLAGS ints) after synchronising `stream`. */
+md_status md_flags_read(const md_nlist *nl, int32_t *out, void *stream);
+/* Zero nl->flags (enqueued on `stream`). */
+md_status md_flags_clear(md_nlist *nl, void *stream);
+
+/* Library version string. */
+const char *md_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD_H */
