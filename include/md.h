@@ -194,6 +194,8 @@ typedef struct {
     double alpha;     /* current mixing factor */
     double fmax;      /* max_i |F_i| after the last step */
     double power;     /* P = F . v of the last step */
+    double mix_v;     /* velocity update still to apply before the next drift: */
+    double mix_f;     /*   v = mix_v v + mix_f F  (0, 0 after P <= 0)        */
     int64_t steps;    /* steps taken since fire_init */
     int32_t n_pos;    /* steps since P was last <= 0 */
     int32_t converged;/* 1 once max_i |F_i| < f_tol */

@@ -1,0 +1,504 @@
+"""Python binding of libmdcore.so (include/md.h): argument marshalling only.
+
+Every array is a torch tensor on the GPU; its ``data_ptr()`` and the current
+torch stream are handed to the C ABI.  All arithmetic of the path runs in the
+HIP kernels behind these calls.  If the library is missing, or there is no GPU,
+the first call raises: there is no fallback.
+
+The functions keep the C names (``nl_build``, ``pair_energy_force``,
+``verlet_step``, ``fire_init``, ``fire_step``, ...).  On top of them sit small
+init/update helpers in the style of the paper's ``simulate.nve`` and
+``minimize.fire_descent`` (Sec. 3.3.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdcore.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
+
+MD_LJ, MD_SOFT_SPHERE = 0, 1
+FLAG_OVERFLOW, FLAG_MAXCOUNT, FLAG_NONFINITE, FLAG_REBUILDS = 0, 1, 2, 3
+FLAG_PENDING0, FLAG_STEPS, NFLAGS = 4, 7, 8
+
+STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_BOX", -3: "MD_ERR_CAPACITY", -4: "MD_ERR_HIP",
+          -5: "MD_ERR_NOT_CONVERGED", -6: "MD_ERR_NONFINITE"}
+
+
+class MDError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} returned {STATUS.get(code, code)}")
+        self.code = code
+
+
+class c_box(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_float * 3)]
+
+
+class c_potential(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32), ("sigma", ctypes.c_float * 64),
+                ("epsilon", ctypes.c_float * 64), ("alpha", ctypes.c_float), ("r_cut", ctypes.c_float),
+                ("shift", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class c_nlist(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("capacity", ctypes.c_int32), ("r_list", ctypes.c_float),
+                ("skin", ctypes.c_float), ("idx", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("pos_ref", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class c_fire_params(ctypes.Structure):
+    _fields_ = [("dt_start", ctypes.c_float), ("dt_max", ctypes.c_float), ("f_inc", ctypes.c_float),
+                ("f_dec", ctypes.c_float), ("alpha_start", ctypes.c_float), ("f_alpha", ctypes.c_float),
+                ("n_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class c_fire_state(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("fmax", ctypes.c_double),
+                ("power", ctypes.c_double), ("mix_v", ctypes.c_double), ("mix_f", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("n_pos", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+
+FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
+_lib = None
+
+P = ctypes.c_void_p
+_SIGNATURES = {
+    "md_ctx_create": [ctypes.c_int, ctypes.POINTER(P)],
+    "md_ctx_destroy": [P],
+    "md_ctx_reserve": [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "md_cell_count": [ctypes.POINTER(c_box), ctypes.c_float],
+    "md_positions_from_float": [ctypes.POINTER(c_box), P, P, ctypes.c_int32, P],
+    "md_positions_to_float": [ctypes.POINTER(c_box), P, P, ctypes.c_int32, P],
+    "nl_build": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P],
+    "pair_energy_force": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, ctypes.c_int32,
+                          ctypes.POINTER(c_nlist), P, P, P, P],
+    "verlet_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
+                    ctypes.POINTER(c_nlist), ctypes.c_float, ctypes.c_int32, P],
+    "fire_init": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
+                  ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_double, P],
+    "fire_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
+                  ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_int32, ctypes.c_double, P],
+    "md_sum": [P, P, ctypes.c_int64, P, P],
+    "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
+    "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
+    "md_flags_clear": [ctypes.POINTER(c_nlist), P],
+    "md_version": [],
+}
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/md.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:md_status|int32_t|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def load(path: str = LIB_PATH):
+    """Load libmdcore.so and attach the C signatures.  Raises if the library is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} not built: run `python -m paper_1912_04232_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, args in _SIGNATURES.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "md_version" else ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(fn, code):
+    if code != 0:
+        raise MDError(fn, code)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the MD library needs a GPU; none is visible")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+# ------------------------------------------------------------------ value types
+
+@dataclass
+class Box:
+    """Periodic orthorhombic box [0, L) (paper Sec. 3.2.1)."""
+    L: tuple
+    dim: int = 3
+
+    def c(self) -> c_box:
+        b = c_box()
+        b.dim = self.dim
+        for k in range(3):
+            b.L[k] = float(self.L[k]) if k < len(self.L) else 0.0
+        return b
+
+
+@dataclass
+class Potential:
+    """Pair potential (paper Sec. 3.3.2): kind 'lj' or 'soft_sphere', S x S sigma / epsilon."""
+    kind: str = "lj"
+    sigma: object = ((1.0,),)
+    epsilon: object = ((1.0,),)
+    alpha: float = 2.0
+    r_cut: float = 2.5
+    shift: bool = True
+
+    @property
+    def n_species(self) -> int:
+        return int(np.atleast_2d(np.asarray(self.sigma)).shape[0])
+
+    def cutoff(self) -> float:
+        if self.kind == "lj":
+            return float(self.r_cut)
+        return float(np.max(np.asarray(self.sigma, dtype=np.float64)))
+
+    def c(self) -> c_potential:
+        s = np.atleast_2d(np.asarray(self.sigma, dtype=np.float64))
+        e = np.atleast_2d(np.asarray(self.epsilon, dtype=np.float64))
+        S = s.shape[0]
+        if e.shape != (S, S) or S > 8:
+            raise ValueError("sigma / epsilon must be S x S with S <= 8")
+        p = c_potential()
+        p.kind = MD_LJ if self.kind == "lj" else MD_SOFT_SPHERE
+        p.n_species = S
+        for q in range(S * S):
+            p.sigma[q] = float(s.reshape(-1)[q])
+            p.epsilon[q] = float(e.reshape(-1)[q])
+        p.alpha = float(self.alpha)
+        p.r_cut = float(self.r_cut)
+        p.shift = 1 if self.shift else 0
+        return p
+
+
+@dataclass
+class FireParams:
+    """FIRE parameters; n_min, f_inc, f_dec, alpha_start, f_alpha are Bitzek et al.'s published values."""
+    dt_start: float = 0.1
+    dt_max: float = 0.4
+    n_min: int = 5
+    f_inc: float = 1.1
+    f_dec: float = 0.5
+    alpha_start: float = 0.1
+    f_alpha: float = 0.99
+
+    def c(self) -> c_fire_params:
+        return c_fire_params(self.dt_start, self.dt_max, self.f_inc, self.f_dec, self.alpha_start, self.f_alpha,
+                             self.n_min, 0)
+
+
+class Context:
+    """md_ctx: owns the library's scratch on one device."""
+
+    def __init__(self, device: int | None = None):
+        lib = load()
+        dev = _dev() if device is None else torch.device("cuda", device)
+        self.device = dev
+        h = ctypes.c_void_p()
+        _check("md_ctx_create", lib.md_ctx_create(dev.index, ctypes.byref(h)))
+        self.h = h
+        self.N = self.dim = self.C = 0
+
+    def reserve(self, N: int, dim: int, max_cells: int):
+        if N > self.N or dim > self.dim or max_cells > self.C:
+            self.N, self.dim, self.C = max(N, self.N), max(dim, self.dim), max(max_cells, self.C)
+            _check("md_ctx_reserve", load().md_ctx_reserve(self.h, self.N, self.dim, self.C))
+
+    def close(self):
+        if self.h:
+            load().md_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cell_count(box: Box, r_list: float) -> int:
+    b = box.c()
+    return int(load().md_cell_count(ctypes.byref(b), ctypes.c_float(r_list)))
+
+
+class NeighborList:
+    """md_nlist with its arrays held as torch tensors (ELL idx[capacity][N], count[N], pos_ref[N][dim], flags)."""
+
+    def __init__(self, N: int, dim: int, capacity: int, r_list: float, skin: float, device=None):
+        dev = device or _dev()
+        self.N, self.dim, self.capacity = N, dim, capacity
+        self.r_list, self.skin = float(np.float32(r_list)), float(np.float32(skin))
+        self.idx = torch.empty((capacity, max(N, 1)), dtype=torch.int32, device=dev)
+        self.count = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
+        self.pos_ref = torch.zeros((max(N, 1), dim), dtype=torch.int32, device=dev)
+        self.flags = torch.zeros(NFLAGS, dtype=torch.int32, device=dev)
+
+    def c(self) -> c_nlist:
+        n = c_nlist()
+        n.N, n.capacity, n.r_list, n.skin = self.N, self.capacity, self.r_list, self.skin
+        n.idx, n.count = self.idx.data_ptr(), self.count.data_ptr()
+        n.pos_ref, n.flags = self.pos_ref.data_ptr(), self.flags.data_ptr()
+        return n
+
+    def read_flags(self) -> np.ndarray:
+        out = (ctypes.c_int32 * NFLAGS)()
+        n = self.c()
+        _check("md_flags_read", load().md_flags_read(ctypes.byref(n), out, _stream()))
+        return np.array(out[:], dtype=np.int32)
+
+    def clear_flags(self):
+        n = self.c()
+        _check("md_flags_clear", load().md_flags_clear(ctypes.byref(n), _stream()))
+
+    def rows(self) -> list:
+        """Host copy of the rows (list of int arrays), for inspection and tests."""
+        idx = self.idx.cpu().numpy()
+        cnt = self.count.cpu().numpy()
+        return [idx[: min(c, self.capacity), i].copy() for i, c in enumerate(cnt[: self.N])]
+
+
+# ------------------------------------------------------------ C entry points
+
+def positions_from_float(box: Box, x: torch.Tensor) -> torch.Tensor:
+    x = x.contiguous()
+    u = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    b = box.c()
+    _check("md_positions_from_float",
+           load().md_positions_from_float(ctypes.byref(b), _ptr(x), _ptr(u), x.shape[0], _stream()))
+    return u
+
+
+def positions_to_float(box: Box, u: torch.Tensor) -> torch.Tensor:
+    x = torch.empty(u.shape, dtype=torch.float32, device=u.device)
+    b = box.c()
+    _check("md_positions_to_float",
+           load().md_positions_to_float(ctypes.byref(b), _ptr(u), _ptr(x), u.shape[0], _stream()))
+    return x
+
+
+def nl_build(ctx: Context, box: Box, pos: torch.Tensor, nl: NeighborList):
+    N = pos.shape[0]
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    b, n = box.c(), nl.c()
+    _check("nl_build", load().nl_build(ctx.h, ctypes.byref(b), _ptr(pos), N, ctypes.byref(n), _stream()))
+
+
+def pair_energy_force(ctx: Context, box: Box, pot: Potential, pos: torch.Tensor, species=None,
+                      nl: NeighborList | None = None, force=None, energy=None, virial=None):
+    N = pos.shape[0]
+    ctx.reserve(N, box.dim, 1)
+    b, p = box.c(), pot.c()
+    n = nl.c() if nl is not None else None
+    _check("pair_energy_force", load().pair_energy_force(
+        ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(species), N,
+        ctypes.byref(n) if n is not None else None, _ptr(force), _ptr(energy), _ptr(virial), _stream()))
+
+
+def verlet_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList, dt: float,
+                n_steps: int):
+    N = pos.shape[0]
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    b, p, n = box.c(), pot.c(), nl.c()
+    _check("verlet_step", load().verlet_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
+                                             _ptr(force), _ptr(species), N, ctypes.byref(n),
+                                             ctypes.c_float(dt), int(n_steps), _stream()))
+
+
+def fire_init(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
+              fp: FireParams, state: torch.Tensor, f_tol: float):
+    N = pos.shape[0]
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    b, p, n, f = box.c(), pot.c(), nl.c(), fp.c()
+    _check("fire_init", load().fire_init(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
+                                         _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
+                                         _ptr(state), ctypes.c_double(f_tol), _stream()))
+
+
+def fire_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
+              fp: FireParams, state: torch.Tensor, n_steps: int, f_tol: float):
+    N = pos.shape[0]
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    b, p, n, f = box.c(), pot.c(), nl.c(), fp.c()
+    _check("fire_step", load().fire_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
+                                         _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
+                                         _ptr(state), int(n_steps), ctypes.c_double(f_tol), _stream()))
+
+
+def md_sum(ctx: Context, x: torch.Tensor, out: torch.Tensor):
+    _check("md_sum", load().md_sum(ctx.h, _ptr(x), x.numel(), _ptr(out), _stream()))
+
+
+def kinetic_energy(ctx: Context, vel: torch.Tensor, out: torch.Tensor):
+    _check("md_kinetic_energy", load().md_kinetic_energy(ctx.h, _ptr(vel), vel.shape[0], vel.shape[1], _ptr(out),
+                                                         _stream()))
+
+
+def fire_state_tensor(device=None) -> torch.Tensor:
+    return torch.zeros(FIRE_STATE_BYTES, dtype=torch.uint8, device=device or _dev())
+
+
+def fire_state_read(state: torch.Tensor) -> dict:
+    raw = state.cpu().numpy().tobytes()
+    s = c_fire_state.from_buffer_copy(raw)
+    return dict(dt=s.dt, alpha=s.alpha, fmax=s.fmax, power=s.power, mix_v=s.mix_v, mix_f=s.mix_f, steps=s.steps,
+                n_pos=s.n_pos, converged=bool(s.converged))
+
+
+# --------------------------------------------------------- init / update helpers
+
+def to_device_u32(u: np.ndarray, device=None) -> torch.Tensor:
+    """uint32 torus coordinates (numpy) -> int32 tensor holding the same bits."""
+    return torch.from_numpy(np.ascontiguousarray(u, dtype=np.uint32).view(np.int32)).to(device or _dev())
+
+
+def from_device_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+class System:
+    """A periodic system on the GPU: positions, velocities, forces, species, and its neighbor list."""
+
+    def __init__(self, box: Box, pot: Potential, u: np.ndarray, v=None, species=None, skin: float = 0.3,
+                 capacity: int | None = None, ctx: Context | None = None):
+        self.ctx = ctx or Context()
+        dev = self.ctx.device
+        self.box, self.pot = box, pot
+        self.N, self.dim = u.shape
+        self.pos = to_device_u32(u, dev)
+        self.vel = torch.zeros((self.N, self.dim), dtype=torch.float32, device=dev) if v is None else \
+            torch.as_tensor(np.asarray(v, dtype=np.float32), device=dev).contiguous()
+        self.force = torch.zeros((self.N, self.dim), dtype=torch.float32, device=dev)
+        self.species = None if species is None else torch.as_tensor(np.asarray(species, dtype=np.int32),
+                                                                     device=dev).contiguous()
+        if pot.n_species > 1 and self.species is None:
+            raise ValueError("multi-species potential needs species")
+        r_list = float(np.float32(pot.cutoff() + skin))
+        if capacity is None:
+            vol = float(np.prod(np.asarray(box.L[: self.dim], dtype=np.float64)))
+            ball = (4.0 / 3.0 * np.pi * r_list ** 3) if self.dim == 3 else (np.pi * r_list ** 2)
+            capacity = int(max(16, 1.4 * self.N / vol * ball + 16))
+            capacity = (capacity + 7) // 8 * 8
+        self.nl = NeighborList(self.N, self.dim, capacity, r_list, skin, dev)
+
+    def build(self):
+        """Build the neighbor list, growing its capacity if a row did not fit."""
+        for _ in range(4):
+            self.nl.clear_flags()
+            nl_build(self.ctx, self.box, self.pos, self.nl)
+            f = self.nl.read_flags()
+            if not f[FLAG_OVERFLOW]:
+                return
+            self.grow(int(f[FLAG_MAXCOUNT]))
+        raise RuntimeError("neighbor list did not fit after growing")
+
+    def grow(self, need: int):
+        cap = (int(need * 1.25) + 8) // 8 * 8
+        self.nl = NeighborList(self.N, self.dim, cap, self.nl.r_list, self.nl.skin, self.ctx.device)
+
+    def forces(self, energy: bool = False):
+        e = torch.zeros(self.N, dtype=torch.float64, device=self.ctx.device) if energy else None
+        w = torch.zeros(self.N, dtype=torch.float64, device=self.ctx.device) if energy else None
+        pair_energy_force(self.ctx, self.box, self.pot, self.pos, self.species, self.nl, self.force, e, w)
+        return e, w
+
+    def potential_energy(self) -> float:
+        e = torch.zeros(self.N, dtype=torch.float64, device=self.ctx.device)
+        pair_energy_force(self.ctx, self.box, self.pot, self.pos, self.species, self.nl, None, e, None)
+        out = torch.zeros(1, dtype=torch.float64, device=self.ctx.device)
+        md_sum(self.ctx, e, out)
+        return float(out.item())
+
+    def kinetic_energy(self) -> float:
+        out = torch.zeros(1, dtype=torch.float64, device=self.ctx.device)
+        kinetic_energy(self.ctx, self.vel, out)
+        return float(out.item())
+
+
+def nve(system: System, dt: float):
+    """init_fn / update_fn pair for constant-energy dynamics (paper Sec. 3.3.1, ``simulate.nve``).
+
+    ``init_fn()`` builds the list and the forces; ``update_fn(n)`` advances n velocity-Verlet steps on the
+    device, re-running from a saved copy with a larger list if a rebuild overflowed.
+    """
+
+    def init_fn():
+        system.build()
+        system.forces()
+        return system
+
+    def update_fn(n_steps: int = 1):
+        saved = (system.pos.clone(), system.vel.clone(), system.force.clone(), system.nl)
+        for _ in range(4):
+            system.nl.clear_flags()
+            verlet_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
+                        system.nl, dt, n_steps)
+            f = system.nl.read_flags()
+            if not f[FLAG_OVERFLOW]:
+                if f[FLAG_NONFINITE]:
+                    raise FloatingPointError("non-finite force in verlet_step")
+                return system
+            system.pos.copy_(saved[0])
+            system.vel.copy_(saved[1])
+            system.force.copy_(saved[2])
+            system.grow(int(f[FLAG_MAXCOUNT]))
+            system.build()
+        raise RuntimeError("neighbor list kept overflowing")
+
+    return init_fn, update_fn
+
+
+def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e-6):
+    """init_fn / step_fn pair for FIRE minimization (paper Sec. 3.3.1, App. A ``minimize.fire_descent``)."""
+    fp = fp or FireParams()
+    state = fire_state_tensor(system.ctx.device)
+
+    def init_fn():
+        system.build()
+        system.vel.zero_()
+        fire_init(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
+                  system.nl, fp, state, f_tol)
+        return state
+
+    def step_fn(n_steps: int = 1):
+        saved = (system.pos.clone(), system.vel.clone(), system.force.clone(), state.clone())
+        for _ in range(4):
+            fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
+                      system.nl, fp, state, n_steps, f_tol)
+            f = system.nl.read_flags()
+            if not f[FLAG_OVERFLOW]:
+                return fire_state_read(state)
+            system.pos.copy_(saved[0])
+            system.vel.copy_(saved[1])
+            system.force.copy_(saved[2])
+            state.copy_(saved[3])
+            system.grow(int(f[FLAG_MAXCOUNT]))
+            system.build()
+        raise RuntimeError("neighbor list kept overflowing")
+
+    def minimize(max_steps: int = 100000, chunk: int = 200):
+        st = fire_state_read(state)
+        while not st["converged"] and st["steps"] < max_steps:
+            st = step_fn(min(chunk, max_steps - st["steps"]))
+        return st
+
+    return init_fn, step_fn, minimize

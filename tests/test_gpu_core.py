@@ -1,0 +1,387 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: neighbor rows bit-identical to brute force after sorting; forces
+||F_gpu - F_orc||_2 / ||F_orc||_2 <= 1e-5 over all components; energies
+|E_gpu - E_orc| / |E_orc| <= 1e-6 (or relative to sum |e_i| when E is near 0).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_04232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+E_TOL = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1912_04232_amd import md as m
+    m.load()
+    return m
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_system(md, cfg, skin=None, capacity=None):
+    dim = cfg["dim"]
+    box = md.Box(tuple(cfg["L"][:dim]), dim)
+    if cfg["kind"] == "lj":
+        pot = md.Potential("lj", cfg["sigma"], cfg["epsilon"], r_cut=cfg["r_cut"])
+    else:
+        pot = md.Potential("soft_sphere", cfg["sigma"], cfg["epsilon"], alpha=cfg.get("alpha", 2.0))
+    sp = cfg.get("species") if pot.n_species > 1 else None
+    return md.System(box, pot, cfg["u"], cfg.get("v"), sp, skin=cfg.get("skin", 0.3) if skin is None else skin,
+                     capacity=capacity)
+
+
+def orc_pot(orc, cfg):
+    if cfg["kind"] == "lj":
+        return orc.Potential("lj", np.array(cfg["sigma"]), np.array(cfg["epsilon"]), r_cut=cfg["r_cut"])
+    return orc.Potential("soft_sphere", np.array(cfg["sigma"]), np.array(cfg["epsilon"]), alpha=cfg.get("alpha", 2.0))
+
+
+def lj_cfg(N, rho, seed, skin=0.3, rmin=0.8):
+    L = inputs.box_for_density(N, rho)
+    u = inputs.random_insertion_torus(N, L, 3, rmin, seed)
+    return dict(N=N, dim=3, L=[L, L, L], u=u, v=inputs.maxwell_velocities(N, 3, 1.0, seed + 1), kind="lj",
+                sigma=[[1.0]], epsilon=[[1.0]], r_cut=2.5, skin=skin)
+
+
+def ss_cfg(N, phi, seed, skin=0.3):
+    L = inputs.box_for_packing([1.0, 1.4], [N // 2, N - N // 2], phi, 2)
+    d = np.array([1.0, 1.4])
+    return dict(N=N, dim=2, L=[L, L, 0.0], u=inputs.uniform_torus(N, 2, seed), species=inputs.bidisperse_species(N),
+                kind="soft_sphere", sigma=(0.5 * (d[:, None] + d[None, :])).tolist(),
+                epsilon=[[1.0, 1.0], [1.0, 1.0]], alpha=2.0, skin=skin)
+
+
+def check_rows(orc, sysm, cfg, rows=None):
+    got = sysm.nl.rows()
+    want = orc.neighbors(cfg["u"], cfg["L"], sysm.nl.r_list, rows=rows)
+    ids = range(len(got)) if rows is None else rows
+    for q, i in enumerate(ids):
+        g = np.sort(got[i])
+        assert np.array_equal(g, want[q]), (i, g[:10], want[q][:10])
+
+
+# ------------------------------------------------------------------ neighbor list
+
+@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "ss2d", "tiny_box", "two", "one"])
+def test_nl_build_bitexact(md, orc, case):
+    say("nl_build", case)
+    if case == "lj1000":
+        cfg = inputs.lj_small()
+    elif case == "lj_ragged":
+        cfg = lj_cfg(3333, 0.84, 77)
+    elif case == "ss2d":
+        cfg = ss_cfg(5000, 0.9, 21)
+    elif case == "tiny_box":
+        cfg = lj_cfg(40, 0.12, 5, rmin=0.9)         # L = 6.93 < 3 r_list: whole-box scan
+    elif case == "two":
+        cfg = lj_cfg(2, 0.01, 6)
+    else:
+        cfg = lj_cfg(1, 0.002, 6)
+    s = make_system(md, cfg)
+    s.build()
+    check_rows(orc, s, cfg)
+    f = s.nl.read_flags()
+    assert f[md.FLAG_OVERFLOW] == 0
+    assert f[md.FLAG_MAXCOUNT] == max((len(r) for r in s.nl.rows()), default=0)
+
+
+def test_nl_rows_are_canonical(md):
+    """Two builds give identical rows (same order), and each row is ordered by stencil cell then index."""
+    cfg = lj_cfg(4000, 0.84, 3)
+    s = make_system(md, cfg)
+    s.build()
+    a = s.nl.idx.clone(), s.nl.count.clone()
+    s.build()
+    cnt = s.nl.count.cpu().numpy()
+    idx0, idx1 = a[0].cpu().numpy(), s.nl.idx.cpu().numpy()
+    for i in range(0, 4000, 97):
+        assert np.array_equal(idx0[: cnt[i], i], idx1[: cnt[i], i])
+
+
+def test_nl_overflow_flag_and_regrow(md, orc):
+    cfg = lj_cfg(2000, 0.84, 8)
+    s = make_system(md, cfg, capacity=16)
+    s.nl.clear_flags()
+    md.nl_build(s.ctx, s.box, s.pos, s.nl)
+    f = s.nl.read_flags()
+    assert f[md.FLAG_OVERFLOW] == 1 and f[md.FLAG_MAXCOUNT] > 16
+    s.build()   # grows and rebuilds
+    assert s.nl.capacity >= f[md.FLAG_MAXCOUNT]
+    check_rows(orc, s, cfg, rows=list(range(0, 2000, 7)))
+
+
+def test_nl_box_too_small_is_rejected(md):
+    cfg = lj_cfg(10, 0.5, 4)
+    cfg["L"] = [5.0, 5.0, 5.0]
+    s = make_system(md, cfg)
+    with pytest.raises(md.MDError) as e:
+        md.nl_build(s.ctx, s.box, s.pos, s.nl)    # r_list 2.8 >= L/2
+    assert e.value.code == -2
+
+
+# ------------------------------------------------------------------------- forces
+
+@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "ss2d", "ss2d_alpha25", "lj_species"])
+def test_forces_energy_virial_vs_oracle(md, orc, case):
+    say("pair_energy_force", case)
+    if case == "lj1000":
+        cfg = inputs.lj_small()
+    elif case == "lj_ragged":
+        cfg = lj_cfg(3333, 0.84, 77)
+    elif case.startswith("ss2d"):
+        cfg = ss_cfg(3000, 0.9, 22)
+        if case == "ss2d_alpha25":
+            cfg["alpha"] = 2.5
+    else:
+        cfg = lj_cfg(2500, 0.8, 31)
+        cfg["species"] = inputs.bidisperse_species(2500)
+        cfg["sigma"] = [[1.0, 0.8], [0.8, 0.88]]
+        cfg["epsilon"] = [[1.0, 1.5], [1.5, 0.5]]
+    s = make_system(md, cfg)
+    s.build()
+    e, w = s.forces(energy=True)
+    F = s.force.cpu().numpy()
+    x = orc.decode(cfg["u"], cfg["L"])
+    sp = cfg.get("species")
+    Fo, eo, wo = orc.pair_rows(x, cfg["L"], orc_pot(orc, cfg), sp)
+    assert rel_l2(F, Fo) <= F_TOL
+    eg = e.cpu().numpy()
+    scale = max(abs(math.fsum(eo)), math.fsum(np.abs(eo)) * 1e-3)
+    assert abs(math.fsum(eg) - math.fsum(eo)) / scale <= E_TOL
+    assert abs(math.fsum(w.cpu().numpy()) - math.fsum(wo)) / max(abs(math.fsum(wo)), 1e-12) <= 10 * E_TOL
+    assert rel_l2(eg, eo) <= 1e-5
+    assert s.potential_energy() == pytest.approx(math.fsum(eg), rel=1e-12)
+
+
+@pytest.mark.parametrize("case", ["lj1000", "ss_small", "ragged"])
+def test_dense_vs_oracle_and_nl(md, orc, case):
+    say("dense", case)
+    if case == "lj1000":
+        cfg = inputs.lj_small()
+    elif case == "ss_small":
+        cfg = ss_cfg(700, 0.9, 9)
+    else:
+        cfg = lj_cfg(517, 0.6, 12)
+    s = make_system(md, cfg)
+    import torch
+    Fd = torch.zeros_like(s.force)
+    ed = torch.zeros(s.N, dtype=torch.float64, device=s.force.device)
+    md.pair_energy_force(s.ctx, s.box, s.pot, s.pos, s.species, None, Fd, ed, None)
+    Fo, eo, _ = orc.pair_rows(orc.decode(cfg["u"], cfg["L"]), cfg["L"], orc_pot(orc, cfg), cfg.get("species"))
+    assert rel_l2(Fd.cpu().numpy(), Fo) <= F_TOL
+    assert abs(float(ed.sum()) - math.fsum(eo)) / max(abs(math.fsum(eo)), 1e-9) <= E_TOL
+    s.build()
+    s.forces()
+    assert rel_l2(s.force.cpu().numpy(), Fd.cpu().numpy()) <= F_TOL
+
+
+def test_nonfinite_flag(md):
+    cfg = lj_cfg(64, 0.3, 2)
+    u = cfg["u"].copy()
+    u[1] = u[0]
+    u[1, 0] += 1000   # r ~ 2e-5 sigma: force overflows float
+    cfg["u"] = u
+    s = make_system(md, cfg)
+    s.build()
+    s.nl.clear_flags()
+    s.forces()
+    assert s.nl.read_flags()[md.FLAG_NONFINITE] == 1
+
+
+# --------------------------------------------------------------- velocity Verlet
+
+def test_verlet_steps_vs_oracle(md, orc):
+    """A few velocity-Verlet steps from identical states agree with the FP64 oracle."""
+    cfg = lj_cfg(1500, 0.84, 41)
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.005)
+    init()
+    x = orc.decode(cfg["u"], cfg["L"])
+    p = orc_pot(orc, cfg)
+    F, _, _ = orc.pair_rows(x, cfg["L"], p)
+    v = cfg["v"].astype(np.float64)
+    for n in (1, 4):
+        say("verlet", n)
+        update(n)
+        x, v, F = orc.verlet(x, v, F, cfg["L"], p, 0.005, n)
+        xg = orc.decode(md.from_device_u32(s.pos), cfg["L"])
+        d = xg - x
+        d -= np.array(cfg["L"]) * np.rint(d / np.array(cfg["L"]))
+        assert np.abs(d).max() < 1e-5
+        assert rel_l2(s.vel.cpu().numpy(), v) < 1e-5
+        assert rel_l2(s.force.cpu().numpy(), F) < 1e-4
+
+
+def test_verlet_rebuilds_keep_every_pair(md, orc):
+    """Over 300 steps with device-side rebuilds the list always contains every pair inside the cutoff and the
+    final forces agree with a fresh evaluation from a fresh list (a fresh build orders rows differently, so the
+    float sums agree to rounding, not bit for bit)."""
+    cfg = lj_cfg(2000, 0.84, 51)
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.005)
+    init()
+    s.nl.clear_flags()
+    reb = 0
+    for _ in range(6):
+        update(50)
+        f = s.nl.read_flags()
+        reb += int(f[md.FLAG_REBUILDS])
+        u = md.from_device_u32(s.pos)
+        rows = s.nl.rows()
+        inner = orc.neighbors(u, cfg["L"], 2.5)
+        for i in range(0, 2000, 11):
+            assert set(inner[i].tolist()) <= set(rows[i].tolist())
+        s.nl.clear_flags()
+    assert reb >= 2
+    F_run = s.force.clone()
+    s.build()
+    s.forces()
+    assert rel_l2(F_run.cpu().numpy(), s.force.cpu().numpy()) <= 1e-6
+
+
+def test_verlet_energy_conservation(md):
+    cfg = inputs.lj_large(n_cells=6)   # 864-particle FCC at rho 0.84, T = 1
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.005)
+    init()
+    E0 = s.potential_energy() + s.kinetic_energy()
+    worst = 0.0
+    for _ in range(10):
+        update(20)
+        worst = max(worst, abs(s.potential_energy() + s.kinetic_energy() - E0))
+    say("max |dE|/N", worst / s.N)
+    assert worst / s.N < 2e-3
+
+
+def test_verlet_deterministic_and_overflow_regrow(md):
+    """Two runs are bitwise identical; a run whose list is sized exactly to the first build overflows at a later
+    device-side rebuild, is re-run from its saved input with a larger list, and still equals the others bit for bit
+    (rows are canonical, so the capacity does not change the summation order)."""
+    cfg = lj_cfg(3000, 0.84, 61)
+    outs = []
+    grew = False
+    for tight in (False, False, True):
+        s = make_system(md, cfg, capacity=256)
+        init, update = md.nve(s, 0.005)
+        init()
+        if tight:
+            need = int(s.nl.read_flags()[md.FLAG_MAXCOUNT])
+            s.nl = md.NeighborList(s.N, 3, need, s.nl.r_list, s.nl.skin, s.ctx.device)
+            s.build()
+            s.forces()
+        update(150)
+        if tight:
+            grew = s.nl.capacity > need
+        outs.append((md.from_device_u32(s.pos).copy(), s.vel.cpu().numpy(), s.force.cpu().numpy()))
+    say("tight list grew:", grew)
+    for k in range(3):
+        assert np.array_equal(outs[0][k], outs[1][k])
+        assert np.array_equal(outs[0][k], outs[2][k])
+
+
+def test_verlet_2d_soft_spheres(md, orc):
+    cfg = ss_cfg(2000, 0.8, 71)
+    cfg["v"] = inputs.maxwell_velocities(2000, 2, 0.01, 3)
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.01)
+    init()
+    x = orc.decode(cfg["u"], cfg["L"][:2])
+    p = orc_pot(orc, cfg)
+    F, _, _ = orc.pair_rows(x, cfg["L"][:2], p, cfg["species"])
+    update(3)
+    x, v, F = orc.verlet(x, cfg["v"].astype(np.float64), F, cfg["L"][:2], p, 0.01, 3, cfg["species"])
+    assert rel_l2(s.force.cpu().numpy(), F) < 1e-4
+    assert rel_l2(s.vel.cpu().numpy(), v) < 1e-5
+
+
+# ---------------------------------------------------------------------------- FIRE
+
+def test_fire_one_step_vs_oracle(md, orc):
+    cfg = ss_cfg(1000, 0.9, 81)
+    s = make_system(md, cfg)
+    init, step, _ = md.fire_descent(s, f_tol=1e-6)
+    init()
+    st = step(1)
+    p = orc_pot(orc, cfg)
+    res = orc.fire(orc.decode(cfg["u"], cfg["L"][:2]), cfg["L"][:2], p, cfg["species"], max_steps=1, f_tol=0.0)
+    # the GPU applies the velocity mixing of a step at the start of the next one
+    v = st["mix_v"] * s.vel.cpu().numpy().astype(np.float64) + st["mix_f"] * s.force.cpu().numpy()
+    assert rel_l2(v, res["v"]) < 1e-4
+    assert rel_l2(s.force.cpu().numpy(), res["F"]) < 1e-4
+    assert st["dt"] == pytest.approx(res["dt"]) and st["n_pos"] == res["n_pos"] and st["steps"] == 1
+
+
+def test_fire_lattice_reaches_closed_form(md):
+    """A jittered compressed triangular lattice relaxes to E/N = 3/2 (1 - a)^2 with max |F| < 1e-6."""
+    a = 0.98
+    u, Lx, Ly = inputs.triangular_torus(40, 40, a)
+    rng = np.random.default_rng(5)
+    jit = inputs.to_torus(rng.normal(0, 0.01, (1600, 2)), [Lx, Ly])
+    u = (u.astype(np.uint64) + jit.astype(np.uint64)) % 2 ** 32
+    cfg = dict(N=1600, dim=2, L=[Lx, Ly, 0.0], u=u.astype(np.uint32), kind="soft_sphere", sigma=[[1.0]],
+               epsilon=[[1.0]], alpha=2.0, skin=0.3)
+    s = make_system(md, cfg)
+    init, step, minimize = md.fire_descent(s, f_tol=1e-6)
+    init()
+    st = minimize(20000)
+    assert st["converged"] and st["fmax"] < 1e-6
+    assert s.potential_energy() / 1600 == pytest.approx(1.5 * (1 - a) ** 2, rel=1e-5)
+
+
+def test_fire_converges_and_oracle_agrees(md, orc):
+    """C2-style packing at N=4096: GPU FIRE reaches max |F| < 1e-6; the oracle confirms forces and energy there."""
+    cfg = ss_cfg(4096, 0.9, 2001)
+    s = make_system(md, cfg)
+    init, step, minimize = md.fire_descent(s, f_tol=1e-6)
+    init()
+    st = minimize(200000, chunk=500)
+    say("fire steps", st["steps"], "fmax", st["fmax"])
+    assert st["converged"]
+    u = md.from_device_u32(s.pos)
+    x = orc.decode(u, cfg["L"][:2])
+    Fo, eo, _ = orc.pair_rows(x, cfg["L"][:2], orc_pot(orc, cfg), cfg["species"])
+    assert np.sqrt((Fo ** 2).sum(1)).max() < 2e-6
+    E = s.potential_energy()
+    assert abs(E - math.fsum(eo)) <= 1e-6 * max(abs(math.fsum(eo)), math.fsum(np.abs(eo)))
+
+
+# --------------------------------------------------------------- full-size sample
+
+def test_lj_large_sampled_parity(md, orc):
+    """N = 256000 FCC LJ (the benchmark workload): sampled rows bit-exact and sampled forces within tolerance,
+    after 40 steps so that the lattice has melted enough to exercise rebuilds."""
+    cfg = inputs.lj_large()
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.005)
+    init()
+    update(40)
+    s.build()
+    s.forces()
+    u = md.from_device_u32(s.pos)
+    rows = np.random.default_rng(0).choice(cfg["N"], 600, replace=False)
+    got = s.nl.rows()
+    want = orc.neighbors(u, cfg["L"], s.nl.r_list, rows=rows)
+    for q, i in enumerate(rows):
+        assert np.array_equal(np.sort(got[i]), want[q])
+    Fo, _, _ = orc.pair_rows(orc.decode(u, cfg["L"]), cfg["L"], orc_pot(orc, cfg), rows=rows)
+    assert rel_l2(s.force.cpu().numpy()[rows], Fo) <= F_TOL
