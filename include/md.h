@@ -85,34 +85,38 @@ typedef struct {
 
 /* Device flag words in md_nlist.flags (int32 each). */
 enum {
-    MD_FLAG_OVERFLOW = 0,   /* a row needed more than `capacity` entries; the list is invalid */
-    MD_FLAG_MAXCOUNT = 1,   /* largest row length seen by any build (the capacity needed) */
-    MD_FLAG_NONFINITE = 2,  /* a non-finite force was produced */
-    MD_FLAG_REBUILDS = 3,   /* number of builds performed (incremented by every build) */
-    MD_FLAG_PENDING0 = 4,   /* rebuild-pending words used in rotation by verlet_step/fire_step */
-    MD_FLAG_PENDING1 = 5,
-    MD_FLAG_PENDING2 = 6,
-    MD_FLAG_STEPS = 7,      /* steps completed by the last verlet_step / fire_step call */
+    MD_FLAG_OVERFLOW = 0,      /* a row needed more than `capacity` entries; the list is invalid */
+    MD_FLAG_MAXCOUNT = 1,      /* largest row length seen by any build (the capacity needed) */
+    MD_FLAG_NONFINITE = 2,     /* a non-finite force was produced */
+    MD_FLAG_REBUILDS = 3,      /* number of builds performed (incremented by every build) */
+    MD_FLAG_CELL_OVERFLOW = 4, /* a cell held more than max_per_cell particles; the list is invalid */
+    MD_FLAG_STALE = 5,         /* a force used a list older than skin/2 allows; the run is invalid */
+    MD_FLAG_MAXCELL = 6,       /* largest cell occupancy seen (the max_per_cell needed) */
+    MD_FLAG_STEPS = 7,         /* index of the last step of verlet_step / fire_step that ran */
     MD_NFLAGS = 8
 };
 
 /*
- * Neighbor list (Sec. 3.2.3) in ELL layout: row i holds the indices j of all
- * particles with |d(r_i, r_j)| < r_list, j != i (both directions, "full"
- * list).  Entry k of row i is idx[k*N + i]; count[i] is the row length.
- * Rows list neighbor cells in a fixed stencil order and, inside a cell,
- * increasing j, so a build is deterministic.  r_list = cutoff + skin; the
- * list stays valid while every particle has moved less than skin/2 from
- * pos_ref, the positions at the last build (Sec. 3.1: rebuilt when particles
- * have moved farther than the halo allows).
+ * Neighbor list (Sec. 3.2.3): row i holds the indices j of all particles with
+ * |d(r_i, r_j)| < r_list, j != i (both directions, "full" list), split into
+ * `lanes` (W = 1, 2, 4 or 8) interleaved sub-rows that W GPU lanes walk
+ * together: entry t of sub-row l of particle i is idx[(t*N + i)*W + l], and
+ * count[i*W + l] is that sub-row's length (at most capacity/W).  The stencil
+ * cells' members are numbered in a fixed order (stencil cell, then index)
+ * and sub-row l takes every W-th of them, so a build is deterministic.
+ * r_list = cutoff + skin; the list stays valid while every particle has moved
+ * less than skin/2 from pos_ref, the positions at the last build (Sec. 3.1:
+ * the list is rebuilt when particles have moved farther than the halo allows).
  */
 typedef struct {
     int32_t N;
-    int32_t capacity;    /* entries per row */
+    int32_t capacity;    /* entries per row, a multiple of lanes */
+    int32_t lanes;       /* W: 1, 2, 4 or 8 */
+    int32_t reserved;
     float r_list;        /* list radius */
     float skin;          /* r_list - cutoff; rebuild when a particle moved > skin/2 */
-    int32_t *idx;        /* [capacity][N] */
-    int32_t *count;      /* [N] */
+    int32_t *idx;        /* [capacity/W][N][W] */
+    int32_t *count;      /* [N][W] */
     uint32_t *pos_ref;   /* [N][dim] positions at the last build */
     int32_t *flags;      /* [MD_NFLAGS] */
 } md_nlist;
@@ -124,12 +128,15 @@ md_status md_ctx_create(int device, md_ctx **out);
 /* Synchronise the device and free the context's scratch. */
 md_status md_ctx_destroy(md_ctx *ctx);
 /*
- * Reserve scratch for up to N particles in `dim` dimensions and up to
- * max_cells cells.  This is the only call that allocates; it synchronises
- * the device when it has to grow.  Every other call returns MD_ERR_CAPACITY
- * when it would need more than was reserved.
+ * Reserve scratch for up to N particles in `dim` dimensions, up to max_cells
+ * cells holding up to max_per_cell particles each, and a second neighbor-list
+ * generation of up to `capacity` entries per row in up to `lanes` sub-rows
+ * (used while rebuilding during verlet_step).  This is the only call that allocates; it
+ * synchronises the device when it has to grow.  Every other call returns
+ * MD_ERR_CAPACITY when it would need more than was reserved.
  */
-md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells);
+md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells, int32_t capacity, int32_t lanes,
+                         int32_t max_per_cell);
 /* Number of cells the cell list uses for this box and list radius (host only). */
 int32_t md_cell_count(const md_box *box, float r_list);
 
@@ -141,7 +148,8 @@ md_status md_positions_to_float(const md_box *box, const uint32_t *pos, float *x
 /*
  * Build the neighbor list of `pos` (Sec. 3.2.3): counting-sort cell binning
  * with cells of edge >= r_list (27 or 9 stencil cells; a dimension with fewer
- * than 3 cells is scanned whole), then one candidate scan per particle.  The
+ * than 3 cells is scanned whole) into bins of max_per_cell members (more
+ * raises MD_FLAG_CELL_OVERFLOW), then one candidate scan per particle.  The
  * predicate is r2 < r_list^2 with r2 evaluated in IEEE double as
  * d_0*d_0 + d_1*d_1 (+ d_2*d_2), d_k = (double)wrap32(pos_ik - pos_jk) *
  * (L_k / 2^32): a single-precision filter decides pairs far from the
@@ -168,14 +176,19 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
 /*
  * n_steps of velocity-Verlet NVE (Sec. 3.3.1), unit masses:
  *   v += dt/2 F;  r = shift(r, dt v);  F = F(r);  v += dt/2 F.
- * On entry `force` must hold F(pos) (pair_energy_force) and nl must be a
- * valid list for pos (nl_build).  Before each force evaluation the list is
- * rebuilt on the device when some particle has moved more than nl->skin/2
- * since the last build; no host synchronisation happens.  On return pos,
- * vel and force hold the state after n_steps.  If a rebuild overflows, the
- * remaining steps do nothing, MD_FLAG_OVERFLOW stays set, MD_FLAG_STEPS
- * counts the steps that were done, and the state is partial: the caller
- * re-runs from its own copy of the input with a larger capacity.
+ * On entry `force` must hold F(pos).  The call first rebuilds nl for pos, then
+ * enqueues one launch per step, in which nl->lanes lanes share a particle.  The list is kept valid on the device with no
+ * host synchronisation: when a particle's displacement since the last build
+ * plus twice its last step (and dt^2 |F|) would exceed nl->skin/2, the next
+ * two launches rebuild it into a second generation while forces still use the
+ * current one, and the launch after that switches (Sec. 3.1: the list is
+ * rebuilt when particles have moved too far for the halo).  Every step checks
+ * that the list it uses is within skin/2 of the positions and raises
+ * MD_FLAG_STALE otherwise.  On return pos, vel, force and nl hold the state
+ * after n_steps.  If a build overflows (MD_FLAG_OVERFLOW / _CELL_OVERFLOW) or
+ * a list went stale, the remaining steps do nothing, MD_FLAG_STEPS tells the
+ * last step that ran, and the state is partial: the caller re-runs from its
+ * own copy of the input with larger capacities (or shorter calls).
  */
 md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                       float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt,
@@ -202,8 +215,8 @@ typedef struct {
 } md_fire_state;
 
 /*
- * FIRE descent init (Sec. 3.3.1, App. A "fire_descent"): vel = 0,
- * force = F(pos) over nl, st = {dt_start, alpha_start, n_pos 0}, fmax and
+ * FIRE descent init (Sec. 3.3.1, App. A "fire_descent"): rebuilds nl for pos,
+ * vel = 0, force = F(pos), st = {dt_start, alpha_start, n_pos 0}, fmax and
  * converged from the initial forces against f_tol.
  */
 md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos,
@@ -217,8 +230,11 @@ md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, con
  *   else : dt *= f_dec, v = 0, a = alpha_start, n_pos = 0.
  * Steps after convergence do nothing, so the call can be enqueued in fixed
  * chunks; st->converged / st->steps tell the caller where it stopped.  The
- * neighbor list is rebuilt on the device as in verlet_step.  Global sums are
- * double and summed in a fixed order.
+ * call rebuilds nl for pos first; before each force evaluation a rebuild runs
+ * on the device when a particle has moved more than skin/2 since the last
+ * one (its launches return at once otherwise).  The velocity mixing decided by a step is applied at the start
+ * of the next one (st->mix_v, st->mix_f).  Global sums are double and summed
+ * in a fixed order by one workgroup.
  */
 md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                     float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,

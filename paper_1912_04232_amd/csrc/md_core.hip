@@ -1,99 +1,156 @@
 // gfx950 kernels of the short-range MD path and the C ABI that launches them.
 //
-//   cell list      counting sort of particles by cell (Sec. 3.2.3): integer
-//                  counts, an atomics-free exclusive scan in LDS, placement,
-//                  then each cell's members ordered by index so every build
-//                  is deterministic.
-//   neighbor list  27 (3D) / 9 (2D) stencil cells per particle, float filter
-//                  with a guard band, double recheck near r_list; ELL rows.
-//   forces         one lane per particle i walks its ELL row; neighbor
-//                  positions are gathered as packed uint32 torus coordinates
-//                  whose integer difference is the nearest image (Sec. 3.2.1).
-//   velocity Verlet / FIRE  one cooperative launch per step; the neighbor list
-//                  is rebuilt inside that launch, behind grid barriers, when
-//                  the previous step flagged a particle that moved more than
-//                  skin/2 (Sec. 3.1), so no host round trip is needed.
-#include <hip/hip_cooperative_groups.h>
+//   lanes          every per-particle kernel gives a particle W lanes (W = nl->lanes, 1..8):
+//                  the lanes split the particle's neighbor list (and, when building it,
+//                  its stencil candidates) and meet again through __shfl_xor.  With one
+//                  lane per particle a 256k-particle system is only ~4k waves, too few to
+//                  hide gather latency on 256 CUs; W = 4 gives ~16k.
+//   neighbor list  ELL with W interleaved sub-rows: entry t of lane l of particle i lives at
+//                  idx[(t*N + i)*W + l], lane l's length at count[i*W + l].  A lane walks the
+//                  stencil cells in a fixed order and takes every W-th candidate, so rows are
+//                  deterministic.  A float filter with a guard band decides most pairs, the
+//                  defining double expression the rest (Sec. 3.2.3).
+//   cell list      fixed-capacity bins: bin c holds up to M (index, position) members.
+//                  A standalone build fills them by a counting sort (integer counts, an
+//                  atomics-free exclusive scan in LDS, placement, members ordered by index).
+//                  Inside a Verlet run the bins are refreshed without atomics: one wave per
+//                  cell gathers, from the previous bins of its stencil cells, the particles
+//                  whose cell it now is (ballot compaction keeps the order deterministic).
+//   forces         neighbor positions are uint32 torus coordinates whose integer difference
+//                  is the nearest image exactly (Sec. 3.2.1).
+//   velocity Verlet one regular launch per step.  A rebuild is pipelined over the next two
+//                  step launches (bins, then rows of a second list generation) while forces
+//                  keep using the current list; it starts when a particle's displacement plus
+//                  twice its last step would exceed skin/2 (Sec. 3.1), and every step checks
+//                  that the list it uses is still valid.  No grid barrier, no host round trip.
+//   FIRE           per step: mix + drift, a counting-sort rebuild gated on the device (its
+//                  launches return at once unless a particle moved more than skin/2), forces
+//                  with per-workgroup double partial sums, and a one-workgroup reduction that
+//                  applies the FIRE rules in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
-#include <mutex>
-#include <unordered_map>
-
 #include "../../include/md.h"
 #include "md_device.h"
 
-namespace cg = cooperative_groups;
 using namespace md;
 
 // ------------------------------------------------------------------------------------------------
 // argument blocks
 
-struct CellScratch {
+struct Bins {
+    int32_t *cnt;   // [C]
+    int32_t *id;    // [C][M]
+    uint32_t *pos;  // [C][M][D]
+};
+
+struct ListGen {
+    int32_t *idx;       // [cap/W][N][W]
+    int32_t *count;     // [N][W]
+    uint32_t *pos_ref;  // [N][D]
+};
+
+struct ListParams {
+    int32_t N, cap, W, capW, M;
+    float rl2f_lo, rl2f_hi;  // float guard band around r_list^2
+    double rl2;              // (double)r_list * (double)r_list
+    float half_skin;         // skin / 2
+    float kappa;             // pipelined rebuild starts when disp + kappa * (last step + dt^2 |F|) > skin/2
+};
+
+struct CountSort {
     int32_t *cell_of;
     int32_t *slot;
     int32_t *sorted_idx;
-    uint32_t *pos_sorted;
     int32_t *cell_count;
     int32_t *cell_start;
 };
 
-struct NLView {
-    int32_t N, cap;
-    float rl2f_lo, rl2f_hi;  // float guard band around r_list^2
-    double rl2;              // (double)r_list * (double)r_list
-    float half_skin2;        // (skin/2)^2
-    int32_t *idx;
-    int32_t *count;
-    uint32_t *pos_ref;
-    int32_t *flags;
-};
+enum { M_IDLE = 0, M_BIN = 1, M_BUILD = 2 };
+// Control words (device).  Verlet: ctl[2*slot] = mode and ctl[2*slot+1] = generation of step s at
+// slot s % 3, written by workgroup 0 of step s-1; ctl[6 + slot] = rebuild request for step s, written
+// by any workgroup of step s-1; ctl[kGenWord] = generation to use after the last step that ran.
+// FIRE: ctl[kTrigWord] = rebuild needed before this step's forces.
+constexpr int kCtlWords = 16;
+constexpr int kGenWord = 9;
+constexpr int kTrigWord = 10;
 
-struct StepArgs {
-    DevBox box;
-    CellScratch cs;
-    NLView nl;
-    const uint32_t *pos_in;
-    uint32_t *pos_out;
-    float *vel;
-    float *force;
-    const int32_t *species;
-    int32_t N;
-    float dt;
-    int32_t step;      // step index s >= 1
-    int32_t rot_read, rot_set, rot_clear;
-    int32_t mode;      // 1 = interior step (kick dt, drift), 2 = last step (kick dt/2, store F)
-    int32_t force_rebuild;
-};
-
-// ------------------------------------------------------------------------------------------------
-// cell list and neighbor list phases; (tid, nth) is a grid-stride range
-
-__device__ void phase_zero_counts(const CellScratch &cs, int C, int tid, int nth)
+// Set *addr = 1 when any lane of the wave has cond (one store per wave instead of one per lane).
+__device__ __forceinline__ void wave_flag(bool cond, int32_t *addr)
 {
-    for (int c = tid; c < C; c += nth) cs.cell_count[c] = 0;
+    uint64_t m = __ballot(cond);
+    if (m != 0 && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) *addr = 1;
+}
+
+__device__ __forceinline__ int wrapc(int c, int n)
+{
+    return c < 0 ? c + n : (c >= n ? c - n : c);
+}
+
+// Block index remapped so that the workgroups one XCD receives (round-robin over 8 XCDs) own one
+// contiguous range of particles: neighbor gathers then mostly hit that XCD's L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb)
+{
+    if ((nb & 7) != 0) return bid;
+    return (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ bool gate_closed(const int32_t *gate)
+{
+    return gate != nullptr && *gate == 0;
+}
+
+// Stencil cell number t (0 .. nst-1) around cell (cx, cy, cz), in z-major, then y, then x order.
+template <int D>
+__device__ __forceinline__ int stencil_cell(const DevBox &b, int cx, int cy, int cz, int t)
+{
+    int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1;
+    int x = wrapc(cx + b.lo[0] + t % n0, b.nc[0]);
+    int y = wrapc(cy + b.lo[1] + (t / n0) % n1, b.nc[1]);
+    int z = 0;
+    if constexpr (D == 3) z = wrapc(cz + b.lo[2] + t / (n0 * n1), b.nc[2]);
+    return x + b.nc[0] * (y + b.nc[1] * z);
 }
 
 template <int D>
-__device__ void phase_bin(const uint32_t *__restrict__ pos, int N, const DevBox &b, const CellScratch &cs, int tid,
-                          int nth)
+__device__ __forceinline__ int stencil_size(const DevBox &b)
 {
-    for (int i = tid; i < N; i += nth) {
-        uint32_t u[D];
-        load_pos<D>(pos, i, u);
-        int c = cell_index<D>(u, b);
-        cs.cell_of[i] = c;
-        cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: order-free result
-    }
+    int n = (b.hi[0] - b.lo[0] + 1) * (b.hi[1] - b.lo[1] + 1);
+    if constexpr (D == 3) n *= b.hi[2] - b.lo[2] + 1;
+    return n;
 }
 
-// Exclusive scan of cell_count into cell_start[0..C], run by one workgroup.
-__device__ void phase_scan_block(const CellScratch &cs, int C)
+// ------------------------------------------------------------------------------------------------
+// counting sort into bins (deterministic); every kernel returns at once when its gate word is 0
+
+__global__ void k_cs_zero(int32_t *cell_count, int C, const int32_t *gate)
+{
+    if (gate_closed(gate)) return;
+    int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c < C) cell_count[c] = 0;
+}
+
+template <int D>
+__global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, DevBox b, CountSort cs, const int32_t *gate)
+{
+    if (gate_closed(gate)) return;
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    uint32_t u[D];
+    load_pos<D>(pos, i, u);
+    int c = cell_index<D>(u, b);
+    cs.cell_of[i] = c;
+    cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: the totals do not depend on order
+}
+
+// Exclusive scan of cell_count into cell_start[0..C] by one workgroup (LDS, no atomics).
+__global__ __launch_bounds__(kBlock) void k_cs_scan(CountSort cs, int C, const int32_t *gate)
 {
     __shared__ int lds[kBlock];
+    if (gate_closed(gate)) return;
     int t = threadIdx.x;
     int chunk = (C + kBlock - 1) / kBlock;
     int lo = min(C, t * chunk), hi = min(C, lo + chunk);
@@ -108,165 +165,231 @@ __device__ void phase_scan_block(const CellScratch &cs, int C)
     if (t == 0) cs.cell_start[C] = total;
 }
 
-__device__ void phase_place(const CellScratch &cs, int N, int tid, int nth)
+__global__ void k_cs_place(CountSort cs, int N, const int32_t *gate)
 {
-    for (int i = tid; i < N; i += nth) cs.sorted_idx[cs.cell_start[cs.cell_of[i]] + cs.slot[i]] = i;
+    if (gate_closed(gate)) return;
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < N) cs.sorted_idx[cs.cell_start[cs.cell_of[i]] + cs.slot[i]] = i;
 }
 
-// Order each cell's members by particle index and gather their positions in that order.
+// One thread per cell: order the members by index and write them, with their positions, to the bin.
 template <int D>
-__device__ void phase_sort_cells(const uint32_t *__restrict__ pos, const CellScratch &cs, int C, int tid, int nth)
+__global__ __launch_bounds__(kBlock) void k_cs_fill_bins(const uint32_t *__restrict__ pos, CountSort cs, Bins bins,
+                                                         int C, int M, int32_t *flags, const int32_t *gate)
 {
-    for (int c = tid; c < C; c += nth) {
+    __shared__ int red[kBlock];
+    if (gate_closed(gate)) return;
+    int c = blockIdx.x * kBlock + threadIdx.x;
+    int occ = 0;
+    if (c < C) {
         int s = cs.cell_start[c], e = cs.cell_start[c + 1];
         for (int a = s + 1; a < e; ++a) {
             int key = cs.sorted_idx[a];
-            int b = a - 1;
-            while (b >= s && cs.sorted_idx[b] > key) {
-                cs.sorted_idx[b + 1] = cs.sorted_idx[b];
-                --b;
+            int q = a - 1;
+            while (q >= s && cs.sorted_idx[q] > key) {
+                cs.sorted_idx[q + 1] = cs.sorted_idx[q];
+                --q;
             }
-            cs.sorted_idx[b + 1] = key;
+            cs.sorted_idx[q + 1] = key;
         }
-        for (int a = s; a < e; ++a) {
+        occ = e - s;
+        int n = min(occ, M);
+        bins.cnt[c] = n;
+        for (int a = 0; a < n; ++a) {
+            int j = cs.sorted_idx[s + a];
+            bins.id[(size_t)c * M + a] = j;
             uint32_t u[D];
-            load_pos<D>(pos, cs.sorted_idx[a], u);
-            store_pos<D>(cs.pos_sorted, a, u);
+            load_pos<D>(pos, j, u);
+            store_pos<D>(bins.pos + (size_t)c * M * D, a, u);
         }
+    }
+    wave_flag(occ > M, &flags[MD_FLAG_CELL_OVERFLOW]);
+    occ = block_max(occ, red);
+    if (threadIdx.x == 0) atomicMax(&flags[MD_FLAG_MAXCELL], occ);
+}
+
+// Lane l's share of particle i's row at reference position ui: walk the stencil bins in order,
+// numbering candidates g = 0, 1, ...; lane l tests the candidates with g % W == l.
+template <int D, int W>
+__device__ __forceinline__ int build_lane(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
+                                          const ListParams &lp, int32_t *__restrict__ idx)
+{
+    int cx = cell_coord(ui[0], b.nc[0]);
+    int cy = cell_coord(ui[1], b.nc[1]);
+    int cz = 0;
+    if constexpr (D == 3) cz = cell_coord(ui[2], b.nc[2]);
+    int nst = stencil_size<D>(b);
+    int n = 0, g = 0;
+    for (int t = 0; t < nst; ++t) {
+        int cell = stencil_cell<D>(b, cx, cy, cz, t);
+        int m = bins.cnt[cell];
+        const int32_t *bid = bins.id + (size_t)cell * lp.M;
+        const uint32_t *bpos = bins.pos + (size_t)cell * lp.M * D;
+        int k = (l - g % W + W) % W;
+        g += m;
+        for (; k < m; k += W) {
+            uint32_t uj[D];
+            load_pos<D>(bpos, k, uj);
+            float r2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                float d = tdisp(ui[q], uj[q], b.s[q]);
+                r2 = __builtin_fmaf(d, d, r2);
+            }
+            bool acc;
+            if (r2 < lp.rl2f_lo) {
+                acc = true;
+            } else if (r2 > lp.rl2f_hi) {
+                acc = false;
+            } else {
+                // the defining double expression, evaluated without contraction
+                double r2d = 0.0;
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    double d = tdisp_d(ui[q], uj[q], b.sd[q]);
+                    r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                }
+                acc = r2d < lp.rl2;
+            }
+            int j = bid[k];
+            if (acc && j != i) {
+                if (n < lp.capW) idx[((size_t)n * lp.N + i) * W + l] = j;
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
+// Rows of every particle from the bins; pos_ref = the positions the rows were built from.
+template <int D, int W>
+__global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restrict__ pos, DevBox b, Bins bins,
+                                                       ListParams lp, ListGen g, int32_t *flags, const int32_t *gate)
+{
+    __shared__ int red[kBlock];
+    if (gate_closed(gate)) return;
+    int gt = blockIdx.x * kBlock + threadIdx.x;
+    int i = gt / W, l = gt % W;
+    int n = 0;
+    if (i < lp.N) {
+        uint32_t ui[D];
+        load_pos<D>(pos, i, ui);
+        n = build_lane<D, W>(i, l, ui, b, bins, lp, g.idx);
+        g.count[(size_t)i * W + l] = n;
+        if (l == 0) store_pos<D>(g.pos_ref, i, ui);
+    }
+    wave_flag(n > lp.capW, &flags[MD_FLAG_OVERFLOW]);
+    n = block_max(n, red);
+    if (threadIdx.x == 0) {
+        atomicMax(&flags[MD_FLAG_MAXCOUNT], n * W);
+        if (blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
     }
 }
 
-__device__ __forceinline__ int wrapc(int c, int n)
-{
-    return c < 0 ? c + n : (c >= n ? c - n : c);
-}
+// ------------------------------------------------------------------------------------------------
+// in-run bin refresh (no atomics): one wave per cell
 
-// One ELL row per particle.  Returns the largest row length this thread saw.
+// Gather, from the previous bins of cell c's stencil, the members whose cell at the current positions
+// `pos` is c.  The stencil's candidates are numbered in stencil order, then previous bin order, and
+// handed out 64 at a time to the wave's lanes; ballot compaction keeps that order.
 template <int D>
-__device__ int phase_build(const uint32_t *__restrict__ pos, int N, const DevBox &b, const CellScratch &cs,
-                           const NLView &nl, int tid, int nth)
+__device__ int bin_gather(const uint32_t *__restrict__ pos, const DevBox &b, const Bins &prev, const Bins &next,
+                          int M, int32_t *flags, int wave, int nwaves)
 {
+    int lane = threadIdx.x & 63;
+    int nst = stencil_size<D>(b);
     int mymax = 0;
-    for (int i = tid; i < N; i += nth) {
-        uint32_t ui[D];
-        load_pos<D>(pos, i, ui);
-        int cx = cell_coord(ui[0], b.nc[0]);
-        int cy = cell_coord(ui[1], b.nc[1]);
-        int cz = 0;
-        if constexpr (D == 3) cz = cell_coord(ui[2], b.nc[2]);
-        int n = 0;
-        int zlo = D == 3 ? b.lo[2] : 0, zhi = D == 3 ? b.hi[2] : 0;
-        for (int oz = zlo; oz <= zhi; ++oz) {
-            int z = D == 3 ? wrapc(cz + oz, b.nc[2]) : 0;
-            for (int oy = b.lo[1]; oy <= b.hi[1]; ++oy) {
-                int y = wrapc(cy + oy, b.nc[1]);
-                for (int ox = b.lo[0]; ox <= b.hi[0]; ++ox) {
-                    int x = wrapc(cx + ox, b.nc[0]);
-                    int cell = x + b.nc[0] * (y + b.nc[1] * z);
-                    int s = cs.cell_start[cell], e = cs.cell_start[cell + 1];
-                    for (int k = s; k < e; ++k) {
-                        uint32_t uj[D];
-                        load_pos<D>(cs.pos_sorted, k, uj);
-                        float r2 = 0.0f;
-#pragma unroll
-                        for (int q = 0; q < D; ++q) {
-                            float d = tdisp(ui[q], uj[q], b.s[q]);
-                            r2 = __builtin_fmaf(d, d, r2);
-                        }
-                        bool acc;
-                        if (r2 < nl.rl2f_lo) {
-                            acc = true;
-                        } else if (r2 > nl.rl2f_hi) {
-                            acc = false;
-                        } else {
-                            // the defining double expression, no contraction
-                            double r2d = 0.0;
-#pragma unroll
-                            for (int q = 0; q < D; ++q) {
-                                double d = tdisp_d(ui[q], uj[q], b.sd[q]);
-                                r2d = __dadd_rn(r2d, __dmul_rn(d, d));
-                            }
-                            acc = r2d < nl.rl2;
-                        }
-                        int j = cs.sorted_idx[k];
-                        if (acc && j != i) {
-                            if (n < nl.cap) nl.idx[(size_t)n * N + i] = j;
-                            ++n;
-                        }
-                    }
-                }
-            }
+    for (int c = wave; c < b.C; c += nwaves) {
+        int cx = c % b.nc[0];
+        int cy = (c / b.nc[0]) % b.nc[1];
+        int cz = D == 3 ? c / (b.nc[0] * b.nc[1]) : 0;
+        int src = 0, m = 0;
+        if (lane < nst) {
+            src = stencil_cell<D>(b, cx, cy, cz, lane);
+            m = prev.cnt[src];
         }
-        nl.count[i] = n;
-        if (n > nl.cap) nl.flags[MD_FLAG_OVERFLOW] = 1;
-        mymax = max(mymax, n);
-        store_pos<D>(nl.pos_ref, i, ui);
+        int incl = m;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        int excl = incl - m;
+        int total = __shfl(incl, 63);
+        int cnt = 0;
+        for (int base = 0; base < total; base += 64) {
+            int q = base + lane;
+            // stencil cell holding candidate q: the largest t with excl_t <= q
+            int t = 0;
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1) {
+                int cand = t + step;
+                int e = __shfl(excl, cand < nst ? cand : nst - 1);
+                if (cand < nst && e <= q) t = cand;
+            }
+            int s_src = __shfl(src, t);
+            int s_ex = __shfl(excl, t);
+            bool take = false;
+            int j = 0;
+            uint32_t u[D];
+            if (q < total) {
+                j = prev.id[(size_t)s_src * M + (q - s_ex)];
+                load_pos<D>(pos, j, u);
+                take = cell_index<D>(u, b) == c;
+            }
+            uint64_t mask = __ballot(take);
+            int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+            int slot = cnt + before;
+            if (take && slot < M) {
+                next.id[(size_t)c * M + slot] = j;
+                store_pos<D>(next.pos + (size_t)c * M * D, slot, u);
+            }
+            cnt += __popcll(mask);
+        }
+        if (lane == 0) {
+            next.cnt[c] = min(cnt, M);
+            if (cnt > M) flags[MD_FLAG_CELL_OVERFLOW] = 1;  // one store per overflowing cell
+        }
+        mymax = max(mymax, cnt);
     }
     return mymax;
 }
 
-__device__ __forceinline__ int32_t load_flag(int32_t *flags, int w)
-{
-    return __hip_atomic_load(&flags[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Full rebuild inside a cooperative launch.  Every workgroup must call it.
-template <int D>
-__device__ void rebuild_coop(cg::grid_group &g, const uint32_t *pos, int N, const DevBox &b, const CellScratch &cs,
-                             const NLView &nl, int tid, int nth)
-{
-    __shared__ int red[kBlock];
-    phase_zero_counts(cs, b.C, tid, nth);
-    g.sync();
-    phase_bin<D>(pos, N, b, cs, tid, nth);
-    g.sync();
-    if (blockIdx.x == 0) phase_scan_block(cs, b.C);
-    g.sync();
-    phase_place(cs, N, tid, nth);
-    g.sync();
-    phase_sort_cells<D>(pos, cs, b.C, tid, nth);
-    g.sync();
-    int m = phase_build<D>(pos, N, b, cs, nl, tid, nth);
-    m = block_max(m, red);
-    if (threadIdx.x == 0) {
-        atomicMax(&nl.flags[MD_FLAG_MAXCOUNT], m);
-        if (blockIdx.x == 0) nl.flags[MD_FLAG_REBUILDS] += 1;
-    }
-    g.sync();
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_nl_build(DevBox b, CellScratch cs, NLView nl, const uint32_t *pos, int N)
-{
-    cg::grid_group g = cg::this_grid();
-    int tid = blockIdx.x * kBlock + threadIdx.x, nth = gridDim.x * kBlock;
-    rebuild_coop<D>(g, pos, N, b, cs, nl, tid, nth);
-}
-
 // ------------------------------------------------------------------------------------------------
-// forces over the neighbor list / all pairs
+// forces
 
-template <int D, int KIND, bool MULTI, bool WANT_EW>
-__global__ __launch_bounds__(kBlock) void k_pair_nl(DevBox b, DevPot p, const uint32_t *__restrict__ pos,
-                                                     const int32_t *__restrict__ species, int N,
-                                                     const int32_t *__restrict__ idx,
-                                                     const int32_t *__restrict__ count, int cap,
-                                                     float *__restrict__ force,
-                                                     double *__restrict__ energy, double *__restrict__ virial,
-                                                     int32_t *flags)
+// Force from lane l's sub-row of particle i (the hot loop), then summed over the W lanes.
+template <int D, int KIND, bool MULTI, int W>
+__device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, const uint32_t *__restrict__ pos,
+                                           const int32_t *__restrict__ species, int N,
+                                           const int32_t *__restrict__ idx, int n, int i, int l, const uint32_t *ui,
+                                           int si, float *F)
 {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= N) return;
-    uint32_t ui[D];
-    load_pos<D>(pos, i, ui);
-    int si = MULTI ? species[i] : 0;
-    float F[D];
+    int t = 0;
+    for (; t + 4 <= n; t += 4) {
+        int j[4];
 #pragma unroll
-    for (int q = 0; q < D; ++q) F[q] = 0.0f;
-    double e = 0.0, w = 0.0;
-    int n = min(count[i], cap);  // an overflowed row holds only its first cap entries
-    for (int k = 0; k < n; ++k) {
-        int j = idx[(size_t)k * N + i];
+        for (int a = 0; a < 4; ++a) j[a] = idx[((size_t)(t + a) * N + i) * W + l];
+        uint32_t uj[4][D];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) load_pos<D>(pos, j[a], uj[a]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            float d[D], r2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                d[q] = tdisp(ui[q], uj[a][q], b.s[q]);
+                r2 = __builtin_fmaf(d[q], d[q], r2);
+            }
+            int pt = MULTI ? si * p.S + species[j[a]] : 0;
+            float u;
+            float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
+#pragma unroll
+            for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+        }
+    }
+    for (; t < n; ++t) {
+        int j = idx[((size_t)t * N + i) * W + l];
         uint32_t uj[D];
         load_pos<D>(pos, j, uj);
         float d[D], r2 = 0.0f;
@@ -276,27 +399,72 @@ __global__ __launch_bounds__(kBlock) void k_pair_nl(DevBox b, DevPot p, const ui
             r2 = __builtin_fmaf(d[q], d[q], r2);
         }
         int pt = MULTI ? si * p.S + species[j] : 0;
-        float u = 0.0f;
-        float fs = pair_fs<KIND, MULTI, WANT_EW>(p, pt, r2, u);
+        float u;
+        float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
 #pragma unroll
         for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+    }
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) F[q] += __shfl_xor(F[q], o);
+    }
+}
+
+// Forces (and optionally e_i, w_i) over a list: one thread per particle walks all W sub-rows.
+template <int D, int KIND, bool MULTI, bool WANT_EW>
+__global__ __launch_bounds__(kBlock) void k_pair_nl(DevBox b, DevPot p, const uint32_t *__restrict__ pos,
+                                                     const int32_t *__restrict__ species, int N,
+                                                     const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ count, int W, int capW,
+                                                     float *__restrict__ force, double *__restrict__ energy,
+                                                     double *__restrict__ virial, int32_t *flags)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    bool bad = false;
+    if (i < N) {
+        uint32_t ui[D];
+        load_pos<D>(pos, i, ui);
+        int si = MULTI ? species[i] : 0;
+        float F[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) F[q] = 0.0f;
+        double e = 0.0, w = 0.0;
+        for (int l = 0; l < W; ++l) {
+            int n = min(count[(size_t)i * W + l], capW);  // an overflowed sub-row holds its first capW entries
+            for (int t = 0; t < n; ++t) {
+                int j = idx[((size_t)t * N + i) * W + l];
+                uint32_t uj[D];
+                load_pos<D>(pos, j, uj);
+                float d[D], r2 = 0.0f;
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    d[q] = tdisp(ui[q], uj[q], b.s[q]);
+                    r2 = __builtin_fmaf(d[q], d[q], r2);
+                }
+                int pt = MULTI ? si * p.S + species[j] : 0;
+                float u = 0.0f;
+                float fs = pair_fs<KIND, MULTI, WANT_EW>(p, pt, r2, u);
+#pragma unroll
+                for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+                if (WANT_EW) {
+                    e += (double)u;
+                    w += (double)(fs * r2);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
+        if (force) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) force[(size_t)i * D + q] = F[q];
+        }
         if (WANT_EW) {
-            e += (double)u;
-            w += (double)(fs * r2);
+            if (energy) energy[i] = 0.5 * e;
+            if (virial) virial[i] = 0.5 * w;
         }
     }
-    bool fin = true;
-#pragma unroll
-    for (int q = 0; q < D; ++q) fin = fin && isfinite(F[q]);
-    if (!fin) flags[MD_FLAG_NONFINITE] = 1;
-    if (force) {
-#pragma unroll
-        for (int q = 0; q < D; ++q) force[(size_t)i * D + q] = F[q];
-    }
-    if (WANT_EW) {
-        if (energy) energy[i] = 0.5 * e;
-        if (virial) virial[i] = 0.5 * w;
-    }
+    wave_flag(bad, &flags[MD_FLAG_NONFINITE]);
 }
 
 // Dense O(N^2): each workgroup owns kBlock particles i and streams every j through LDS.
@@ -349,177 +517,223 @@ __global__ __launch_bounds__(kBlock) void k_pair_dense(DevBox b, DevPot p, const
         }
         __syncthreads();
     }
-    if (!live) return;
-    bool fin = true;
+    bool bad = false;
+    if (live) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) fin = fin && isfinite(F[q]);
-    if (!fin) flags[MD_FLAG_NONFINITE] = 1;
-    if (force) {
+        for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
+        if (force) {
 #pragma unroll
-        for (int q = 0; q < D; ++q) force[(size_t)i * D + q] = F[q];
+            for (int q = 0; q < D; ++q) force[(size_t)i * D + q] = F[q];
+        }
+        if (WANT_EW) {
+            if (energy) energy[i] = 0.5 * e;
+            if (virial) virial[i] = 0.5 * w;
+        }
     }
-    if (WANT_EW) {
-        if (energy) energy[i] = 0.5 * e;
-        if (virial) virial[i] = 0.5 * w;
-    }
+    wave_flag(bad, &flags[MD_FLAG_NONFINITE]);
 }
 
 // ------------------------------------------------------------------------------------------------
 // velocity Verlet
 
-// Force on particle i from its ELL row (the hot loop of every step).
-template <int D, int KIND, bool MULTI>
-__device__ __forceinline__ void row_force(const DevBox &b, const DevPot &p, const uint32_t *__restrict__ pos,
-                                          const int32_t *__restrict__ species, int N,
-                                          const int32_t *__restrict__ idx, int n, int i, const uint32_t *ui, int si,
-                                          float *F)
-{
-    int k = 0;
-    for (; k + 4 <= n; k += 4) {
-        int j[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) j[t] = idx[(size_t)(k + t) * N + i];
-        uint32_t uj[4][D];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) load_pos<D>(pos, j[t], uj[t]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float d[D], r2 = 0.0f;
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                d[q] = tdisp(ui[q], uj[t][q], b.s[q]);
-                r2 = __builtin_fmaf(d[q], d[q], r2);
-            }
-            int pt = MULTI ? si * p.S + species[j[t]] : 0;
-            float u;
-            float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
-#pragma unroll
-            for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
-        }
-    }
-    for (; k < n; ++k) {
-        int j = idx[(size_t)k * N + i];
-        uint32_t uj[D];
-        load_pos<D>(pos, j, uj);
-        float d[D], r2 = 0.0f;
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            d[q] = tdisp(ui[q], uj[q], b.s[q]);
-            r2 = __builtin_fmaf(d[q], d[q], r2);
-        }
-        int pt = MULTI ? si * p.S + species[j] : 0;
-        float u;
-        float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
-#pragma unroll
-        for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
-    }
-}
-
-// Shift (Sec. 3.2.1) by a real displacement: add its nearest integer number of 2^-32 L units; wraps mod 2^32.
+// Shift (Sec. 3.2.1) by a real displacement: add its nearest whole number of 2^-32 L units (wraps mod 2^32).
 __device__ __forceinline__ uint32_t shift_coord(uint32_t u, float dx, float inv_s)
 {
     return u + (uint32_t)__float2int_rn(dx * inv_s);
 }
 
 template <int D>
-__device__ __forceinline__ bool moved_too_far(const uint32_t *un, const uint32_t *__restrict__ ref, int i,
-                                              const DevBox &b, float half_skin2)
+__device__ __forceinline__ float disp2(const uint32_t *a, const uint32_t *__restrict__ ref, int i, const DevBox &b)
 {
     float r2 = 0.0f;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-        float d = tdisp(un[q], ref[(size_t)i * D + q], b.s[q]);
+        float d = tdisp(a[q], ref[(size_t)i * D + q], b.s[q]);
         r2 = __builtin_fmaf(d, d, r2);
     }
-    return r2 > half_skin2;
+    return r2;
 }
 
-// First half kick and drift: v += dt/2 F; r += dt v.  Flags a rebuild for step 1.
+struct StepArgs {
+    DevBox box;
+    ListParams lp;
+    ListGen gen[2];
+    Bins bins[2];
+    int32_t *flags;
+    int32_t *ctl;
+    const uint32_t *pos_in;
+    uint32_t *pos_out;
+    float *vel;
+    float *force;
+    const int32_t *species;
+    float dt;
+    int32_t step;  // s >= 1
+    int32_t last;  // 1: kick dt/2, store F, no drift
+};
+
+// Control state of step s: {mode, gen} from the previous step's workgroup 0, upgraded to BIN when a
+// rebuild was requested.  Workgroup 0 publishes step s+1's words and clears the request slot of s+2.
+__device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s, int &mode, int &gen)
+{
+    int r = s % 3;
+    mode = ctl[2 * r];
+    gen = ctl[2 * r + 1];
+    if (mode == M_IDLE && ctl[6 + r]) mode = M_BIN;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int nm = mode == M_BIN ? M_BUILD : M_IDLE;
+        int ng = mode == M_BUILD ? gen ^ 1 : gen;
+        ctl[2 * ((s + 1) % 3)] = nm;
+        ctl[2 * ((s + 1) % 3) + 1] = ng;
+        ctl[6 + (s + 2) % 3] = 0;
+        ctl[kGenWord] = ng;
+        flags[MD_FLAG_STEPS] = s;
+        if (mode == M_BUILD) flags[MD_FLAG_REBUILDS] += 1;
+    }
+}
+
+__device__ __forceinline__ bool frozen(const int32_t *flags)
+{
+    return flags[MD_FLAG_OVERFLOW] | flags[MD_FLAG_CELL_OVERFLOW] | flags[MD_FLAG_STALE];
+}
+
+// First half kick and drift of a verlet_step call: v += dt/2 F; r(1) = r(0) + dt v; rebuild request for step 1.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_verlet_begin(DevBox b, const uint32_t *__restrict__ pos_in,
-                                                          uint32_t *__restrict__ pos_out, float *__restrict__ vel,
-                                                          const float *__restrict__ force, const uint32_t *pos_ref,
-                                                          int N, float dt, float half_skin2, int32_t *flags,
-                                                          int rot_set)
+__global__ __launch_bounds__(kBlock) void k_verlet_begin(StepArgs a)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= N) return;
+    bool req = false;
+    if (i < a.lp.N) {
+        uint32_t ui[D], un[D];
+        float step2 = 0.0f, f2 = 0.0f;
+        load_pos<D>(a.pos_in, i, ui);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            float f = a.force[(size_t)i * D + q];
+            float v = __builtin_fmaf(0.5f * a.dt, f, a.vel[(size_t)i * D + q]);
+            a.vel[(size_t)i * D + q] = v;
+            float dx = a.dt * v;
+            un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
+            step2 = __builtin_fmaf(dx, dx, step2);
+            f2 = __builtin_fmaf(f, f, f2);
+        }
+        store_pos<D>(a.pos_out, i, un);
+        float d = sqrtf(disp2<D>(un, a.gen[0].pos_ref, i, a.box));
+        float ahead = sqrtf(step2) + a.dt * a.dt * sqrtf(f2);
+        req = d + a.lp.kappa * ahead > a.lp.half_skin;
+    }
+    wave_flag(req, &a.ctl[6 + 1]);
+}
+
+// One velocity-Verlet step s >= 1 on r(s): rebuild work if one is in progress, F(s) over the current
+// list by W lanes per particle, then v += dt F and r(s+1) = r(s) + dt v (interior step) or
+// v += dt/2 F and F stored (last step).
+template <int D, int KIND, bool MULTI, int W>
+__global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
+{
+    __shared__ int red[kBlock];
+    if (frozen(a.flags)) return;
+    int mode, gen;
+    step_control(a.ctl, a.flags, a.step, mode, gen);
+    const ListParams &lp = a.lp;
+    if (mode == M_BIN) {
+        // bins and reference positions of the other generation from r(s)
+        int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+        int nwaves = (gridDim.x * kBlock) >> 6;
+        int occ = bin_gather<D>(a.pos_in, a.box, a.bins[gen], a.bins[gen ^ 1], lp.M, a.flags, wave, nwaves);
+        occ = block_max(occ, red);
+        if (threadIdx.x == 0) atomicMax(&a.flags[MD_FLAG_MAXCELL], occ);
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < lp.N; i += gridDim.x * kBlock) {
+            uint32_t ui[D];
+            load_pos<D>(a.pos_in, i, ui);
+            store_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
+        }
+    } else if (mode == M_BUILD) {
+        // rows of the other generation from those bins
+        int gt = blockIdx.x * kBlock + threadIdx.x;
+        int i = gt / W, l = gt % W;
+        int n = 0;
+        if (i < lp.N) {
+            uint32_t ui[D];
+            load_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
+            n = build_lane<D, W>(i, l, ui, a.box, a.bins[gen ^ 1], lp, a.gen[gen ^ 1].idx);
+            a.gen[gen ^ 1].count[(size_t)i * W + l] = n;
+        }
+        wave_flag(n > lp.capW, &a.flags[MD_FLAG_OVERFLOW]);
+        n = block_max(n, red);
+        if (threadIdx.x == 0) atomicMax(&a.flags[MD_FLAG_MAXCOUNT], n * W);
+    }
+    const ListGen &g = a.gen[gen];
+    int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    int i = gt / W, l = gt % W;
+    bool live = i < lp.N;
+    int ii = live ? i : lp.N - 1;  // dead lanes shadow the last particle so the lane reduction stays uniform
+    uint32_t ui[D];
+    load_pos<D>(a.pos_in, ii, ui);
+    bool stale = live && l == 0 && disp2<D>(ui, g.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
+    wave_flag(stale, &a.flags[MD_FLAG_STALE]);
+    int si = MULTI ? a.species[ii] : 0;
+    float F[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) F[q] = 0.0f;
+    int n = live ? min(g.count[(size_t)ii * W + l], lp.capW) : 0;
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos_in, a.species, lp.N, g.idx, n, ii, l, ui, si, F);
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
+    wave_flag(live && bad, &a.flags[MD_FLAG_NONFINITE]);
+    if (!live || l != 0) return;
+    if (a.last) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            a.vel[(size_t)i * D + q] = __builtin_fmaf(0.5f * a.dt, F[q], a.vel[(size_t)i * D + q]);
+            a.force[(size_t)i * D + q] = F[q];
+        }
+        return;
+    }
     uint32_t un[D];
+    float step2 = 0.0f, f2 = 0.0f;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-        float v = __builtin_fmaf(0.5f * dt, force[(size_t)i * D + q], vel[(size_t)i * D + q]);
-        vel[(size_t)i * D + q] = v;
-        un[q] = shift_coord(pos_in[(size_t)i * D + q], dt * v, b.inv_s[q]);
-        pos_out[(size_t)i * D + q] = un[q];
+        float v = __builtin_fmaf(a.dt, F[q], a.vel[(size_t)i * D + q]);
+        a.vel[(size_t)i * D + q] = v;
+        float dx = a.dt * v;
+        un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
+        step2 = __builtin_fmaf(dx, dx, step2);
+        f2 = __builtin_fmaf(F[q], F[q], f2);
     }
-    if (moved_too_far<D>(un, pos_ref, i, b, half_skin2)) flags[MD_FLAG_PENDING0 + rot_set] = 1;
+    store_pos<D>(a.pos_out, i, un);
+    if (mode == M_IDLE) {
+        float d = sqrtf(disp2<D>(un, g.pos_ref, i, a.box));
+        float ahead = sqrtf(step2) + a.dt * a.dt * sqrtf(f2);
+        if (d + lp.kappa * ahead > lp.half_skin) a.ctl[6 + (a.step + 1) % 3] = 1;
+    }
 }
 
-// Block index remapped so that the workgroups an XCD receives (round-robin over 8 XCDs) own one
-// contiguous range of particles: neighbor gathers then mostly hit that XCD's L2.
-__device__ __forceinline__ int xcd_block(int bid, int nb)
+__global__ void k_ctl_init(int32_t *ctl)
 {
-    if ((nb & 7) != 0) return bid;
-    return (bid & 7) * (nb >> 3) + (bid >> 3);
+    int t = threadIdx.x;
+    if (t < kCtlWords) ctl[t] = 0;
 }
 
-// One velocity-Verlet step s >= 1 on positions r(s): (rebuild if flagged), F(s),
-// then v += dt F (interior: completes step s-1 and opens step s) and r(s+1) = r(s) + dt v,
-// or v += dt/2 F and store F (last step).
-template <int D, int KIND, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_verlet_step(StepArgs a, DevPot p)
+// After a run: if the list in use is the second generation, copy it into the caller's list.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_list_finalize(const int32_t *ctl, ListGen dst, ListGen src, ListParams lp)
 {
-    cg::grid_group g = cg::this_grid();
-    int tid = blockIdx.x * kBlock + threadIdx.x, nth = gridDim.x * kBlock;
-    int32_t *flags = a.nl.flags;
-    if (flags[MD_FLAG_OVERFLOW]) return;  // written before this launch: same value in every workgroup
-    if (a.force_rebuild || flags[MD_FLAG_PENDING0 + a.rot_read]) {
-        rebuild_coop<D>(g, a.pos_in, a.N, a.box, a.cs, a.nl, tid, nth);
-        if (load_flag(flags, MD_FLAG_OVERFLOW)) return;  // read after the barrier: same value everywhere
+    if (ctl[kGenWord] == 0) return;
+    int gt = blockIdx.x * kBlock + threadIdx.x;
+    int i = gt / lp.W, l = gt % lp.W;
+    if (i >= lp.N) return;
+    int n = src.count[(size_t)i * lp.W + l];
+    dst.count[(size_t)i * lp.W + l] = n;
+    n = min(n, lp.capW);
+    for (int t = 0; t < n; ++t) {
+        size_t q = ((size_t)t * lp.N + i) * lp.W + l;
+        dst.idx[q] = src.idx[q];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        flags[MD_FLAG_PENDING0 + a.rot_clear] = 0;
-        flags[MD_FLAG_STEPS] = a.step;
+    if (l == 0) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) dst.pos_ref[(size_t)i * D + q] = src.pos_ref[(size_t)i * D + q];
     }
-    int lb = xcd_block(blockIdx.x, gridDim.x);
-    int per = (a.N + gridDim.x - 1) / gridDim.x;
-    per = (per + kBlock - 1) / kBlock * kBlock;
-    int i0 = lb * per, i1 = min(a.N, i0 + per);
-    bool far = false, bad = false;
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        uint32_t ui[D];
-        load_pos<D>(a.pos_in, i, ui);
-        int si = MULTI ? a.species[i] : 0;
-        float F[D];
-#pragma unroll
-        for (int q = 0; q < D; ++q) F[q] = 0.0f;
-        row_force<D, KIND, MULTI>(a.box, p, a.pos_in, a.species, a.N, a.nl.idx, min(a.nl.count[i], a.nl.cap), i, ui, si,
-                                  F);
-#pragma unroll
-        for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
-        if (a.mode == 2) {
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                float v = __builtin_fmaf(0.5f * a.dt, F[q], a.vel[(size_t)i * D + q]);
-                a.vel[(size_t)i * D + q] = v;
-                a.force[(size_t)i * D + q] = F[q];
-            }
-        } else {
-            uint32_t un[D];
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                float v = __builtin_fmaf(a.dt, F[q], a.vel[(size_t)i * D + q]);
-                a.vel[(size_t)i * D + q] = v;
-                un[q] = shift_coord(ui[q], a.dt * v, a.box.inv_s[q]);
-            }
-            store_pos<D>(a.pos_out, i, un);
-            far = far || moved_too_far<D>(un, a.nl.pos_ref, i, a.box, a.nl.half_skin2);
-        }
-    }
-    (void)tid;
-    (void)nth;
-    if (far) flags[MD_FLAG_PENDING0 + a.rot_set] = 1;
-    if (bad) flags[MD_FLAG_NONFINITE] = 1;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -527,87 +741,89 @@ __global__ __launch_bounds__(kBlock) void k_verlet_step(StepArgs a, DevPot p)
 
 struct FireArgs {
     DevBox box;
-    CellScratch cs;
-    NLView nl;
+    ListParams lp;
+    ListGen list;
+    int32_t *flags;
+    int32_t *ctl;
     uint32_t *pos;
     float *vel;
     float *force;
     const int32_t *species;
-    int32_t N;
     md_fire_state *st;
-    double *partials;   // [4 * gridDim.x]
+    double *partials;  // [4 * blocks]
     double f_tol;
     float dt_max, f_inc, f_dec, alpha_start, f_alpha;
     int32_t n_min;
-    int32_t init;       // 1: no drift/mix, forces only (fire_init)
 };
 
-template <int D, int KIND, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
+// Velocity mixing decided by the previous step, then r += dt v + dt^2/2 F; requests a rebuild
+// (ctl[kTrigWord]) when a particle is now farther than skin/2 from its position at the last build.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_fire_drift(FireArgs a)
 {
-    cg::grid_group g = cg::this_grid();
-    __shared__ double red[kBlock];
-    int tid = blockIdx.x * kBlock + threadIdx.x, nth = gridDim.x * kBlock;
-    int32_t *flags = a.nl.flags;
-    md_fire_state *st = a.st;
-    if (flags[MD_FLAG_OVERFLOW] || st->converged) return;  // values from before this launch
-    int lb = xcd_block(blockIdx.x, gridDim.x);
-    int per = (a.N + gridDim.x - 1) / gridDim.x;
-    per = (per + kBlock - 1) / kBlock * kBlock;
-    int i0 = lb * per, i1 = min(a.N, i0 + per);
-    double dt = st->dt;
-    if (!a.init) {
-        // mixing decided by the previous step, then r += dt v + dt^2/2 F
-        double mv = st->mix_v, mf = st->mix_f;
-        bool far = false;
-        for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-            uint32_t un[D];
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                float f = a.force[(size_t)i * D + q];
-                float v = (float)(mv * (double)a.vel[(size_t)i * D + q] + mf * (double)f);
-                a.vel[(size_t)i * D + q] = v;
-                float dx = (float)(dt * (double)v + 0.5 * dt * dt * (double)f);
-                un[q] = shift_coord(a.pos[(size_t)i * D + q], dx, a.box.inv_s[q]);
-            }
-            store_pos<D>(a.pos, i, un);
-            far = far || moved_too_far<D>(un, a.nl.pos_ref, i, a.box, a.nl.half_skin2);
-        }
-        if (far) flags[MD_FLAG_PENDING0] = 1;
-        g.sync();
-        if (load_flag(flags, MD_FLAG_PENDING0)) {
-            rebuild_coop<D>(g, a.pos, a.N, a.box, a.cs, a.nl, tid, nth);
-            if (load_flag(flags, MD_FLAG_OVERFLOW)) return;
-        }
-    }
-    // F' = F(r); v += dt/2 (F + F'); partial sums of F.v, v.v, F.F and max |F_i|^2
-    double P = 0.0, vv = 0.0, ff = 0.0, fm = 0.0;
-    bool bad = false;
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        uint32_t ui[D];
+    if (frozen(a.flags) || a.st->converged) return;
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < a.lp.N) {
+        double dt = a.st->dt, mv = a.st->mix_v, mf = a.st->mix_f;
+        uint32_t ui[D], un[D];
         load_pos<D>(a.pos, i, ui);
-        int si = MULTI ? a.species[i] : 0;
-        float F[D];
 #pragma unroll
-        for (int q = 0; q < D; ++q) F[q] = 0.0f;
-        row_force<D, KIND, MULTI>(a.box, p, a.pos, a.species, a.N, a.nl.idx, min(a.nl.count[i], a.nl.cap), i, ui, si,
-                                  F);
-        double fi2 = 0.0;
+        for (int q = 0; q < D; ++q) {
+            float f = a.force[(size_t)i * D + q];
+            float v = (float)(mv * (double)a.vel[(size_t)i * D + q] + mf * (double)f);
+            a.vel[(size_t)i * D + q] = v;
+            float dx = (float)(dt * (double)v + 0.5 * dt * dt * (double)f);
+            un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
+        }
+        store_pos<D>(a.pos, i, un);
+        far = disp2<D>(un, a.list.pos_ref, i, a.box) > a.lp.half_skin * a.lp.half_skin;
+    }
+    wave_flag(far, &a.ctl[kTrigWord]);
+}
+
+// F' = F(r) over the list by W lanes per particle; v += dt/2 (F + F'); workgroup partials of
+// F.v, v.v, F.F and max |F_i|^2 in double.
+template <int D, int KIND, bool MULTI, int W>
+__global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p, int init)
+{
+    __shared__ double red[kBlock];
+    if (frozen(a.flags) || a.st->converged) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[kTrigWord] = 0;  // the gated rebuild of this step is done
+    const ListParams &lp = a.lp;
+    double dt = a.st->dt;
+    int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    int i = gt / W, l = gt % W;
+    bool live = i < lp.N;
+    int ii = live ? i : lp.N - 1;
+    uint32_t ui[D];
+    load_pos<D>(a.pos, ii, ui);
+    bool stale = live && l == 0 && disp2<D>(ui, a.list.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
+    wave_flag(stale, &a.flags[MD_FLAG_STALE]);
+    int si = MULTI ? a.species[ii] : 0;
+    float F[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) F[q] = 0.0f;
+    int n = live ? min(a.list.count[(size_t)ii * W + l], lp.capW) : 0;
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, a.list.idx, n, ii, l, ui, si, F);
+    double P = 0.0, vv = 0.0, ff = 0.0;
+    bool bad = false;
+    if (live && l == 0) {
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             bad = bad || !isfinite(F[q]);
-            float v = a.init ? 0.0f : (float)((double)a.vel[(size_t)i * D + q] +
-                                              0.5 * dt * ((double)a.force[(size_t)i * D + q] + (double)F[q]));
+            float v = init ? 0.0f
+                           : (float)((double)a.vel[(size_t)i * D + q] +
+                                     0.5 * dt * ((double)a.force[(size_t)i * D + q] + (double)F[q]));
             a.vel[(size_t)i * D + q] = v;
             a.force[(size_t)i * D + q] = F[q];
             P += (double)F[q] * (double)v;
             vv += (double)v * (double)v;
-            fi2 += (double)F[q] * (double)F[q];
+            ff += (double)F[q] * (double)F[q];
         }
-        ff += fi2;
-        fm = fmax(fm, fi2);
     }
-    if (bad) flags[MD_FLAG_NONFINITE] = 1;
+    wave_flag(bad, &a.flags[MD_FLAG_NONFINITE]);
+    double fm = ff;
     P = block_sum(P, red);
     vv = block_sum(vv, red);
     ff = block_sum(ff, red);
@@ -618,11 +834,17 @@ __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
         a.partials[4 * blockIdx.x + 2] = ff;
         a.partials[4 * blockIdx.x + 3] = fm;
     }
-    g.sync();
-    if (blockIdx.x != 0) return;
-    // workgroup 0: global sums in a fixed order, convergence test, FIRE rules
+}
+
+// One workgroup: global sums in a fixed order, convergence test and the FIRE rules.
+__global__ __launch_bounds__(kBlock) void k_fire_reduce(FireArgs a, int nblocks, int init)
+{
+    __shared__ double red[kBlock];
+    if (frozen(a.flags)) return;
+    md_fire_state *st = a.st;
+    if (st->converged) return;
     double sP = 0.0, svv = 0.0, sff = 0.0, sfm = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
         sP += a.partials[4 * b + 0];
         svv += a.partials[4 * b + 1];
         sff += a.partials[4 * b + 2];
@@ -633,16 +855,15 @@ __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
     sff = block_sum(sff, red);
     sfm = block_max(sfm, red);
     if (threadIdx.x != 0) return;
-    flags[MD_FLAG_PENDING0] = 0;
     st->fmax = sqrt(sfm);
     st->power = sP;
-    if (!a.init) st->steps += 1;
-    flags[MD_FLAG_STEPS] = (int32_t)st->steps;
+    if (!init) st->steps += 1;
+    a.flags[MD_FLAG_STEPS] = (int32_t)st->steps;
     if (st->fmax < a.f_tol) {
         st->converged = 1;
         return;
     }
-    if (a.init) {
+    if (init) {
         st->mix_v = 1.0;
         st->mix_f = 0.0;
         return;
@@ -664,6 +885,19 @@ __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
         st->alpha = (double)a.alpha_start;
         st->n_pos = 0;
     }
+}
+
+__global__ void k_fire_state_init(md_fire_state *st, double dt, double alpha)
+{
+    st->dt = dt;
+    st->alpha = alpha;
+    st->fmax = 0.0;
+    st->power = 0.0;
+    st->mix_v = 1.0;
+    st->mix_f = 0.0;
+    st->steps = 0;
+    st->n_pos = 0;
+    st->converged = 0;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -698,11 +932,6 @@ __global__ void k_fill_i32(int n, int32_t *a, int32_t v)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t < n) a[t] = v;
-}
-
-__global__ void k_zero_pending(int32_t *flags)
-{
-    if (threadIdx.x < 3) flags[MD_FLAG_PENDING0 + threadIdx.x] = 0;
 }
 
 constexpr int kRedBlocks = 256;
@@ -743,18 +972,21 @@ __global__ __launch_bounds__(kBlock) void k_sum_final(const double *partials, in
 
 struct md_ctx {
     int device = 0;
-    int num_cu = 0;
-    int32_t N_cap = 0, dim_cap = 0, C_cap = 0;
+    int32_t N_cap = 0, dim_cap = 0, C_cap = 0, cap_cap = 0, M_cap = 0, W_cap = 0;
     uint32_t *pos_alt = nullptr;
-    uint32_t *pos_sorted = nullptr;
-    int32_t *cell_of = nullptr, *slot = nullptr, *sorted_idx = nullptr;
-    int32_t *cell_count = nullptr, *cell_start = nullptr;
-    double *partials = nullptr;  // 4 * kMaxCoopBlocks doubles
+    CountSort cs = {};
+    int32_t *bin_cnt[2] = {nullptr, nullptr};
+    int32_t *bin_id[2] = {nullptr, nullptr};
+    uint32_t *bin_pos[2] = {nullptr, nullptr};
+    int32_t *g1_idx = nullptr, *g1_count = nullptr;
+    uint32_t *g1_pos_ref = nullptr;
+    int32_t *ctl = nullptr;        // kCtlWords
+    double *partials = nullptr;    // 4 * kMaxBlocks doubles
     int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
-    std::unordered_map<const void *, int> coop_blocks;
 };
 
-static constexpr int kMaxCoopBlocks = 4096;
+static constexpr int kMaxBlocks = 1 << 16;
+static constexpr float kKappa = 2.0f;
 
 #define HIP_OK(x)                                    \
     do {                                             \
@@ -839,65 +1071,21 @@ static bool box_ok(const md_box *box, float r)
     return true;
 }
 
-static NLView make_view(const md_nlist *nl)
+static ListParams make_lp(const md_nlist *nl, int M)
 {
-    NLView v;
+    ListParams v;
     v.N = nl->N;
     v.cap = nl->capacity;
+    v.W = nl->lanes;
+    v.capW = nl->capacity / nl->lanes;
+    v.M = M;
     float rl2 = nl->r_list * nl->r_list;
     v.rl2f_lo = rl2 * (1.0f - 1e-5f);
     v.rl2f_hi = rl2 * (1.0f + 1e-5f);
     v.rl2 = (double)nl->r_list * (double)nl->r_list;
-    float hs = 0.5f * nl->skin;
-    v.half_skin2 = hs * hs;
-    v.idx = nl->idx;
-    v.count = nl->count;
-    v.pos_ref = nl->pos_ref;
-    v.flags = nl->flags;
+    v.half_skin = 0.5f * nl->skin;
+    v.kappa = kKappa;
     return v;
-}
-
-static CellScratch make_cs(md_ctx *ctx)
-{
-    CellScratch cs;
-    cs.cell_of = ctx->cell_of;
-    cs.slot = ctx->slot;
-    cs.sorted_idx = ctx->sorted_idx;
-    cs.pos_sorted = ctx->pos_sorted;
-    cs.cell_count = ctx->cell_count;
-    cs.cell_start = ctx->cell_start;
-    return cs;
-}
-
-static int coop_grid(md_ctx *ctx, const void *kernel, int N)
-{
-    static std::mutex mu;
-    int per_cu;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = ctx->coop_blocks.find(kernel);
-        if (it == ctx->coop_blocks.end()) {
-            int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
-            ctx->coop_blocks[kernel] = nb;
-            per_cu = nb;
-        } else {
-            per_cu = it->second;
-        }
-    }
-    int maxb = per_cu * ctx->num_cu;
-    if (maxb > kMaxCoopBlocks) maxb = kMaxCoopBlocks;
-    int want = (N + kBlock - 1) / kBlock;
-    if (want < 1) want = 1;
-    int g = want < maxb ? want : maxb;
-    if (g >= 8) g &= ~7;  // multiple of the XCD count so the remap is a permutation
-    return g;
-}
-
-static md_status coop_launch(const void *kernel, int grid, void **args, hipStream_t s)
-{
-    hipError_t e = hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
-    return e == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
 static inline int nblk(int64_t n)
@@ -906,44 +1094,118 @@ static inline int nblk(int64_t n)
 }
 
 // dispatch over (dim, kind, species) template instances
-#define MD_DISPATCH(D_, KIND_, MULTI_, ...)                                  \
+#define MD_DISPATCH(D_, KIND_, MULTI_, ...)                                   \
     do {                                                                     \
         if (D_ == 3) {                                                       \
             constexpr int D = 3;                                             \
             if (KIND_ == 0) {                                                \
                 constexpr int KIND = 0;                                      \
-                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }           \
-                else { constexpr bool MULTI = false; __VA_ARGS__; }                 \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \
                 constexpr int KIND = 1;                                      \
-                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }           \
-                else { constexpr bool MULTI = false; __VA_ARGS__; }                 \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             }                                                                \
         } else {                                                             \
             constexpr int D = 2;                                             \
             if (KIND_ == 0) {                                                \
                 constexpr int KIND = 0;                                      \
-                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }           \
-                else { constexpr bool MULTI = false; __VA_ARGS__; }                 \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \
                 constexpr int KIND = 1;                                      \
-                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }           \
-                else { constexpr bool MULTI = false; __VA_ARGS__; }                 \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             }                                                                \
         }                                                                    \
     } while (0)
 
+// dispatch over the lane count
+#define MD_LANES(W_, ...)                                                    \
+    do {                                                                     \
+        switch (W_) {                                                        \
+        case 1: { constexpr int W = 1; __VA_ARGS__; } break;                 \
+        case 2: { constexpr int W = 2; __VA_ARGS__; } break;                 \
+        case 4: { constexpr int W = 4; __VA_ARGS__; } break;                 \
+        default: { constexpr int W = 8; __VA_ARGS__; } break;                \
+        }                                                                    \
+    } while (0)
+
+static bool lanes_ok(int W)
+{
+    return W == 1 || W == 2 || W == 4 || W == 8;
+}
+
 static bool nl_ok(const md_nlist *nl, int N)
 {
-    return nl && nl->N == N && nl->capacity >= 1 && nl->idx && nl->count && nl->pos_ref && nl->flags &&
-           nl->r_list > 0.0f && nl->skin >= 0.0f;
+    return nl && nl->N == N && lanes_ok(nl->lanes) && nl->capacity >= nl->lanes && nl->capacity % nl->lanes == 0 &&
+           nl->idx && nl->count && nl->pos_ref && nl->flags && nl->r_list > 0.0f && nl->skin >= 0.0f;
+}
+
+static ListGen caller_gen(const md_nlist *nl)
+{
+    return ListGen{nl->idx, nl->count, nl->pos_ref};
+}
+
+static Bins ctx_bins(md_ctx *ctx, int g)
+{
+    return Bins{ctx->bin_cnt[g], ctx->bin_id[g], ctx->bin_pos[g]};
+}
+
+static md_status check_common(md_ctx *ctx, const md_box *box, int32_t N)
+{
+    if (!ctx || !box || (box->dim != 2 && box->dim != 3) || N < 0) return MD_ERR_ARG;
+    if (N > ctx->N_cap || box->dim > ctx->dim_cap) return MD_ERR_CAPACITY;
+    return MD_OK;
+}
+
+static md_status check_list(md_ctx *ctx, const md_box *box, const md_nlist *nl, int32_t N, DevBox &b)
+{
+    if (!nl_ok(nl, N)) return MD_ERR_ARG;
+    if (!box_ok(box, nl->r_list)) return MD_ERR_BOX;
+    if (!make_box(box, nl->r_list, b)) return MD_ERR_ARG;
+    if (b.C > ctx->C_cap) return MD_ERR_CAPACITY;
+    if ((int64_t)N * nl->lanes > (int64_t)kBlock * kMaxBlocks) return MD_ERR_CAPACITY;
+    return MD_OK;
+}
+
+// Counting-sort bins of generation 0 and rows of the caller's list; with a gate, every launch
+// returns at once unless *gate != 0 on the device.
+static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint32_t *pos, int32_t N,
+                              const md_nlist *nl, hipStream_t s, const int32_t *gate)
+{
+    CountSort cs = ctx->cs;
+    Bins bins = ctx_bins(ctx, 0);
+    ListParams lp = make_lp(nl, ctx->M_cap);
+    ListGen g = caller_gen(nl);
+    int rows_grid = nblk((int64_t)N * lp.W);
+    hipLaunchKernelGGL(k_cs_zero, dim3(nblk(b.C)), dim3(kBlock), 0, s, cs.cell_count, b.C, gate);
+    if (dim == 3) {
+        hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, b, cs, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, b.C, gate);
+        hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
+        hipLaunchKernelGGL(k_cs_fill_bins<3>, dim3(nblk(b.C)), dim3(kBlock), 0, s, pos, cs, bins, b.C, lp.M,
+                           nl->flags, gate);
+        MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
+                                          lp, g, nl->flags, gate));
+    } else {
+        hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, b, cs, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, b.C, gate);
+        hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
+        hipLaunchKernelGGL(k_cs_fill_bins<2>, dim3(nblk(b.C)), dim3(kBlock), 0, s, pos, cs, bins, b.C, lp.M,
+                           nl->flags, gate);
+        MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
+                                          lp, g, nl->flags, gate));
+    }
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
 extern "C" {
 
 const char *md_version(void)
 {
-    return "md-gfx950 0.1";
+    return "md-gfx950 0.3";
 }
 
 md_status md_ctx_create(int device, md_ctx **out)
@@ -953,16 +1215,14 @@ md_status md_ctx_create(int device, md_ctx **out)
     HIP_OK(hipSetDevice(device));
     md_ctx *c = new md_ctx();
     c->device = device;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-        delete c;
-        return MD_ERR_HIP;
-    }
-    c->num_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->partials, sizeof(double) * 4 * kMaxCoopBlocks) != hipSuccess ||
+    if (hipMalloc(&c->partials, sizeof(double) * 4 * kMaxBlocks) != hipSuccess ||
         hipMalloc(&c->own_flags, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
-        hipMemset(c->own_flags, 0, sizeof(int32_t) * MD_NFLAGS) != hipSuccess) {
+        hipMalloc(&c->ctl, sizeof(int32_t) * kCtlWords) != hipSuccess ||
+        hipMemset(c->own_flags, 0, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
+        hipMemset(c->ctl, 0, sizeof(int32_t) * kCtlWords) != hipSuccess) {
         (void)hipFree(c->partials);
+        (void)hipFree(c->own_flags);
+        (void)hipFree(c->ctl);
         delete c;
         return MD_ERR_HIP;
     }
@@ -972,15 +1232,19 @@ md_status md_ctx_create(int device, md_ctx **out)
 
 static void free_scratch(md_ctx *c)
 {
-    (void)hipFree(c->pos_alt);
-    (void)hipFree(c->pos_sorted);
-    (void)hipFree(c->cell_of);
-    (void)hipFree(c->slot);
-    (void)hipFree(c->sorted_idx);
-    (void)hipFree(c->cell_count);
-    (void)hipFree(c->cell_start);
-    c->pos_alt = c->pos_sorted = nullptr;
-    c->cell_of = c->slot = c->sorted_idx = c->cell_count = c->cell_start = nullptr;
+    void *ptrs[] = {c->pos_alt, c->cs.cell_of, c->cs.slot, c->cs.sorted_idx, c->cs.cell_count, c->cs.cell_start,
+                    c->bin_cnt[0], c->bin_cnt[1], c->bin_id[0], c->bin_id[1], c->bin_pos[0], c->bin_pos[1],
+                    c->g1_idx, c->g1_count, c->g1_pos_ref};
+    for (void *p : ptrs) (void)hipFree(p);
+    c->pos_alt = nullptr;
+    c->cs = CountSort{};
+    for (int g = 0; g < 2; ++g) {
+        c->bin_cnt[g] = nullptr;
+        c->bin_id[g] = nullptr;
+        c->bin_pos[g] = nullptr;
+    }
+    c->g1_idx = c->g1_count = nullptr;
+    c->g1_pos_ref = nullptr;
 }
 
 md_status md_ctx_destroy(md_ctx *ctx)
@@ -991,32 +1255,52 @@ md_status md_ctx_destroy(md_ctx *ctx)
     free_scratch(ctx);
     (void)hipFree(ctx->partials);
     (void)hipFree(ctx->own_flags);
+    (void)hipFree(ctx->ctl);
     delete ctx;
     return MD_OK;
 }
 
-md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells)
+md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells, int32_t capacity, int32_t lanes,
+                         int32_t max_per_cell)
 {
-    if (!ctx || N < 0 || (dim != 2 && dim != 3) || max_cells < 1) return MD_ERR_ARG;
-    if (N <= ctx->N_cap && dim <= ctx->dim_cap && max_cells <= ctx->C_cap) return MD_OK;
+    if (!ctx || N < 0 || (dim != 2 && dim != 3) || max_cells < 1 || capacity < 1 || !lanes_ok(lanes) ||
+        max_per_cell < 1)
+        return MD_ERR_ARG;
+    if (N <= ctx->N_cap && dim <= ctx->dim_cap && max_cells <= ctx->C_cap && capacity <= ctx->cap_cap &&
+        lanes <= ctx->W_cap && max_per_cell <= ctx->M_cap)
+        return MD_OK;
     HIP_OK(hipSetDevice(ctx->device));
     HIP_OK(hipDeviceSynchronize());
     int32_t n = N > ctx->N_cap ? N : ctx->N_cap;
     int32_t d = dim > ctx->dim_cap ? dim : ctx->dim_cap;
     int32_t C = max_cells > ctx->C_cap ? max_cells : ctx->C_cap;
+    int32_t cap = capacity > ctx->cap_cap ? capacity : ctx->cap_cap;
+    int32_t W = lanes > ctx->W_cap ? lanes : ctx->W_cap;
+    int32_t M = max_per_cell > ctx->M_cap ? max_per_cell : ctx->M_cap;
     free_scratch(ctx);
-    ctx->N_cap = ctx->dim_cap = ctx->C_cap = 0;
+    ctx->N_cap = ctx->dim_cap = ctx->C_cap = ctx->cap_cap = ctx->W_cap = ctx->M_cap = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
     HIP_OK(hipMalloc(&ctx->pos_alt, sizeof(uint32_t) * nn * d));
-    HIP_OK(hipMalloc(&ctx->pos_sorted, sizeof(uint32_t) * nn * d));
-    HIP_OK(hipMalloc(&ctx->cell_of, sizeof(int32_t) * nn));
-    HIP_OK(hipMalloc(&ctx->slot, sizeof(int32_t) * nn));
-    HIP_OK(hipMalloc(&ctx->sorted_idx, sizeof(int32_t) * nn));
-    HIP_OK(hipMalloc(&ctx->cell_count, sizeof(int32_t) * (size_t)C));
-    HIP_OK(hipMalloc(&ctx->cell_start, sizeof(int32_t) * ((size_t)C + 1)));
+    HIP_OK(hipMalloc(&ctx->cs.cell_of, sizeof(int32_t) * nn));
+    HIP_OK(hipMalloc(&ctx->cs.slot, sizeof(int32_t) * nn));
+    HIP_OK(hipMalloc(&ctx->cs.sorted_idx, sizeof(int32_t) * nn));
+    HIP_OK(hipMalloc(&ctx->cs.cell_count, sizeof(int32_t) * (size_t)C));
+    HIP_OK(hipMalloc(&ctx->cs.cell_start, sizeof(int32_t) * ((size_t)C + 1)));
+    for (int g = 0; g < 2; ++g) {
+        HIP_OK(hipMalloc(&ctx->bin_cnt[g], sizeof(int32_t) * (size_t)C));
+        HIP_OK(hipMalloc(&ctx->bin_id[g], sizeof(int32_t) * (size_t)C * M));
+        HIP_OK(hipMalloc(&ctx->bin_pos[g], sizeof(uint32_t) * (size_t)C * M * d));
+    }
+    // second list generation: idx sized for any capacity <= cap, count for any lane count <= W
+    HIP_OK(hipMalloc(&ctx->g1_idx, sizeof(int32_t) * nn * cap));
+    HIP_OK(hipMalloc(&ctx->g1_count, sizeof(int32_t) * nn * W));
+    HIP_OK(hipMalloc(&ctx->g1_pos_ref, sizeof(uint32_t) * nn * d));
     ctx->N_cap = n;
     ctx->dim_cap = d;
     ctx->C_cap = C;
+    ctx->cap_cap = cap;
+    ctx->W_cap = W;
+    ctx->M_cap = M;
     return MD_OK;
 }
 
@@ -1049,34 +1333,16 @@ md_status md_positions_to_float(const md_box *box, const uint32_t *pos, float *x
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
-static md_status check_common(md_ctx *ctx, const md_box *box, int32_t N)
-{
-    if (!ctx || !box || (box->dim != 2 && box->dim != 3) || N < 0) return MD_ERR_ARG;
-    if (N > ctx->N_cap || box->dim > ctx->dim_cap) return MD_ERR_CAPACITY;
-    return MD_OK;
-}
-
-static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint32_t *pos, int32_t N, md_nlist *nl,
-                              hipStream_t s)
-{
-    CellScratch cs = make_cs(ctx);
-    NLView v = make_view(nl);
-    void *args[] = {(void *)&b, (void *)&cs, (void *)&v, (void *)&pos, (void *)&N};
-    const void *k = dim == 3 ? (const void *)k_nl_build<3> : (const void *)k_nl_build<2>;
-    return coop_launch(k, coop_grid(ctx, k, N), args, s);
-}
-
 md_status nl_build(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream)
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!pos || !nl_ok(nl, N)) return MD_ERR_ARG;
-    if (!box_ok(box, nl->r_list)) return MD_ERR_BOX;
+    if (!pos) return MD_ERR_ARG;
     DevBox b;
-    if (!make_box(box, nl->r_list, b)) return MD_ERR_ARG;
-    if (b.C > ctx->C_cap) return MD_ERR_CAPACITY;
+    st = check_list(ctx, box, nl, N, b);
+    if (st != MD_OK) return st;
     if (N == 0) return MD_OK;
-    return launch_build(ctx, box->dim, b, pos, N, nl, (hipStream_t)stream);
+    return launch_build(ctx, box->dim, b, pos, N, nl, (hipStream_t)stream, nullptr);
 }
 
 md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos,
@@ -1101,14 +1367,17 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
     int32_t *flags = nl ? nl->flags : ctx->own_flags;
     int grid = nblk(N);
     if (nl) {
+        int W = nl->lanes, capW = nl->capacity / nl->lanes;
         if (ew) {
             MD_DISPATCH(box->dim, pot->kind, multi,
                         hipLaunchKernelGGL((k_pair_nl<D, KIND, MULTI, true>), dim3(grid), dim3(kBlock), 0, s, b, p,
-                                           pos, species, N, nl->idx, nl->count, nl->capacity, force, energy, virial, flags));
+                                           pos, species, N, nl->idx, nl->count, W, capW, force, energy, virial,
+                                           flags));
         } else {
             MD_DISPATCH(box->dim, pot->kind, multi,
                         hipLaunchKernelGGL((k_pair_nl<D, KIND, MULTI, false>), dim3(grid), dim3(kBlock), 0, s, b, p,
-                                           pos, species, N, nl->idx, nl->count, nl->capacity, force, energy, virial, flags));
+                                           pos, species, N, nl->idx, nl->count, W, capW, force, energy, virial,
+                                           flags));
         }
     } else {
         if (ew) {
@@ -1124,94 +1393,105 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
+static md_status run_checks(md_ctx *ctx, const md_box *box, const md_potential *pot, const md_nlist *nl, int32_t N,
+                            const int32_t *species, DevBox &b, DevPot &p)
+{
+    md_status st = check_common(ctx, box, N);
+    if (st != MD_OK) return st;
+    if (!make_pot(pot, p)) return MD_ERR_ARG;
+    if (pot->n_species > 1 && !species) return MD_ERR_ARG;
+    st = check_list(ctx, box, nl, N, b);
+    if (st != MD_OK) return st;
+    if (nl->r_list < max_cutoff(pot)) return MD_ERR_ARG;
+    if (nl->capacity > ctx->cap_cap || nl->lanes > ctx->W_cap) return MD_ERR_CAPACITY;
+    return MD_OK;
+}
+
 md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                       float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, int32_t n_steps,
                       void *stream)
 {
-    md_status st = check_common(ctx, box, N);
-    if (st != MD_OK) return st;
-    DevPot p;
-    if (!pos || !vel || !force || !make_pot(pot, p) || !nl_ok(nl, N) || n_steps < 0 || !isfinite(dt))
-        return MD_ERR_ARG;
-    bool multi = pot->n_species > 1;
-    if (multi && !species) return MD_ERR_ARG;
-    if (nl->r_list < max_cutoff(pot)) return MD_ERR_ARG;
-    if (!box_ok(box, nl->r_list)) return MD_ERR_BOX;
     DevBox b;
-    if (!make_box(box, nl->r_list, b)) return MD_ERR_ARG;
-    if (b.C > ctx->C_cap) return MD_ERR_CAPACITY;
+    DevPot p;
+    if (!pos || !vel || !force || n_steps < 0 || !isfinite(dt)) return MD_ERR_ARG;
+    md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
+    if (st != MD_OK) return st;
     if (N == 0 || n_steps == 0) return MD_OK;
     hipStream_t s = (hipStream_t)stream;
-    NLView v = make_view(nl);
-    hipLaunchKernelGGL(k_zero_pending, dim3(1), dim3(64), 0, s, nl->flags);
-    uint32_t *buf[2] = {pos, ctx->pos_alt};
-    if (box->dim == 3)
-        hipLaunchKernelGGL(k_verlet_begin<3>, dim3(nblk(N)), dim3(kBlock), 0, s, b, buf[0], buf[1], vel, force,
-                           nl->pos_ref, N, dt, v.half_skin2, nl->flags, 1);
-    else
-        hipLaunchKernelGGL(k_verlet_begin<2>, dim3(nblk(N)), dim3(kBlock), 0, s, b, buf[0], buf[1], vel, force,
-                           nl->pos_ref, N, dt, v.half_skin2, nl->flags, 1);
-    HIP_OK(hipGetLastError());
+    bool multi = pot->n_species > 1;
+    // a fresh list (and generation-0 bins) for the input positions
+    st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
+    if (st != MD_OK) return st;
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
     StepArgs a;
     a.box = b;
-    a.cs = make_cs(ctx);
-    a.nl = v;
+    a.lp = make_lp(nl, ctx->M_cap);
+    a.gen[0] = caller_gen(nl);
+    a.gen[1] = ListGen{ctx->g1_idx, ctx->g1_count, ctx->g1_pos_ref};
+    a.bins[0] = ctx_bins(ctx, 0);
+    a.bins[1] = ctx_bins(ctx, 1);
+    a.flags = nl->flags;
+    a.ctl = ctx->ctl;
     a.vel = vel;
     a.force = force;
     a.species = species;
-    a.N = N;
     a.dt = dt;
-    a.force_rebuild = 0;
-    const void *kern = nullptr;
-    MD_DISPATCH(box->dim, pot->kind, multi, kern = (const void *)k_verlet_step<D, KIND, MULTI>);
-    int grid = coop_grid(ctx, kern, N);
-    void *args[] = {(void *)&a, (void *)&p};
+    uint32_t *buf[2] = {pos, ctx->pos_alt};
+    a.pos_in = buf[0];
+    a.pos_out = buf[1];
+    a.step = 0;
+    a.last = 0;
+    if (box->dim == 3)
+        hipLaunchKernelGGL(k_verlet_begin<3>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_verlet_begin<2>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+    HIP_OK(hipGetLastError());
+    int grid = nblk((int64_t)N * a.lp.W);
     for (int32_t sidx = 1; sidx <= n_steps; ++sidx) {
         a.step = sidx;
         a.pos_in = buf[sidx & 1];
         a.pos_out = buf[(sidx + 1) & 1];
-        a.rot_read = sidx % 3;
-        a.rot_set = (sidx + 1) % 3;
-        a.rot_clear = (sidx + 2) % 3;
-        a.mode = sidx == n_steps ? 2 : 1;
-        md_status r = coop_launch(kern, grid, args, s);
-        if (r != MD_OK) return r;
+        a.last = sidx == n_steps;
+        MD_DISPATCH(box->dim, pot->kind, multi,
+                    MD_LANES(a.lp.W, hipLaunchKernelGGL((k_md_step<D, KIND, MULTI, W>), dim3(grid), dim3(kBlock), 0,
+                                                        s, a, p)));
     }
+    HIP_OK(hipGetLastError());
     if (n_steps & 1) {
         int n = N * box->dim;
         hipLaunchKernelGGL(k_copy_u32, dim3(nblk(n)), dim3(kBlock), 0, s, n, buf[1], buf[0]);
-        HIP_OK(hipGetLastError());
     }
-    return MD_OK;
+    if (box->dim == 3)
+        hipLaunchKernelGGL(k_list_finalize<3>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
+    else
+        hipLaunchKernelGGL(k_list_finalize<2>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
-static md_status fire_launch(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
-                             float *force, const int32_t *species, int32_t N, md_nlist *nl,
-                             const md_fire_params *fp, md_fire_state *fst, int32_t n_steps, double f_tol, int init,
-                             hipStream_t s)
+static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                          float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
+                          md_fire_state *fst, int32_t n_steps, double f_tol, int init, hipStream_t s)
 {
-    md_status st = check_common(ctx, box, N);
-    if (st != MD_OK) return st;
-    DevPot p;
-    if (!pos || !vel || !force || !fst || !fp || !make_pot(pot, p) || !nl_ok(nl, N) || n_steps < 0)
-        return MD_ERR_ARG;
-    bool multi = pot->n_species > 1;
-    if (multi && !species) return MD_ERR_ARG;
-    if (nl->r_list < max_cutoff(pot)) return MD_ERR_ARG;
-    if (!box_ok(box, nl->r_list)) return MD_ERR_BOX;
     DevBox b;
-    if (!make_box(box, nl->r_list, b)) return MD_ERR_ARG;
-    if (b.C > ctx->C_cap) return MD_ERR_CAPACITY;
+    DevPot p;
+    if (!pos || !vel || !force || !fst || !fp || n_steps < 0) return MD_ERR_ARG;
+    md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
+    if (st != MD_OK) return st;
     if (N == 0) return MD_OK;
+    bool multi = pot->n_species > 1;
+    st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
+    if (st != MD_OK) return st;
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
     FireArgs a;
     a.box = b;
-    a.cs = make_cs(ctx);
-    a.nl = make_view(nl);
+    a.lp = make_lp(nl, ctx->M_cap);
+    a.list = caller_gen(nl);
+    a.flags = nl->flags;
+    a.ctl = ctx->ctl;
     a.pos = pos;
     a.vel = vel;
     a.force = force;
     a.species = species;
-    a.N = N;
     a.st = fst;
     a.partials = ctx->partials;
     a.f_tol = f_tol;
@@ -1221,53 +1501,44 @@ static md_status fire_launch(md_ctx *ctx, const md_box *box, const md_potential 
     a.alpha_start = fp->alpha_start;
     a.f_alpha = fp->f_alpha;
     a.n_min = fp->n_min;
-    a.init = init;
-    const void *kern = nullptr;
-    MD_DISPATCH(box->dim, pot->kind, multi, kern = (const void *)k_fire_step<D, KIND, MULTI>);
-    int grid = coop_grid(ctx, kern, N);
-    void *args[] = {(void *)&a, (void *)&p};
+    int grid = nblk((int64_t)N * a.lp.W);
+    const int32_t *gate = ctx->ctl + kTrigWord;
     int n = init ? 1 : n_steps;
     for (int q = 0; q < n; ++q) {
-        md_status r = coop_launch(kern, grid, args, s);
-        if (r != MD_OK) return r;
+        if (!init) {
+            if (box->dim == 3)
+                hipLaunchKernelGGL(k_fire_drift<3>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+            else
+                hipLaunchKernelGGL(k_fire_drift<2>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+            st = launch_build(ctx, box->dim, b, pos, N, nl, s, gate);
+            if (st != MD_OK) return st;
+        }
+        MD_DISPATCH(box->dim, pot->kind, multi,
+                    MD_LANES(a.lp.W, hipLaunchKernelGGL((k_fire_force<D, KIND, MULTI, W>), dim3(grid), dim3(kBlock),
+                                                        0, s, a, p, init)));
+        hipLaunchKernelGGL(k_fire_reduce, dim3(1), dim3(kBlock), 0, s, a, grid, init);
     }
-    return MD_OK;
-}
-
-__global__ void k_fire_state_init(md_fire_state *st, double dt, double alpha, int32_t *flags)
-{
-    st->dt = dt;
-    st->alpha = alpha;
-    st->fmax = 0.0;
-    st->power = 0.0;
-    st->mix_v = 1.0;
-    st->mix_f = 0.0;
-    st->steps = 0;
-    st->n_pos = 0;
-    st->converged = 0;
-    flags[MD_FLAG_PENDING0] = 0;
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
 md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos, float *vel,
                     float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
                     md_fire_state *st, double f_tol, void *stream)
 {
-    if (!st || !fp || !nl || !nl->flags) return MD_ERR_ARG;
+    if (!st || !fp) return MD_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     md_status r = check_common(ctx, box, N);
     if (r != MD_OK) return r;
-    hipLaunchKernelGGL(k_fire_state_init, dim3(1), dim3(1), 0, s, st, (double)fp->dt_start, (double)fp->alpha_start,
-                       nl->flags);
+    hipLaunchKernelGGL(k_fire_state_init, dim3(1), dim3(1), 0, s, st, (double)fp->dt_start, (double)fp->alpha_start);
     HIP_OK(hipGetLastError());
-    return fire_launch(ctx, box, pot, (uint32_t *)pos, vel, force, species, N, nl, fp, st, 1, f_tol, 1, s);
+    return fire_run(ctx, box, pot, (uint32_t *)pos, vel, force, species, N, nl, fp, st, 1, f_tol, 1, s);
 }
 
 md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                     float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
                     md_fire_state *st, int32_t n_steps, double f_tol, void *stream)
 {
-    return fire_launch(ctx, box, pot, pos, vel, force, species, N, nl, fp, st, n_steps, f_tol, 0,
-                       (hipStream_t)stream);
+    return fire_run(ctx, box, pot, pos, vel, force, species, N, nl, fp, st, n_steps, f_tol, 0, (hipStream_t)stream);
 }
 
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream)

@@ -26,7 +26,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
 
 MD_LJ, MD_SOFT_SPHERE = 0, 1
 FLAG_OVERFLOW, FLAG_MAXCOUNT, FLAG_NONFINITE, FLAG_REBUILDS = 0, 1, 2, 3
-FLAG_PENDING0, FLAG_STEPS, NFLAGS = 4, 7, 8
+FLAG_CELL_OVERFLOW, FLAG_STALE, FLAG_MAXCELL, FLAG_STEPS, NFLAGS = 4, 5, 6, 7, 8
 
 STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_BOX", -3: "MD_ERR_CAPACITY", -4: "MD_ERR_HIP",
           -5: "MD_ERR_NOT_CONVERGED", -6: "MD_ERR_NONFINITE"}
@@ -49,9 +49,10 @@ class c_potential(ctypes.Structure):
 
 
 class c_nlist(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int32), ("capacity", ctypes.c_int32), ("r_list", ctypes.c_float),
-                ("skin", ctypes.c_float), ("idx", ctypes.c_void_p), ("count", ctypes.c_void_p),
-                ("pos_ref", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+    _fields_ = [("N", ctypes.c_int32), ("capacity", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("r_list", ctypes.c_float), ("skin", ctypes.c_float),
+                ("idx", ctypes.c_void_p), ("count", ctypes.c_void_p), ("pos_ref", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p)]
 
 
 class c_fire_params(ctypes.Structure):
@@ -73,7 +74,8 @@ P = ctypes.c_void_p
 _SIGNATURES = {
     "md_ctx_create": [ctypes.c_int, ctypes.POINTER(P)],
     "md_ctx_destroy": [P],
-    "md_ctx_reserve": [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "md_ctx_reserve": [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                       ctypes.c_int32],
     "md_cell_count": [ctypes.POINTER(c_box), ctypes.c_float],
     "md_positions_from_float": [ctypes.POINTER(c_box), P, P, ctypes.c_int32, P],
     "md_positions_to_float": [ctypes.POINTER(c_box), P, P, ctypes.c_int32, P],
@@ -217,12 +219,16 @@ class Context:
         h = ctypes.c_void_p()
         _check("md_ctx_create", lib.md_ctx_create(dev.index, ctypes.byref(h)))
         self.h = h
-        self.N = self.dim = self.C = 0
+        self.N = self.dim = self.C = self.cap = self.W = self.M = 0
 
-    def reserve(self, N: int, dim: int, max_cells: int):
-        if N > self.N or dim > self.dim or max_cells > self.C:
+    def reserve(self, N: int, dim: int, max_cells: int = 1, capacity: int = 1, lanes: int = 1,
+                max_per_cell: int = 1):
+        if (N > self.N or dim > self.dim or max_cells > self.C or capacity > self.cap or lanes > self.W
+                or max_per_cell > self.M):
             self.N, self.dim, self.C = max(N, self.N), max(dim, self.dim), max(max_cells, self.C)
-            _check("md_ctx_reserve", load().md_ctx_reserve(self.h, self.N, self.dim, self.C))
+            self.cap, self.W, self.M = max(capacity, self.cap), max(lanes, self.W), max(max_per_cell, self.M)
+            _check("md_ctx_reserve", load().md_ctx_reserve(self.h, self.N, self.dim, self.C, self.cap, self.W,
+                                                           self.M))
 
     def close(self):
         if self.h:
@@ -242,20 +248,25 @@ def cell_count(box: Box, r_list: float) -> int:
 
 
 class NeighborList:
-    """md_nlist with its arrays held as torch tensors (ELL idx[capacity][N], count[N], pos_ref[N][dim], flags)."""
+    """md_nlist with its arrays held as torch tensors: idx[capacity/W][N][W], count[N][W], pos_ref[N][dim], flags.
 
-    def __init__(self, N: int, dim: int, capacity: int, r_list: float, skin: float, device=None):
+    ``lanes`` (W) is the number of GPU lanes per particle; ``max_per_cell`` is the bin size the context
+    reserves for this list's cell list."""
+
+    def __init__(self, N: int, dim: int, capacity: int, r_list: float, skin: float, device=None,
+                 max_per_cell: int = 64, lanes: int = 1):
         dev = device or _dev()
-        self.N, self.dim, self.capacity = N, dim, capacity
+        capacity = (capacity + lanes - 1) // lanes * lanes
+        self.N, self.dim, self.capacity, self.max_per_cell, self.lanes = N, dim, capacity, max_per_cell, lanes
         self.r_list, self.skin = float(np.float32(r_list)), float(np.float32(skin))
-        self.idx = torch.empty((capacity, max(N, 1)), dtype=torch.int32, device=dev)
-        self.count = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
+        self.idx = torch.empty((capacity // lanes, max(N, 1), lanes), dtype=torch.int32, device=dev)
+        self.count = torch.zeros((max(N, 1), lanes), dtype=torch.int32, device=dev)
         self.pos_ref = torch.zeros((max(N, 1), dim), dtype=torch.int32, device=dev)
         self.flags = torch.zeros(NFLAGS, dtype=torch.int32, device=dev)
 
     def c(self) -> c_nlist:
         n = c_nlist()
-        n.N, n.capacity, n.r_list, n.skin = self.N, self.capacity, self.r_list, self.skin
+        n.N, n.capacity, n.lanes, n.r_list, n.skin = self.N, self.capacity, self.lanes, self.r_list, self.skin
         n.idx, n.count = self.idx.data_ptr(), self.count.data_ptr()
         n.pos_ref, n.flags = self.pos_ref.data_ptr(), self.flags.data_ptr()
         return n
@@ -271,10 +282,13 @@ class NeighborList:
         _check("md_flags_clear", load().md_flags_clear(ctypes.byref(n), _stream()))
 
     def rows(self) -> list:
-        """Host copy of the rows (list of int arrays), for inspection and tests."""
+        """Host copy of the rows (list of int arrays, sub-rows concatenated), for inspection and tests."""
         idx = self.idx.cpu().numpy()
-        cnt = self.count.cpu().numpy()
-        return [idx[: min(c, self.capacity), i].copy() for i, c in enumerate(cnt[: self.N])]
+        cnt = np.minimum(self.count.cpu().numpy(), self.capacity // self.lanes)
+        return [np.concatenate([idx[: cnt[i, l], i, l] for l in range(self.lanes)]) for i in range(self.N)]
+
+    def lengths(self) -> np.ndarray:
+        return self.count.cpu().numpy()[: self.N].sum(axis=1)
 
 
 # ------------------------------------------------------------ C entry points
@@ -296,9 +310,13 @@ def positions_to_float(box: Box, u: torch.Tensor) -> torch.Tensor:
     return x
 
 
+def _reserve_for(ctx: Context, box: Box, N: int, nl: NeighborList):
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)), nl.capacity, nl.lanes, nl.max_per_cell)
+
+
 def nl_build(ctx: Context, box: Box, pos: torch.Tensor, nl: NeighborList):
     N = pos.shape[0]
-    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    _reserve_for(ctx, box, N, nl)
     b, n = box.c(), nl.c()
     _check("nl_build", load().nl_build(ctx.h, ctypes.byref(b), _ptr(pos), N, ctypes.byref(n), _stream()))
 
@@ -317,7 +335,7 @@ def pair_energy_force(ctx: Context, box: Box, pot: Potential, pos: torch.Tensor,
 def verlet_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList, dt: float,
                 n_steps: int):
     N = pos.shape[0]
-    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    _reserve_for(ctx, box, N, nl)
     b, p, n = box.c(), pot.c(), nl.c()
     _check("verlet_step", load().verlet_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                              _ptr(force), _ptr(species), N, ctypes.byref(n),
@@ -327,7 +345,7 @@ def verlet_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species
 def fire_init(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
               fp: FireParams, state: torch.Tensor, f_tol: float):
     N = pos.shape[0]
-    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    _reserve_for(ctx, box, N, nl)
     b, p, n, f = box.c(), pot.c(), nl.c(), fp.c()
     _check("fire_init", load().fire_init(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                          _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
@@ -337,7 +355,7 @@ def fire_init(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, 
 def fire_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
               fp: FireParams, state: torch.Tensor, n_steps: int, f_tol: float):
     N = pos.shape[0]
-    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)))
+    _reserve_for(ctx, box, N, nl)
     b, p, n, f = box.c(), pot.c(), nl.c(), fp.c()
     _check("fire_step", load().fire_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                          _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
@@ -379,7 +397,8 @@ class System:
     """A periodic system on the GPU: positions, velocities, forces, species, and its neighbor list."""
 
     def __init__(self, box: Box, pot: Potential, u: np.ndarray, v=None, species=None, skin: float = 0.3,
-                 capacity: int | None = None, ctx: Context | None = None):
+                 capacity: int | None = None, ctx: Context | None = None, max_per_cell: int | None = None,
+                 lanes: int | None = None):
         self.ctx = ctx or Context()
         dev = self.ctx.device
         self.box, self.pot = box, pot
@@ -393,27 +412,46 @@ class System:
         if pot.n_species > 1 and self.species is None:
             raise ValueError("multi-species potential needs species")
         r_list = float(np.float32(pot.cutoff() + skin))
+        vol = float(np.prod(np.asarray(box.L[: self.dim], dtype=np.float64)))
+        ball = (4.0 / 3.0 * np.pi * r_list ** 3) if self.dim == 3 else (np.pi * r_list ** 2)
+        mean_row = self.N / vol * ball
+        if lanes is None:
+            # enough lanes per particle that a lane walks ~20 entries
+            lanes = 1
+            while lanes < 8 and mean_row / lanes > 24:
+                lanes *= 2
         if capacity is None:
-            vol = float(np.prod(np.asarray(box.L[: self.dim], dtype=np.float64)))
-            ball = (4.0 / 3.0 * np.pi * r_list ** 3) if self.dim == 3 else (np.pi * r_list ** 2)
-            capacity = int(max(16, 1.4 * self.N / vol * ball + 16))
+            capacity = int(max(16, 1.4 * mean_row + 16 + 2 * lanes))
             capacity = (capacity + 7) // 8 * 8
-        self.nl = NeighborList(self.N, self.dim, capacity, r_list, skin, dev)
+        if max_per_cell is None:
+            cells = max(1, cell_count(box, r_list))
+            mean = self.N / cells
+            max_per_cell = 8
+            while max_per_cell < 2.5 * mean + 8:
+                max_per_cell *= 2
+        self.nl = NeighborList(self.N, self.dim, capacity, r_list, skin, dev, max_per_cell, lanes)
 
     def build(self):
-        """Build the neighbor list, growing its capacity if a row did not fit."""
-        for _ in range(4):
+        """Build the neighbor list, growing its capacity or bin size if something did not fit."""
+        for _ in range(6):
             self.nl.clear_flags()
             nl_build(self.ctx, self.box, self.pos, self.nl)
             f = self.nl.read_flags()
-            if not f[FLAG_OVERFLOW]:
+            if not (f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW]):
                 return
-            self.grow(int(f[FLAG_MAXCOUNT]))
+            self.grow(f)
         raise RuntimeError("neighbor list did not fit after growing")
 
-    def grow(self, need: int):
-        cap = (int(need * 1.25) + 8) // 8 * 8
-        self.nl = NeighborList(self.N, self.dim, cap, self.nl.r_list, self.nl.skin, self.ctx.device)
+    def grow(self, f):
+        """New list sized from the flag words of a failed build or run."""
+        cap, M = self.nl.capacity, self.nl.max_per_cell
+        if f[FLAG_OVERFLOW]:
+            cap = (int(f[FLAG_MAXCOUNT] * 1.25) + 8) // 8 * 8
+        if f[FLAG_CELL_OVERFLOW]:
+            while M <= f[FLAG_MAXCELL]:
+                M *= 2
+        self.nl = NeighborList(self.N, self.dim, cap, self.nl.r_list, self.nl.skin, self.ctx.device, M,
+                               self.nl.lanes)
 
     def forces(self, energy: bool = False):
         e = torch.zeros(self.N, dtype=torch.float64, device=self.ctx.device) if energy else None
@@ -434,11 +472,36 @@ class System:
         return float(out.item())
 
 
+def _run_checked(system: System, saved, call, n_steps: int):
+    """Run call(n) and re-run from `saved` when the device reported a list that did not fit (grow it) or went
+    stale (run again one step per call: each call starts from a fresh list)."""
+    for _ in range(6):
+        system.nl.clear_flags()
+        call(n_steps)
+        f = system.nl.read_flags()
+        if not (f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW] or f[FLAG_STALE]):
+            if f[FLAG_NONFINITE]:
+                raise FloatingPointError("non-finite force")
+            return f
+        for t, v in zip(saved[0], saved[1]):
+            t.copy_(v)
+        if f[FLAG_STALE]:
+            for _ in range(n_steps):
+                system.nl.clear_flags()
+                call(1)
+                g = system.nl.read_flags()
+                if g[FLAG_OVERFLOW] or g[FLAG_CELL_OVERFLOW] or g[FLAG_STALE]:
+                    raise RuntimeError(f"single steps failed: flags {g.tolist()}")
+            return g
+        system.grow(f)
+    raise RuntimeError("neighbor list kept overflowing")
+
+
 def nve(system: System, dt: float):
     """init_fn / update_fn pair for constant-energy dynamics (paper Sec. 3.3.1, ``simulate.nve``).
 
     ``init_fn()`` builds the list and the forces; ``update_fn(n)`` advances n velocity-Verlet steps on the
-    device, re-running from a saved copy with a larger list if a rebuild overflowed.
+    device (one verlet_step call), re-running from a saved copy if the device reported a problem.
     """
 
     def init_fn():
@@ -447,22 +510,15 @@ def nve(system: System, dt: float):
         return system
 
     def update_fn(n_steps: int = 1):
-        saved = (system.pos.clone(), system.vel.clone(), system.force.clone(), system.nl)
-        for _ in range(4):
-            system.nl.clear_flags()
+        tensors = (system.pos, system.vel, system.force)
+        saved = (tensors, tuple(t.clone() for t in tensors))
+
+        def call(n):
             verlet_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
-                        system.nl, dt, n_steps)
-            f = system.nl.read_flags()
-            if not f[FLAG_OVERFLOW]:
-                if f[FLAG_NONFINITE]:
-                    raise FloatingPointError("non-finite force in verlet_step")
-                return system
-            system.pos.copy_(saved[0])
-            system.vel.copy_(saved[1])
-            system.force.copy_(saved[2])
-            system.grow(int(f[FLAG_MAXCOUNT]))
-            system.build()
-        raise RuntimeError("neighbor list kept overflowing")
+                        system.nl, dt, n)
+
+        _run_checked(system, saved, call, n_steps)
+        return system
 
     return init_fn, update_fn
 
@@ -480,20 +536,15 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         return state
 
     def step_fn(n_steps: int = 1):
-        saved = (system.pos.clone(), system.vel.clone(), system.force.clone(), state.clone())
-        for _ in range(4):
+        tensors = (system.pos, system.vel, system.force, state)
+        saved = (tensors, tuple(t.clone() for t in tensors))
+
+        def call(n):
             fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
-                      system.nl, fp, state, n_steps, f_tol)
-            f = system.nl.read_flags()
-            if not f[FLAG_OVERFLOW]:
-                return fire_state_read(state)
-            system.pos.copy_(saved[0])
-            system.vel.copy_(saved[1])
-            system.force.copy_(saved[2])
-            state.copy_(saved[3])
-            system.grow(int(f[FLAG_MAXCOUNT]))
-            system.build()
-        raise RuntimeError("neighbor list kept overflowing")
+                      system.nl, fp, state, n, f_tol)
+
+        _run_checked(system, saved, call, n_steps)
+        return fire_state_read(state)
 
     def minimize(max_steps: int = 100000, chunk: int = 200):
         st = fire_state_read(state)

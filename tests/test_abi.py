@@ -27,7 +27,7 @@ def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/md.h (natural alignment, x86-64)
     assert ctypes.sizeof(md.c_box) == 16
     assert ctypes.sizeof(md.c_potential) == 4 * 2 + 4 * 64 * 2 + 4 * 4
-    assert ctypes.sizeof(md.c_nlist) == 16 + 4 * 8
+    assert ctypes.sizeof(md.c_nlist) == 24 + 4 * 8
     assert ctypes.sizeof(md.c_fire_params) == 32
     assert ctypes.sizeof(md.c_fire_state) == 6 * 8 + 8 + 8
 
@@ -51,5 +51,5 @@ def test_argument_errors_are_returned_synchronously():
     b = md.c_box()
     b.dim = 4
     assert lib.nl_build(None, ctypes.byref(b), None, 0, None, None) == -1
-    assert lib.md_ctx_reserve(None, 10, 3, 1) == -1
+    assert lib.md_ctx_reserve(None, 10, 3, 1, 1, 1, 1) == -1
     assert lib.md_sum(None, None, 0, None, None) == -1

@@ -102,7 +102,8 @@ def test_nl_build_bitexact(md, orc, case):
     check_rows(orc, s, cfg)
     f = s.nl.read_flags()
     assert f[md.FLAG_OVERFLOW] == 0
-    assert f[md.FLAG_MAXCOUNT] == max((len(r) for r in s.nl.rows()), default=0)
+    cnt = s.nl.count.cpu().numpy()[: s.N]
+    assert f[md.FLAG_MAXCOUNT] == cnt.max(initial=0) * s.nl.lanes
 
 
 def test_nl_rows_are_canonical(md):
@@ -110,12 +111,13 @@ def test_nl_rows_are_canonical(md):
     cfg = lj_cfg(4000, 0.84, 3)
     s = make_system(md, cfg)
     s.build()
-    a = s.nl.idx.clone(), s.nl.count.clone()
+    rows0, cnt0 = s.nl.rows(), s.nl.count.cpu().numpy().copy()
     s.build()
-    cnt = s.nl.count.cpu().numpy()
-    idx0, idx1 = a[0].cpu().numpy(), s.nl.idx.cpu().numpy()
-    for i in range(0, 4000, 97):
-        assert np.array_equal(idx0[: cnt[i], i], idx1[: cnt[i], i])
+    rows1, cnt1 = s.nl.rows(), s.nl.count.cpu().numpy()
+    assert np.array_equal(cnt0, cnt1)
+    assert all(np.array_equal(a, b) for a, b in zip(rows0, rows1))
+    # sub-rows are balanced: lane lengths differ by at most a few entries
+    assert (cnt1.max(axis=1) - cnt1.min(axis=1)).max() <= 8
 
 
 def test_nl_overflow_flag_and_regrow(md, orc):
@@ -286,7 +288,8 @@ def test_verlet_deterministic_and_overflow_regrow(md):
         init()
         if tight:
             need = int(s.nl.read_flags()[md.FLAG_MAXCOUNT])
-            s.nl = md.NeighborList(s.N, 3, need, s.nl.r_list, s.nl.skin, s.ctx.device)
+            s.nl = md.NeighborList(s.N, 3, need, s.nl.r_list, s.nl.skin, s.ctx.device, s.nl.max_per_cell,
+                                   s.nl.lanes)
             s.build()
             s.forces()
         update(150)
