@@ -240,6 +240,55 @@ md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uin
                     float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
                     md_fire_state *st, int32_t n_steps, double f_tol, void *stream);
 
+/*
+ * A batch of independent periodic 2D replicas of uneven size (the batched
+ * minimizations of Sec. 4.2, which the paper vectorizes over diameters and
+ * random keys).  Replica b owns particles offset[b] .. offset[b+1]-1 of the
+ * concatenated arrays and has its own box.  max_n and max_cells are host-side
+ * bounds the caller promises (largest replica, largest cell count for cells
+ * of edge >= the interaction range); a replica that exceeds the per-workgroup
+ * limits (4096 particles, 3072 cells) is skipped and reported with status -1.
+ */
+typedef struct {
+    int32_t B;               /* number of replicas */
+    int32_t dim;             /* 2 */
+    int32_t max_n;           /* largest replica size (host bound) */
+    int32_t max_cells;       /* largest cell count (host bound) */
+    const int32_t *offset;   /* [B+1], offset[0] = 0 */
+    const float *box;        /* [B][dim] box edges */
+    uint32_t *pos;           /* [offset[B]][dim] torus coordinates, updated in place */
+    const int32_t *species;  /* [offset[B]] or NULL when the potential has one species */
+} md_batch;
+
+/*
+ * FIRE (same rules as fire_step, v = 0 and dt_start / alpha_start at the
+ * start) on every replica of the batch in one launch: one workgroup per
+ * replica at a time, replicas taken from a work queue, positions and the cell
+ * list held in LDS (cell list rebuilt for each force evaluation, so no
+ * neighbor list or skin is involved).  Outputs per replica: final energy
+ * (double), max_i |F_i|, steps taken, status (1 converged, 0 not converged
+ * within max_steps, -1 replica too large).  All outputs are device arrays of
+ * length B.  Calls that share a ctx must not overlap (the work queue lives in
+ * the ctx).
+ */
+md_status fire_batched(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const md_fire_params *fp,
+                       int32_t max_steps, double f_tol, double *energy, double *fmax, int32_t *steps,
+                       int32_t *status, void *stream);
+
+/*
+ * Gradient of each replica's energy U = 1/2 sum_{i != j} u(r_ij) with respect
+ * to the pair parameters at fixed positions: g_sigma[b][a*S+c] =
+ * 1/2 sum over ordered pairs (i, j) with species (a, c) of du/dsigma, likewise
+ * g_eps (entries (a,c) and (c,a) of a symmetric matrix are one parameter: add
+ * both).  At a converged FIRE minimum this is the derivative of the minimized
+ * energy E*(theta) (envelope theorem), which the paper obtains by
+ * differentiating through the minimizer (Sec. 4.2); diameters enter through
+ * sigma_ab = (d_a + d_b)/2 (App. A).  energy [B] and status [B] may be NULL.
+ * Pair arithmetic is single precision, sums double.  S <= 4.
+ */
+md_status envelope_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, double *g_sigma,
+                        double *g_eps, double *energy, int32_t *status, void *stream);
+
 /* out[0] = sum of x[0..n) in double, summed in a fixed order (deterministic). out is device memory. */
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
 /* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */

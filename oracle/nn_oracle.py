@@ -1,0 +1,198 @@
+"""FP64 reference for the neural pair potential (radial descriptors + per-atom MLP).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py): used by tests/, the smoke check and the benchmark's
+cpu_baseline; the product path never imports it.
+
+The paper builds energy models from featurizations of each particle's neighborhood (Sec. 3.2.4, radial
+symmetry functions), sums per-atom network outputs into the energy of a configuration (Behler-Parrinello,
+Sec. 4.1), obtains forces as F = -grad E (Sec. 3.3.2, ``quantity.force``) and trains on a loss that adds
+the energy MSE and the force MSE (Sec. 4.1).  Written out:
+
+  descriptor  G_i^k = sum_{j != i, r_ij < r_c} g_k(r_ij),   g_k(r) = exp(-eta (r - mu_k)^2) f_c(r),
+              f_c(r) = (cos(pi r / r_c) + 1) / 2,   mu_k = mu_0 + k (mu_1 - mu_0)/(K-1)
+  network     x = (G - m) / s,  h1 = act(W1 x + b1),  h2 = act(W2 h1 + b2),  E_i = w3 . h2 + b3
+  energy      E = sum_i E_i
+  forces      F_i = -sum_j sum_k (e_i^k + e_j^k) g_k'(r_ij) (r_i - r_j)/r_ij,   e_i = dE_i/dG_i
+  loss        L = mean_s ((E_s - E^_s)/N_s)^2 + lam_F * mean_{s,i,a} (F_sia - F^_sia)^2
+
+Weight gradients of L are analytic, including the force term (the gradient of a gradient): with
+lam_i = dL/dF_i, the pair adjoint  ebar_i = dL/de_i = -sum_j g'(r_ij) ((r_i - r_j)/r_ij . (lam_i - lam_j)),
+and dL/dtheta gets sum_i d/dtheta [ebar_i . e_i(theta)], the reverse pass of the network's tangent
+(forward-mode) pass along ebar_i / s.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class NNSpec:
+    K: int = 16
+    mu0: float = 0.8
+    mu1: float = 2.5
+    r_c: float = 2.5
+    H: int = 64
+    act: str = "softplus"   # "softplus" or "linear" (a linear network reduces the model to a pair potential)
+
+    @property
+    def mu(self) -> np.ndarray:
+        return self.mu0 + np.arange(self.K) * (self.mu1 - self.mu0) / (self.K - 1)
+
+    @property
+    def eta(self) -> float:
+        delta = (self.mu1 - self.mu0) / (self.K - 1)
+        return 1.0 / (2.0 * delta * delta)
+
+
+@dataclass
+class NNParams:
+    W1: np.ndarray   # [H, K]
+    b1: np.ndarray   # [H]
+    W2: np.ndarray   # [H, H]
+    b2: np.ndarray   # [H]
+    w3: np.ndarray   # [H]
+    b3: float
+    m: np.ndarray = field(default=None)   # [K] descriptor mean
+    s: np.ndarray = field(default=None)   # [K] descriptor scale
+
+    def names(self):
+        return ["W1", "b1", "W2", "b2", "w3", "b3"]
+
+
+def _act(x, kind):
+    if kind == "linear":
+        return x, np.ones_like(x), np.zeros_like(x)
+    # softplus and its first two derivatives, evaluated stably
+    sp = np.logaddexp(0.0, x)
+    sig = 0.5 * (1.0 + np.tanh(0.5 * x))
+    return sp, sig, sig * (1.0 - sig)
+
+
+def neighbor_pairs(x: np.ndarray, L, r_c: float, chunk: int = 2048):
+    """Ordered pairs (i, j), i != j, with r_ij < r_c by brute force: returns i, j, d = r_i - r_j (nearest image), r."""
+    x = np.asarray(x, dtype=np.float64)
+    N, D = x.shape
+    Lv = np.asarray(L, dtype=np.float64)[:D]
+    I, J, DD, R = [], [], [], []
+    for a in range(0, N, chunk):
+        d = x[a:a + chunk, None, :] - x[None, :, :]
+        d -= Lv * np.rint(d / Lv)
+        r2 = np.einsum("ijk,ijk->ij", d, d)
+        ii, jj = np.nonzero(r2 < r_c * r_c)
+        keep = (ii + a) != jj
+        ii, jj = ii[keep], jj[keep]
+        I.append(ii + a)
+        J.append(jj)
+        DD.append(d[ii, jj])
+        R.append(np.sqrt(r2[ii, jj]))
+    return np.concatenate(I), np.concatenate(J), np.concatenate(DD), np.concatenate(R)
+
+
+def basis(r: np.ndarray, spec: NNSpec):
+    """g_k(r) and g_k'(r) for each pair, [P, K]."""
+    mu = spec.mu[None, :]
+    rr = r[:, None]
+    gauss = np.exp(-spec.eta * (rr - mu) ** 2)
+    fc = 0.5 * (np.cos(np.pi * rr / spec.r_c) + 1.0)
+    dfc = -0.5 * np.pi / spec.r_c * np.sin(np.pi * rr / spec.r_c)
+    g = gauss * fc
+    dg = gauss * (-2.0 * spec.eta * (rr - mu)) * fc + gauss * dfc
+    return g, dg
+
+
+def descriptors(x, L, spec: NNSpec, pairs=None):
+    i, j, d, r = pairs if pairs is not None else neighbor_pairs(x, L, spec.r_c)
+    g, dg = basis(r, spec)
+    G = np.zeros((x.shape[0], spec.K))
+    np.add.at(G, i, g)
+    return G, (i, j, d, r, g, dg)
+
+
+def mlp(G, P: NNParams, spec: NNSpec):
+    """Per-atom energies E_i and e_i = dE_i/dG_i, with the intermediate values."""
+    x = (G - P.m) / P.s
+    z1 = x @ P.W1.T + P.b1
+    h1, a1, aa1 = _act(z1, spec.act)
+    z2 = h1 @ P.W2.T + P.b2
+    h2, a2, aa2 = _act(z2, spec.act)
+    Ei = h2 @ P.w3 + P.b3
+    d2 = a2 * P.w3[None, :]            # dE/dz2
+    d1 = a1 * (d2 @ P.W2)              # dE/dz1
+    dx = d1 @ P.W1                     # dE/dx
+    e = dx / P.s                       # dE/dG
+    cache = dict(x=x, z1=z1, h1=h1, a1=a1, aa1=aa1, z2=z2, h2=h2, a2=a2, aa2=aa2, d1=d1, d2=d2)
+    return Ei, e, cache
+
+
+def energy_forces(xpos, L, P: NNParams, spec: NNSpec):
+    """Total energy, per-atom energies, forces [N][D] and e [N][K] of one configuration."""
+    G, (i, j, d, r, g, dg) = descriptors(xpos, L, spec)
+    Ei, e, _ = mlp(G, P, spec)
+    coef = ((e[i] + e[j]) * dg).sum(axis=1)          # sum_k (e_i + e_j) g_k'(r_ij)
+    F = np.zeros_like(np.asarray(xpos, dtype=np.float64))
+    np.add.at(F, i, -coef[:, None] * d / r[:, None])
+    return float(np.sum(Ei)), Ei, F, e, G
+
+
+def loss_and_grad(snapshots, P: NNParams, spec: NNSpec, lam_f: float = 1.0):
+    """L and dL/dtheta over a batch of snapshots [(x, L, E_ref, F_ref), ...]."""
+    grads = {k: np.zeros_like(np.asarray(getattr(P, k), dtype=np.float64)) for k in P.names()}
+    loss = 0.0
+    ns = len(snapshots)
+    nF = sum(np.asarray(s[0]).size for s in snapshots)
+    for (xpos, L, E_ref, F_ref) in snapshots:
+        N = xpos.shape[0]
+        G, (i, j, d, r, g, dg) = descriptors(xpos, L, spec)
+        Ei, e, c = mlp(G, P, spec)
+        E = float(np.sum(Ei))
+        coef = ((e[i] + e[j]) * dg).sum(axis=1)
+        F = np.zeros_like(np.asarray(xpos, dtype=np.float64))
+        np.add.at(F, i, -coef[:, None] * d / r[:, None])
+        rE = (E - E_ref) / N
+        rF = F - F_ref
+        loss += rE * rE / ns + lam_f * float(np.sum(rF * rF)) / nF
+        # energy term: dL/dE_i = 2 rE / (N ns) for every atom
+        gE = 2.0 * rE / (N * ns)
+        # force term: lam_i = dL/dF_i, pair adjoint ebar_i = dL/de_i
+        lam = 2.0 * lam_f * rF / nF
+        u = d / r[:, None]
+        t = ((lam[i] - lam[j]) * u).sum(axis=1)       # u_ij . (lam_i - lam_j)
+        ebar = np.zeros_like(e)
+        np.add.at(ebar, i, -dg * t[:, None])
+        # backprop: E_i with seed gE, plus the tangent (JVP) of E_i along xdot = ebar / s with seed 1
+        xd = ebar / P.s
+        zd1 = xd @ P.W1.T
+        hd1 = c["a1"] * zd1
+        zd2 = hd1 @ P.W2.T
+        hd2 = c["a2"] * zd2
+        # Q = sum_i [ gE * E_i + w3 . hd2_i ]
+        g_h2 = gE * np.ones((N, 1)) * P.w3[None, :]
+        g_hd2 = np.ones((N, 1)) * P.w3[None, :]
+        grads["w3"] += gE * c["h2"].sum(axis=0) + hd2.sum(axis=0)
+        grads["b3"] += gE * N
+        g_z2 = g_h2 * c["a2"] + g_hd2 * c["aa2"] * zd2
+        g_zd2 = g_hd2 * c["a2"]
+        grads["W2"] += g_z2.T @ c["h1"] + g_zd2.T @ hd1
+        grads["b2"] += g_z2.sum(axis=0)
+        g_h1 = g_z2 @ P.W2
+        g_hd1 = g_zd2 @ P.W2
+        g_z1 = g_h1 * c["a1"] + g_hd1 * c["aa1"] * zd1
+        g_zd1 = g_hd1 * c["a1"]
+        grads["W1"] += g_z1.T @ c["x"] + g_zd1.T @ xd
+        grads["b1"] += g_z1.sum(axis=0)
+    return loss, grads
+
+
+def init_params(spec: NNSpec, seed: int, m=None, s=None) -> NNParams:
+    """Glorot-uniform weights from a seed (the same draw the GPU trainer starts from)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def glorot(o, i):
+        lim = np.sqrt(6.0 / (o + i))
+        return rng.uniform(-lim, lim, size=(o, i))
+
+    K, H = spec.K, spec.H
+    return NNParams(W1=glorot(H, K), b1=np.zeros(H), W2=glorot(H, H), b2=np.zeros(H), w3=glorot(1, H)[0] * 0.1,
+                    b3=0.0, m=np.zeros(K) if m is None else m, s=np.ones(K) if s is None else s)

@@ -1,0 +1,558 @@
+// Batched replicas: many independent periodic 2D systems of uneven size in one launch, FIRE on
+// each of them, and the parameter gradient of their energies.
+//
+// One workgroup of 512 threads owns one replica at a time and takes the next one from a work
+// queue when it is done (an integer counter; every workgroup leaves when the queue is empty).
+// The replica lives inside the workgroup: positions (uint32 torus coordinates), species and the
+// cell list in LDS, velocities and forces in registers (thread t owns particles t, t + 512, ...).
+// The cell list is rebuilt in LDS for every force evaluation (LDS counting sort, each cell's
+// members ordered by index so sums are deterministic), so there is no skin and no neighbor-list
+// bookkeeping; cells have edge >= the interaction range and 9 stencil cells are scanned.
+//
+//   k_fire_batched   FIRE (Bitzek et al. 2006, the minimizer of Sec. 3.3.1 and App. A) on every
+//                    replica until max_i |F_i| < f_tol or max_steps; global sums in double.
+//   k_param_grad     dU/dsigma_ab, dU/deps_ab and U at the given positions.  At a converged
+//                    minimum this is dE*/dtheta by the envelope theorem, i.e. the derivative of
+//                    the minimized energy that Sec. 4.2 obtains by differentiating the minimizer.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/md.h"
+#include "md_device.h"
+#include "md_host.h"
+
+using namespace md;
+
+namespace {
+
+constexpr int kRB = 512;          // threads per replica workgroup
+constexpr int kPerThread = 8;     // particles per thread
+constexpr int kMaxRepN = kRB * kPerThread;
+constexpr int kMaxRepCells = 3072;
+constexpr int kWaves = kRB / 64;
+constexpr int kMaxS = 8;          // species handled by the gradient kernel
+
+struct RepGeom {
+    float s[2], inv_s[2];
+    int nc[2], lo[2], hi[2], C;
+};
+
+struct BatchArgs {
+    int32_t B;
+    const int32_t *offset;  // [B+1]
+    const float *box;       // [B][2]
+    uint32_t *pos;          // [total][2]
+    const int32_t *species; // [total] or null
+    int32_t *queue;         // work counter, zeroed before the launch
+};
+
+struct Lds {
+    uint32_t pos[kMaxRepN * 2];
+    int32_t start[kMaxRepCells + 1];  // counts, then exclusive starts
+    int16_t sorted[kMaxRepN];
+    int8_t spec[kMaxRepN];
+    int32_t wtot[kWaves];
+    double red[kWaves];
+    int32_t rep;
+    DevPot pot;       // pair coefficients, indexed by pair type from LDS (not from kernel arguments)
+    md_potential raw; // the caller's parameters, for the gradient kernel
+};
+
+__device__ __forceinline__ int wrap2(int c, int n)
+{
+    return c < 0 ? c + n : (c >= n ? c - n : c);
+}
+
+__device__ __forceinline__ RepGeom rep_geom(float Lx, float Ly, float range)
+{
+    RepGeom g;
+    float L[2] = {Lx, Ly};
+    g.C = 1;
+    for (int k = 0; k < 2; ++k) {
+        g.s[k] = L[k] / 4294967296.0f;
+        g.inv_s[k] = 4294967296.0f / L[k];
+        int m = (int)floor((double)L[k] / ((double)range * (1.0 + 1e-6)));
+        int nc = m >= 3 ? m : 1;
+        g.nc[k] = nc;
+        g.lo[k] = nc >= 3 ? -1 : 0;
+        g.hi[k] = nc >= 3 ? 1 : 0;
+        g.C *= nc;
+    }
+    return g;
+}
+
+__device__ __forceinline__ int rep_cell(const uint32_t *u, const RepGeom &g)
+{
+    return cell_coord(u[0], g.nc[0]) + g.nc[0] * cell_coord(u[1], g.nc[1]);
+}
+
+// Workgroup-wide sum / max of one double per thread; every thread gets the same value.
+__device__ __forceinline__ double wg_sum(double v, Lds &s)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < kWaves; ++w) r += s.red[w];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double wg_max(double v, Lds &s)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < kWaves; ++w) r = fmax(r, s.red[w]);
+    __syncthreads();
+    return r;
+}
+
+// Exclusive scan of one int per thread over the workgroup (shuffles + LDS, no atomics).
+__device__ __forceinline__ int wg_excl_scan(int v, Lds &s, int &total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s.wtot[w] = incl;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int q = 0; q < kWaves; ++q) {
+        if (q < w) off += s.wtot[q];
+        total += s.wtot[q];
+    }
+    __syncthreads();
+    return off + incl - v;
+}
+
+// Cell list of the replica's LDS positions: counts (LDS integer atomics), exclusive scan,
+// placement, then each cell's members ordered by index.
+__device__ void rep_cells(Lds &s, int n, const RepGeom &g)
+{
+    int t = threadIdx.x;
+    for (int c = t; c < g.C; c += kRB) s.start[c] = 0;
+    __syncthreads();
+    int cell[kPerThread], slot[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int i = t + k * kRB;
+        cell[k] = 0;
+        slot[k] = 0;
+        if (i < n) {
+            cell[k] = rep_cell(&s.pos[2 * i], g);
+            slot[k] = atomicAdd(&s.start[cell[k]], 1);
+        }
+    }
+    __syncthreads();
+    int chunk = (g.C + kRB - 1) / kRB;
+    int lo = min(g.C, t * chunk), hi = min(g.C, lo + chunk);
+    int local = 0;
+    for (int c = lo; c < hi; ++c) local += s.start[c];
+    int total;
+    int run = wg_excl_scan(local, s, total);
+    for (int c = lo; c < hi; ++c) {
+        int v = s.start[c];
+        s.start[c] = run;
+        run += v;
+    }
+    if (t == 0) s.start[g.C] = n;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int i = t + k * kRB;
+        if (i < n) s.sorted[s.start[cell[k]] + slot[k]] = (int16_t)i;
+    }
+    __syncthreads();
+    for (int c = t; c < g.C; c += kRB) {
+        int a0 = s.start[c], a1 = s.start[c + 1];
+        for (int a = a0 + 1; a < a1; ++a) {
+            int16_t key = s.sorted[a];
+            int q = a - 1;
+            while (q >= a0 && s.sorted[q] > key) {
+                s.sorted[q + 1] = s.sorted[q];
+                --q;
+            }
+            s.sorted[q + 1] = key;
+        }
+    }
+    __syncthreads();
+}
+
+// Visit every neighbor j of particle i from the 9 stencil cells: f(j, dx, dy, r2, pair type).
+template <typename Fn>
+__device__ __forceinline__ void rep_pairs(const Lds &s, const RepGeom &g, int i, int S, Fn &&f)
+{
+    uint32_t ui[2] = {s.pos[2 * i], s.pos[2 * i + 1]};
+    int cx = cell_coord(ui[0], g.nc[0]), cy = cell_coord(ui[1], g.nc[1]);
+    int si = s.spec[i];
+    for (int oy = g.lo[1]; oy <= g.hi[1]; ++oy) {
+        int y = wrap2(cy + oy, g.nc[1]);
+        for (int ox = g.lo[0]; ox <= g.hi[0]; ++ox) {
+            int c = wrap2(cx + ox, g.nc[0]) + g.nc[0] * y;
+            for (int q = s.start[c]; q < s.start[c + 1]; ++q) {
+                int j = s.sorted[q];
+                if (j == i) continue;
+                float dx = tdisp(ui[0], s.pos[2 * j], g.s[0]);
+                float dy = tdisp(ui[1], s.pos[2 * j + 1], g.s[1]);
+                float r2 = __builtin_fmaf(dx, dx, dy * dy);
+                f(j, dx, dy, r2, si * S + s.spec[j]);
+            }
+        }
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void rep_forces(const Lds &s, const RepGeom &g, const DevPot &p, int n, float (*F)[2])
+{
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int i = threadIdx.x + k * kRB;
+        float fx = 0.0f, fy = 0.0f;
+        if (i < n) {
+            rep_pairs(s, g, i, p.S, [&](int, float dx, float dy, float r2, int pt) {
+                float u;
+                float fs = pair_fs<KIND, true, false>(p, pt, r2, u);
+                fx = __builtin_fmaf(fs, dx, fx);
+                fy = __builtin_fmaf(fs, dy, fy);
+            });
+        }
+        F[k][0] = fx;
+        F[k][1] = fy;
+    }
+}
+
+__device__ bool rep_load(Lds &s, const BatchArgs &a, int b, float range, int &n, int &off, RepGeom &g)
+{
+    off = a.offset[b];
+    n = a.offset[b + 1] - off;
+    g = rep_geom(a.box[2 * b], a.box[2 * b + 1], range);
+    if (n < 0 || n > kMaxRepN || g.C > kMaxRepCells) return false;
+    for (int i = threadIdx.x; i < n; i += kRB) {
+        s.pos[2 * i] = a.pos[2 * (size_t)(off + i)];
+        s.pos[2 * i + 1] = a.pos[2 * (size_t)(off + i) + 1];
+        s.spec[i] = a.species ? (int8_t)a.species[off + i] : (int8_t)0;
+    }
+    __syncthreads();
+    return true;
+}
+
+__device__ __forceinline__ int next_replica(Lds &s, int32_t *queue)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) s.rep = atomicAdd(queue, 1);
+    __syncthreads();
+    return s.rep;
+}
+
+struct FireBatchParams {
+    double *energy;
+    double *fmax;
+    int32_t *steps;
+    int32_t *status;  // 1 converged, 0 not converged, -1 replica too large for a workgroup
+    float dt_start, dt_max, f_inc, f_dec, alpha_start, f_alpha, range;
+    int32_t n_min, max_steps;
+    double f_tol;
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, FireBatchParams fp)
+{
+    __shared__ Lds s;
+    if (threadIdx.x == 0) s.pot = pin;
+    __syncthreads();
+    const DevPot &p = s.pot;
+    for (int b = next_replica(s, a.queue); b < a.B; b = next_replica(s, a.queue)) {
+        int n, off;
+        RepGeom g;
+        if (!rep_load(s, a, b, fp.range, n, off, g)) {
+            if (threadIdx.x == 0) fp.status[b] = -1;
+            continue;
+        }
+        float v[kPerThread][2], F[kPerThread][2], Fn[kPerThread][2];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) v[k][0] = v[k][1] = 0.0f;
+        rep_cells(s, n, g);
+        rep_forces<KIND>(s, g, p, n, F);
+        double fm = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            fm = fmax(fm, (double)F[k][0] * F[k][0] + (double)F[k][1] * F[k][1]);
+        fm = wg_max(fm, s);
+        double dt = fp.dt_start, alpha = fp.alpha_start, mix_v = 1.0, mix_f = 0.0;
+        int n_pos = 0, steps = 0;
+        bool conv = sqrt(fm) < fp.f_tol;
+        while (!conv && steps < fp.max_steps) {
+            // velocity mixing decided by the previous step, then r += dt v + dt^2/2 F
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                int i = threadIdx.x + k * kRB;
+                if (i < n) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        v[k][q] = (float)(mix_v * (double)v[k][q] + mix_f * (double)F[k][q]);
+                        float dx = (float)(dt * (double)v[k][q] + 0.5 * dt * dt * (double)F[k][q]);
+                        s.pos[2 * i + q] += (uint32_t)__float2int_rn(dx * g.inv_s[q]);
+                    }
+                }
+            }
+            __syncthreads();
+            rep_cells(s, n, g);
+            rep_forces<KIND>(s, g, p, n, Fn);
+            double P = 0.0, vv = 0.0, ff = 0.0;
+            fm = 0.0;
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                int i = threadIdx.x + k * kRB;
+                if (i < n) {
+                    double f2 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        v[k][q] = (float)((double)v[k][q] + 0.5 * dt * ((double)F[k][q] + (double)Fn[k][q]));
+                        F[k][q] = Fn[k][q];
+                        P += (double)F[k][q] * (double)v[k][q];
+                        vv += (double)v[k][q] * (double)v[k][q];
+                        f2 += (double)F[k][q] * (double)F[k][q];
+                    }
+                    ff += f2;
+                    fm = fmax(fm, f2);
+                }
+            }
+            P = wg_sum(P, s);
+            vv = wg_sum(vv, s);
+            ff = wg_sum(ff, s);
+            fm = wg_max(fm, s);
+            ++steps;
+            if (sqrt(fm) < fp.f_tol) {
+                conv = true;
+                break;
+            }
+            if (P > 0.0) {
+                double fn = sqrt(ff), vn = sqrt(vv);
+                mix_v = 1.0 - alpha;
+                mix_f = fn > 0.0 ? alpha * vn / fn : 0.0;
+                if (++n_pos > fp.n_min) {
+                    dt = fmin(dt * (double)fp.f_inc, (double)fp.dt_max);
+                    alpha *= (double)fp.f_alpha;
+                }
+            } else {
+                mix_v = 0.0;
+                mix_f = 0.0;
+                dt *= (double)fp.f_dec;
+                alpha = (double)fp.alpha_start;
+                n_pos = 0;
+            }
+        }
+        // energy at the final positions, written back with them
+        double e = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            int i = threadIdx.x + k * kRB;
+            if (i < n) {
+                rep_pairs(s, g, i, p.S, [&](int, float, float, float r2, int pt) {
+                    float u = 0.0f;
+                    pair_fs<KIND, true, true>(p, pt, r2, u);
+                    e += (double)u;
+                });
+            }
+        }
+        e = 0.5 * wg_sum(e, s);
+        for (int i = threadIdx.x; i < n; i += kRB) {
+            a.pos[2 * (size_t)(off + i)] = s.pos[2 * i];
+            a.pos[2 * (size_t)(off + i) + 1] = s.pos[2 * i + 1];
+        }
+        if (threadIdx.x == 0) {
+            fp.energy[b] = e;
+            fp.fmax[b] = sqrt(fm);
+            fp.steps[b] = steps;
+            fp.status[b] = conv ? 1 : 0;
+        }
+    }
+}
+
+// du/dsigma and du/deps of one pair at fixed r (KIND 0: LJ, 1: soft sphere), and u.
+template <int KIND>
+__device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, float r2, float &dus, float &due,
+                                            float &u)
+    /* pot lives in LDS */
+{
+    float sig = pot.sigma[pt], eps = pot.epsilon[pt];
+    dus = due = u = 0.0f;
+    if (KIND == 0) {
+        if (!(r2 < pot.r_cut * pot.r_cut)) return;
+        float q = sig * sig / r2;
+        float s6 = q * q * q, s12 = s6 * s6;
+        float uu = 4.0f * eps * (s12 - s6);
+        float ds = 4.0f * eps * (12.0f * s12 - 6.0f * s6) / sig;
+        if (pot.shift) {
+            float qc = sig * sig / (pot.r_cut * pot.r_cut);
+            float c6 = qc * qc * qc, c12 = c6 * c6;
+            uu -= 4.0f * eps * (c12 - c6);
+            ds -= 4.0f * eps * (12.0f * c12 - 6.0f * c6) / sig;
+        }
+        u = uu;
+        dus = ds;
+        due = uu / eps;
+    } else {
+        float r = sqrtf(r2);
+        if (!(r < sig)) return;
+        float t = 1.0f - r / sig;
+        float a = pot.alpha;
+        float tp = a == 2.0f ? t : powf(t, a - 1.0f);
+        u = eps / a * tp * t;
+        dus = eps * tp * r / (sig * sig);
+        due = tp * t / a;
+    }
+}
+
+struct GradParams {
+    double *g_sigma;  // [B][S*S]
+    double *g_eps;    // [B][S*S]
+    double *energy;   // [B] or null
+    int32_t *status;  // [B] or null: -1 replica too large
+    float range;
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kRB) void k_param_grad(BatchArgs a, md_potential pin, GradParams gp)
+{
+    __shared__ Lds s;
+    if (threadIdx.x == 0) s.raw = pin;
+    __syncthreads();
+    const md_potential &pot = s.raw;
+    int S = pot.n_species;
+    for (int b = next_replica(s, a.queue); b < a.B; b = next_replica(s, a.queue)) {
+        int n, off;
+        RepGeom g;
+        if (!rep_load(s, a, b, gp.range, n, off, g)) {
+            if (threadIdx.x == 0 && gp.status) gp.status[b] = -1;
+            continue;
+        }
+        rep_cells(s, n, g);
+        // one pass per pair type keeps the accumulators in two registers
+        for (int q = 0; q < S * S; ++q) {
+            double gs = 0.0, ge = 0.0, e = 0.0;
+            for (int i = threadIdx.x; i < n; i += kRB) {
+                rep_pairs(s, g, i, S, [&](int, float, float, float r2, int pt) {
+                    if (pt != q) return;
+                    float dus, due, u;
+                    pair_dparam<KIND>(pot, pt, r2, dus, due, u);
+                    gs += (double)dus;
+                    ge += (double)due;
+                    e += (double)u;
+                });
+            }
+            gs = 0.5 * wg_sum(gs, s);
+            ge = 0.5 * wg_sum(ge, s);
+            e = 0.5 * wg_sum(e, s);
+            if (threadIdx.x == 0) {
+                gp.g_sigma[(size_t)b * S * S + q] = gs;
+                gp.g_eps[(size_t)b * S * S + q] = ge;
+                if (gp.energy) gp.energy[b] = (q == 0 ? 0.0 : gp.energy[b]) + e;
+            }
+        }
+        if (threadIdx.x == 0 && gp.status) gp.status[b] = 1;
+    }
+}
+
+__global__ void k_zero_queue(int32_t *q)
+{
+    if (threadIdx.x == 0) q[0] = 0;
+}
+
+md_status batch_check(md_ctx *ctx, const md_batch *bt, const md_potential *pot, DevPot &p)
+{
+    if (!ctx || !bt || !pot || bt->B < 0 || bt->dim != 2 || !bt->offset || !bt->box || !bt->pos) return MD_ERR_ARG;
+    if (!md_make_pot(pot, p)) return MD_ERR_ARG;
+    if (pot->n_species > 1 && !bt->species) return MD_ERR_ARG;
+    if (bt->max_n > kMaxRepN || bt->max_cells > kMaxRepCells) return MD_ERR_CAPACITY;
+    return MD_OK;
+}
+
+BatchArgs batch_args(md_ctx *ctx, const md_batch *bt)
+{
+    BatchArgs a;
+    a.B = bt->B;
+    a.offset = bt->offset;
+    a.box = bt->box;
+    a.pos = bt->pos;
+    a.species = bt->species;
+    a.queue = ctx->queue;
+    return a;
+}
+
+int batch_grid(int B)
+{
+    return B < 512 ? (B > 0 ? B : 1) : 512;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status fire_batched(md_ctx *ctx, const md_batch *bt, const md_potential *pot, const md_fire_params *fp,
+                       int32_t max_steps, double f_tol, double *energy, double *fmax, int32_t *steps,
+                       int32_t *status, void *stream)
+{
+    DevPot p;
+    md_status st = batch_check(ctx, bt, pot, p);
+    if (st != MD_OK) return st;
+    if (!fp || !energy || !fmax || !steps || !status || max_steps < 0) return MD_ERR_ARG;
+    if (bt->B == 0) return MD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    BatchArgs a = batch_args(ctx, bt);
+    FireBatchParams q;
+    q.energy = energy;
+    q.fmax = fmax;
+    q.steps = steps;
+    q.status = status;
+    q.dt_start = fp->dt_start;
+    q.dt_max = fp->dt_max;
+    q.f_inc = fp->f_inc;
+    q.f_dec = fp->f_dec;
+    q.alpha_start = fp->alpha_start;
+    q.f_alpha = fp->f_alpha;
+    q.range = md_max_cutoff(pot);
+    q.n_min = fp->n_min;
+    q.max_steps = max_steps;
+    q.f_tol = f_tol;
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, ctx->queue);
+    if (pot->kind == MD_LJ)
+        hipLaunchKernelGGL(k_fire_batched<0>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, p, q);
+    else
+        hipLaunchKernelGGL(k_fire_batched<1>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, p, q);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status envelope_grad(md_ctx *ctx, const md_batch *bt, const md_potential *pot, double *g_sigma, double *g_eps,
+                        double *energy, int32_t *status, void *stream)
+{
+    DevPot p;
+    md_status st = batch_check(ctx, bt, pot, p);
+    if (st != MD_OK) return st;
+    if (!g_sigma || !g_eps || pot->n_species > kMaxS) return MD_ERR_ARG;
+    if (bt->B == 0) return MD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    BatchArgs a = batch_args(ctx, bt);
+    GradParams gp;
+    gp.g_sigma = g_sigma;
+    gp.g_eps = g_eps;
+    gp.energy = energy;
+    gp.status = status;
+    gp.range = md_max_cutoff(pot);
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, ctx->queue);
+    if (pot->kind == MD_LJ)
+        hipLaunchKernelGGL(k_param_grad<0>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, *pot, gp);
+    else
+        hipLaunchKernelGGL(k_param_grad<1>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, *pot, gp);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+}  // extern "C"

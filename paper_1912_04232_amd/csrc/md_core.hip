@@ -35,6 +35,7 @@
 
 #include "../../include/md.h"
 #include "md_device.h"
+#include "md_host.h"
 
 using namespace md;
 
@@ -61,13 +62,6 @@ struct ListParams {
     float kappa;             // pipelined rebuild starts when disp + kappa * (last step + dt^2 |F|) > skin/2
 };
 
-struct CountSort {
-    int32_t *cell_of;
-    int32_t *slot;
-    int32_t *sorted_idx;
-    int32_t *cell_count;
-    int32_t *cell_start;
-};
 
 enum { M_IDLE = 0, M_BIN = 1, M_BUILD = 2 };
 // Control words (device).  Verlet: ctl[2*slot] = mode and ctl[2*slot+1] = generation of step s at
@@ -970,28 +964,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_final(const double *partials, in
 // ------------------------------------------------------------------------------------------------
 // host side: context, argument checks, dispatch
 
-struct md_ctx {
-    int device = 0;
-    int32_t N_cap = 0, dim_cap = 0, C_cap = 0, cap_cap = 0, M_cap = 0, W_cap = 0;
-    uint32_t *pos_alt = nullptr;
-    CountSort cs = {};
-    int32_t *bin_cnt[2] = {nullptr, nullptr};
-    int32_t *bin_id[2] = {nullptr, nullptr};
-    uint32_t *bin_pos[2] = {nullptr, nullptr};
-    int32_t *g1_idx = nullptr, *g1_count = nullptr;
-    uint32_t *g1_pos_ref = nullptr;
-    int32_t *ctl = nullptr;        // kCtlWords
-    double *partials = nullptr;    // 4 * kMaxBlocks doubles
-    int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
-};
-
 static constexpr int kMaxBlocks = 1 << 16;
 static constexpr float kKappa = 2.0f;
-
-#define HIP_OK(x)                                    \
-    do {                                             \
-        if ((x) != hipSuccess) return MD_ERR_HIP;    \
-    } while (0)
 
 static bool make_box(const md_box *box, float r_list, DevBox &b)
 {
@@ -1022,7 +996,7 @@ static bool make_box(const md_box *box, float r_list, DevBox &b)
     return true;
 }
 
-static bool make_pot(const md_potential *pot, DevPot &p)
+bool md_make_pot(const md_potential *pot, DevPot &p)
 {
     if (!pot || (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE)) return false;
     int S = pot->n_species;
@@ -1056,7 +1030,7 @@ static bool make_pot(const md_potential *pot, DevPot &p)
     return true;
 }
 
-static float max_cutoff(const md_potential *pot)
+float md_max_cutoff(const md_potential *pot)
 {
     if (pot->kind == MD_LJ) return pot->r_cut;
     float m = 0.0f;
@@ -1218,11 +1192,13 @@ md_status md_ctx_create(int device, md_ctx **out)
     if (hipMalloc(&c->partials, sizeof(double) * 4 * kMaxBlocks) != hipSuccess ||
         hipMalloc(&c->own_flags, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
         hipMalloc(&c->ctl, sizeof(int32_t) * kCtlWords) != hipSuccess ||
+        hipMalloc(&c->queue, sizeof(int32_t) * 4) != hipSuccess ||
         hipMemset(c->own_flags, 0, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
         hipMemset(c->ctl, 0, sizeof(int32_t) * kCtlWords) != hipSuccess) {
         (void)hipFree(c->partials);
         (void)hipFree(c->own_flags);
         (void)hipFree(c->ctl);
+        (void)hipFree(c->queue);
         delete c;
         return MD_ERR_HIP;
     }
@@ -1256,6 +1232,7 @@ md_status md_ctx_destroy(md_ctx *ctx)
     (void)hipFree(ctx->partials);
     (void)hipFree(ctx->own_flags);
     (void)hipFree(ctx->ctl);
+    (void)hipFree(ctx->queue);
     delete ctx;
     return MD_OK;
 }
@@ -1352,12 +1329,12 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
     DevPot p;
-    if (!pos || !make_pot(pot, p)) return MD_ERR_ARG;
+    if (!pos || !md_make_pot(pot, p)) return MD_ERR_ARG;
     bool multi = pot->n_species > 1;
     if (multi && !species) return MD_ERR_ARG;
     if (nl && !nl_ok(nl, N)) return MD_ERR_ARG;
-    if (nl && nl->r_list < max_cutoff(pot)) return MD_ERR_ARG;
-    if (!box_ok(box, nl ? nl->r_list : max_cutoff(pot))) return MD_ERR_BOX;
+    if (nl && nl->r_list < md_max_cutoff(pot)) return MD_ERR_ARG;
+    if (!box_ok(box, nl ? nl->r_list : md_max_cutoff(pot))) return MD_ERR_BOX;
     DevBox b;
     if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
     if (N == 0) return MD_OK;
@@ -1398,11 +1375,11 @@ static md_status run_checks(md_ctx *ctx, const md_box *box, const md_potential *
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!make_pot(pot, p)) return MD_ERR_ARG;
+    if (!md_make_pot(pot, p)) return MD_ERR_ARG;
     if (pot->n_species > 1 && !species) return MD_ERR_ARG;
     st = check_list(ctx, box, nl, N, b);
     if (st != MD_OK) return st;
-    if (nl->r_list < max_cutoff(pot)) return MD_ERR_ARG;
+    if (nl->r_list < md_max_cutoff(pot)) return MD_ERR_ARG;
     if (nl->capacity > ctx->cap_cap || nl->lanes > ctx->W_cap) return MD_ERR_CAPACITY;
     return MD_OK;
 }

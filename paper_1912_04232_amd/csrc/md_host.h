@@ -1,0 +1,43 @@
+// Host-side internals shared by the library's translation units: the context and helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/md.h"
+#include "md_device.h"
+
+#define HIP_OK(x)                                    \
+    do {                                             \
+        if ((x) != hipSuccess) return MD_ERR_HIP;    \
+    } while (0)
+
+struct CountSort {
+    int32_t *cell_of;
+    int32_t *slot;
+    int32_t *sorted_idx;
+    int32_t *cell_count;
+    int32_t *cell_start;
+};
+
+struct md_ctx {
+    int device = 0;
+    int32_t N_cap = 0, dim_cap = 0, C_cap = 0, cap_cap = 0, M_cap = 0, W_cap = 0;
+    uint32_t *pos_alt = nullptr;
+    CountSort cs = {};
+    int32_t *bin_cnt[2] = {nullptr, nullptr};
+    int32_t *bin_id[2] = {nullptr, nullptr};
+    uint32_t *bin_pos[2] = {nullptr, nullptr};
+    int32_t *g1_idx = nullptr, *g1_count = nullptr;
+    uint32_t *g1_pos_ref = nullptr;
+    int32_t *ctl = nullptr;        // kCtlWords
+    double *partials = nullptr;    // 4 * kMaxBlocks doubles
+    int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
+    int32_t *queue = nullptr;      // work counter of batched launches
+};
+
+
+// Pair-potential coefficients for the kernels; false for an invalid potential.
+bool md_make_pot(const md_potential *pot, md::DevPot &p);
+// Largest interaction range of the potential (LJ cutoff, or the largest soft-sphere sigma).
+float md_max_cutoff(const md_potential *pot);

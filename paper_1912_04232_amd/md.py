@@ -67,6 +67,12 @@ class c_fire_state(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("n_pos", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
+class c_batch(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("dim", ctypes.c_int32), ("max_n", ctypes.c_int32),
+                ("max_cells", ctypes.c_int32), ("offset", ctypes.c_void_p), ("box", ctypes.c_void_p),
+                ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p)]
+
+
 FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
 _lib = None
 
@@ -88,6 +94,9 @@ _SIGNATURES = {
                   ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_double, P],
     "fire_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
                   ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_int32, ctypes.c_double, P],
+    "fire_batched": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
+                     ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
+    "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
     "md_sum": [P, P, ctypes.c_int64, P, P],
     "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
@@ -360,6 +369,77 @@ def fire_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, 
     _check("fire_step", load().fire_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                          _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
                                          _ptr(state), int(n_steps), ctypes.c_double(f_tol), _stream()))
+
+
+class Batch:
+    """md_batch: B independent 2D replicas of uneven size, concatenated (offset[B+1], box[B][2], pos, species)."""
+
+    def __init__(self, replicas, device=None):
+        dev = device or _dev()
+        self.B = len(replicas)
+        self.dim = 2
+        sizes = [int(r["u"].shape[0]) for r in replicas]
+        self.sizes = sizes
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        self.offset = torch.as_tensor(off, device=dev)
+        boxes = np.array([[r["L"][0], r["L"][1]] for r in replicas], dtype=np.float32)
+        self.boxes = boxes
+        self.box = torch.as_tensor(boxes, device=dev)
+        u = np.concatenate([np.asarray(r["u"], dtype=np.uint32) for r in replicas]) if replicas else \
+            np.zeros((0, 2), np.uint32)
+        self.pos = to_device_u32(u, dev)
+        sp = [r.get("species") for r in replicas]
+        self.species = None if sp and sp[0] is None else torch.as_tensor(
+            np.concatenate([np.asarray(x, dtype=np.int32) for x in sp]), device=dev)
+        self.max_n = max(sizes) if sizes else 0
+
+    def max_cells(self, r_range: float) -> int:
+        m = 1
+        for Lx, Ly in self.boxes:
+            c = 1
+            for L in (Lx, Ly):
+                k = int(np.floor(float(L) / (r_range * (1 + 1e-6))))
+                c *= k if k >= 3 else 1
+            m = max(m, c)
+        return m
+
+    def c(self, r_range: float) -> c_batch:
+        b = c_batch()
+        b.B, b.dim, b.max_n, b.max_cells = self.B, 2, self.max_n, self.max_cells(r_range)
+        b.offset, b.box, b.pos = self.offset.data_ptr(), self.box.data_ptr(), self.pos.data_ptr()
+        b.species = self.species.data_ptr() if self.species is not None else None
+        return b
+
+    def replica_positions(self, b: int) -> np.ndarray:
+        off = self.offset.cpu().numpy()
+        return from_device_u32(self.pos)[off[b]:off[b + 1]]
+
+
+def fire_batched(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, max_steps: int, f_tol: float):
+    """FIRE on every replica in one launch.  Returns (energy[B] f64, fmax[B] f64, steps[B] i32, status[B] i32)."""
+    dev = batch.pos.device
+    e = torch.zeros(max(batch.B, 1), dtype=torch.float64, device=dev)
+    fm = torch.zeros_like(e)
+    st = torch.zeros(max(batch.B, 1), dtype=torch.int32, device=dev)
+    status = torch.zeros_like(st)
+    b, p, f = batch.c(pot.cutoff()), pot.c(), fp.c()
+    _check("fire_batched", load().fire_batched(ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f),
+                                               int(max_steps), ctypes.c_double(f_tol), _ptr(e), _ptr(fm), _ptr(st),
+                                               _ptr(status), _stream()))
+    return e[: batch.B], fm[: batch.B], st[: batch.B], status[: batch.B]
+
+
+def envelope_grad(ctx: Context, batch: Batch, pot: Potential):
+    """dU/dsigma_ab, dU/deps_ab (each [B][S][S], per ordered species pair) and U[B] at the batch positions."""
+    dev = batch.pos.device
+    S = pot.n_species
+    gs = torch.zeros((max(batch.B, 1), S, S), dtype=torch.float64, device=dev)
+    ge = torch.zeros_like(gs)
+    e = torch.zeros(max(batch.B, 1), dtype=torch.float64, device=dev)
+    b, p = batch.c(pot.cutoff()), pot.c()
+    _check("envelope_grad", load().envelope_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(gs), _ptr(ge),
+                                                 _ptr(e), None, _stream()))
+    return gs[: batch.B], ge[: batch.B], e[: batch.B]
 
 
 def md_sum(ctx: Context, x: torch.Tensor, out: torch.Tensor):

@@ -470,3 +470,27 @@ def test_workload_boxes():
     v = inputs.maxwell_velocities(500, 3, 1.5, 1)
     assert np.abs(v.astype(np.float64).sum(0)).max() < 1e-4
     assert math.isclose(float(np.sum(v.astype(np.float64) ** 2)) / (3 * 499), 1.5, rel_tol=1e-5)
+
+
+def test_envelope_theorem_through_fire(orc):
+    """dE*/dd_s of the FIRE-minimized energy (box fixed, same start) by central differences (h = 1e-4) equals
+    dU/dd_s at the minimum: the oracle's parameter gradient is the adjoint of the minimizer."""
+    N = 40
+    L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], 0.9, 2)
+    x0 = orc.decode(inputs.uniform_torus(N, 2, 77), [L, L])
+    sp = inputs.bidisperse_species(N)
+    d = np.array([1.0, 1.4])
+    res = orc.fire(x0, [L, L], ss_pot(orc, d=d), sp, f_tol=1e-11, max_steps=200000)
+    assert res["converged"]
+    g = orc.diameter_grad(res["x"], [L, L], d, 1.0, sp)
+    h = 1e-4
+    for s in range(2):
+        E = []
+        for sgn in (1, -1):
+            dd = d.copy()
+            dd[s] += sgn * h
+            r = orc.fire(x0, [L, L], ss_pot(orc, d=dd), sp, f_tol=1e-11, max_steps=200000)
+            assert r["converged"]
+            E.append(orc.energy(r["x"], [L, L], ss_pot(orc, d=dd), sp))
+        fd = (E[0] - E[1]) / (2 * h)
+        assert math.isclose(g[s], fd, rel_tol=1e-5, abs_tol=1e-10), (s, g[s], fd)
