@@ -104,7 +104,7 @@ def main():
     N = cfg["N"]
     box = md.Box(tuple(cfg["L"]), 3)
     pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=cfg["r_cut"])
-    s = md.System(box, pot, cfg["u"], cfg["v"], skin=cfg["skin"], capacity=128, lanes=args.lanes)
+    s = md.System(box, pot, cfg["u"], cfg["v"], skin=cfg["skin"], lanes=args.lanes)
     init, update = md.nve(s, cfg["dt"])
     init()
     E_init = s.potential_energy() + s.kinetic_energy()

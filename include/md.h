@@ -289,6 +289,35 @@ md_status fire_batched(md_ctx *ctx, const md_batch *batch, const md_potential *p
 md_status envelope_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, double *g_sigma,
                         double *g_eps, double *energy, int32_t *status, void *stream);
 
+/*
+ * Neural pair potential (Sec. 3.2.4 featurizations, Sec. 4.1 per-atom networks, forces as -grad E by
+ * Sec. 3.3.2): K = 16 radial basis functions
+ *   G_i^k = sum_{j != i, r_ij < r_c} exp(-eta (r_ij - mu_k)^2) (cos(pi r_ij / r_c) + 1)/2,
+ *   mu_k = mu0 + k (mu1 - mu0)/(K-1), eta = 1/(2 ((mu1 - mu0)/(K-1))^2),
+ * and an MLP with H = 64: x = (G - m)/s, E_i = w3 . sp(W2 sp(W1 x + b1) + b2) + b3, sp = softplus.
+ * W1, W2 are BF16 (the MFMA operands), everything else float.  All pointers are device memory.
+ */
+typedef struct {
+    int32_t K;              /* 16 */
+    int32_t H;              /* 64 */
+    float mu0, mu1, r_c;    /* basis centres and cutoff */
+    float b3;               /* output bias */
+    const uint16_t *W1;     /* bf16 [H][K] */
+    const uint16_t *W2;     /* bf16 [H][H] */
+    const float *b1, *b2;   /* [H] */
+    const float *w3;        /* [H] */
+    const float *m, *s;     /* [K] descriptor shift and scale */
+} md_nn_params;
+
+/* G[i][k] (float [N][K]) over a neighbor list with r_list >= r_c (3D). */
+md_status nn_descriptors(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
+                         const md_nlist *nl, float *G, void *stream);
+/* Per-atom energies Ei [N] and input gradients e[i][k] = dE_i/dG_i^k [N][K] (BF16 MFMA, FP32 accumulate). */
+md_status nn_mlp(md_ctx *ctx, const md_nn_params *nn, const float *G, int32_t N, float *Ei, float *e, void *stream);
+/* F_i = -sum_j sum_k (e_i^k + e_j^k) g_k'(r_ij) (r_i - r_j)/r_ij over the list (3D). */
+md_status nn_forces(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
+                    const md_nlist *nl, const float *e, float *force, void *stream);
+
 /* out[0] = sum of x[0..n) in double, summed in a fixed order (deterministic). out is device memory. */
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
 /* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */

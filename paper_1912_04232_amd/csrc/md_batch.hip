@@ -37,6 +37,7 @@ constexpr int kMaxS = 8;          // species handled by the gradient kernel
 
 struct RepGeom {
     float s[2], inv_s[2];
+    double sd[2];
     int nc[2], lo[2], hi[2], C;
 };
 
@@ -74,6 +75,7 @@ __device__ __forceinline__ RepGeom rep_geom(float Lx, float Ly, float range)
     for (int k = 0; k < 2; ++k) {
         g.s[k] = L[k] / 4294967296.0f;
         g.inv_s[k] = 4294967296.0f / L[k];
+        g.sd[k] = (double)L[k] / 4294967296.0;
         int m = (int)floor((double)L[k] / ((double)range * (1.0 + 1e-6)));
         int nc = m >= 3 ? m : 1;
         g.nc[k] = nc;
@@ -186,7 +188,7 @@ __device__ void rep_cells(Lds &s, int n, const RepGeom &g)
     __syncthreads();
 }
 
-// Visit every neighbor j of particle i from the 9 stencil cells: f(j, dx, dy, r2, pair type).
+// Visit every neighbor j of particle i from the 9 stencil cells: f(j, ui, uj, pair type).
 template <typename Fn>
 __device__ __forceinline__ void rep_pairs(const Lds &s, const RepGeom &g, int i, int S, Fn &&f)
 {
@@ -200,10 +202,8 @@ __device__ __forceinline__ void rep_pairs(const Lds &s, const RepGeom &g, int i,
             for (int q = s.start[c]; q < s.start[c + 1]; ++q) {
                 int j = s.sorted[q];
                 if (j == i) continue;
-                float dx = tdisp(ui[0], s.pos[2 * j], g.s[0]);
-                float dy = tdisp(ui[1], s.pos[2 * j + 1], g.s[1]);
-                float r2 = __builtin_fmaf(dx, dx, dy * dy);
-                f(j, dx, dy, r2, si * S + s.spec[j]);
+                uint32_t uj[2] = {s.pos[2 * j], s.pos[2 * j + 1]};
+                f(j, ui, uj, si * S + s.spec[j]);
             }
         }
     }
@@ -217,11 +217,11 @@ __device__ __forceinline__ void rep_forces(const Lds &s, const RepGeom &g, const
         int i = threadIdx.x + k * kRB;
         float fx = 0.0f, fy = 0.0f;
         if (i < n) {
-            rep_pairs(s, g, i, p.S, [&](int, float dx, float dy, float r2, int pt) {
-                float u;
-                float fs = pair_fs<KIND, true, false>(p, pt, r2, u);
-                fx = __builtin_fmaf(fs, dx, fx);
-                fy = __builtin_fmaf(fs, dy, fy);
+            rep_pairs(s, g, i, p.S, [&](int, const uint32_t *ui, const uint32_t *uj, int pt) {
+                float d[2], r2, u;
+                float fs = pair_eval<2, KIND, true, false>(p, pt, ui, uj, g.s, g.sd, d, r2, u);
+                fx = __builtin_fmaf(fs, d[0], fx);
+                fy = __builtin_fmaf(fs, d[1], fy);
             });
         }
         F[k][0] = fx;
@@ -356,9 +356,9 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
         for (int k = 0; k < kPerThread; ++k) {
             int i = threadIdx.x + k * kRB;
             if (i < n) {
-                rep_pairs(s, g, i, p.S, [&](int, float, float, float r2, int pt) {
-                    float u = 0.0f;
-                    pair_fs<KIND, true, true>(p, pt, r2, u);
+                rep_pairs(s, g, i, p.S, [&](int, const uint32_t *ui, const uint32_t *uj, int pt) {
+                    float d[2], r2, u = 0.0f;
+                    pair_eval<2, KIND, true, true>(p, pt, ui, uj, g.s, g.sd, d, r2, u);
                     e += (double)u;
                 });
             }
@@ -379,9 +379,8 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
 
 // du/dsigma and du/deps of one pair at fixed r (KIND 0: LJ, 1: soft sphere), and u.
 template <int KIND>
-__device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, float r2, float &dus, float &due,
-                                            float &u)
-    /* pot lives in LDS */
+__device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, float r2, double rd, float &dus,
+                                            float &due, float &u)
 {
     float sig = pot.sigma[pt], eps = pot.epsilon[pt];
     dus = due = u = 0.0f;
@@ -401,9 +400,10 @@ __device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, flo
         dus = ds;
         due = uu / eps;
     } else {
-        float r = sqrtf(r2);
-        if (!(r < sig)) return;
-        float t = 1.0f - r / sig;
+        // overlap from the double distance (see ss_fs_precise)
+        if (!(rd < (double)sig)) return;
+        float r = (float)rd;
+        float t = (float)(((double)sig - rd) / (double)sig);
         float a = pot.alpha;
         float tp = a == 2.0f ? t : powf(t, a - 1.0f);
         u = eps / a * tp * t;
@@ -440,10 +440,12 @@ __global__ __launch_bounds__(kRB) void k_param_grad(BatchArgs a, md_potential pi
         for (int q = 0; q < S * S; ++q) {
             double gs = 0.0, ge = 0.0, e = 0.0;
             for (int i = threadIdx.x; i < n; i += kRB) {
-                rep_pairs(s, g, i, S, [&](int, float, float, float r2, int pt) {
+                rep_pairs(s, g, i, S, [&](int, const uint32_t *ui, const uint32_t *uj, int pt) {
                     if (pt != q) return;
+                    double dx = tdisp_d(ui[0], uj[0], g.sd[0]), dy = tdisp_d(ui[1], uj[1], g.sd[1]);
+                    double r2d = __builtin_fma(dx, dx, dy * dy);
                     float dus, due, u;
-                    pair_dparam<KIND>(pot, pt, r2, dus, due, u);
+                    pair_dparam<KIND>(pot, pt, (float)r2d, __builtin_sqrt(r2d), dus, due, u);
                     gs += (double)dus;
                     ge += (double)due;
                     e += (double)u;

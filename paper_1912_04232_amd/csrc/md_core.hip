@@ -72,6 +72,13 @@ constexpr int kCtlWords = 16;
 constexpr int kGenWord = 9;
 constexpr int kTrigWord = 10;
 
+// Raise *addr to v.  Every workgroup calls this with its own maximum; atomics on one address from thousands
+// of workgroups serialize (~0.1 us each), so only a workgroup that exceeds the value already there issues one.
+__device__ __forceinline__ void raise_max(int32_t *addr, int v)
+{
+    if (v > __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(addr, v);
+}
+
 // Set *addr = 1 when any lane of the wave has cond (one store per wave instead of one per lane).
 __device__ __forceinline__ void wave_flag(bool cond, int32_t *addr)
 {
@@ -199,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_cs_fill_bins(const uint32_t *__restr
     }
     wave_flag(occ > M, &flags[MD_FLAG_CELL_OVERFLOW]);
     occ = block_max(occ, red);
-    if (threadIdx.x == 0) atomicMax(&flags[MD_FLAG_MAXCELL], occ);
+    if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCELL], occ);
 }
 
 // Lane l's share of particle i's row at reference position ui: walk the stencil bins in order,
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restric
     wave_flag(n > lp.capW, &flags[MD_FLAG_OVERFLOW]);
     n = block_max(n, red);
     if (threadIdx.x == 0) {
-        atomicMax(&flags[MD_FLAG_MAXCOUNT], n * W);
+        raise_max(&flags[MD_FLAG_MAXCOUNT], n * W);
         if (blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
     }
 }
@@ -369,15 +376,9 @@ __device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, con
         for (int a = 0; a < 4; ++a) load_pos<D>(pos, j[a], uj[a]);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            float d[D], r2 = 0.0f;
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                d[q] = tdisp(ui[q], uj[a][q], b.s[q]);
-                r2 = __builtin_fmaf(d[q], d[q], r2);
-            }
+            float d[D], r2, u;
             int pt = MULTI ? si * p.S + species[j[a]] : 0;
-            float u;
-            float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
+            float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, uj[a], b.s, b.sd, d, r2, u);
 #pragma unroll
             for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
         }
@@ -386,15 +387,9 @@ __device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, con
         int j = idx[((size_t)t * N + i) * W + l];
         uint32_t uj[D];
         load_pos<D>(pos, j, uj);
-        float d[D], r2 = 0.0f;
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            d[q] = tdisp(ui[q], uj[q], b.s[q]);
-            r2 = __builtin_fmaf(d[q], d[q], r2);
-        }
+        float d[D], r2, u;
         int pt = MULTI ? si * p.S + species[j] : 0;
-        float u;
-        float fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
+        float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, uj, b.s, b.sd, d, r2, u);
 #pragma unroll
         for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
     }
@@ -430,15 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_nl(DevBox b, DevPot p, const ui
                 int j = idx[((size_t)t * N + i) * W + l];
                 uint32_t uj[D];
                 load_pos<D>(pos, j, uj);
-                float d[D], r2 = 0.0f;
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    d[q] = tdisp(ui[q], uj[q], b.s[q]);
-                    r2 = __builtin_fmaf(d[q], d[q], r2);
-                }
+                float d[D], r2, u = 0.0f;
                 int pt = MULTI ? si * p.S + species[j] : 0;
-                float u = 0.0f;
-                float fs = pair_fs<KIND, MULTI, WANT_EW>(p, pt, r2, u);
+                float fs = pair_eval<D, KIND, MULTI, WANT_EW>(p, pt, ui, uj, b.s, b.sd, d, r2, u);
 #pragma unroll
                 for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
                 if (WANT_EW) {
@@ -492,15 +481,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_dense(DevBox b, DevPot p, const
         if (live) {
             for (int jj = 0; jj < jn; ++jj) {
                 if (j0 + jj == i) continue;
-                float d[D], r2 = 0.0f;
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    d[q] = tdisp(ui[q], tile[jj * D + q], b.s[q]);
-                    r2 = __builtin_fmaf(d[q], d[q], r2);
-                }
+                float d[D], r2, u = 0.0f;
                 int pt = MULTI ? si * p.S + tsp[jj] : 0;
-                float u = 0.0f;
-                float fs = pair_fs<KIND, MULTI, WANT_EW>(p, pt, r2, u);
+                float fs = pair_eval<D, KIND, MULTI, WANT_EW>(p, pt, ui, &tile[jj * D], b.s, b.sd, d, r2, u);
 #pragma unroll
                 for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
                 if (WANT_EW) {
@@ -635,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
         int nwaves = (gridDim.x * kBlock) >> 6;
         int occ = bin_gather<D>(a.pos_in, a.box, a.bins[gen], a.bins[gen ^ 1], lp.M, a.flags, wave, nwaves);
         occ = block_max(occ, red);
-        if (threadIdx.x == 0) atomicMax(&a.flags[MD_FLAG_MAXCELL], occ);
+        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCELL], occ);
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < lp.N; i += gridDim.x * kBlock) {
             uint32_t ui[D];
             load_pos<D>(a.pos_in, i, ui);
@@ -654,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
         }
         wave_flag(n > lp.capW, &a.flags[MD_FLAG_OVERFLOW]);
         n = block_max(n, red);
-        if (threadIdx.x == 0) atomicMax(&a.flags[MD_FLAG_MAXCOUNT], n * W);
+        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCOUNT], n * W);
     }
     const ListGen &g = a.gen[gen];
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;

@@ -88,6 +88,44 @@ __device__ __forceinline__ float pair_fs(const DevPot &p, int pt, float r2, floa
     }
 }
 
+// Soft sphere with the overlap t = 1 - r/sigma formed in double from the exact integer displacement
+// (dd[k] = wrap32(u_ik - u_jk) * L_k/2^32): near contact t is a small difference of two numbers close to
+// 1 and a float r would leave it with a relative error ~1e-7/t.  Returns f/r; u when WANT_U.
+template <int D, bool MULTI, bool WANT_U>
+__device__ __forceinline__ float ss_fs_precise(const DevPot &p, int pt, const double *dd, float &u)
+{
+    int q = MULTI ? pt : 0;
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) r2 = __builtin_fma(dd[k], dd[k], r2);
+    double r = __builtin_sqrt(r2);
+    double sig = (double)p.sig[q];
+    bool in = r < sig;
+    float t = (float)((sig - r) / sig);
+    float tp = p.alpha_is_2 ? t : __builtin_exp2f((p.alpha - 1.0f) * __builtin_log2f(fmaxf(t, 1e-30f)));
+    float fs = p.eps_over_sig[q] * tp / (float)r;
+    if (WANT_U) u = in ? p.eps_over_alpha[q] * tp * t : 0.0f;
+    return in ? fs : 0.0f;
+}
+
+// f/r (and u) of one pair from the torus coordinates ui, uj; d[] receives the float displacement.
+template <int D, int KIND, bool MULTI, bool WANT_U>
+__device__ __forceinline__ float pair_eval(const DevPot &p, int pt, const uint32_t *ui, const uint32_t *uj,
+                                           const float *s, const double *sd, float *d, float &r2, float &u)
+{
+    r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        d[k] = tdisp(ui[k], uj[k], s[k]);
+        r2 = __builtin_fmaf(d[k], d[k], r2);
+    }
+    if (KIND == 0) return pair_fs<KIND, MULTI, WANT_U>(p, pt, r2, u);
+    double dd[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) dd[k] = tdisp_d(ui[k], uj[k], sd[k]);
+    return ss_fs_precise<D, MULTI, WANT_U>(p, pt, dd, u);
+}
+
 // Cell coordinate along one dimension: floor(u * nc / 2^32), exact in integers.
 __device__ __forceinline__ int cell_coord(uint32_t u, int nc)
 {

@@ -73,6 +73,13 @@ class c_batch(ctypes.Structure):
                 ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p)]
 
 
+class c_nn_params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("H", ctypes.c_int32), ("mu0", ctypes.c_float), ("mu1", ctypes.c_float),
+                ("r_c", ctypes.c_float), ("b3", ctypes.c_float), ("W1", ctypes.c_void_p), ("W2", ctypes.c_void_p),
+                ("b1", ctypes.c_void_p), ("b2", ctypes.c_void_p), ("w3", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("s", ctypes.c_void_p)]
+
+
 FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
 _lib = None
 
@@ -97,6 +104,11 @@ _SIGNATURES = {
     "fire_batched": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
                      ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
     "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
+    "nn_descriptors": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32,
+                       ctypes.POINTER(c_nlist), P, P],
+    "nn_mlp": [P, ctypes.POINTER(c_nn_params), P, ctypes.c_int32, P, P, P],
+    "nn_forces": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32, ctypes.POINTER(c_nlist),
+                  P, P, P],
     "md_sum": [P, P, ctypes.c_int64, P, P],
     "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
@@ -440,6 +452,64 @@ def envelope_grad(ctx: Context, batch: Batch, pot: Potential):
     _check("envelope_grad", load().envelope_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(gs), _ptr(ge),
                                                  _ptr(e), None, _stream()))
     return gs[: batch.B], ge[: batch.B], e[: batch.B]
+
+
+class NNParams:
+    """Device copy of the neural pair potential: BF16 W1 [H][K], W2 [H][H]; float b1, b2, w3 [H], b3; m, s [K]."""
+
+    def __init__(self, W1, b1, W2, b2, w3, b3, m, s, mu0=0.8, mu1=2.5, r_c=2.5, device=None):
+        dev = device or _dev()
+
+        def f32(a):
+            return torch.as_tensor(np.asarray(a, dtype=np.float32), device=dev).contiguous()
+
+        self.W1 = f32(W1).to(torch.bfloat16).contiguous()
+        self.W2 = f32(W2).to(torch.bfloat16).contiguous()
+        self.b1, self.b2, self.w3, self.m, self.s = f32(b1), f32(b2), f32(w3), f32(m), f32(s)
+        self.b3 = float(b3)
+        self.mu0, self.mu1, self.r_c = float(mu0), float(mu1), float(r_c)
+        self.K, self.H = int(self.W1.shape[1]), int(self.W1.shape[0])
+
+    def c(self) -> c_nn_params:
+        q = c_nn_params()
+        q.K, q.H, q.mu0, q.mu1, q.r_c, q.b3 = self.K, self.H, self.mu0, self.mu1, self.r_c, self.b3
+        q.W1, q.W2 = self.W1.data_ptr(), self.W2.data_ptr()
+        q.b1, q.b2, q.w3, q.m, q.s = (t.data_ptr() for t in (self.b1, self.b2, self.w3, self.m, self.s))
+        return q
+
+    def host(self) -> dict:
+        """Weights as float64 numpy arrays (W1, W2 exactly the BF16 values)."""
+        return dict(W1=self.W1.float().cpu().numpy().astype(np.float64),
+                    W2=self.W2.float().cpu().numpy().astype(np.float64),
+                    b1=self.b1.cpu().numpy().astype(np.float64), b2=self.b2.cpu().numpy().astype(np.float64),
+                    w3=self.w3.cpu().numpy().astype(np.float64), b3=self.b3,
+                    m=self.m.cpu().numpy().astype(np.float64), s=self.s.cpu().numpy().astype(np.float64))
+
+
+def nn_descriptors(ctx: Context, box: Box, nn: NNParams, pos: torch.Tensor, nl: NeighborList) -> torch.Tensor:
+    N = pos.shape[0]
+    G = torch.zeros((N, nn.K), dtype=torch.float32, device=pos.device)
+    b, q, n = box.c(), nn.c(), nl.c()
+    _check("nn_descriptors", load().nn_descriptors(ctx.h, ctypes.byref(b), ctypes.byref(q), _ptr(pos), N,
+                                                   ctypes.byref(n), _ptr(G), _stream()))
+    return G
+
+
+def nn_mlp(ctx: Context, nn: NNParams, G: torch.Tensor):
+    N = G.shape[0]
+    Ei = torch.zeros(N, dtype=torch.float32, device=G.device)
+    e = torch.zeros((N, nn.K), dtype=torch.float32, device=G.device)
+    q = nn.c()
+    _check("nn_mlp", load().nn_mlp(ctx.h, ctypes.byref(q), _ptr(G), N, _ptr(Ei), _ptr(e), _stream()))
+    return Ei, e
+
+
+def nn_forces(ctx: Context, box: Box, nn: NNParams, pos: torch.Tensor, nl: NeighborList, e: torch.Tensor,
+              force: torch.Tensor):
+    N = pos.shape[0]
+    b, q, n = box.c(), nn.c(), nl.c()
+    _check("nn_forces", load().nn_forces(ctx.h, ctypes.byref(b), ctypes.byref(q), _ptr(pos), N, ctypes.byref(n),
+                                         _ptr(e), _ptr(force), _stream()))
 
 
 def md_sum(ctx: Context, x: torch.Tensor, out: torch.Tensor):
