@@ -75,8 +75,8 @@ enum { MD_LJ = 0, MD_SOFT_SPHERE = 1 };
 typedef struct {
     int32_t kind;
     int32_t n_species;
-    float sigma[64];
-    float epsilon[64];
+    double sigma[64];
+    double epsilon[64];
     float alpha;      /* soft-sphere exponent, >= 1 (2 = harmonic) */
     float r_cut;      /* Lennard-Jones cutoff distance (absolute) */
     int32_t shift;    /* Lennard-Jones energy shift on/off */
@@ -101,18 +101,24 @@ enum {
  * |d(r_i, r_j)| < r_list, j != i (both directions, "full" list), split into
  * `lanes` (W = 1, 2, 4 or 8) interleaved sub-rows that W GPU lanes walk
  * together: entry t of sub-row l of particle i is idx[(t*N + i)*W + l], and
- * count[i*W + l] is that sub-row's length (at most capacity/W).  The stencil
- * cells' members are numbered in a fixed order (stencil cell, then index)
- * and sub-row l takes every W-th of them, so a build is deterministic.
+ * count[i*W + l] is that sub-row's length (at most capacity/W).  A build
+ * numbers the accepted neighbors in a fixed order (stencil cell, then index)
+ * and deals them round-robin to the sub-rows: neighbor n goes to sub-row
+ * n % W at position n / W, so sub-row lengths differ by at most one and a
+ * build is deterministic.
  * r_list = cutoff + skin; the list stays valid while every particle has moved
  * less than skin/2 from pos_ref, the positions at the last build (Sec. 3.1:
  * the list is rebuilt when particles have moved farther than the halo allows).
+ * segment > 0 splits the N particles into N/segment independent periodic
+ * systems of `segment` particles each (same box; no pair across systems), as
+ * used for batches of configurations; nl_build, pair_energy_force and the
+ * neural-potential calls accept such lists, verlet_step and fire_step do not.
  */
 typedef struct {
     int32_t N;
     int32_t capacity;    /* entries per row, a multiple of lanes */
     int32_t lanes;       /* W: 1, 2, 4 or 8 */
-    int32_t reserved;
+    int32_t segment;     /* 0, or the size of each independent system (divides N) */
     float r_list;        /* list radius */
     float skin;          /* r_list - cutoff; rebuild when a particle moved > skin/2 */
     int32_t *idx;        /* [capacity/W][N][W] */
@@ -137,7 +143,8 @@ md_status md_ctx_destroy(md_ctx *ctx);
  */
 md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells, int32_t capacity, int32_t lanes,
                          int32_t max_per_cell);
-/* Number of cells the cell list uses for this box and list radius (host only). */
+/* Number of cells the cell list uses for this box and list radius, per system (host only); a segmented
+ * list of S systems needs S times as many (md_ctx_reserve's max_cells). */
 int32_t md_cell_count(const md_box *box, float r_list);
 
 /* x (float [N][dim], any real value) -> torus coordinates pos (nearest 2^-32 L, wrapped). */
@@ -295,33 +302,76 @@ md_status envelope_grad(md_ctx *ctx, const md_batch *batch, const md_potential *
  *   G_i^k = sum_{j != i, r_ij < r_c} exp(-eta (r_ij - mu_k)^2) (cos(pi r_ij / r_c) + 1)/2,
  *   mu_k = mu0 + k (mu1 - mu0)/(K-1), eta = 1/(2 ((mu1 - mu0)/(K-1))^2),
  * and an MLP with H = 64: x = (G - m)/s, E_i = w3 . sp(W2 sp(W1 x + b1) + b2) + b3, sp = softplus.
- * W1, W2 are BF16 (the MFMA operands), everything else float.  All pointers are device memory.
+ * W1, W2 are BF16 (the MFMA operands, the model's own values), everything else float.  All pointers are
+ * device memory.  The network's parameters as one float vector theta (nn_param_count() = 5313 entries):
+ * W1 [H][K], b1 [H], W2 [H][H], b2 [H], w3 [H], b3; b1, b2, w3 and b3 may point into it.
  */
 typedef struct {
     int32_t K;              /* 16 */
     int32_t H;              /* 64 */
     float mu0, mu1, r_c;    /* basis centres and cutoff */
-    float b3;               /* output bias */
+    int32_t reserved;
     const uint16_t *W1;     /* bf16 [H][K] */
     const uint16_t *W2;     /* bf16 [H][H] */
     const float *b1, *b2;   /* [H] */
     const float *w3;        /* [H] */
+    const float *b3;        /* [1] output bias */
     const float *m, *s;     /* [K] descriptor shift and scale */
 } md_nn_params;
 
-/* G[i][k] (float [N][K]) over a neighbor list with r_list >= r_c (3D). */
+/* Number of network parameters (the length of theta). */
+int32_t nn_param_count(void);
+/* G[i][k] (float [N][K]) over a neighbor list with r_list >= r_c (3D; a segmented list gives each system's). */
 md_status nn_descriptors(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
                          const md_nlist *nl, float *G, void *stream);
-/* Per-atom energies Ei [N] and input gradients e[i][k] = dE_i/dG_i^k [N][K] (BF16 MFMA, FP32 accumulate). */
+/*
+ * Per-atom energies Ei [N] and input gradients e[i][k] = dE_i/dG_i^k [N][K].  BF16 MFMA with FP32
+ * accumulation; each activation operand enters as a pair of BF16 numbers (value and remainder), so only the
+ * weights are rounded to BF16.
+ */
 md_status nn_mlp(md_ctx *ctx, const md_nn_params *nn, const float *G, int32_t N, float *Ei, float *e, void *stream);
 /* F_i = -sum_j sum_k (e_i^k + e_j^k) g_k'(r_ij) (r_i - r_j)/r_ij over the list (3D). */
 md_status nn_forces(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
                     const md_nlist *nl, const float *e, float *force, void *stream);
+/*
+ * Training (Sec. 4.1: energy and force loss over configurations).  For N = S * segment atoms of S systems
+ * (a segmented list), with reference energies E_ref [S] (double) and forces F_ref [N][3]:
+ *   L = (1/S) sum_s ((E_s - E_ref_s)/segment)^2 + lam_F/(3N) sum_i |F_i - F_ref_i|^2,  E_s = sum of Ei over s.
+ * nn_loss writes loss[0] (double), gE[s] = dL/dE_i for the atoms of system s, and lam[i] = dL/dF_i [N][3].
+ * S <= 262144.
+ */
+md_status nn_loss(md_ctx *ctx, const float *Ei, const float *F, const double *E_ref, const float *F_ref, int32_t N,
+                  int32_t segment, float lam_F, double *loss, float *gE, float *lam, void *stream);
+/*
+ * Pair adjoint of the force map at fixed positions: ebar[i][k] = dL/de_i^k
+ *   = -sum_j g_k'(r_ij) (r_i - r_j)/r_ij . (lam_i - lam_j)   [N][K].
+ */
+md_status nn_pair_adjoint(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
+                          const md_nlist *nl, const float *lam, float *ebar, void *stream);
+/*
+ * Weight gradient grad[5313] (layout of theta) of the loss: the network's reverse pass with seed gE (per
+ * system of `segment` atoms; segment 0: one system, gE[0]) plus the reverse pass of its tangent along
+ * ebar_i / s, which carries the force term.  Weight-gradient products are BF16 MFMA with FP32 accumulation;
+ * the partial gradients (one per wave, in the context) are summed in a fixed order.
+ */
+md_status nn_mlp_grad(md_ctx *ctx, const md_nn_params *nn, const float *G, int32_t N, int32_t segment,
+                      const float *gE, const float *ebar, float *grad, void *stream);
+/*
+ * One Adam step (Kingma and Ba, bias-corrected; step >= 1) on theta [n = 5313] with moments m, v, and the
+ * BF16 copies W1 [H][K], W2 [H][H] of the updated weights (round to nearest even).
+ */
+md_status nn_adam(md_ctx *ctx, float *theta, float *m, float *v, const float *grad, int32_t n, int32_t step, float lr,
+                  float beta1, float beta2, float eps, uint16_t *W1, uint16_t *W2, void *stream);
+/* BF16 copies W1, W2 of the weights in theta. */
+md_status nn_cast_weights(md_ctx *ctx, const float *theta, uint16_t *W1, uint16_t *W2, void *stream);
 
 /* out[0] = sum of x[0..n) in double, summed in a fixed order (deterministic). out is device memory. */
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
 /* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */
 md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t dim, double *out, void *stream);
+/* Scale vel [N][dim] so that sum |v_i|^2 = dim (N - 1) T (unit mass, net momentum assumed zero): velocity
+ * rescaling to a temperature, for preparing configurations at a given T.  No host synchronisation. */
+md_status md_rescale_velocities(md_ctx *ctx, float *vel, int32_t N, int32_t dim, double T, void *stream);
 
 /* Copy nl->flags to host `out` (MD_NFLAGS ints) after synchronising `stream`. */
 md_status md_flags_read(const md_nlist *nl, int32_t *out, void *stream);

@@ -136,6 +136,27 @@ def energy_forces(xpos, L, P: NNParams, spec: NNSpec):
     return float(np.sum(Ei)), Ei, F, e, G
 
 
+def pair_adjoint(xpos, L, spec: NNSpec, lam):
+    """ebar_i = -sum_j g'(r_ij) (r_i - r_j)/r_ij . (lam_i - lam_j) [N][K]: the transpose of e -> F at fixed x."""
+    G, (i, j, d, r, g, dg) = descriptors(xpos, L, spec)
+    lam = np.asarray(lam, dtype=np.float64)
+    u = d / r[:, None]
+    t = ((lam[i] - lam[j]) * u).sum(axis=1)
+    ebar = np.zeros((np.asarray(xpos).shape[0], spec.K))
+    np.add.at(ebar, i, -dg * t[:, None])
+    return ebar
+
+
+def forces_from_e(xpos, L, spec: NNSpec, e):
+    """F_i = -sum_j sum_k (e_i + e_j)_k g_k'(r_ij) (r_i - r_j)/r_ij for given per-atom vectors e [N][K]."""
+    G, (i, j, d, r, g, dg) = descriptors(xpos, L, spec)
+    e = np.asarray(e, dtype=np.float64)
+    coef = ((e[i] + e[j]) * dg).sum(axis=1)
+    F = np.zeros((np.asarray(xpos).shape[0], 3))
+    np.add.at(F, i, -coef[:, None] * d / r[:, None])
+    return F
+
+
 def loss_and_grad(snapshots, P: NNParams, spec: NNSpec, lam_f: float = 1.0):
     """L and dL/dtheta over a batch of snapshots [(x, L, E_ref, F_ref), ...]."""
     grads = {k: np.zeros_like(np.asarray(getattr(P, k), dtype=np.float64)) for k in P.names()}
@@ -186,13 +207,8 @@ def loss_and_grad(snapshots, P: NNParams, spec: NNSpec, lam_f: float = 1.0):
 
 
 def init_params(spec: NNSpec, seed: int, m=None, s=None) -> NNParams:
-    """Glorot-uniform weights from a seed (the same draw the GPU trainer starts from)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-
-    def glorot(o, i):
-        lim = np.sqrt(6.0 / (o + i))
-        return rng.uniform(-lim, lim, size=(o, i))
-
-    K, H = spec.K, spec.H
-    return NNParams(W1=glorot(H, K), b1=np.zeros(H), W2=glorot(H, H), b2=np.zeros(H), w3=glorot(1, H)[0] * 0.1,
-                    b3=0.0, m=np.zeros(K) if m is None else m, s=np.ones(K) if s is None else s)
+    """The seeded initial weights the GPU trainer starts from (the shared input generator)."""
+    from paper_1912_04232_amd.inputs import nn_init
+    w = nn_init(seed, spec.K, spec.H)
+    return NNParams(W1=w["W1"], b1=w["b1"], W2=w["W2"], b2=w["b2"], w3=w["w3"], b3=w["b3"],
+                    m=np.zeros(spec.K) if m is None else m, s=np.ones(spec.K) if s is None else s)

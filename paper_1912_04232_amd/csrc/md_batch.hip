@@ -382,7 +382,8 @@ template <int KIND>
 __device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, float r2, double rd, float &dus,
                                             float &due, float &u)
 {
-    float sig = pot.sigma[pt], eps = pot.epsilon[pt];
+    double sigd = pot.sigma[pt];
+    float sig = (float)sigd, eps = (float)pot.epsilon[pt];
     dus = due = u = 0.0f;
     if (KIND == 0) {
         if (!(r2 < pot.r_cut * pot.r_cut)) return;
@@ -401,9 +402,9 @@ __device__ __forceinline__ void pair_dparam(const md_potential &pot, int pt, flo
         due = uu / eps;
     } else {
         // overlap from the double distance (see ss_fs_precise)
-        if (!(rd < (double)sig)) return;
+        if (!(rd < sigd)) return;
         float r = (float)rd;
-        float t = (float)(((double)sig - rd) / (double)sig);
+        float t = (float)((sigd - rd) / sigd);
         float a = pot.alpha;
         float tp = a == 2.0f ? t : powf(t, a - 1.0f);
         u = eps / a * tp * t;

@@ -42,11 +42,22 @@ using namespace md;
 // ------------------------------------------------------------------------------------------------
 // argument blocks
 
+// Bin c holds cnt[c] <= M member records {u_x, u_y, u_z (0 in 2D), index} of 16 bytes at mem[(c*M + k)*4].
 struct Bins {
     int32_t *cnt;   // [C]
-    int32_t *id;    // [C][M]
-    uint32_t *pos;  // [C][M][D]
+    uint32_t *mem;  // [C][M][4]
 };
+
+template <int D>
+__device__ __forceinline__ void store_rec(uint32_t *mem, uint32_t slot, const uint32_t *u, int j)
+{
+    uint4 r;
+    r.x = u[0];
+    r.y = u[1];
+    r.z = D == 3 ? u[D - 1] : 0u;
+    r.w = (uint32_t)j;
+    *(uint4 *)(mem + (size_t)slot * 4) = r;
+}
 
 struct ListGen {
     int32_t *idx;       // [cap/W][N][W]
@@ -56,8 +67,10 @@ struct ListGen {
 
 struct ListParams {
     int32_t N, cap, W, capW, M;
+    int32_t seg;             // 0, or particles per independent system (cells of system s are s*C .. s*C + C-1)
     float rl2f_lo, rl2f_hi;  // float guard band around r_list^2
     double rl2;              // (double)r_list * (double)r_list
+    float cull2;             // a stencil cell farther than this (squared) from the particle holds no neighbor
     float half_skin;         // skin / 2
     float kappa;             // pipelined rebuild starts when disp + kappa * (last step + dt^2 |F|) > skin/2
 };
@@ -135,14 +148,15 @@ __global__ void k_cs_zero(int32_t *cell_count, int C, const int32_t *gate)
 }
 
 template <int D>
-__global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, DevBox b, CountSort cs, const int32_t *gate)
+__global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, DevBox b, CountSort cs,
+                           const int32_t *gate)
 {
     if (gate_closed(gate)) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= N) return;
     uint32_t u[D];
     load_pos<D>(pos, i, u);
-    int c = cell_index<D>(u, b);
+    int c = cell_index<D>(u, b) + (seg > 0 ? (i / seg) * b.C : 0);
     cs.cell_of[i] = c;
     cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: the totals do not depend on order
 }
@@ -198,10 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_cs_fill_bins(const uint32_t *__restr
         bins.cnt[c] = n;
         for (int a = 0; a < n; ++a) {
             int j = cs.sorted_idx[s + a];
-            bins.id[(size_t)c * M + a] = j;
             uint32_t u[D];
             load_pos<D>(pos, j, u);
-            store_pos<D>(bins.pos + (size_t)c * M * D, a, u);
+            store_rec<D>(bins.mem, (uint32_t)(c * M + a), u, j);
         }
     }
     wave_flag(occ > M, &flags[MD_FLAG_CELL_OVERFLOW]);
@@ -209,80 +222,233 @@ __global__ __launch_bounds__(kBlock) void k_cs_fill_bins(const uint32_t *__restr
     if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCELL], occ);
 }
 
-// Lane l's share of particle i's row at reference position ui: walk the stencil bins in order,
-// numbering candidates g = 0, 1, ...; lane l tests the candidates with g % W == l.
-template <int D, int W>
-__device__ __forceinline__ int build_lane(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
-                                          const ListParams &lp, int32_t *__restrict__ idx)
+// Stencil table of particle i at reference position ui: the stencil cells that can hold a neighbor, in
+// stencil order, packed as (cell << 8) | count at tab[e * ts].  A cell is left out when its slab distance
+// from the particle (the distance to the faces it lies beyond) already exceeds r_list, or when it is empty.
+// Every lane of the particle computes the table; only lanes with `write` store it.  Returns the number of
+// entries; `chunks` receives the number of 4-record chunks they hold.
+template <int D>
+__device__ __forceinline__ int stencil_table(int i, const uint32_t *ui, const DevBox &b, const Bins &bins,
+                                             const ListParams &lp, uint32_t *tab, int ts, bool write, int &chunks)
 {
-    int cx = cell_coord(ui[0], b.nc[0]);
-    int cy = cell_coord(ui[1], b.nc[1]);
-    int cz = 0;
-    if constexpr (D == 3) cz = cell_coord(ui[2], b.nc[2]);
-    int nst = stencil_size<D>(b);
-    int n = 0, g = 0;
-    for (int t = 0; t < nst; ++t) {
-        int cell = stencil_cell<D>(b, cx, cy, cz, t);
-        int m = bins.cnt[cell];
-        const int32_t *bid = bins.id + (size_t)cell * lp.M;
-        const uint32_t *bpos = bins.pos + (size_t)cell * lp.M * D;
-        int k = (l - g % W + W) % W;
-        g += m;
-        for (; k < m; k += W) {
-            uint32_t uj[D];
-            load_pos<D>(bpos, k, uj);
+    constexpr int NST = D == 3 ? 27 : 9;
+    int cc[3][3];
+    float lo2[3], hi2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        cc[q][0] = cc[q][1] = cc[q][2] = 0;
+        lo2[q] = hi2[q] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        uint64_t pr = (uint64_t)ui[q] * (uint64_t)b.nc[q];
+        int c = (int)(pr >> 32);
+        float f = (float)(uint32_t)pr * 2.3283064365386963e-10f;  // position within the cell, [0, 1)
+        float dl = f * b.cw[q], dh = (1.0f - f) * b.cw[q];
+        lo2[q] = dl * dl;
+        hi2[q] = dh * dh;
+        cc[q][0] = wrapc(c - 1, b.nc[q]);
+        cc[q][1] = c;
+        cc[q][2] = wrapc(c + 1, b.nc[q]);
+    }
+    const int cbase = lp.seg > 0 ? (i / lp.seg) * b.C : 0;  // first cell of the particle's system
+    int cell[NST], m[NST];
+#pragma unroll
+    for (int t = 0; t < NST; ++t) {
+        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = D == 3 ? t / 9 - 1 : 0;
+        bool ok = ox >= b.lo[0] && ox <= b.hi[0] && oy >= b.lo[1] && oy <= b.hi[1];
+        if (D == 3) ok = ok && oz >= b.lo[2] && oz <= b.hi[2];
+        float g = (ox < 0 ? lo2[0] : ox > 0 ? hi2[0] : 0.0f) + (oy < 0 ? lo2[1] : oy > 0 ? hi2[1] : 0.0f) +
+                  (oz < 0 ? lo2[2] : oz > 0 ? hi2[2] : 0.0f);
+        ok = ok && g <= lp.cull2;
+        cell[t] = cbase + cc[0][ox + 1] + b.nc[0] * (cc[1][oy + 1] + b.nc[1] * cc[2][oz + 1]);
+        m[t] = ok ? bins.cnt[cell[t]] : 0;
+    }
+    int ne = 0;
+    chunks = 0;
+#pragma unroll
+    for (int t = 0; t < NST; ++t) {
+        if (m[t] > 0) {
+            if (write) tab[ne * ts] = ((uint32_t)cell[t] << 8) | (uint32_t)m[t];
+            ++ne;
+            chunks += (m[t] + 3) >> 2;
+        }
+    }
+    return ne;
+}
+
+// Row of particle i (Sec. 3.2.3) built by its W lanes; lane l of the particle calls this with the particle's
+// stencil table (ne entries holding `chunks` chunks of four 16-byte member records, one cache line each).
+//
+// The listed cells' records form one flat sequence of chunks; lane l tests chunks l, l + W, l + 2W, ...,
+// loading its next chunk while it tests the current one, so the walk does not stall at cell boundaries.
+// Accepted neighbors are numbered in sequence order (a prefix sum over the W lanes after each round) and
+// dealt round-robin to the interleaved sub-rows: neighbor n goes to sub-row n % W at position n / W, so the
+// W lanes that later share the row differ by at most one entry.  Returns the row length (the same in every
+// lane of the particle; it may exceed the capacity, and only the first `cap` entries are stored).
+template <int D, int W>
+__device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
+                                         const ListParams &lp, int32_t *__restrict__ idx, const uint32_t *tab, int ts,
+                                         int ne, int chunks)
+{
+    const uint4 *mem4 = (const uint4 *)bins.mem;
+    const uint32_t M = (uint32_t)lp.M;
+    // cursor of this lane: entry e, chunk c within it, the entry's first slot cb and count mc
+    int e = 0, c = l, mc = 0;
+    uint32_t cb = 0;
+    bool have = false;
+    while (e < ne) {
+        uint32_t en = tab[e * ts];
+        mc = (int)(en & 255u);
+        int nch = (mc + 3) >> 2;
+        if (c < nch) {
+            cb = (en >> 8) * M;
+            have = true;
+            break;
+        }
+        c -= nch;
+        ++e;
+    }
+    // the current chunk's records as separate registers (a chunk past the end re-reads slot 0, always mapped)
+    uint32_t cx[4], cy[4], cz[4], cj[4];
+    {
+        uint32_t base = have ? cb + 4u * (uint32_t)c : 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint4 r = mem4[base + q];
+            cx[q] = r.x;
+            cy[q] = r.y;
+            cz[q] = r.z;
+            cj[q] = r.w;
+        }
+    }
+    const int iters = (chunks + W - 1) / W;  // the same in every lane of the particle
+    int n = 0;
+    for (int it = 0; it < iters; ++it) {
+        // the lane's next chunk, W chunks on
+        int e2 = e, c2 = c + W, mc2 = mc;
+        uint32_t cb2 = cb;
+        bool have2 = have;
+        if (have2) {
+            while (true) {
+                int nch = (mc2 + 3) >> 2;
+                if (c2 < nch) break;
+                c2 -= nch;
+                ++e2;
+                if (e2 >= ne) {
+                    have2 = false;
+                    break;
+                }
+                uint32_t en = tab[e2 * ts];
+                mc2 = (int)(en & 255u);
+                cb2 = (en >> 8) * M;
+            }
+        }
+        uint32_t nxx[4], nxy[4], nxz[4], nxj[4];
+        {
+            uint32_t base = have2 ? cb2 + 4u * (uint32_t)c2 : 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 r = mem4[base + q];
+                nxx[q] = r.x;
+                nxy[q] = r.y;
+                nxz[q] = r.z;
+                nxj[q] = r.w;
+            }
+        }
+        int bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t uj[3] = {cx[q], cy[q], cz[q]};
             float r2 = 0.0f;
 #pragma unroll
-            for (int q = 0; q < D; ++q) {
-                float d = tdisp(ui[q], uj[q], b.s[q]);
+            for (int z = 0; z < D; ++z) {
+                float d = tdisp(ui[z], uj[z], b.s[z]);
                 r2 = __builtin_fmaf(d, d, r2);
             }
-            bool acc;
-            if (r2 < lp.rl2f_lo) {
-                acc = true;
-            } else if (r2 > lp.rl2f_hi) {
-                acc = false;
-            } else {
+            bool acc = r2 < lp.rl2f_lo;
+            if (r2 >= lp.rl2f_lo && r2 <= lp.rl2f_hi) {
                 // the defining double expression, evaluated without contraction
                 double r2d = 0.0;
 #pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    double d = tdisp_d(ui[q], uj[q], b.sd[q]);
+                for (int z = 0; z < D; ++z) {
+                    double d = tdisp_d(ui[z], uj[z], b.sd[z]);
                     r2d = __dadd_rn(r2d, __dmul_rn(d, d));
                 }
                 acc = r2d < lp.rl2;
             }
-            int j = bid[k];
-            if (acc && j != i) {
-                if (n < lp.capW) idx[((size_t)n * lp.N + i) * W + l] = j;
-                ++n;
+            acc = acc && have && 4 * c + q < mc && (int)cj[q] != i;
+            bits |= acc ? 1 << q : 0;
+        }
+        // numbering across the particle's lanes: this round's chunks are in lane order
+        int a = __popc(bits);
+        int incl = a;
+#pragma unroll
+        for (int o = 1; o < W; o <<= 1) {
+            int v = __shfl_up(incl, o, W);
+            if (l >= o) incl += v;
+        }
+        int tot = __shfl(incl, W - 1, W);
+        int slot = n + incl - a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (bits & (1 << q)) {
+                if (slot < lp.cap) idx[((size_t)(slot / W) * lp.N + i) * W + (slot % W)] = (int)cj[q];
+                ++slot;
             }
         }
+        n += tot;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cx[q] = nxx[q];
+            cy[q] = nxy[q];
+            cz[q] = nxz[q];
+            cj[q] = nxj[q];
+        }
+        e = e2;
+        c = c2;
+        mc = mc2;
+        cb = cb2;
+        have = have2;
     }
     return n;
 }
 
-// Rows of every particle from the bins; pos_ref = the positions the rows were built from.
+// Sub-row length of lane l for a row of n entries dealt round-robin over W sub-rows.
+template <int W>
+__device__ __forceinline__ int sub_count(int n, int l)
+{
+    return (n + W - 1 - l) / W;
+}
+
+// Rows of every particle from the bins, W lanes per particle; pos_ref = the positions the rows were built from.
 template <int D, int W>
 __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restrict__ pos, DevBox b, Bins bins,
                                                        ListParams lp, ListGen g, int32_t *flags, const int32_t *gate)
 {
+    constexpr int TS = kBlock / W;
+    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * TS];
     __shared__ int red[kBlock];
     if (gate_closed(gate)) return;
     int gt = blockIdx.x * kBlock + threadIdx.x;
     int i = gt / W, l = gt % W;
-    int n = 0;
-    if (i < lp.N) {
-        uint32_t ui[D];
+    bool live = i < lp.N;
+    uint32_t ui[D];
+    int ne = 0, chunks = 0, n = 0;
+    if (live) {
         load_pos<D>(pos, i, ui);
-        n = build_lane<D, W>(i, l, ui, b, bins, lp, g.idx);
-        g.count[(size_t)i * W + l] = n;
+        ne = stencil_table<D>(i, ui, b, bins, lp, tab + threadIdx.x / W, TS, l == 0, chunks);
+    }
+    __syncthreads();
+    if (live) {
+        n = build_row<D, W>(i, l, ui, b, bins, lp, g.idx, tab + threadIdx.x / W, TS, ne, chunks);
+        g.count[(size_t)i * W + l] = sub_count<W>(n, l);
         if (l == 0) store_pos<D>(g.pos_ref, i, ui);
     }
-    wave_flag(n > lp.capW, &flags[MD_FLAG_OVERFLOW]);
+    wave_flag(n > lp.cap, &flags[MD_FLAG_OVERFLOW]);
     n = block_max(n, red);
     if (threadIdx.x == 0) {
-        raise_max(&flags[MD_FLAG_MAXCOUNT], n * W);
+        raise_max(&flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
         if (blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
     }
 }
@@ -334,17 +500,14 @@ __device__ int bin_gather(const uint32_t *__restrict__ pos, const DevBox &b, con
             int j = 0;
             uint32_t u[D];
             if (q < total) {
-                j = prev.id[(size_t)s_src * M + (q - s_ex)];
+                j = (int)prev.mem[((size_t)s_src * M + (q - s_ex)) * 4 + 3];
                 load_pos<D>(pos, j, u);
                 take = cell_index<D>(u, b) == c;
             }
             uint64_t mask = __ballot(take);
             int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
             int slot = cnt + before;
-            if (take && slot < M) {
-                next.id[(size_t)c * M + slot] = j;
-                store_pos<D>(next.pos + (size_t)c * M * D, slot, u);
-            }
+            if (take && slot < M) store_rec<D>(next.mem, (uint32_t)(c * M + slot), u, j);
             cnt += __popcll(mask);
         }
         if (lane == 0) {
@@ -359,39 +522,95 @@ __device__ int bin_gather(const uint32_t *__restrict__ pos, const DevBox &b, con
 // ------------------------------------------------------------------------------------------------
 // forces
 
-// Force from lane l's sub-row of particle i (the hot loop), then summed over the W lanes.
+// Byte-offset loads from a uniform base: the offsets are 32-bit (the host keeps every array below 4 GiB),
+// so the address is one scalar base plus one vector register.
+template <typename T>
+__device__ __forceinline__ T ld_off(const void *base, uint32_t off)
+{
+    return *(const T *)((const char *)base + off);
+}
+
+template <int D>
+__device__ __forceinline__ void ld_pos(const uint32_t *__restrict__ pos, int j, uint32_t *u)
+{
+    // j < 2^24 (checked on the host): a 24-bit multiply gives the byte offset
+    const char *p = (const char *)pos + __umul24((uint32_t)j, (uint32_t)(4 * D));
+#pragma unroll
+    for (int q = 0; q < D; ++q) u[q] = ((const uint32_t *)p)[q];
+}
+
+// Four pairs of one lane: positions pc of neighbors jc against ui; `live` masks slots past the row's end.
+template <int D, int KIND, bool MULTI, bool MASK>
+__device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, const int32_t *__restrict__ species,
+                                           int si, const uint32_t *ui, const int *jc, const uint32_t (*pc)[D],
+                                           int t0, int n, float *F)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        float d[D], r2, u;
+        int pt = MULTI ? si * p.S + species[jc[a]] : 0;
+        float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, pc[a], b.s, b.sd, d, r2, u);
+        if (MASK) fs = t0 + a < n ? fs : 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+    }
+}
+
+// Force from lane l's sub-row of particle i (the hot loop), then summed over the W lanes.  Entries go in
+// groups of four, two groups per iteration with the register sets alternating: the indices two groups ahead
+// and the neighbor positions one group ahead are loaded while a group is evaluated.  Loads past the row's end
+// re-read its last entry (always a valid particle) and those slots are masked out.
 template <int D, int KIND, bool MULTI, int W>
 __device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, const uint32_t *__restrict__ pos,
                                            const int32_t *__restrict__ species, int N,
                                            const int32_t *__restrict__ idx, int n, int i, int l, const uint32_t *ui,
                                            int si, float *F)
 {
-    int t = 0;
-    for (; t + 4 <= n; t += 4) {
-        int j[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) j[a] = idx[((size_t)(t + a) * N + i) * W + l];
-        uint32_t uj[4][D];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) load_pos<D>(pos, j[a], uj[a]);
+    if (n > 0) {
+        const uint32_t step = (uint32_t)N * W * 4u;          // bytes between consecutive entries of a sub-row
+        const uint32_t off = ((uint32_t)i * W + (uint32_t)l) * 4u;
+        const uint32_t olast = off + (uint32_t)(n - 1) * step;
+        // t is the same in every lane, so t * step is scalar; the clamp is one vector min
+        auto ldj = [&](int t) -> int { return ld_off<int32_t>(idx, min(off + (uint32_t)t * step, olast)); };
+        int jA[4], jB[4];
+        uint32_t pA[4][D], pB[4][D];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            float d[D], r2, u;
-            int pt = MULTI ? si * p.S + species[j[a]] : 0;
-            float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, uj[a], b.s, b.sd, d, r2, u);
-#pragma unroll
-            for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+            jA[a] = ldj(a);
+            jB[a] = ldj(4 + a);
         }
-    }
-    for (; t < n; ++t) {
-        int j = idx[((size_t)t * N + i) * W + l];
-        uint32_t uj[D];
-        load_pos<D>(pos, j, uj);
-        float d[D], r2, u;
-        int pt = MULTI ? si * p.S + species[j] : 0;
-        float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, uj, b.s, b.sd, d, r2, u);
 #pragma unroll
-        for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
+        for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jA[a], pA[a]);
+        int t = 0;
+        // full pairs of groups: A holds group t/4 (positions loaded), B the next group's indices
+        for (; t + 8 <= n; t += 8) {
+            int jC[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jB[a], pB[a]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) jC[a] = ldj(t + 8 + a);
+            asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
+            quad_force<D, KIND, MULTI, false>(b, p, species, si, ui, jA, pA, t, n, F);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jC[a], pA[a]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) jA[a] = ldj(t + 12 + a);
+            asm volatile("" ::: "memory");
+            quad_force<D, KIND, MULTI, false>(b, p, species, si, ui, jB, pB, t + 4, n, F);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                int x = jA[a];
+                jA[a] = jC[a];
+                jB[a] = x;
+            }
+        }
+        // at most two groups remain: A (positions loaded) and B (indices loaded)
+        if (t < n) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jB[a], pB[a]);
+            quad_force<D, KIND, MULTI, true>(b, p, species, si, ui, jA, pA, t, n, F);
+            if (t + 4 < n) quad_force<D, KIND, MULTI, true>(b, p, species, si, ui, jB, pB, t + 4, n, F);
+        }
     }
 #pragma unroll
     for (int o = 1; o < W; o <<= 1) {
@@ -608,6 +827,7 @@ template <int D, int KIND, bool MULTI, int W>
 __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 {
     __shared__ int red[kBlock];
+    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * (kBlock / W)];
     if (frozen(a.flags)) return;
     int mode, gen;
     step_control(a.ctl, a.flags, a.step, mode, gen);
@@ -625,19 +845,27 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
             store_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
         }
     } else if (mode == M_BUILD) {
-        // rows of the other generation from those bins
-        int gt = blockIdx.x * kBlock + threadIdx.x;
+        // rows of the other generation from those bins, W lanes per particle as in the force pass
+        int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
         int i = gt / W, l = gt % W;
-        int n = 0;
-        if (i < lp.N) {
-            uint32_t ui[D];
-            load_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
-            n = build_lane<D, W>(i, l, ui, a.box, a.bins[gen ^ 1], lp, a.gen[gen ^ 1].idx);
-            a.gen[gen ^ 1].count[(size_t)i * W + l] = n;
+        bool live = i < lp.N;
+        uint32_t ui[D];
+        int ne = 0, chunks = 0, n = 0;
+        const ListGen &g1 = a.gen[gen ^ 1];
+        if (live) {
+            load_pos<D>(g1.pos_ref, i, ui);
+            ne = stencil_table<D>(i, ui, a.box, a.bins[gen ^ 1], lp, tab + threadIdx.x / W, kBlock / W, l == 0,
+                                  chunks);
         }
-        wave_flag(n > lp.capW, &a.flags[MD_FLAG_OVERFLOW]);
+        __syncthreads();
+        if (live) {
+            n = build_row<D, W>(i, l, ui, a.box, a.bins[gen ^ 1], lp, g1.idx, tab + threadIdx.x / W, kBlock / W, ne,
+                                chunks);
+            g1.count[(size_t)i * W + l] = sub_count<W>(n, l);
+        }
+        wave_flag(n > lp.cap, &a.flags[MD_FLAG_OVERFLOW]);
         n = block_max(n, red);
-        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCOUNT], n * W);
+        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
     }
     const ListGen &g = a.gen[gen];
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -935,6 +1163,14 @@ __global__ __launch_bounds__(kBlock) void k_ke_partial(const float *v, int64_t n
     if (threadIdx.x == 0) partials[blockIdx.x] = 0.5 * s;
 }
 
+// v *= sqrt(dim (N - 1) T / sum v^2), with sum v^2 = 2 ke[0].
+__global__ __launch_bounds__(kBlock) void k_rescale(float *v, int64_t n, const double *ke, double target)
+{
+    double f = ke[0] > 0.0 ? sqrt(target / (2.0 * ke[0])) : 1.0;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)gridDim.x * kBlock)
+        v[q] = (float)((double)v[q] * f);
+}
+
 __global__ __launch_bounds__(kBlock) void k_sum_final(const double *partials, int n, double *out)
 {
     __shared__ double red[kBlock];
@@ -948,6 +1184,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_final(const double *partials, in
 // host side: context, argument checks, dispatch
 
 static constexpr int kMaxBlocks = 1 << 16;
+static constexpr int kMaxPerCell = 252;                 // bin occupancy fits the 8-bit field of a stencil entry
+static constexpr int64_t kMaxBytes = (int64_t)1 << 32;  // list and bin arrays stay below 4 GiB
 static constexpr float kKappa = 2.0f;
 
 static bool make_box(const md_box *box, float r_list, DevBox &b)
@@ -969,6 +1207,7 @@ static bool make_box(const md_box *box, float r_list, DevBox &b)
                 nc = m >= 3.0 ? (int)fmin(m, 1 << 20) : 1;
             }
             b.nc[k] = nc;
+            b.cw[k] = (float)((double)L / nc);
             b.lo[k] = nc >= 3 ? -1 : 0;
             b.hi[k] = nc >= 3 ? 1 : 0;
             b.C *= nc;
@@ -1006,6 +1245,7 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
             double sc6 = pow(s / rc, 6.0);
             p.ushift[q] = pot->shift ? (float)(4.0 * e * (sc6 * sc6 - sc6)) : 0.0f;
             p.sig[q] = (float)s;
+            p.sigd[q] = s;
             p.inv_sig[q] = (float)(1.0 / s);
             p.eps_over_sig[q] = (float)(e / s);
             p.eps_over_alpha[q] = (float)(e / pot->alpha);
@@ -1013,11 +1253,16 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
     return true;
 }
 
+int md_partials_blocks()
+{
+    return kMaxBlocks;
+}
+
 float md_max_cutoff(const md_potential *pot)
 {
     if (pot->kind == MD_LJ) return pot->r_cut;
     float m = 0.0f;
-    for (int q = 0; q < pot->n_species * pot->n_species; ++q) m = fmaxf(m, pot->sigma[q]);
+    for (int q = 0; q < pot->n_species * pot->n_species; ++q) m = fmaxf(m, (float)pot->sigma[q]);
     return m;
 }
 
@@ -1036,10 +1281,12 @@ static ListParams make_lp(const md_nlist *nl, int M)
     v.W = nl->lanes;
     v.capW = nl->capacity / nl->lanes;
     v.M = M;
+    v.seg = nl->segment;
     float rl2 = nl->r_list * nl->r_list;
     v.rl2f_lo = rl2 * (1.0f - 1e-5f);
     v.rl2f_hi = rl2 * (1.0f + 1e-5f);
     v.rl2 = (double)nl->r_list * (double)nl->r_list;
+    v.cull2 = rl2 * (1.0f + 1e-4f);
     v.half_skin = 0.5f * nl->skin;
     v.kappa = kKappa;
     return v;
@@ -1096,6 +1343,7 @@ static bool lanes_ok(int W)
 
 static bool nl_ok(const md_nlist *nl, int N)
 {
+    if (nl && (nl->segment < 0 || (nl->segment > 0 && N % nl->segment != 0))) return false;
     return nl && nl->N == N && lanes_ok(nl->lanes) && nl->capacity >= nl->lanes && nl->capacity % nl->lanes == 0 &&
            nl->idx && nl->count && nl->pos_ref && nl->flags && nl->r_list > 0.0f && nl->skin >= 0.0f;
 }
@@ -1107,7 +1355,7 @@ static ListGen caller_gen(const md_nlist *nl)
 
 static Bins ctx_bins(md_ctx *ctx, int g)
 {
-    return Bins{ctx->bin_cnt[g], ctx->bin_id[g], ctx->bin_pos[g]};
+    return Bins{ctx->bin_cnt[g], ctx->bin_mem[g]};
 }
 
 static md_status check_common(md_ctx *ctx, const md_box *box, int32_t N)
@@ -1117,13 +1365,21 @@ static md_status check_common(md_ctx *ctx, const md_box *box, int32_t N)
     return MD_OK;
 }
 
+// Cells of the whole list: C per system times the number of systems of a segmented list.
+static int list_cells(const DevBox &b, const md_nlist *nl)
+{
+    return nl->segment > 0 ? b.C * (nl->N / nl->segment) : b.C;
+}
+
 static md_status check_list(md_ctx *ctx, const md_box *box, const md_nlist *nl, int32_t N, DevBox &b)
 {
     if (!nl_ok(nl, N)) return MD_ERR_ARG;
     if (!box_ok(box, nl->r_list)) return MD_ERR_BOX;
     if (!make_box(box, nl->r_list, b)) return MD_ERR_ARG;
-    if (b.C > ctx->C_cap) return MD_ERR_CAPACITY;
+    int64_t C = nl->segment > 0 ? (int64_t)b.C * (N / nl->segment) : b.C;
+    if (C > ctx->C_cap || C >= (1 << 24)) return MD_ERR_CAPACITY;  // cell numbers fit 24 bits of a stencil entry
     if ((int64_t)N * nl->lanes > (int64_t)kBlock * kMaxBlocks) return MD_ERR_CAPACITY;
+    if ((int64_t)N * nl->capacity * 4 >= kMaxBytes || N >= (1 << 24)) return MD_ERR_CAPACITY;
     return MD_OK;
 }
 
@@ -1137,20 +1393,21 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     ListParams lp = make_lp(nl, ctx->M_cap);
     ListGen g = caller_gen(nl);
     int rows_grid = nblk((int64_t)N * lp.W);
-    hipLaunchKernelGGL(k_cs_zero, dim3(nblk(b.C)), dim3(kBlock), 0, s, cs.cell_count, b.C, gate);
+    int C = list_cells(b, nl);  // cells over all systems of a segmented list
+    hipLaunchKernelGGL(k_cs_zero, dim3(nblk(C)), dim3(kBlock), 0, s, cs.cell_count, C, gate);
     if (dim == 3) {
-        hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, b.C, gate);
+        hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, C, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_fill_bins<3>, dim3(nblk(b.C)), dim3(kBlock), 0, s, pos, cs, bins, b.C, lp.M,
+        hipLaunchKernelGGL(k_cs_fill_bins<3>, dim3(nblk(C)), dim3(kBlock), 0, s, pos, cs, bins, C, lp.M,
                            nl->flags, gate);
         MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
                                           lp, g, nl->flags, gate));
     } else {
-        hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, b.C, gate);
+        hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, C, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_fill_bins<2>, dim3(nblk(b.C)), dim3(kBlock), 0, s, pos, cs, bins, b.C, lp.M,
+        hipLaunchKernelGGL(k_cs_fill_bins<2>, dim3(nblk(C)), dim3(kBlock), 0, s, pos, cs, bins, C, lp.M,
                            nl->flags, gate);
         MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
                                           lp, g, nl->flags, gate));
@@ -1176,12 +1433,14 @@ md_status md_ctx_create(int device, md_ctx **out)
         hipMalloc(&c->own_flags, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
         hipMalloc(&c->ctl, sizeof(int32_t) * kCtlWords) != hipSuccess ||
         hipMalloc(&c->queue, sizeof(int32_t) * 4) != hipSuccess ||
+        hipMalloc(&c->nn_partial, sizeof(float) * (size_t)kNNTrainWaves * kNNParams) != hipSuccess ||
         hipMemset(c->own_flags, 0, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
         hipMemset(c->ctl, 0, sizeof(int32_t) * kCtlWords) != hipSuccess) {
         (void)hipFree(c->partials);
         (void)hipFree(c->own_flags);
         (void)hipFree(c->ctl);
         (void)hipFree(c->queue);
+        (void)hipFree(c->nn_partial);
         delete c;
         return MD_ERR_HIP;
     }
@@ -1192,15 +1451,14 @@ md_status md_ctx_create(int device, md_ctx **out)
 static void free_scratch(md_ctx *c)
 {
     void *ptrs[] = {c->pos_alt, c->cs.cell_of, c->cs.slot, c->cs.sorted_idx, c->cs.cell_count, c->cs.cell_start,
-                    c->bin_cnt[0], c->bin_cnt[1], c->bin_id[0], c->bin_id[1], c->bin_pos[0], c->bin_pos[1],
+                    c->bin_cnt[0], c->bin_cnt[1], c->bin_mem[0], c->bin_mem[1],
                     c->g1_idx, c->g1_count, c->g1_pos_ref};
     for (void *p : ptrs) (void)hipFree(p);
     c->pos_alt = nullptr;
     c->cs = CountSort{};
     for (int g = 0; g < 2; ++g) {
         c->bin_cnt[g] = nullptr;
-        c->bin_id[g] = nullptr;
-        c->bin_pos[g] = nullptr;
+        c->bin_mem[g] = nullptr;
     }
     c->g1_idx = c->g1_count = nullptr;
     c->g1_pos_ref = nullptr;
@@ -1216,6 +1474,7 @@ md_status md_ctx_destroy(md_ctx *ctx)
     (void)hipFree(ctx->own_flags);
     (void)hipFree(ctx->ctl);
     (void)hipFree(ctx->queue);
+    (void)hipFree(ctx->nn_partial);
     delete ctx;
     return MD_OK;
 }
@@ -1224,8 +1483,11 @@ md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells,
                          int32_t max_per_cell)
 {
     if (!ctx || N < 0 || (dim != 2 && dim != 3) || max_cells < 1 || capacity < 1 || !lanes_ok(lanes) ||
-        max_per_cell < 1)
+        max_per_cell < 1 || max_per_cell > kMaxPerCell)
         return MD_ERR_ARG;
+    // kernels address lists and bins with 32-bit byte offsets
+    if ((int64_t)N * capacity * 4 >= kMaxBytes || (int64_t)max_cells * max_per_cell * 16 >= kMaxBytes)
+        return MD_ERR_CAPACITY;
     if (N <= ctx->N_cap && dim <= ctx->dim_cap && max_cells <= ctx->C_cap && capacity <= ctx->cap_cap &&
         lanes <= ctx->W_cap && max_per_cell <= ctx->M_cap)
         return MD_OK;
@@ -1237,6 +1499,7 @@ md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells,
     int32_t cap = capacity > ctx->cap_cap ? capacity : ctx->cap_cap;
     int32_t W = lanes > ctx->W_cap ? lanes : ctx->W_cap;
     int32_t M = max_per_cell > ctx->M_cap ? max_per_cell : ctx->M_cap;
+    M = (M + 3) / 4 * 4;  // bins are read in chunks of four records
     free_scratch(ctx);
     ctx->N_cap = ctx->dim_cap = ctx->C_cap = ctx->cap_cap = ctx->W_cap = ctx->M_cap = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -1248,8 +1511,7 @@ md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells,
     HIP_OK(hipMalloc(&ctx->cs.cell_start, sizeof(int32_t) * ((size_t)C + 1)));
     for (int g = 0; g < 2; ++g) {
         HIP_OK(hipMalloc(&ctx->bin_cnt[g], sizeof(int32_t) * (size_t)C));
-        HIP_OK(hipMalloc(&ctx->bin_id[g], sizeof(int32_t) * (size_t)C * M));
-        HIP_OK(hipMalloc(&ctx->bin_pos[g], sizeof(uint32_t) * (size_t)C * M * d));
+        HIP_OK(hipMalloc(&ctx->bin_mem[g], sizeof(uint32_t) * 4 * (size_t)C * M));
     }
     // second list generation: idx sized for any capacity <= cap, count for any lane count <= W
     HIP_OK(hipMalloc(&ctx->g1_idx, sizeof(int32_t) * nn * cap));
@@ -1373,7 +1635,7 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
 {
     DevBox b;
     DevPot p;
-    if (!pos || !vel || !force || n_steps < 0 || !isfinite(dt)) return MD_ERR_ARG;
+    if (!pos || !vel || !force || n_steps < 0 || !isfinite(dt) || (nl && nl->segment != 0)) return MD_ERR_ARG;
     md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
     if (st != MD_OK) return st;
     if (N == 0 || n_steps == 0) return MD_OK;
@@ -1434,7 +1696,7 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
 {
     DevBox b;
     DevPot p;
-    if (!pos || !vel || !force || !fst || !fp || n_steps < 0) return MD_ERR_ARG;
+    if (!pos || !vel || !force || !fst || !fp || n_steps < 0 || (nl && nl->segment != 0)) return MD_ERR_ARG;
     md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
     if (st != MD_OK) return st;
     if (N == 0) return MD_OK;
@@ -1516,6 +1778,18 @@ md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t di
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, (int64_t)N * dim, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_rescale_velocities(md_ctx *ctx, float *vel, int32_t N, int32_t dim, double T, void *stream)
+{
+    if (!ctx || !vel || N < 2 || (dim != 2 && dim != 3) || !(T >= 0.0)) return MD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    double *ke = ctx->partials + kRedBlocks;  // past the partial sums
+    int64_t n = (int64_t)N * dim;
+    hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, n, ctx->partials);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, ke);
+    hipLaunchKernelGGL(k_rescale, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, n, ke, (double)dim * (N - 1) * T);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -20,6 +20,7 @@ struct DevBox {
     int nc[3];        // cells per dimension (1 = dimension scanned whole)
     int C;            // total cells
     int lo[3], hi[3]; // stencil offsets per dimension: [-1, 1] or [0, 0]
+    float cw[3];      // cell width L_k / nc_k
 };
 
 // Per-pair-type coefficients (Sec. 3.3.2).  For LJ with r2i = 1/r^2 and
@@ -35,6 +36,7 @@ struct DevPot {
     int pad;
     float a12[64], a6[64], c12[64], c6[64], ushift[64];  // LJ
     float sig[64], inv_sig[64], eps_over_sig[64], eps_over_alpha[64];  // soft sphere
+    double sigd[64];                                                    // sigma in double (overlap)
 };
 
 __device__ __forceinline__ float tdisp(uint32_t a, uint32_t b, float s)
@@ -99,7 +101,7 @@ __device__ __forceinline__ float ss_fs_precise(const DevPot &p, int pt, const do
 #pragma unroll
     for (int k = 0; k < D; ++k) r2 = __builtin_fma(dd[k], dd[k], r2);
     double r = __builtin_sqrt(r2);
-    double sig = (double)p.sig[q];
+    double sig = p.sigd[q];
     bool in = r < sig;
     float t = (float)((sig - r) / sig);
     float tp = p.alpha_is_2 ? t : __builtin_exp2f((p.alpha - 1.0f) * __builtin_log2f(fmaxf(t, 1e-30f)));

@@ -26,15 +26,22 @@ struct md_ctx {
     uint32_t *pos_alt = nullptr;
     CountSort cs = {};
     int32_t *bin_cnt[2] = {nullptr, nullptr};
-    int32_t *bin_id[2] = {nullptr, nullptr};
-    uint32_t *bin_pos[2] = {nullptr, nullptr};
+    uint32_t *bin_mem[2] = {nullptr, nullptr};  // [C][M][4] member records
     int32_t *g1_idx = nullptr, *g1_count = nullptr;
     uint32_t *g1_pos_ref = nullptr;
     int32_t *ctl = nullptr;        // kCtlWords
     double *partials = nullptr;    // 4 * kMaxBlocks doubles
     int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
     int32_t *queue = nullptr;      // work counter of batched launches
+    float *nn_partial = nullptr;   // partial weight gradients of the neural-potential training pass
 };
+
+// neural-potential training: parameter count and the number of partial gradients (one per wave)
+constexpr int kNNParams = 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1;
+constexpr int kNNTrainWaves = 512;
+
+// ctx->partials holds this many doubles (4 per workgroup of the largest reduction launch).
+int md_partials_blocks();
 
 
 // Pair-potential coefficients for the kernels; false for an invalid potential.

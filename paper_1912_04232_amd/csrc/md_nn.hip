@@ -1,18 +1,30 @@
-// Neural pair potential on gfx950: radial descriptors, a per-atom MLP on BF16 MFMA, forces.
+// Neural pair potential on gfx950: radial descriptors, a per-atom MLP on BF16 MFMA, forces, and the
+// training pass (loss, pair adjoint, weight gradient, Adam).
 //
 // The model (the paper's neural-network energies, Sec. 3.2.4 / 4.1, with forces F = -grad E, Sec. 3.3.2):
 //   G_i^k = sum_{j != i, r_ij < r_c} g_k(r_ij),  g_k(r) = exp(-eta (r - mu_k)^2) fc(r),
 //   fc(r) = (cos(pi r / r_c) + 1)/2,  mu_k = mu0 + k (mu1 - mu0)/(K - 1)
 //   x = (G - m)/s,  h1 = sp(W1 x + b1),  h2 = sp(W2 h1 + b2),  E_i = w3 . h2 + b3,  sp = softplus
 //   F_i = -sum_j sum_k (e_i^k + e_j^k) g_k'(r_ij) (r_i - r_j)/r_ij,  e_i = dE_i/dG_i
-// K = 16, H = 64.
+// K = 16, H = 64.  Training (Sec. 4.1) minimises
+//   L = (1/S) sum_s ((E_s - E^_s)/n)^2 + lam_F/(3N) sum_i |F_i - F^_i|^2
+// over S configurations of n atoms (N = S n).  With lam_i = dL/dF_i, the force term reaches the weights
+// through the pair adjoint  ebar_i = dL/de_i = -sum_j g'(r_ij) u_ij . (lam_i - lam_j)  and the tangent
+// (forward-mode) pass of each atom's network along ebar_i / s, whose reverse pass gives the weight gradient.
 //
-//   k_nn_descriptor  W lanes per atom walk its neighbor list (the ELL list of md_core) and sum the 16
-//                    basis functions; lanes meet through __shfl_xor.
+//   k_nn_descriptor  W lanes per atom walk its neighbor list and sum the 16 basis functions.
 //   k_nn_mlp         one wave per tile of 32 atoms: X W1^T, H1 W2^T (forward) and D2 W2, D1 W1 (the input
-//                    gradient e) as v_mfma_f32_32x32x16_bf16 products with BF16 operands staged in LDS and
-//                    FP32 accumulation; activation derivatives stay in registers in the accumulator layout.
+//                    gradient e) as v_mfma_f32_32x32x16_bf16 products.  Weights are BF16 (the model's own
+//                    values); activations enter as a BF16 pair hi + lo (hi = bf16(a), lo = bf16(a - hi)), two
+//                    products per layer, so the activation side keeps ~16 mantissa bits; FP32 accumulation.
 //   k_nn_force       W lanes per atom gather e_j and sum the pair terms.
+//   k_nn_adjoint     the same walk with lam_j: ebar_i.
+//   k_nn_train       one wave per tile: the forward pass again, the tangent pass along ebar/s, the reverse
+//                    pass, and the weight gradients as MFMA products over the tile's atoms (per-unit adjoints
+//                    transposed times the layer inputs, BF16), accumulated across tiles in registers; one
+//                    partial gradient per wave, summed in a fixed order by k_nn_grad_reduce.
+//   k_nn_loss_*      per-system energy residuals, force residuals lam_i and the loss (double, fixed order).
+//   k_nn_adam        Adam on FP32 master weights; writes the BF16 copies the other kernels read.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -29,9 +41,12 @@ namespace {
 
 constexpr int kK = 16;
 constexpr int kH = 64;
-constexpr int kTile = 32;          // atoms per wave tile
-constexpr int kMlpWaves = 4;
-constexpr int kMlpThreads = 64 * kMlpWaves;
+constexpr int kTile = 32;  // atoms per wave tile
+// flat parameter vector: W1 [H][K], b1 [H], W2 [H][H], b2 [H], w3 [H], b3
+constexpr int oW1 = 0, ob1 = kH * kK, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH, ob3 = ow3 + kH;
+constexpr int kNP = ob3 + 1;
+static_assert(kNP == kNNParams, "parameter layout");
+constexpr int kTrainWaves = kNNTrainWaves;  // partial gradients (one per wave of a training launch)
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -49,12 +64,17 @@ __device__ __forceinline__ float bf2f(uint16_t h)
     return __uint_as_float((uint32_t)h << 16);
 }
 
+__device__ __forceinline__ void split_bf(float x, uint16_t &hi, uint16_t &lo)
+{
+    hi = f2bf(x);
+    lo = f2bf(x - bf2f(hi));
+}
+
 struct NNDev {
     float mu0, dmu, r_c, eta;
     const uint16_t *W1;  // [H][K]
     const uint16_t *W2;  // [H][H]
-    const float *b1, *b2, *w3;
-    float b3;
+    const float *b1, *b2, *w3, *b3;
     const float *m, *s;  // [K]
 };
 
@@ -183,37 +203,111 @@ __global__ __launch_bounds__(kBlock) void k_nn_force(DevBox b, NNDev p, const ui
     }
 }
 
+// ebar_i^k = -sum_j g_k'(r_ij) u_ij . (lam_i - lam_j), u_ij = (r_i - r_j)/r_ij: the transpose of the force map
+// F(e) at fixed positions applied to lam.
+template <int D, int W>
+__global__ __launch_bounds__(kBlock) void k_nn_adjoint(DevBox b, NNDev p, const uint32_t *__restrict__ pos, int N,
+                                                       const int32_t *__restrict__ idx,
+                                                       const int32_t *__restrict__ count, int capW,
+                                                       const float *__restrict__ lam, float *__restrict__ ebar)
+{
+    int gt = blockIdx.x * kBlock + threadIdx.x;
+    int i = gt / W, l = gt % W;
+    bool live = i < N;
+    int ii = live ? i : N - 1;
+    uint32_t ui[D];
+    load_pos<D>(pos, ii, ui);
+    float li[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) li[q] = lam[(size_t)ii * D + q];
+    float acc[kK];
+#pragma unroll
+    for (int k = 0; k < kK; ++k) acc[k] = 0.0f;
+    int n = live ? min(count[(size_t)ii * W + l], capW) : 0;
+    float rc2 = p.r_c * p.r_c;
+    for (int t = 0; t < n; ++t) {
+        int j = idx[((size_t)t * N + ii) * W + l];
+        uint32_t uj[D];
+        load_pos<D>(pos, j, uj);
+        float d[D];
+        float r2 = pair_r<D>(ui, uj, b, d);
+        if (r2 < rc2) {
+            float r = sqrtf(r2);
+            float g[kK], dg[kK];
+            rbf<true>(p, r, g, dg);
+            float tt = 0.0f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) tt = __builtin_fmaf(d[q], li[q] - lam[(size_t)j * D + q], tt);
+            tt = -tt / r;
+#pragma unroll
+            for (int k = 0; k < kK; ++k) acc[k] = __builtin_fmaf(dg[k], tt, acc[k]);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < kK; ++k) acc[k] += __shfl_xor(acc[k], o);
+    }
+    if (live && l == 0) {
+#pragma unroll
+        for (int k = 0; k < kK; ++k) ebar[(size_t)i * kK + k] = acc[k];
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
-// MFMA helpers.  v_mfma_f32_32x32x16_bf16 on a 32 x 16 A tile and a 16 x 32 B tile: lane l supplies
-// A row (l % 32), k = 8 (l / 32) .. +7 and B column (l % 32), the same k; accumulator register r of lane
-// l holds C[row][col] with col = l % 32, row = (r % 4) + 4 (l / 32) + 8 (r / 4).
+// MFMA.  v_mfma_f32_32x32x16_bf16 on a 32 x 16 A tile and a 16 x 32 B tile: lane l supplies A row (l % 32),
+// k = 8 (l / 32) .. +7 and B column (l % 32), the same k; accumulator register r of lane l holds C[row][col]
+// with col = l % 32, row = (r % 4) + 4 (l / 32) + 8 (r / 4).  The products are C = A Bt^T with A and Bt
+// row-major in LDS, K contiguous, rows padded by 8 elements against bank conflicts; or C = A M with the B
+// columns read down a row-major M.
 
 __device__ __forceinline__ int acc_row(int r, int lane)
 {
     return (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2);
 }
 
-// C[32][32 * half .. +32] = A[32][K] (row-major bf16, LDS, row stride lda) x B where B column n is row
-// (32 * half + n) of a row-major bf16 matrix Bt (LDS, row stride ldb): C = A Bt^T.
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p)
+{
+    return *(const bf16x8 *)p;  // 16-byte aligned: row strides and k offsets are multiples of 8 elements
+}
+
 template <int K>
-__device__ __forceinline__ f32x16 mfma_tile(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, int half)
+__device__ __forceinline__ f32x16 mma(f32x16 c, const uint16_t *A, int lda, const uint16_t *Bt, int ldb)
 {
     int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int kk = 0; kk < K; kk += 16) {
+        bf16x8 av = ld8(A + (lane & 31) * lda + kk + 8 * (lane >> 5));
+        bf16x8 bv = ld8(Bt + (lane & 31) * ldb + kk + 8 * (lane >> 5));
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+    }
+    return c;
+}
+
+// c += A B with B[k][n] = M[k][n0 + n] (columns n >= ncols are zero)
+template <int K>
+__device__ __forceinline__ f32x16 mma_bcol(f32x16 c, const uint16_t *A, int lda, const uint16_t *M, int ldm, int n0,
+                                           int ncols)
+{
+    int lane = threadIdx.x & 63;
+    bool live = (lane & 31) < ncols;
+    int n = n0 + (live ? (lane & 31) : 0);
+#pragma unroll
+    for (int kk = 0; kk < K; kk += 16) {
+        bf16x8 av = ld8(A + (lane & 31) * lda + kk + 8 * (lane >> 5));
+        bf16x8 bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bv[q] = live ? (short)M[(kk + 8 * (lane >> 5) + q) * ldm + n] : (short)0;
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ f32x16 zero16()
+{
     f32x16 c;
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < K; kk += 16) {
-        const uint16_t *ap = A + (lane & 31) * lda + kk + 8 * (lane >> 5);
-        const uint16_t *bp = Bt + (32 * half + (lane & 31)) * ldb + kk + 8 * (lane >> 5);
-        bf16x8 av, bv;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            av[q] = (short)ap[q];
-            bv[q] = (short)bp[q];
-        }
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
-    }
     return c;
 }
 
@@ -227,87 +321,118 @@ __device__ __forceinline__ float sigmoid(float z)
     return 1.0f / (1.0f + __expf(-z));
 }
 
-struct MlpLds {
-    uint16_t W1[kH * kK];        // [H][K]
-    uint16_t W1t[32 * kH];       // [32][H]: rows k < K hold column k of W1, rows K..31 are zero
-    uint16_t W2[kH * kH];        // [H][H]
-    uint16_t W2t[kH * kH];       // [H][H] transposed
-    float b1[kH], b2[kH], w3[kH], m[kK], s[kK];
-    uint16_t X[kMlpWaves][kTile * kK];
-    uint16_t T[kMlpWaves][kTile * kH];
-    float Erow[kMlpWaves][kTile];
+// padded row strides (elements)
+constexpr int L16 = 24, L32 = 40, L64 = 72;
+
+// activation tile (32 atoms) as a BF16 pair hi + lo
+template <int LD>
+struct Pair {
+    uint16_t h[kTile * LD];
+    uint16_t l[kTile * LD];
 };
 
-// Per-atom energies E_i and input gradients e_i = dE_i/dG_i for atoms [0, N), 32 per wave tile.
-__global__ __launch_bounds__(kMlpThreads) void k_nn_mlp(NNDev p, const float *__restrict__ G, int N,
-                                                        float *__restrict__ Ei, float *__restrict__ e)
+template <int LD>
+__device__ __forceinline__ void put_pair(Pair<LD> &t, int row, int col, float v)
 {
-    __shared__ MlpLds s;
-    int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int q = t; q < kH * kK; q += kMlpThreads) s.W1[q] = p.W1[q];
-    for (int q = t; q < 32 * kH; q += kMlpThreads) {
-        int k = q / kH, h = q % kH;
-        s.W1t[q] = k < kK ? p.W1[h * kK + k] : (uint16_t)0;
+    uint16_t h, l;
+    split_bf(v, h, l);
+    t.h[row * LD + col] = h;
+    t.l[row * LD + col] = l;
+}
+
+// A(hi, lo) Bt^T for the 32 columns of Bt: the two products of a split activation operand.
+template <int K, int LD>
+__device__ __forceinline__ f32x16 mma_split(const Pair<LD> &A, const uint16_t *Bt, int ldb)
+{
+    f32x16 c = mma<K>(zero16(), A.h, LD, Bt, ldb);
+    return mma<K>(c, A.l, LD, Bt, ldb);
+}
+
+template <int K, int LD>
+__device__ __forceinline__ f32x16 mma_split_bcol(const Pair<LD> &A, const uint16_t *M, int ldm, int n0, int ncols)
+{
+    f32x16 c = mma_bcol<K>(zero16(), A.h, LD, M, ldm, n0, ncols);
+    return mma_bcol<K>(c, A.l, LD, M, ldm, n0, ncols);
+}
+
+// Weights in LDS: W1 [H][K] and W2 [H][H], BF16, padded rows.
+struct WLds {
+    uint16_t W1[kH * L16];
+    uint16_t W2[kH * L64];
+};
+
+__device__ __forceinline__ void load_weights(WLds &w, const NNDev &p, int t, int nt)
+{
+    for (int q = t; q < kH * kK; q += nt) w.W1[(q / kK) * L16 + q % kK] = p.W1[q];
+    for (int q = t; q < kH * kH; q += nt) w.W2[(q / kH) * L64 + q % kH] = p.W2[q];
+}
+
+// X = (G - m)/s of atoms a0 .. a0+31 (zero rows past N) into a split tile.
+__device__ __forceinline__ void load_x(Pair<L16> &X, const NNDev &p, const float *G, int a0, int N, int lane)
+{
+    for (int q = lane; q < kTile * kK; q += 64) {
+        int row = q / kK, k = q % kK, a = a0 + row;
+        float x = a < N ? (G[(size_t)a * kK + k] - p.m[k]) / p.s[k] : 0.0f;
+        put_pair(X, row, k, x);
     }
-    for (int q = t; q < kH * kH; q += kMlpThreads) {
-        s.W2[q] = p.W2[q];
-        s.W2t[q] = p.W2[(q % kH) * kH + q / kH];
+}
+
+struct MlpLds {
+    WLds w;
+    Pair<L16> X;
+    Pair<L64> T;
+    float E[kTile];
+};
+
+// Per-atom energies E_i and input gradients e_i = dE_i/dG_i for atoms [0, N), one wave per 32-atom tile.
+__global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict__ G, int N, float *__restrict__ Ei,
+                                               float *__restrict__ e)
+{
+    __shared__ __align__(16) MlpLds s;
+    int lane = threadIdx.x;
+    int c32 = lane & 31;
+    load_weights(s.w, p, lane, 64);
+    float b1[2], b2[2], w3[2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        b1[hf] = p.b1[32 * hf + c32];
+        b2[hf] = p.b2[32 * hf + c32];
+        w3[hf] = p.w3[32 * hf + c32];
     }
-    for (int q = t; q < kH; q += kMlpThreads) {
-        s.b1[q] = p.b1[q];
-        s.b2[q] = p.b2[q];
-        s.w3[q] = p.w3[q];
-    }
-    for (int q = t; q < kK; q += kMlpThreads) {
-        s.m[q] = p.m[q];
-        s.s[q] = p.s[q];
-    }
-    __syncthreads();
+    float b3 = *p.b3;
     int ntiles = (N + kTile - 1) / kTile;
-    // every wave of the block runs the same iterations (workgroup barriers inside); a wave past the last
-    // tile works on zero rows and stores nothing
-    for (int base = blockIdx.x * kMlpWaves; base < ntiles; base += gridDim.x * kMlpWaves) {
-        int tile = base + w;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int a0 = tile * kTile;
-        // X = (G - m)/s in bf16, rows beyond N are zero
-        for (int q = lane; q < kTile * kK; q += 64) {
-            int row = q / kK, k = q % kK;
-            int a = a0 + row;
-            float x = a < N ? (G[(size_t)a * kK + k] - s.m[k]) / s.s[k] : 0.0f;
-            s.X[w][q] = f2bf(x);
-        }
         __syncthreads();
-        // layer 1: z1 = X W1^T + b1; h1 = sp(z1) -> T (bf16); a1 = sp'(z1) kept in registers
+        load_x(s.X, p, G, a0, N, lane);
+        __syncthreads();
+        // z1 = X W1^T + b1; h1 = sp(z1) -> T; a1 = sp'(z1)
         float a1[2][16];
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf) {
-            f32x16 c = mfma_tile<kK>(s.X[w], kK, s.W1, kK, hf);
+            f32x16 c = mma_split<kK>(s.X, s.w.W1 + 32 * hf * L16, L16);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                int row = acc_row(r, lane), col = 32 * hf + (lane & 31);
-                float z = c[r] + s.b1[col];
+                float z = c[r] + b1[hf];
                 a1[hf][r] = sigmoid(z);
-                s.T[w][row * kH + col] = f2bf(softplus(z));
+                put_pair(s.T, acc_row(r, lane), 32 * hf + c32, softplus(z));
             }
         }
         __syncthreads();
-        // layer 2: z2 = H1 W2^T + b2; E_i = w3 . sp(z2) + b3; d2 = sp'(z2) * w3 -> T
-        float d2[2][16];
-        float erow[16];
+        // z2 = H1 W2^T + b2; E_i = w3 . sp(z2) + b3; d2 = sp'(z2) w3
+        float d2[2][16], erow[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) erow[r] = 0.0f;
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf) {
-            f32x16 c = mfma_tile<kH>(s.T[w], kH, s.W2, kH, hf);
+            f32x16 c = mma_split<kH>(s.T, s.w.W2 + 32 * hf * L64, L64);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                int col = 32 * hf + (lane & 31);
-                float z = c[r] + s.b2[col];
-                erow[r] += s.w3[col] * softplus(z);
-                d2[hf][r] = sigmoid(z) * s.w3[col];
+                float z = c[r] + b2[hf];
+                erow[r] += w3[hf] * softplus(z);
+                d2[hf][r] = sigmoid(z) * w3[hf];
             }
         }
-        // row sums of w3 . h2 over the 64 columns: 32 lanes of a half hold one row's columns
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             float v = erow[r];
@@ -315,51 +440,330 @@ __global__ __launch_bounds__(kMlpThreads) void k_nn_mlp(NNDev p, const float *__
             for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o);
             erow[r] = v;
         }
-        if ((lane & 31) == 0) {
+        if (c32 == 0) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) s.Erow[w][acc_row(r, lane)] = erow[r];
+            for (int r = 0; r < 16; ++r) s.E[acc_row(r, lane)] = erow[r];
         }
         __syncthreads();
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
+        for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int row = acc_row(r, lane), col = 32 * hf + (lane & 31);
-                s.T[w][row * kH + col] = f2bf(d2[hf][r]);
-            }
-        }
+            for (int r = 0; r < 16; ++r) put_pair(s.T, acc_row(r, lane), 32 * hf + c32, d2[hf][r]);
         __syncthreads();
-        if (lane < kTile && a0 + lane < N) Ei[a0 + lane] = s.Erow[w][lane] + p.b3;
-        // d1 = a1 * (D2 W2): B column k of W2 is row k of W2t
+        if (lane < kTile && a0 + lane < N) Ei[a0 + lane] = s.E[lane] + b3;
+        // d1 = a1 * (D2 W2)
         float d1[2][16];
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf) {
-            f32x16 c = mfma_tile<kH>(s.T[w], kH, s.W2t, kH, hf);
+            f32x16 c = mma_split_bcol<kH>(s.T, s.w.W2, L64, 32 * hf, 32);
 #pragma unroll
             for (int r = 0; r < 16; ++r) d1[hf][r] = c[r] * a1[hf][r];
         }
         __syncthreads();
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
+        for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int row = acc_row(r, lane), col = 32 * hf + (lane & 31);
-                s.T[w][row * kH + col] = f2bf(d1[hf][r]);
-            }
-        }
+            for (int r = 0; r < 16; ++r) put_pair(s.T, acc_row(r, lane), 32 * hf + c32, d1[hf][r]);
         __syncthreads();
-        // e = (D1 W1) / s: B column k of W1 is row k of W1t (rows >= K are zero)
-        f32x16 c = mfma_tile<kH>(s.T[w], kH, s.W1t, kH, 0);
-        int col = lane & 31;
-        if (col < kK) {
+        // e = (D1 W1) / s  (columns k < K of the product)
+        f32x16 c = mma_split_bcol<kH>(s.T, s.w.W1, L16, 0, kK);
+        if (c32 < kK) {
+            float sk = p.s[c32];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int a = a0 + acc_row(r, lane);
-                if (a < N) e[(size_t)a * kK + col] = c[r] / s.s[col];
+                if (a < N) e[(size_t)a * kK + c32] = c[r] / sk;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// training pass
+
+struct TrainLds {
+    WLds w;
+    Pair<L16> X;              // x, later xd (the tangent input)
+    uint16_t Xt[32 * L32];    // x transposed [input k][atom], rows >= K zero
+    uint16_t Xdt[32 * L32];   // xd transposed
+    Pair<L64> A1;             // h1, later g_z2
+    Pair<L64> A2;             // d2, later hd1
+    uint16_t H1t[kH * L32];   // h1 transposed [unit][atom], later g_z1 transposed
+    uint16_t D2t[kH * L32];   // d2 (the adjoint of z2 in the tangent's reverse pass) transposed
+    uint16_t D1t[kH * L32];   // d1 (the adjoint of zd1) transposed
+    uint16_t Hd1t[kH * L32];  // hd1 transposed
+    uint16_t Gz2t[kH * L32];  // g_z2 transposed
+};
+
+__device__ __forceinline__ void put_t(uint16_t *t, int unit, int atom, float v)
+{
+    t[unit * L32 + atom] = f2bf(v);
+}
+
+// Weight gradient of the loss over atoms [0, N): the reverse pass of E_i with seed gE (one value per system of
+// `seg` atoms) plus the reverse pass of the tangent w3 . hd2_i along xd_i = ebar_i / s.  One partial gradient
+// (kNP floats) per wave.
+__global__ __launch_bounds__(64) void k_nn_train(NNDev p, const float *__restrict__ G, int N, int seg,
+                                                 const float *__restrict__ gE, const float *__restrict__ ebar,
+                                                 float *__restrict__ partial)
+{
+    __shared__ __align__(16) TrainLds s;
+    int lane = threadIdx.x;
+    int c32 = lane & 31;
+    load_weights(s.w, p, lane, 64);
+    for (int q = lane; q < 32 * L32; q += 64) {
+        s.Xt[q] = 0;
+        s.Xdt[q] = 0;
+    }
+    float b1[2], b2[2], w3[2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        b1[hf] = p.b1[32 * hf + c32];
+        b2[hf] = p.b2[32 * hf + c32];
+        w3[hf] = p.w3[32 * hf + c32];
+    }
+    f32x16 gW2[2][2], gW1[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        gW1[a] = zero16();
+        gW2[a][0] = zero16();
+        gW2[a][1] = zero16();
+    }
+    float gb1[2] = {0.0f, 0.0f}, gb2[2] = {0.0f, 0.0f}, gw3[2] = {0.0f, 0.0f}, gb3 = 0.0f;
+    int ntiles = (N + kTile - 1) / kTile;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int a0 = tile * kTile;
+        __syncthreads();
+        load_x(s.X, p, G, a0, N, lane);
+        for (int q = lane; q < kTile * kK; q += 64) {
+            int row = q / kK, k = q % kK, a = a0 + row;
+            float x = a < N ? (G[(size_t)a * kK + k] - p.m[k]) / p.s[k] : 0.0f;
+            s.Xt[k * L32 + row] = f2bf(x);
+            float xd = a < N ? ebar[(size_t)a * kK + k] / p.s[k] : 0.0f;
+            s.Xdt[k * L32 + row] = f2bf(xd);
+        }
+        float ge[16];  // dL/dE_i of the rows this lane holds
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            int a = a0 + acc_row(r, lane);
+            ge[r] = a < N ? gE[seg > 0 ? a / seg : 0] : 0.0f;
+        }
+        if (lane < kTile && a0 + lane < N) gb3 += gE[seg > 0 ? (a0 + lane) / seg : 0];
+        __syncthreads();
+        // forward: z1, h1 -> A1, H1t
+        float z1[2][16], z2[2][16], g1[2][16], zd1[2][16];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split<kK>(s.X, s.w.W1 + 32 * hf * L16, L16);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                z1[hf][r] = c[r] + b1[hf];
+                float h = softplus(z1[hf][r]);
+                put_pair(s.A1, acc_row(r, lane), 32 * hf + c32, h);
+                put_t(s.H1t, 32 * hf + c32, acc_row(r, lane), h);
             }
         }
         __syncthreads();
+        // z2; d2 = sp'(z2) w3 -> A2, D2t; the energy seed reaches w3 through h2
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split<kH>(s.A1, s.w.W2 + 32 * hf * L64, L64);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                z2[hf][r] = c[r] + b2[hf];
+                float d = sigmoid(z2[hf][r]) * w3[hf];
+                put_pair(s.A2, acc_row(r, lane), 32 * hf + c32, d);
+                put_t(s.D2t, 32 * hf + c32, acc_row(r, lane), d);
+                gw3[hf] += ge[r] * softplus(z2[hf][r]);
+            }
+        }
+        __syncthreads();
+        // g1 = D2 W2 (= dE/dh1); d1 = sp'(z1) g1 -> D1t
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split_bcol<kH>(s.A2, s.w.W2, L64, 32 * hf, 32);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                g1[hf][r] = c[r];
+                put_t(s.D1t, 32 * hf + c32, acc_row(r, lane), sigmoid(z1[hf][r]) * c[r]);
+            }
+        }
+        __syncthreads();
+        // tangent input xd = ebar / s -> X
+        for (int q = lane; q < kTile * kK; q += 64) {
+            int row = q / kK, k = q % kK, a = a0 + row;
+            put_pair(s.X, row, k, a < N ? ebar[(size_t)a * kK + k] / p.s[k] : 0.0f);
+        }
+        __syncthreads();
+        // zd1 = Xd W1^T; hd1 = sp'(z1) zd1 -> A2, Hd1t
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split<kK>(s.X, s.w.W1 + 32 * hf * L16, L16);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                zd1[hf][r] = c[r];
+                float hd = sigmoid(z1[hf][r]) * c[r];
+                put_pair(s.A2, acc_row(r, lane), 32 * hf + c32, hd);
+                put_t(s.Hd1t, 32 * hf + c32, acc_row(r, lane), hd);
+            }
+        }
+        __syncthreads();
+        // zd2 = Hd1 W2^T; hd2 = sp'(z2) zd2; g_z2 = gE w3 sp'(z2) + w3 sp''(z2) zd2 -> A1, Gz2t
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split<kH>(s.A2, s.w.W2 + 32 * hf * L64, L64);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float sg = sigmoid(z2[hf][r]);
+                float zd2 = c[r];
+                gw3[hf] += sg * zd2;
+                float gz2 = w3[hf] * (ge[r] * sg + sg * (1.0f - sg) * zd2);
+                gb2[hf] += gz2;
+                put_pair(s.A1, acc_row(r, lane), 32 * hf + c32, gz2);
+                put_t(s.Gz2t, 32 * hf + c32, acc_row(r, lane), gz2);
+            }
+        }
+        __syncthreads();
+        // dW2 += G_z2^T H1 + D2^T Hd1 (products over the tile's atoms)
+#pragma unroll
+        for (int mh = 0; mh < 2; ++mh)
+#pragma unroll
+            for (int nh = 0; nh < 2; ++nh) {
+                gW2[mh][nh] = mma<kTile>(gW2[mh][nh], s.Gz2t + 32 * mh * L32, L32, s.H1t + 32 * nh * L32, L32);
+                gW2[mh][nh] = mma<kTile>(gW2[mh][nh], s.D2t + 32 * mh * L32, L32, s.Hd1t + 32 * nh * L32, L32);
+            }
+        // g_h1 = G_z2 W2; g_z1 = g_h1 sp'(z1) + g1 sp''(z1) zd1
+        float gz1[2][16];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x16 c = mma_split_bcol<kH>(s.A1, s.w.W2, L64, 32 * hf, 32);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float sg = sigmoid(z1[hf][r]);
+                gz1[hf][r] = c[r] * sg + g1[hf][r] * sg * (1.0f - sg) * zd1[hf][r];
+                gb1[hf] += gz1[hf][r];
+            }
+        }
+        __syncthreads();
+        // g_z1 transposed -> H1t (h1 is no longer needed)
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) put_t(s.H1t, 32 * hf + c32, acc_row(r, lane), gz1[hf][r]);
+        __syncthreads();
+        // dW1 += G_z1^T X + D1^T Xd
+#pragma unroll
+        for (int mh = 0; mh < 2; ++mh) {
+            gW1[mh] = mma<kTile>(gW1[mh], s.H1t + 32 * mh * L32, L32, s.Xt, L32);
+            gW1[mh] = mma<kTile>(gW1[mh], s.D1t + 32 * mh * L32, L32, s.Xdt, L32);
+        }
     }
+    // the wave's partial gradient; bias sums combine the two lane halves of each column
+    float *out = partial + (size_t)blockIdx.x * kNP;
+#pragma unroll
+    for (int mh = 0; mh < 2; ++mh) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            int row = 32 * mh + acc_row(r, lane);
+            if (c32 < kK) out[oW1 + row * kK + c32] = gW1[mh][r];
+#pragma unroll
+            for (int nh = 0; nh < 2; ++nh) out[oW2 + row * kH + 32 * nh + c32] = gW2[mh][nh][r];
+        }
+    }
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        float v1 = gb1[hf] + __shfl_xor(gb1[hf], 32);
+        float v2 = gb2[hf] + __shfl_xor(gb2[hf], 32);
+        float v3 = gw3[hf] + __shfl_xor(gw3[hf], 32);
+        if (lane < 32) {
+            out[ob1 + 32 * hf + lane] = v1;
+            out[ob2 + 32 * hf + lane] = v2;
+            out[ow3 + 32 * hf + lane] = v3;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) gb3 += __shfl_xor(gb3, o);
+    if (lane == 0) out[ob3] = gb3;
+}
+
+// grad[q] = sum over waves w (in order) of partial[w][q], in double.
+__global__ __launch_bounds__(kBlock) void k_nn_grad_reduce(const float *__restrict__ partial, int nw,
+                                                           float *__restrict__ grad)
+{
+    int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= kNP) return;
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) acc += (double)partial[(size_t)w * kNP + q];
+    grad[q] = (float)acc;
+}
+
+// One workgroup per system s of `seg` atoms: E_s (double, fixed order), gE[s] and the system's part of the
+// loss; lam_i = 2 lam_F (F_i - F^_i)/(3N) for its atoms.
+__global__ __launch_bounds__(kBlock) void k_nn_loss_sys(const float *__restrict__ Ei, const float *__restrict__ F,
+                                                        const double *__restrict__ E_ref,
+                                                        const float *__restrict__ F_ref, int N, int seg, int S,
+                                                        float lam_F, float *__restrict__ gE, float *__restrict__ lam,
+                                                        double *__restrict__ part)
+{
+    __shared__ double red[kBlock];
+    int sys = blockIdx.x;
+    int a0 = sys * seg;
+    double e = 0.0, f2 = 0.0;
+    double cf = 2.0 * (double)lam_F / (3.0 * (double)N);
+    for (int a = a0 + threadIdx.x; a < a0 + seg; a += kBlock) {
+        e += (double)Ei[a];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double r = (double)F[(size_t)a * 3 + q] - (double)F_ref[(size_t)a * 3 + q];
+            f2 += r * r;
+            lam[(size_t)a * 3 + q] = (float)(cf * r);
+        }
+    }
+    e = block_sum(e, red);
+    f2 = block_sum(f2, red);
+    if (threadIdx.x == 0) {
+        double rE = (e - E_ref[sys]) / (double)seg;
+        gE[sys] = (float)(2.0 * rE / ((double)seg * (double)S));
+        part[sys] = rE * rE / (double)S + (double)lam_F * f2 / (3.0 * (double)N);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_nn_loss_final(const double *__restrict__ part, int S,
+                                                          double *__restrict__ loss)
+{
+    __shared__ double red[kBlock];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < S; q += kBlock) v += part[q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) loss[0] = v;
+}
+
+// Adam (Kingma & Ba) on the FP32 master vector; W1 and W2 also written as BF16 (round to nearest even).
+__global__ __launch_bounds__(kBlock) void k_nn_adam(float *__restrict__ th, float *__restrict__ m,
+                                                    float *__restrict__ v, const float *__restrict__ g, int n,
+                                                    float lr, float b1, float b2, float eps, float c1, float c2,
+                                                    uint16_t *__restrict__ W1, uint16_t *__restrict__ W2)
+{
+    int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    float gq = g[q];
+    float mq = b1 * m[q] + (1.0f - b1) * gq;
+    float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    float t = th[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+    th[q] = t;
+    if (q >= oW1 && q < oW1 + kH * kK) W1[q - oW1] = f2bf(t);
+    if (q >= oW2 && q < oW2 + kH * kH) W2[q - oW2] = f2bf(t);
+}
+
+// BF16 copies of W1 and W2 from the master vector.
+__global__ __launch_bounds__(kBlock) void k_nn_cast(const float *__restrict__ th, uint16_t *__restrict__ W1,
+                                                    uint16_t *__restrict__ W2)
+{
+    int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q < kH * kK) W1[q] = f2bf(th[oW1 + q]);
+    if (q < kH * kH) W2[q] = f2bf(th[oW2 + q]);
 }
 
 }  // namespace
@@ -369,7 +773,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_nn_mlp(NNDev p, const float *__
 
 static bool make_nn(const md_nn_params *q, NNDev &p)
 {
-    if (!q || q->K != kK || q->H != kH || !q->W1 || !q->W2 || !q->b1 || !q->b2 || !q->w3 || !q->m || !q->s)
+    if (!q || q->K != kK || q->H != kH || !q->W1 || !q->W2 || !q->b1 || !q->b2 || !q->w3 || !q->b3 || !q->m || !q->s)
         return false;
     if (!(q->r_c > 0.0f) || !(q->mu1 > q->mu0)) return false;
     p.mu0 = q->mu0;
@@ -441,9 +845,8 @@ md_status nn_mlp(md_ctx *ctx, const md_nn_params *q, const float *G, int32_t N, 
     if (!ctx || !make_nn(q, p) || !G || !Ei || !e || N < 0) return MD_ERR_ARG;
     if (N == 0) return MD_OK;
     int ntiles = (N + kTile - 1) / kTile;
-    int grid = (ntiles + kMlpWaves - 1) / kMlpWaves;
-    if (grid > 2048) grid = 2048;
-    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(kMlpThreads), 0, (hipStream_t)stream, p, G, N, Ei, e);
+    int grid = ntiles < 8192 ? ntiles : 8192;
+    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(64), 0, (hipStream_t)stream, p, G, N, Ei, e);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
@@ -462,6 +865,77 @@ md_status nn_forces(md_ctx *ctx, const md_box *box, const md_nn_params *q, const
     NN_LANES(W, hipLaunchKernelGGL((k_nn_force<3, W>), dim3(grid), dim3(kBlock), 0, s, b, p, pos, N, nl->idx,
                                    nl->count, capW, e, force, nl->flags));
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_pair_adjoint(md_ctx *ctx, const md_box *box, const md_nn_params *q, const uint32_t *pos, int32_t N,
+                          const md_nlist *nl, const float *lam, float *ebar, void *stream)
+{
+    DevBox b;
+    NNDev p;
+    md_status st = nn_checks(ctx, box, q, pos, N, nl, b, p);
+    if (st != MD_OK) return st;
+    if (!lam || !ebar) return MD_ERR_ARG;
+    if (N == 0) return MD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int W = nl->lanes, capW = nl->capacity / W;
+    int grid = (int)(((int64_t)N * W + kBlock - 1) / kBlock);
+    NN_LANES(W, hipLaunchKernelGGL((k_nn_adjoint<3, W>), dim3(grid), dim3(kBlock), 0, s, b, p, pos, N, nl->idx,
+                                   nl->count, capW, lam, ebar));
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_loss(md_ctx *ctx, const float *Ei, const float *F, const double *E_ref, const float *F_ref, int32_t N,
+                  int32_t segment, float lam_F, double *loss, float *gE, float *lam, void *stream)
+{
+    if (!ctx || !Ei || !F || !E_ref || !F_ref || !loss || !gE || !lam || N <= 0 || segment <= 0 ||
+        N % segment != 0)
+        return MD_ERR_ARG;
+    int S = N / segment;
+    if (S > 4 * md_partials_blocks()) return MD_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_nn_loss_sys, dim3(S), dim3(kBlock), 0, s, Ei, F, E_ref, F_ref, N, segment, S, lam_F, gE,
+                       lam, ctx->partials);
+    hipLaunchKernelGGL(k_nn_loss_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, S, loss);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_mlp_grad(md_ctx *ctx, const md_nn_params *q, const float *G, int32_t N, int32_t segment,
+                      const float *gE, const float *ebar, float *grad, void *stream)
+{
+    NNDev p;
+    if (!ctx || !make_nn(q, p) || !G || !gE || !ebar || !grad || N <= 0 || segment < 0 ||
+        (segment > 0 && N % segment != 0))
+        return MD_ERR_ARG;
+    int ntiles = (N + kTile - 1) / kTile;
+    int nw = ntiles < kTrainWaves ? ntiles : kTrainWaves;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_nn_train, dim3(nw), dim3(64), 0, s, p, G, N, segment, gE, ebar, ctx->nn_partial);
+    hipLaunchKernelGGL(k_nn_grad_reduce, dim3((kNP + kBlock - 1) / kBlock), dim3(kBlock), 0, s, ctx->nn_partial, nw,
+                       grad);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_adam(md_ctx *ctx, float *theta, float *m, float *v, const float *grad, int32_t n, int32_t step, float lr,
+                  float beta1, float beta2, float eps, uint16_t *W1, uint16_t *W2, void *stream)
+{
+    if (!ctx || !theta || !m || !v || !grad || !W1 || !W2 || n != kNP || step < 1) return MD_ERR_ARG;
+    float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_nn_adam, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, (hipStream_t)stream, theta, m, v,
+                       grad, n, lr, beta1, beta2, eps, c1, c2, W1, W2);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_cast_weights(md_ctx *ctx, const float *theta, uint16_t *W1, uint16_t *W2, void *stream)
+{
+    if (!ctx || !theta || !W1 || !W2) return MD_ERR_ARG;
+    hipLaunchKernelGGL(k_nn_cast, dim3((kH * kH + kBlock - 1) / kBlock), dim3(kBlock), 0, (hipStream_t)stream, theta,
+                       W1, W2);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+int32_t nn_param_count(void)
+{
+    return kNP;
 }
 
 }  // extern "C"

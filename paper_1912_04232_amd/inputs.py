@@ -181,3 +181,47 @@ def ss_batch(B: int = 64, seed: int = 4001, n_lo: int = 256, n_hi: int = 4096, p
 
 def lj_train_box(N: int = 4000, rho: float = 0.84) -> float:
     return box_for_density(N, rho)
+
+
+def bcc_torus(n_cells: int, L: float) -> np.ndarray:
+    """BCC lattice with n_cells^3 cubic cells (2 sites each) filling a cube of edge L."""
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0.5]], dtype=np.float64)
+    g = np.arange(n_cells, dtype=np.float64)
+    cz, cy, cx = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
+    pts = (cells[:, None, :] + base[None, :, :] + 0.25).reshape(-1, 3) / n_cells
+    return to_torus(pts * L, [L, L, L])
+
+
+def lj_train_runs(n_runs: int = 20, n_cells: int = 10, rho: float = 0.84, T_lo: float = 0.5, T_hi: float = 1.5,
+                  seed: int = 5001):
+    """Independent 3D LJ runs that supply neural-potential training snapshots: N = 4 n_cells^3 (4000) on an FCC
+    lattice at rho with Maxwell velocities at T_k, T evenly spaced over [T_lo, T_hi] (the runs melt or stay
+    crystalline according to T)."""
+    N = 4 * n_cells ** 3
+    L = box_for_density(N, rho)
+    u = fcc_torus(n_cells, L)
+    runs = []
+    for k in range(n_runs):
+        T = T_lo + (T_hi - T_lo) * k / max(n_runs - 1, 1)
+        runs.append(dict(N=N, L=[L, L, L], T=T, u=u.copy(), v=maxwell_velocities(N, 3, T, seed + k)))
+    return runs
+
+
+def lj_nn_deploy(seed: int = 6001, rho: float = 0.84, T: float = 1.0):
+    """3D LJ N = 65536 (BCC 32^3) at rho 0.84 with Maxwell velocities at T: the neural-potential MD workload."""
+    n = 32
+    N = 2 * n ** 3
+    L = box_for_density(N, rho)
+    return dict(N=N, L=[L, L, L], u=bcc_torus(n, L), v=maxwell_velocities(N, 3, T, seed), dt=0.005, skin=0.3)
+
+
+def nn_init(seed: int, K: int = 16, H: int = 64) -> dict:
+    """Glorot-uniform weights, zero biases, output layer scaled by 0.1 (float64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def glorot(o, i):
+        lim = math.sqrt(6.0 / (o + i))
+        return rng.uniform(-lim, lim, size=(o, i))
+
+    return dict(W1=glorot(H, K), b1=np.zeros(H), W2=glorot(H, H), b2=np.zeros(H), w3=glorot(1, H)[0] * 0.1, b3=0.0)

@@ -43,14 +43,14 @@ class c_box(ctypes.Structure):
 
 
 class c_potential(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32), ("sigma", ctypes.c_float * 64),
-                ("epsilon", ctypes.c_float * 64), ("alpha", ctypes.c_float), ("r_cut", ctypes.c_float),
+    _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32), ("sigma", ctypes.c_double * 64),
+                ("epsilon", ctypes.c_double * 64), ("alpha", ctypes.c_float), ("r_cut", ctypes.c_float),
                 ("shift", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class c_nlist(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("capacity", ctypes.c_int32), ("lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("r_list", ctypes.c_float), ("skin", ctypes.c_float),
+                ("segment", ctypes.c_int32), ("r_list", ctypes.c_float), ("skin", ctypes.c_float),
                 ("idx", ctypes.c_void_p), ("count", ctypes.c_void_p), ("pos_ref", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p)]
 
@@ -75,9 +75,9 @@ class c_batch(ctypes.Structure):
 
 class c_nn_params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("H", ctypes.c_int32), ("mu0", ctypes.c_float), ("mu1", ctypes.c_float),
-                ("r_c", ctypes.c_float), ("b3", ctypes.c_float), ("W1", ctypes.c_void_p), ("W2", ctypes.c_void_p),
-                ("b1", ctypes.c_void_p), ("b2", ctypes.c_void_p), ("w3", ctypes.c_void_p), ("m", ctypes.c_void_p),
-                ("s", ctypes.c_void_p)]
+                ("r_c", ctypes.c_float), ("reserved", ctypes.c_int32), ("W1", ctypes.c_void_p),
+                ("W2", ctypes.c_void_p), ("b1", ctypes.c_void_p), ("b2", ctypes.c_void_p), ("w3", ctypes.c_void_p),
+                ("b3", ctypes.c_void_p), ("m", ctypes.c_void_p), ("s", ctypes.c_void_p)]
 
 
 FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
@@ -109,8 +109,17 @@ _SIGNATURES = {
     "nn_mlp": [P, ctypes.POINTER(c_nn_params), P, ctypes.c_int32, P, P, P],
     "nn_forces": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32, ctypes.POINTER(c_nlist),
                   P, P, P],
+    "nn_param_count": [],
+    "nn_loss": [P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P, P, P],
+    "nn_pair_adjoint": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32,
+                        ctypes.POINTER(c_nlist), P, P, P],
+    "nn_mlp_grad": [P, ctypes.POINTER(c_nn_params), P, ctypes.c_int32, ctypes.c_int32, P, P, P, P],
+    "nn_adam": [P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                ctypes.c_float, P, P, P],
+    "nn_cast_weights": [P, P, P, P, P],
     "md_sum": [P, P, ctypes.c_int64, P, P],
     "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
+    "md_rescale_velocities": [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
     "md_flags_clear": [ctypes.POINTER(c_nlist), P],
     "md_version": [],
@@ -275,10 +284,13 @@ class NeighborList:
     reserves for this list's cell list."""
 
     def __init__(self, N: int, dim: int, capacity: int, r_list: float, skin: float, device=None,
-                 max_per_cell: int = 64, lanes: int = 1):
+                 max_per_cell: int = 64, lanes: int = 1, segment: int = 0):
         dev = device or _dev()
         capacity = (capacity + lanes - 1) // lanes * lanes
+        if segment < 0 or (segment > 0 and N % segment != 0):
+            raise ValueError("segment must divide N")
         self.N, self.dim, self.capacity, self.max_per_cell, self.lanes = N, dim, capacity, max_per_cell, lanes
+        self.segment = segment
         self.r_list, self.skin = float(np.float32(r_list)), float(np.float32(skin))
         self.idx = torch.empty((capacity // lanes, max(N, 1), lanes), dtype=torch.int32, device=dev)
         self.count = torch.zeros((max(N, 1), lanes), dtype=torch.int32, device=dev)
@@ -288,6 +300,7 @@ class NeighborList:
     def c(self) -> c_nlist:
         n = c_nlist()
         n.N, n.capacity, n.lanes, n.r_list, n.skin = self.N, self.capacity, self.lanes, self.r_list, self.skin
+        n.segment = self.segment
         n.idx, n.count = self.idx.data_ptr(), self.count.data_ptr()
         n.pos_ref, n.flags = self.pos_ref.data_ptr(), self.flags.data_ptr()
         return n
@@ -332,7 +345,8 @@ def positions_to_float(box: Box, u: torch.Tensor) -> torch.Tensor:
 
 
 def _reserve_for(ctx: Context, box: Box, N: int, nl: NeighborList):
-    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)), nl.capacity, nl.lanes, nl.max_per_cell)
+    systems = N // nl.segment if nl.segment else 1
+    ctx.reserve(N, box.dim, max(1, cell_count(box, nl.r_list)) * systems, nl.capacity, nl.lanes, nl.max_per_cell)
 
 
 def nl_build(ctx: Context, box: Box, pos: torch.Tensor, nl: NeighborList):
@@ -351,6 +365,12 @@ def pair_energy_force(ctx: Context, box: Box, pot: Potential, pos: torch.Tensor,
     _check("pair_energy_force", load().pair_energy_force(
         ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(species), N,
         ctypes.byref(n) if n is not None else None, _ptr(force), _ptr(energy), _ptr(virial), _stream()))
+
+
+def rescale_velocities(ctx: Context, vel: torch.Tensor, T: float):
+    N, dim = vel.shape
+    _check("md_rescale_velocities", load().md_rescale_velocities(ctx.h, _ptr(vel), N, dim, ctypes.c_double(T),
+                                                                 _stream()))
 
 
 def verlet_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList, dt: float,
@@ -466,15 +486,16 @@ class NNParams:
         self.W1 = f32(W1).to(torch.bfloat16).contiguous()
         self.W2 = f32(W2).to(torch.bfloat16).contiguous()
         self.b1, self.b2, self.w3, self.m, self.s = f32(b1), f32(b2), f32(w3), f32(m), f32(s)
-        self.b3 = float(b3)
+        self.b3 = f32([b3])
         self.mu0, self.mu1, self.r_c = float(mu0), float(mu1), float(r_c)
         self.K, self.H = int(self.W1.shape[1]), int(self.W1.shape[0])
 
     def c(self) -> c_nn_params:
         q = c_nn_params()
-        q.K, q.H, q.mu0, q.mu1, q.r_c, q.b3 = self.K, self.H, self.mu0, self.mu1, self.r_c, self.b3
+        q.K, q.H, q.mu0, q.mu1, q.r_c = self.K, self.H, self.mu0, self.mu1, self.r_c
         q.W1, q.W2 = self.W1.data_ptr(), self.W2.data_ptr()
-        q.b1, q.b2, q.w3, q.m, q.s = (t.data_ptr() for t in (self.b1, self.b2, self.w3, self.m, self.s))
+        q.b1, q.b2, q.w3, q.b3, q.m, q.s = (t.data_ptr() for t in (self.b1, self.b2, self.w3, self.b3, self.m,
+                                                                   self.s))
         return q
 
     def host(self) -> dict:
@@ -482,7 +503,7 @@ class NNParams:
         return dict(W1=self.W1.float().cpu().numpy().astype(np.float64),
                     W2=self.W2.float().cpu().numpy().astype(np.float64),
                     b1=self.b1.cpu().numpy().astype(np.float64), b2=self.b2.cpu().numpy().astype(np.float64),
-                    w3=self.w3.cpu().numpy().astype(np.float64), b3=self.b3,
+                    w3=self.w3.cpu().numpy().astype(np.float64), b3=float(self.b3.cpu()[0]),
                     m=self.m.cpu().numpy().astype(np.float64), s=self.s.cpu().numpy().astype(np.float64))
 
 
@@ -543,6 +564,9 @@ def from_device_u32(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint32)
 
 
+MAX_PER_CELL = 252  # bin capacity limit of the library
+
+
 class System:
     """A periodic system on the GPU: positions, velocities, forces, species, and its neighbor list."""
 
@@ -571,14 +595,15 @@ class System:
             while lanes < 8 and mean_row / lanes > 24:
                 lanes *= 2
         if capacity is None:
-            capacity = int(max(16, 1.4 * mean_row + 16 + 2 * lanes))
+            # rows are dealt round-robin over the lanes, so the capacity only covers the spread of row lengths
+            capacity = int(max(16, 1.3 * mean_row + 16))
             capacity = (capacity + 7) // 8 * 8
         if max_per_cell is None:
             cells = max(1, cell_count(box, r_list))
             mean = self.N / cells
             max_per_cell = 8
-            while max_per_cell < 2.5 * mean + 8:
-                max_per_cell *= 2
+            while max_per_cell < 2.5 * mean + 8 and max_per_cell < MAX_PER_CELL:
+                max_per_cell = min(2 * max_per_cell, MAX_PER_CELL)
         self.nl = NeighborList(self.N, self.dim, capacity, r_list, skin, dev, max_per_cell, lanes)
 
     def build(self):
@@ -598,8 +623,10 @@ class System:
         if f[FLAG_OVERFLOW]:
             cap = (int(f[FLAG_MAXCOUNT] * 1.25) + 8) // 8 * 8
         if f[FLAG_CELL_OVERFLOW]:
-            while M <= f[FLAG_MAXCELL]:
-                M *= 2
+            if f[FLAG_MAXCELL] > MAX_PER_CELL:
+                raise RuntimeError(f"a cell holds {int(f[FLAG_MAXCELL])} particles; bins hold at most {MAX_PER_CELL}")
+            while M < f[FLAG_MAXCELL]:
+                M = min(2 * M, MAX_PER_CELL)
         self.nl = NeighborList(self.N, self.dim, cap, self.nl.r_list, self.nl.skin, self.ctx.device, M,
                                self.nl.lanes)
 

@@ -87,7 +87,9 @@ def test_envelope_grad_matches_oracle_at_same_positions(md, orc):
 
 def test_adjoint_autograd_matches_finite_differences(md):
     """d E*/d d_s from the autograd.Function (batched FIRE forward, envelope_grad backward) against central
-    differences of the same GPU pipeline, h = 1e-4, box fixed."""
+    differences of the same GPU pipeline, h = 1e-4, box fixed.  The perturbed minimizations start from the
+    minimum R* itself, so they follow that minimum (at a few hundred particles a restart from the random
+    initial state can land in another basin, where E* jumps)."""
     import torch
 
     from paper_1912_04232_amd.adjoint import minimized_energy
@@ -98,6 +100,7 @@ def test_adjoint_autograd_matches_finite_differences(md):
     d = torch.tensor([1.0, 1.4], dtype=torch.float64, requires_grad=True)
     eps = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
     E = minimized_energy(d, eps, bt, u0, f_tol=1e-7, md_ctx=ctx)
+    u_star = bt.pos.clone()
     w = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64)
     (E.cpu() * w).sum().backward()
     grad = d.grad.numpy().copy()
@@ -108,11 +111,50 @@ def test_adjoint_autograd_matches_finite_differences(md):
         for sgn in (1, -1):
             dd = d.detach().clone()
             dd[s] += sgn * h
-            vals.append(float((minimized_energy(dd, eps.detach(), bt, u0, f_tol=1e-7, md_ctx=ctx).cpu() * w).sum()))
+            vals.append(float((minimized_energy(dd, eps.detach(), bt, u_star, f_tol=1e-7, md_ctx=ctx).cpu()
+                               * w).sum()))
         fd.append((vals[0] - vals[1]) / (2 * h))
-    say("adjoint", grad, "fd", fd)
+    say("adjoint", grad, "fd", fd, "E*", E.detach().cpu().numpy())
     assert np.allclose(grad, fd, rtol=2e-3, atol=1e-6)
     assert float(eps.grad) == pytest.approx(float((E.detach().cpu() * w).sum()), rel=1e-6)
+
+
+def test_adjoint_same_start_small_packing(md, orc):
+    """The App. A protocol at a size where every restart stays in one basin: N = 40 bidisperse disks at
+    phi = 0.9, each E*(d +- h) minimized from the same random start.  The GPU adjoint matches the central
+    differences of the oracle's own FIRE (FP64) and the oracle's gradient at the GPU minimum."""
+    import torch
+
+    from paper_1912_04232_amd.adjoint import minimized_energy
+    N = 40
+    L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], 0.9, 2)
+    u = inputs.uniform_torus(N, 2, 77)
+    sp = inputs.bidisperse_species(N)
+    rep = dict(N=N, L=np.array([L, L, 0.0]), u=u, species=sp)
+    ctx = md.Context()
+    bt = md.Batch([rep])
+    u0 = bt.pos.clone()
+    d = torch.tensor([1.0, 1.4], dtype=torch.float64, requires_grad=True)
+    E = minimized_energy(d, torch.tensor(1.0, dtype=torch.float64), bt, u0, f_tol=1e-7, md_ctx=ctx)
+    E.sum().backward()
+    grad = d.grad.numpy()
+    x_star = orc.decode(bt.replica_positions(0), [L, L])
+    g_orc = orc.diameter_grad(x_star, [L, L], np.array([1.0, 1.4]), 1.0, sp)
+    x0 = orc.decode(u, [L, L])
+    h = 1e-4
+    fd = []
+    for s in range(2):
+        vals = []
+        for sgn in (1, -1):
+            dd = np.array([1.0, 1.4])
+            dd[s] += sgn * h
+            r = orc.fire(x0, [L, L], orc_pot(orc, dd), sp, f_tol=1e-11, max_steps=200000)
+            assert r["converged"]
+            vals.append(orc.energy(r["x"], [L, L], orc_pot(orc, dd), sp))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    say("adjoint", grad, "oracle grad", g_orc, "oracle fd", fd)
+    assert np.allclose(grad, g_orc, rtol=1e-5, atol=1e-9)
+    assert np.allclose(grad, fd, rtol=1e-3, atol=1e-8)
 
 
 def test_batch_of_uneven_sizes_full_range(md):

@@ -1,4 +1,9 @@
-"""Neural pair potential kernels (descriptors, BF16-MFMA MLP, forces) against the FP64 oracle."""
+"""Neural pair potential kernels (descriptors, BF16-MFMA MLP, forces, training pass) against the FP64 oracle.
+
+The MLP's weights are BF16 (the model's own values; the oracle uses the same values, upcast exactly) and its
+activations enter the MFMA products as BF16 pairs (value + remainder), so inference matches the oracle to
+~1e-5; the weight-gradient products take plain BF16 operands, so the gradient matches to ~1e-2.
+"""
 import sys
 
 import numpy as np
@@ -58,7 +63,7 @@ def test_descriptors_match_oracle(md):
     assert rel_l2(G, Go) < 1e-5
 
 
-def test_mlp_matches_oracle_at_bf16_tolerance(md):
+def test_mlp_matches_oracle(md):
     from oracle import nn_oracle
     import oracle as orc
     s, nn, Q, spec, x, L = setup(md, nn_oracle, orc)
@@ -66,8 +71,8 @@ def test_mlp_matches_oracle_at_bf16_tolerance(md):
     Ei, e = md.nn_mlp(s.ctx, nn, G)
     Eo, eo, _ = nn_oracle.mlp(G.cpu().numpy().astype(np.float64), Q, spec)
     say("Ei rel-L2", rel_l2(Ei.cpu().numpy(), Eo), "e rel-L2", rel_l2(e.cpu().numpy(), eo))
-    assert rel_l2(Ei.cpu().numpy(), Eo) < 1e-2
-    assert rel_l2(e.cpu().numpy(), eo) < 2e-2
+    assert rel_l2(Ei.cpu().numpy(), Eo) < 1e-4
+    assert rel_l2(e.cpu().numpy(), eo) < 1e-4
     # a partial last tile: N not a multiple of 32
     Ei2, e2 = md.nn_mlp(s.ctx, nn, G[:1001].contiguous())
     assert np.array_equal(Ei2.cpu().numpy(), Ei.cpu().numpy()[:1001])
@@ -84,6 +89,92 @@ def test_forces_match_oracle(md):
     md.nn_forces(s.ctx, s.box, nn, s.pos, s.nl, e, F)
     Eo, _, Fo, _, _ = nn_oracle.energy_forces(x, L, Q, spec)
     say("F rel-L2", rel_l2(F.cpu().numpy(), Fo), "E", float(Ei.double().sum()), Eo)
-    assert rel_l2(F.cpu().numpy(), Fo) < 1e-2
-    assert abs(float(Ei.double().sum()) - Eo) / abs(Eo) < 1e-2
+    assert rel_l2(F.cpu().numpy(), Fo) < 1e-4
+    assert abs(float(Ei.double().sum()) - Eo) / abs(Eo) < 1e-4
     assert np.abs(F.cpu().numpy().astype(np.float64).sum(0)).max() < 1e-3 * np.abs(Fo).max()
+
+
+def train_setup(md, S=3, n=400, seed=21):
+    """S independent LJ-like configurations of n atoms as one segmented system, a network with nonzero biases,
+    and arbitrary reference energies / forces (the gradient check does not need physical references)."""
+    import torch
+    from paper_1912_04232_amd import nn as nnmod
+    import oracle as orc
+    from oracle import nn_oracle
+    L = inputs.box_for_density(n, 0.84)
+    us = [inputs.random_insertion_torus(n, L, 3, 0.85, seed + k) for k in range(S)]
+    xs = [orc.decode(u, [L] * 3) for u in us]
+    spec = nn_oracle.NNSpec()
+    G0 = np.concatenate([nn_oracle.descriptors(x, [L] * 3, spec)[0] for x in xs])
+    w = inputs.nn_init(7)
+    rng = np.random.default_rng(seed)
+    w["b1"], w["b2"], w["b3"] = rng.normal(0, 0.3, 64), rng.normal(0, 0.3, 64), 0.4
+    ctx = md.Context()
+    net = nnmod.Network(ctx, w, G0.mean(0), G0.std(0) + 1e-3)
+    box = md.Box((L, L, L), 3)
+    pos = torch.as_tensor(np.concatenate(us).view(np.int32), device="cuda").contiguous()
+    E_ref = torch.as_tensor(rng.normal(-5.0 * n, 30.0, S), dtype=torch.float64, device="cuda")
+    F_ref = torch.as_tensor(rng.normal(0, 3.0, (S * n, 3)).astype(np.float32), device="cuda")
+    batch = nnmod.Batch(ctx, box, net, pos, E_ref, F_ref, n, 2.5)
+    h = net.host()
+    Q = nn_oracle.NNParams(W1=h["W1"], b1=h["b1"], W2=h["W2"], b2=h["b2"], w3=h["w3"], b3=h["b3"], m=h["m"],
+                           s=h["s"])
+    snaps = [(xs[k], [L] * 3, float(E_ref[k]), F_ref[k * n:(k + 1) * n].cpu().numpy().astype(np.float64))
+             for k in range(S)]
+    return ctx, box, net, batch, Q, spec, snaps, xs, [L] * 3, nnmod
+
+
+def test_loss_and_pair_adjoint_match_oracle(md):
+    ctx, box, net, batch, Q, spec, snaps, xs, L, nnmod = train_setup(md)
+    from oracle import nn_oracle
+    Ei, e = nnmod.mlp(ctx, net, batch.G)
+    F = nnmod.forces(ctx, box, net, batch.pos, batch.nl, e)
+    loss, gE, lam = nnmod.loss(ctx, Ei, F, batch.E_ref, batch.F_ref, batch.n)
+    lo, _ = nn_oracle.loss_and_grad(snaps, Q, spec)
+    say("loss", float(loss), lo)
+    assert abs(float(loss) - lo) / lo < 1e-4
+    # the pair adjoint of the GPU's own lam against the oracle's adjoint of the same lam
+    ebar = nnmod.pair_adjoint(ctx, box, net, batch.pos, batch.nl, lam).cpu().numpy()
+    lam_h = lam.cpu().numpy().astype(np.float64)
+    n = batch.n
+    want = np.concatenate([nn_oracle.pair_adjoint(xs[k], L, spec, lam_h[k * n:(k + 1) * n]) for k in range(len(xs))])
+    say("ebar rel-L2", rel_l2(ebar, want))
+    assert rel_l2(ebar, want) < 1e-5
+
+
+def test_weight_gradient_matches_oracle(md):
+    """The full training gradient (energy and force terms, through the pair adjoint and the network's tangent)
+    against the oracle's analytic gradient, parameter group by parameter group."""
+    ctx, box, net, batch, Q, spec, snaps, xs, L, nnmod = train_setup(md)
+    from oracle import nn_oracle
+    Ei, e = nnmod.mlp(ctx, net, batch.G)
+    F = nnmod.forces(ctx, box, net, batch.pos, batch.nl, e)
+    loss, gE, lam = nnmod.loss(ctx, Ei, F, batch.E_ref, batch.F_ref, batch.n)
+    ebar = nnmod.pair_adjoint(ctx, box, net, batch.pos, batch.nl, lam)
+    grad = nnmod.mlp_grad(ctx, net, batch.G, batch.n, gE, ebar).cpu().numpy().astype(np.float64)
+    _, go = nn_oracle.loss_and_grad(snaps, Q, spec)
+    K, H = 16, 64
+    parts = dict(W1=grad[:H * K].reshape(H, K), b1=grad[H * K:H * K + H],
+                 W2=grad[H * K + H:H * K + H + H * H].reshape(H, H), b2=grad[H * K + H + H * H:H * K + 2 * H + H * H],
+                 w3=grad[H * K + 2 * H + H * H:H * K + 3 * H + H * H], b3=grad[-1:])
+    for k, v in parts.items():
+        r = rel_l2(v, np.atleast_1d(go[k]))
+        say("grad", k, r)
+        assert r < 2e-2, (k, r)
+
+
+def test_adam_step_and_bf16_copies(md):
+    """One Adam step from zero moments moves every parameter with a nonzero gradient by lr (bias-corrected), and
+    the BF16 copies are the master weights rounded to nearest even."""
+    import torch
+    ctx, box, net, batch, Q, spec, snaps, xs, L, nnmod = train_setup(md, S=1)
+    th0 = net.theta.clone()
+    g = torch.linspace(-1.0, 1.0, net.P, device="cuda")
+    net.adam(ctx, g, 1e-3)
+    step = (net.theta - th0).cpu().numpy()
+    gg = g.cpu().numpy()
+    nz = np.abs(gg) > 1e-3
+    assert np.allclose(step[nz], -1e-3 * np.sign(gg[nz]), rtol=1e-3, atol=1e-9)
+    w1 = net.theta[:16 * 64].cpu().numpy()
+    want = torch.as_tensor(w1).to(torch.bfloat16).view(torch.int16).numpy()
+    assert np.array_equal(net.W1.cpu().numpy(), want)

@@ -128,3 +128,19 @@ def test_loss_gradients_match_fd(nn):
             fd = (vals[0] - vals[1]) / (2 * h)
             an = float(np.atleast_1d(g[name]).reshape(-1)[q])
             assert abs(fd - an) <= 1e-5 * max(abs(fd), 1e-3), (name, q, fd, an)
+
+
+def test_pair_adjoint_is_transpose_of_force_map(nn):
+    """At fixed positions F is linear in e; the pair adjoint must satisfy <lam, F(e)> = <ebar(lam), e> for any
+    lam and e, and forces_from_e at e = dE_i/dG_i must equal the oracle's energy_forces forces."""
+    spec = nn.NNSpec()
+    x, L = config()
+    rng = np.random.default_rng(11)
+    e = rng.normal(size=(x.shape[0], spec.K))
+    lam = rng.normal(size=(x.shape[0], 3))
+    lhs = float(np.sum(lam * nn.forces_from_e(x, L, spec, e)))
+    rhs = float(np.sum(nn.pair_adjoint(x, L, spec, lam) * e))
+    assert math.isclose(lhs, rhs, rel_tol=1e-12, abs_tol=1e-12)
+    P = params(nn, spec)
+    _, _, F, ee, _ = nn.energy_forces(x, L, P, spec)
+    assert np.allclose(nn.forces_from_e(x, L, spec, ee), F, rtol=1e-12, atol=1e-12)
