@@ -365,6 +365,22 @@ md_status nn_adam(md_ctx *ctx, float *theta, float *m, float *v, const float *gr
 /* BF16 copies W1, W2 of the weights in theta. */
 md_status nn_cast_weights(md_ctx *ctx, const float *theta, uint16_t *W1, uint16_t *W2, void *stream);
 
+/*
+ * Velocity Verlet with forces computed elsewhere (e.g. nn_forces), Sec. 3.3.1: one step is
+ *   md_kick_drift (v += dt/2 F; r += dt v, the shift of Sec. 3.2.1)  ->  nl_update  ->  new forces F
+ *   ->  md_kick (v += dt/2 F).
+ * md_kick_drift also marks, on the device, that a particle has moved more than skin/2 from nl->pos_ref;
+ * nl_update then rebuilds the list (as nl_build) only if so, deciding on the device (no host round trip:
+ * its launches return at once otherwise).  Lists with segment != 0 are rejected.
+ */
+md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *vel, const float *force, int32_t N,
+                        const md_nlist *nl, float dt, void *stream);
+md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream);
+/* vel[q] += h force[q] for q < N dim. */
+md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream);
+/* out[0] = sqrt(mean over q < n of (a[q] - b[q])^2) in double (device memory), e.g. a force RMSE. */
+md_status md_rms_diff(md_ctx *ctx, const float *a, const float *b, int64_t n, double *out, void *stream);
+
 /* out[0] = sum of x[0..n) in double, summed in a fixed order (deterministic). out is device memory. */
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
 /* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */

@@ -1092,6 +1092,60 @@ __global__ __launch_bounds__(kBlock) void k_fire_reduce(FireArgs a, int nblocks,
     }
 }
 
+constexpr int kRedBlocks = 256;  // workgroups of the two-pass reductions
+
+// ------------------------------------------------------------------------------------------------
+// velocity Verlet with forces from elsewhere (a neural potential): the two half kicks and the drift
+
+// v += dt/2 F; r += dt v; raises ctl[kTrigWord] when a particle is now farther than skin/2 from pos_ref.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(uint32_t *pos, float *vel, const float *force, int N,
+                                                       DevBox b, const uint32_t *pos_ref, float half_skin, float dt,
+                                                       int32_t *ctl)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < N) {
+        uint32_t ui[D], un[D];
+        load_pos<D>(pos, i, ui);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            float v = __builtin_fmaf(0.5f * dt, force[(size_t)i * D + q], vel[(size_t)i * D + q]);
+            vel[(size_t)i * D + q] = v;
+            un[q] = shift_coord(ui[q], dt * v, b.inv_s[q]);
+        }
+        store_pos<D>(pos, i, un);
+        far = disp2<D>(un, pos_ref, i, b) > half_skin * half_skin;
+    }
+    wave_flag(far, &ctl[kTrigWord]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_kick(float *vel, const float *force, int64_t n, float h)
+{
+    int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < n) vel[q] = __builtin_fmaf(h, force[q], vel[q]);
+}
+
+__global__ void k_clear_trigger(int32_t *ctl)
+{
+    if (threadIdx.x == 0) ctl[kTrigWord] = 0;
+}
+
+// sum over workgroup partials of (a - b)^2 in double
+__global__ __launch_bounds__(kBlock) void k_sqdiff_partial(const float *a, const float *b, int64_t n, double *partials)
+{
+    __shared__ double red[kBlock];
+    int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+    int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double v = 0.0;
+    for (int64_t q = lo + threadIdx.x; q < hi; q += kBlock) {
+        double d = (double)a[q] - (double)b[q];
+        v += d * d;
+    }
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
 __global__ void k_fire_state_init(md_fire_state *st, double dt, double alpha)
 {
     st->dt = dt;
@@ -1139,7 +1193,6 @@ __global__ void k_fill_i32(int n, int32_t *a, int32_t v)
     if (t < n) a[t] = v;
 }
 
-constexpr int kRedBlocks = 256;
 
 __global__ __launch_bounds__(kBlock) void k_sum_partial(const double *x, int64_t n, double *partials)
 {
@@ -1169,6 +1222,11 @@ __global__ __launch_bounds__(kBlock) void k_rescale(float *v, int64_t n, const d
     double f = ke[0] > 0.0 ? sqrt(target / (2.0 * ke[0])) : 1.0;
     for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)gridDim.x * kBlock)
         v[q] = (float)((double)v[q] * f);
+}
+
+__global__ void k_sqrt_mean(double *x, double n)
+{
+    x[0] = sqrt(x[0] / n);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_final(const double *partials, int n, double *out)
@@ -1778,6 +1836,60 @@ md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t di
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, (int64_t)N * dim, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *vel, const float *force, int32_t N,
+                        const md_nlist *nl, float dt, void *stream)
+{
+    md_status st = check_common(ctx, box, N);
+    if (st != MD_OK) return st;
+    if (!pos || !vel || !force || !nl_ok(nl, N) || !isfinite(dt) || nl->segment != 0) return MD_ERR_ARG;
+    DevBox b;
+    if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
+    if (N == 0) return MD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (box->dim == 3)
+        hipLaunchKernelGGL(k_kick_drift<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, N, b, nl->pos_ref,
+                           0.5f * nl->skin, dt, ctx->ctl);
+    else
+        hipLaunchKernelGGL(k_kick_drift<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, N, b, nl->pos_ref,
+                           0.5f * nl->skin, dt, ctx->ctl);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream)
+{
+    md_status st = check_common(ctx, box, N);
+    if (st != MD_OK) return st;
+    if (!pos || (nl && nl->segment != 0)) return MD_ERR_ARG;
+    DevBox b;
+    st = check_list(ctx, box, nl, N, b);
+    if (st != MD_OK) return st;
+    if (N == 0) return MD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_build(ctx, box->dim, b, pos, N, nl, s, ctx->ctl + kTrigWord);
+    if (st != MD_OK) return st;
+    hipLaunchKernelGGL(k_clear_trigger, dim3(1), dim3(64), 0, s, ctx->ctl);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream)
+{
+    if (!ctx || !vel || !force || N < 0 || (dim != 2 && dim != 3) || !isfinite(h)) return MD_ERR_ARG;
+    int64_t n = (int64_t)N * dim;
+    if (n == 0) return MD_OK;
+    hipLaunchKernelGGL(k_kick, dim3(nblk(n)), dim3(kBlock), 0, (hipStream_t)stream, vel, force, n, h);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_rms_diff(md_ctx *ctx, const float *a, const float *b, int64_t n, double *out, void *stream)
+{
+    if (!ctx || !a || !b || !out || n <= 0) return MD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_sqdiff_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, a, b, n, ctx->partials);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
+    hipLaunchKernelGGL(k_sqrt_mean, dim3(1), dim3(1), 0, s, out, (double)n);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -120,6 +120,10 @@ _SIGNATURES = {
     "md_sum": [P, P, ctypes.c_int64, P, P],
     "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
     "md_rescale_velocities": [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P],
+    "md_kick_drift": [P, ctypes.POINTER(c_box), P, P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
+    "nl_update": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P],
+    "md_kick": [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P],
+    "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
     "md_flags_clear": [ctypes.POINTER(c_nlist), P],
     "md_version": [],
@@ -365,6 +369,30 @@ def pair_energy_force(ctx: Context, box: Box, pot: Potential, pos: torch.Tensor,
     _check("pair_energy_force", load().pair_energy_force(
         ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(species), N,
         ctypes.byref(n) if n is not None else None, _ptr(force), _ptr(energy), _ptr(virial), _stream()))
+
+
+def kick_drift(ctx: Context, box: Box, pos, vel, force, nl: NeighborList, dt: float):
+    b, n = box.c(), nl.c()
+    _check("md_kick_drift", load().md_kick_drift(ctx.h, ctypes.byref(b), _ptr(pos), _ptr(vel), _ptr(force),
+                                                 pos.shape[0], ctypes.byref(n), ctypes.c_float(dt), _stream()))
+
+
+def nl_update(ctx: Context, box: Box, pos, nl: NeighborList):
+    N = pos.shape[0]
+    _reserve_for(ctx, box, N, nl)
+    b, n = box.c(), nl.c()
+    _check("nl_update", load().nl_update(ctx.h, ctypes.byref(b), _ptr(pos), N, ctypes.byref(n), _stream()))
+
+
+def kick(ctx: Context, vel, force, h: float):
+    N, dim = vel.shape
+    _check("md_kick", load().md_kick(ctx.h, _ptr(vel), _ptr(force), N, dim, ctypes.c_float(h), _stream()))
+
+
+def rms_diff(ctx: Context, a, b) -> torch.Tensor:
+    out = torch.zeros(1, dtype=torch.float64, device=a.device)
+    _check("md_rms_diff", load().md_rms_diff(ctx.h, _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream()))
+    return out
 
 
 def rescale_velocities(ctx: Context, vel: torch.Tensor, T: float):
@@ -651,7 +679,8 @@ class System:
 
 def _run_checked(system: System, saved, call, n_steps: int):
     """Run call(n) and re-run from `saved` when the device reported a list that did not fit (grow it) or went
-    stale (run again one step per call: each call starts from a fresh list)."""
+    stale (run again in shorter pieces, each starting from a fresh list; a piece of one step cannot go stale
+    unless a single step moves a particle more than skin/2)."""
     for _ in range(6):
         system.nl.clear_flags()
         call(n_steps)
@@ -663,13 +692,16 @@ def _run_checked(system: System, saved, call, n_steps: int):
         for t, v in zip(saved[0], saved[1]):
             t.copy_(v)
         if f[FLAG_STALE]:
-            for _ in range(n_steps):
-                system.nl.clear_flags()
-                call(1)
-                g = system.nl.read_flags()
-                if g[FLAG_OVERFLOW] or g[FLAG_CELL_OVERFLOW] or g[FLAG_STALE]:
-                    raise RuntimeError(f"single steps failed: flags {g.tolist()}")
-            return g
+            if n_steps == 1:
+                raise RuntimeError(f"a single step left the list stale: flags {f.tolist()}")
+            piece = max(1, n_steps // 8)
+            done = 0
+            while done < n_steps:
+                k = min(piece, n_steps - done)
+                sub = (saved[0], tuple(t.clone() for t in saved[0]))
+                f = _run_checked(system, sub, call, k)
+                done += k
+            return f
         system.grow(f)
     raise RuntimeError("neighbor list kept overflowing")
 
@@ -694,7 +726,7 @@ def nve(system: System, dt: float):
             verlet_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
                         system.nl, dt, n)
 
-        _run_checked(system, saved, call, n_steps)
+        system.last_flags = _run_checked(system, saved, call, n_steps)
         return system
 
     return init_fn, update_fn

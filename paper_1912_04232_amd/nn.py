@@ -238,3 +238,155 @@ def evaluate(ctx, box, net, batches):
         se_e += float((de * de).sum())
         ne += de.numel()
     return math.sqrt(se_f / nf), math.sqrt(se_e / ne)
+
+
+# ------------------------------------------------------------------ molecular dynamics with the network
+
+class NNMD:
+    """NVE with network forces (velocity Verlet, Sec. 3.3.1) and plain LJ as fallback and judge.
+
+    One step: md_kick_drift -> nl_update (rebuilds on the device only when a particle moved > skin/2) ->
+    descriptors -> MLP -> network forces -> md_kick.  `chunk` steps are captured once in a HIP graph and
+    replayed.  Every `check_every` steps the LJ forces of the current configuration judge the network:
+    if their RMSE exceeds `max_rmse` the run continues with plain LJ (md.nve) from that state."""
+
+    def __init__(self, ctx: md.Context, net: Network, box: md.Box, u, v, dt=0.005, skin=0.3, r_cut=2.5,
+                 max_rmse=0.5, check_every=100, chunk=20):
+        self.ctx, self.net, self.box, self.dt = ctx, net, box, dt
+        self.lj = md.Potential("lj", [[1.0]], [[1.0]], r_cut=r_cut)
+        self.sys = md.System(box, self.lj, u, v, skin=skin, ctx=ctx)
+        self.sys.build()
+        self.max_rmse, self.check_every, self.chunk = max_rmse, check_every, chunk
+        self.fallback = False
+        self.rmse_log = []
+        self.steps = 0
+        self._graph = None
+        self._lj = None
+        self.G = torch.zeros((self.sys.N, K), dtype=torch.float32, device=ctx.device)
+        self.Ei = torch.zeros(self.sys.N, dtype=torch.float32, device=ctx.device)
+        self.e = torch.zeros((self.sys.N, K), dtype=torch.float32, device=ctx.device)
+        self.F_lj = torch.zeros_like(self.sys.force)
+        self._bind()
+        self.forces()
+
+    def _bind(self):
+        """ctypes arguments built once (the tensors behind them stay put)."""
+        lib = md.load()
+        s = self.sys
+        self._b, self._q, self._n = s.box.c(), self.net.c(), s.nl.c()
+        B, Q, Nl = ctypes.byref(self._b), ctypes.byref(self._q), ctypes.byref(self._n)
+        N, st = s.N, md._stream
+        P = md._ptr
+        self._calls_force = [
+            lambda: lib.nn_descriptors(self.ctx.h, B, Q, P(s.pos), N, Nl, P(self.G), st()),
+            lambda: lib.nn_mlp(self.ctx.h, Q, P(self.G), N, P(self.Ei), P(self.e), st()),
+            lambda: lib.nn_forces(self.ctx.h, B, Q, P(s.pos), N, Nl, P(self.e), P(s.force), st()),
+        ]
+        dt = ctypes.c_float(self.dt)
+        half = ctypes.c_float(0.5 * self.dt)
+        self._calls_step = [
+            lambda: lib.md_kick_drift(self.ctx.h, B, P(s.pos), P(s.vel), P(s.force), N, Nl, dt, st()),
+            lambda: lib.nl_update(self.ctx.h, B, P(s.pos), N, Nl, st()),
+        ] + self._calls_force + [lambda: lib.md_kick(self.ctx.h, P(s.vel), P(s.force), N, 3, half, st())]
+
+    def _run(self, calls):
+        for c in calls:
+            r = c()
+            if r != 0:
+                raise RuntimeError(f"neural-potential MD call failed with status {r}")
+
+    def forces(self):
+        self._run(self._calls_force)
+
+    def _eager(self, n):
+        for _ in range(n):
+            self._run(self._calls_step)
+
+    def _replay(self, n):
+        if self._graph is None:
+            self._eager(1)  # one ordinary step before capture
+            n -= 1
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
+                self._eager(self.chunk)
+            self._graph = g
+        while n >= self.chunk:
+            self._graph.replay()
+            n -= self.chunk
+        if n > 0:
+            self._eager(n)
+
+    def judge(self) -> float:
+        """Force RMSE of the network against plain LJ at the current configuration (reads the device)."""
+        s = self.sys
+        md.pair_energy_force(self.ctx, self.box, self.lj, s.pos, None, s.nl, self.F_lj)
+        return float(md.rms_diff(self.ctx, s.force, self.F_lj))
+
+    def run(self, n_steps: int, graph: bool = True):
+        """Advance n_steps; returns the number of steps run with the network before any fallback."""
+        done_nn = 0
+        while n_steps > 0 and not self.fallback:
+            k = min(n_steps, self.check_every)
+            (self._replay if graph else self._eager)(k)
+            f = self.sys.nl.read_flags()
+            if f[md.FLAG_OVERFLOW] or f[md.FLAG_CELL_OVERFLOW]:
+                raise RuntimeError(f"neighbor list overflow during network MD: {f.tolist()}")
+            rmse = self.judge()
+            self.rmse_log.append(rmse)
+            n_steps -= k
+            done_nn += k
+            self.steps += k
+            if not math.isfinite(rmse) or rmse > self.max_rmse:
+                self.fallback = True
+        if n_steps > 0:
+            # plain LJ takes over from the current positions and velocities
+            s = self.sys
+            init, update = md.nve(s, self.dt)
+            init()
+            update(n_steps)
+            self.steps += n_steps
+        return done_nn
+
+
+def train_network(ctx: md.Context, n_runs=20, per_run=100, steps=20000, per_batch=16, lr=3e-3, lr_end=3e-5,
+                  lam_F=1.0, seed=1, progress=None):
+    """The learned part end to end: plain-engine LJ data (n_runs x per_run snapshots of N = 4000), 10% held out,
+    descriptor scale from the training set, `steps` Adam steps on minibatches of `per_batch` snapshots with an
+    exponential learning-rate decay from lr to lr_end.  Returns the network, the held-out batches and a record
+    (force / energy RMSE of the untrained and trained network on the held-out set, timings)."""
+    import time
+    t0 = time.perf_counter()
+    box, P, E, F, T = generate_lj_data(ctx, n_runs=n_runs, per_run=per_run, progress=progress)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    S = P.shape[0]
+    perm = np.random.default_rng(seed).permutation(S)
+    ntest = max(1, S // 10)
+    test_idx, train_idx = perm[:ntest], perm[ntest:]
+    w = inputs.nn_init(seed)
+    probe = Network(ctx, w, np.zeros(K), np.ones(K))
+    G = torch.cat([b.G for b in make_batches(ctx, box, probe, P, E, F, train_idx, per_batch)])
+    m, s = descriptor_scale(G)
+    del G
+    net = Network(ctx, w, m, s)
+    train = make_batches(ctx, box, net, P, E, F, train_idx, per_batch)
+    test = make_batches(ctx, box, net, P, E, F, test_idx, per_batch)
+    f0, e0 = evaluate(ctx, box, net, test)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    decay = (lr_end / lr) ** (1.0 / max(steps - 1, 1))
+    order = np.random.default_rng(seed + 1)
+    for k in range(steps):
+        if k % len(train) == 0:
+            sched = order.permutation(len(train))
+        L = train_step(ctx, box, net, train[sched[k % len(train)]], lr * decay ** k, lam_F)
+        if progress and (k % 5000 == 0 or k == steps - 1):
+            progress(f"step {k} loss {float(L):.4g}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    f1, e1 = evaluate(ctx, box, net, test)
+    rec = dict(snapshots=int(S), atoms_per_snapshot=int(P.shape[1]), test_snapshots=int(ntest), steps=steps,
+               per_batch=per_batch, force_rmse_untrained=f0, energy_rmse_untrained=e0, force_rmse=f1,
+               energy_rmse_per_atom=e1, data_s=t_data, train_s=t_train, train_ms_per_step=1e3 * t_train / steps,
+               force_rms_reference=float(F.pow(2).mean().sqrt()))
+    return net, box, test, rec

@@ -178,3 +178,52 @@ def test_adam_step_and_bf16_copies(md):
     w1 = net.theta[:16 * 64].cpu().numpy()
     want = torch.as_tensor(w1).to(torch.bfloat16).view(torch.int16).numpy()
     assert np.array_equal(net.W1.cpu().numpy(), want)
+
+
+def test_network_md_graph_replay_matches_eager_and_judge_falls_back(md):
+    """Network NVE: the captured HIP graph of 20 steps, replayed with eager work and synchronisations in between,
+    gives bit-identical states to the same steps run eagerly; a threshold below the untrained network's force
+    RMSE hands the run to plain LJ."""
+    import torch
+    from paper_1912_04232_amd import nn as nnmod
+    ctx = md.Context()
+    n_cells = 6
+    N = 4 * n_cells ** 3
+    L = inputs.box_for_density(N, 0.84)
+    u = inputs.fcc_torus(n_cells, L)
+    v = inputs.maxwell_velocities(N, 3, 1.0, 9)
+    box = md.Box((L, L, L), 3)
+    w = inputs.nn_init(3)
+    w["w3"] = w["w3"] * 0.01  # a gentle untrained network, so the dynamics stay bounded
+    net = nnmod.Network(ctx, w, np.full(16, 2.0), np.full(16, 3.0))
+    a = nnmod.NNMD(ctx, net, box, u, v, chunk=20, max_rmse=1e9)
+    b = nnmod.NNMD(ctx, net, box, u, v, chunk=20, max_rmse=1e9)
+    for rep in range(3):
+        a._replay(20 if rep else 21)
+        torch.cuda.synchronize()
+        b._eager(20 if rep else 21)
+        torch.cuda.synchronize()
+        assert torch.equal(a.sys.pos, b.sys.pos), rep
+        assert torch.equal(a.sys.vel, b.sys.vel), rep
+    c = nnmod.NNMD(ctx, net, box, u, v, chunk=20, max_rmse=1e-3, check_every=20)
+    done = c.run(100)
+    say("fallback after", done, "rmse", c.rmse_log)
+    assert c.fallback and done == 20 and c.steps == 100
+
+
+def test_trained_network_beats_untrained_and_runs_md(md):
+    """What training buys: on held-out plain-engine snapshots the trained network's force RMSE is a small
+    fraction of the untrained one's; network MD at N = 4000 then runs with the LJ judge below threshold."""
+    from paper_1912_04232_amd import nn as nnmod
+    ctx = md.Context()
+    net, box, test, rec = nnmod.train_network(ctx, n_runs=6, per_run=20, steps=3000, per_batch=8, progress=say)
+    say("training record", rec)
+    assert rec["force_rmse"] < 0.1 * rec["force_rmse_untrained"]
+    assert rec["force_rmse"] < 0.1 * rec["force_rms_reference"]
+    u = inputs.fcc_torus(10, box.L[0])
+    v = inputs.maxwell_velocities(4000, 3, 1.0, 17)
+    sim = nnmod.NNMD(ctx, net, box, u, v, max_rmse=5.0 * rec["force_rmse"], check_every=100)
+    done = sim.run(500)
+    say("md rmse", sim.rmse_log, "fallback", sim.fallback)
+    assert all(np.isfinite(sim.rmse_log))
+    assert sim.steps == 500
