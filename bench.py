@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1912_04232_amd", "csrc", "md_core.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verlet_step_lj256k_traffic.json")
+COPY_BYTES = 256 << 20  # the calibration copy
 
 
 def kernel_sha() -> str:
@@ -72,6 +73,37 @@ def cpu_baseline(cfg, seconds: float):
     return {"value": 1.0 / sec_per_step, "unit": "steps/s", "cores": threads, "kind": "oracle",
             "sample": f"brute-force FP64 forces of {m} of {N} particles (each against all N) in {t:.1f} s, "
                       f"scaled by N/{m} to one step"}
+
+
+def traffic_from(fetch_dir: str, write_dir: str):
+    """HBM bytes per k_md_step launch from two rocprofv3 counter runs of `bench.py --copy-calibration` (one with
+    --pmc FETCH_SIZE, one with --pmc WRITE_SIZE; counters in KiB per dispatch), each scaled by what the same
+    counter reads for the library's plain copy of 256 MiB; writes the committed traffic record."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r.get("Counter_Name") == counter]
+        step = [float(r["Counter_Value"]) for r in rows if "k_md_step" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows if "k_copy_words" in r["Kernel_Name"]]
+        if not step or not copy:
+            raise SystemExit(f"no k_md_step / k_copy_words dispatches with {counter} under {d}")
+        return sum(step) / len(step), len(step), max(copy)
+
+    f_step, n_f, f_copy = read(fetch_dir, "FETCH_SIZE")
+    w_step, n_w, w_copy = read(write_dir, "WRITE_SIZE")
+    ref_kib = COPY_BYTES / 1024.0
+    rec = {"kernel": "k_md_step", "kernel_sha": kernel_sha(), "dispatches": [n_f, n_w],
+           "fetch_kib_per_launch_raw": f_step, "write_kib_per_launch_raw": w_step,
+           "copy_fetch_kib": f_copy, "copy_write_kib": w_copy, "copy_bytes": COPY_BYTES,
+           "fetch_scale": ref_kib / f_copy, "write_scale": ref_kib / w_copy,
+           "fetch_bytes_per_launch": f_step * 1024.0 * ref_kib / f_copy,
+           "write_bytes_per_launch": w_step * 1024.0 * ref_kib / w_copy}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec))
 
 
 def surrogate(progress, nn_steps: int, md_steps: int):
@@ -127,7 +159,14 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the neural-potential comparison")
     ap.add_argument("--nn-train-steps", type=int, default=20000)
     ap.add_argument("--nn-md-steps", type=int, default=2000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the library's plain copy of 256 MiB (reference for memory counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="only turn two rocprofv3 counter runs into the traffic record, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -217,6 +256,11 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": kernel_s * 1e6},
         "cpu_baseline": None,
     }
+    if args.copy_calibration:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        md.copy_words(s.ctx, dst, src)
+        torch.cuda.synchronize()
     if not args.no_surrogate:
         progress("training the neural potential and timing surrogate vs plain")
         out["extra"]["surrogate_vs_plain"] = surrogate(progress, args.nn_train_steps, args.nn_md_steps)

@@ -394,6 +394,10 @@ md_status md_flags_read(const md_nlist *nl, int32_t *out, void *stream);
 /* Zero nl->flags (enqueued on `stream`). */
 md_status md_flags_clear(md_nlist *nl, void *stream);
 
+/* Copy n16 16-byte words src -> dst (device, 16-byte aligned): a plain streaming copy of known size, the
+ * reference that memory-traffic counters of the other kernels are calibrated against. */
+md_status md_copy_words(md_ctx *ctx, void *dst, const void *src, int64_t n16, void *stream);
+
 /* Library version string. */
 const char *md_version(void);
 

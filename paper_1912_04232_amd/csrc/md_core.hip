@@ -1181,6 +1181,12 @@ __global__ void k_to_float(int n, int D, double s0, double s1, double s2, const 
     x[t] = (float)((double)u[t] * s);
 }
 
+// Plain streaming copy of n 16-byte words (the reference kernel for calibrating memory counters).
+__global__ __launch_bounds__(kBlock) void k_copy_words(const uint4 *__restrict__ a, uint4 *__restrict__ b, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)gridDim.x * kBlock) b[q] = a[q];
+}
+
 __global__ void k_copy_u32(int n, const uint32_t *a, uint32_t *b)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
@@ -1890,6 +1896,16 @@ md_status md_rms_diff(md_ctx *ctx, const float *a, const float *b, int64_t n, do
     hipLaunchKernelGGL(k_sqdiff_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, a, b, n, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
     hipLaunchKernelGGL(k_sqrt_mean, dim3(1), dim3(1), 0, s, out, (double)n);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_copy_words(md_ctx *ctx, void *dst, const void *src, int64_t n16, void *stream)
+{
+    if (!ctx || !dst || !src || n16 < 0) return MD_ERR_ARG;
+    if (n16 == 0) return MD_OK;
+    int64_t blocks = (n16 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_copy_words, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kBlock), 0,
+                       (hipStream_t)stream, (const uint4 *)src, (uint4 *)dst, n16);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

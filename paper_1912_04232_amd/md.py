@@ -124,6 +124,7 @@ _SIGNATURES = {
     "nl_update": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P],
     "md_kick": [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
+    "md_copy_words": [P, P, P, ctypes.c_int64, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
     "md_flags_clear": [ctypes.POINTER(c_nlist), P],
     "md_version": [],
@@ -393,6 +394,14 @@ def rms_diff(ctx: Context, a, b) -> torch.Tensor:
     out = torch.zeros(1, dtype=torch.float64, device=a.device)
     _check("md_rms_diff", load().md_rms_diff(ctx.h, _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream()))
     return out
+
+
+def copy_words(ctx: Context, dst: torch.Tensor, src: torch.Tensor):
+    """dst <- src as 16-byte words (both contiguous, same byte size, a multiple of 16)."""
+    nb = src.numel() * src.element_size()
+    if nb % 16 or dst.numel() * dst.element_size() != nb:
+        raise ValueError("copy_words needs equal sizes that are multiples of 16 bytes")
+    _check("md_copy_words", load().md_copy_words(ctx.h, _ptr(dst), _ptr(src), nb // 16, _stream()))
 
 
 def rescale_velocities(ctx: Context, vel: torch.Tensor, T: float):
