@@ -161,23 +161,62 @@ __global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, Dev
     cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: the totals do not depend on order
 }
 
-// Exclusive scan of cell_count into cell_start[0..C] by one workgroup (LDS, no atomics).
-__global__ __launch_bounds__(kBlock) void k_cs_scan(CountSort cs, int C, const int32_t *gate)
+constexpr int kScan = 1024;  // threads of the one-workgroup scan
+
+// Exclusive scan of cell_count into cell_start[0..C] by one workgroup (wave shuffles and LDS, no atomics);
+// also the bin counts min(count, M), the cell-overflow flag and the largest occupancy.
+__global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bins, int M, int32_t *flags,
+                                                   const int32_t *gate)
 {
-    __shared__ int lds[kBlock];
+    __shared__ int wsum[kScan / 64];
+    __shared__ int wmax[kScan / 64];
     if (gate_closed(gate)) return;
-    int t = threadIdx.x;
-    int chunk = (C + kBlock - 1) / kBlock;
+    int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int chunk = (C + kScan - 1) / kScan;
     int lo = min(C, t * chunk), hi = min(C, lo + chunk);
-    int local = 0;
-    for (int c = lo; c < hi; ++c) local += cs.cell_count[c];
-    int total;
-    int run = block_exclusive_scan(local, lds, total);
+    int local = 0, mx = 0;
+    for (int c = lo; c < hi; ++c) {
+        int v = cs.cell_count[c];
+        local += v;
+        mx = max(mx, v);
+    }
+    int incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o));
+    if (lane == 63) wsum[w] = incl;
+    if (lane == 0) wmax[w] = mx;
+    __syncthreads();
+    if (w == 0) {
+        int x = lane < kScan / 64 ? wsum[lane] : 0;
+        int xi = x;
+#pragma unroll
+        for (int o = 1; o < kScan / 64; o <<= 1) {
+            int v = __shfl_up(xi, o);
+            if (lane >= o) xi += v;
+        }
+        int m2 = lane < kScan / 64 ? wmax[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < kScan / 64; o <<= 1) m2 = max(m2, __shfl_xor(m2, o));
+        if (lane < kScan / 64) wsum[lane] = xi - x;
+        if (lane == 0) {
+            raise_max(&flags[MD_FLAG_MAXCELL], m2);
+            if (m2 > M) flags[MD_FLAG_CELL_OVERFLOW] = 1;
+        }
+    }
+    __syncthreads();
+    int run = incl - local + wsum[w];
     for (int c = lo; c < hi; ++c) {
         cs.cell_start[c] = run;
-        run += cs.cell_count[c];
+        int v = cs.cell_count[c];
+        bins.cnt[c] = min(v, M);
+        run += v;
     }
-    if (t == 0) cs.cell_start[C] = total;
+    if (t == kScan - 1) cs.cell_start[C] = run;
 }
 
 __global__ void k_cs_place(CountSort cs, int N, const int32_t *gate)
@@ -187,39 +226,24 @@ __global__ void k_cs_place(CountSort cs, int N, const int32_t *gate)
     if (i < N) cs.sorted_idx[cs.cell_start[cs.cell_of[i]] + cs.slot[i]] = i;
 }
 
-// One thread per cell: order the members by index and write them, with their positions, to the bin.
+// Bin records in index order without sorting: particle i's rank in its cell is the number of members with a
+// smaller index, which makes the bins (and so the rows built from them) deterministic.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_cs_fill_bins(const uint32_t *__restrict__ pos, CountSort cs, Bins bins,
-                                                         int C, int M, int32_t *flags, const int32_t *gate)
+__global__ __launch_bounds__(kBlock) void k_cs_rank_fill(const uint32_t *__restrict__ pos, int N, CountSort cs,
+                                                         Bins bins, int M, const int32_t *gate)
 {
-    __shared__ int red[kBlock];
     if (gate_closed(gate)) return;
-    int c = blockIdx.x * kBlock + threadIdx.x;
-    int occ = 0;
-    if (c < C) {
-        int s = cs.cell_start[c], e = cs.cell_start[c + 1];
-        for (int a = s + 1; a < e; ++a) {
-            int key = cs.sorted_idx[a];
-            int q = a - 1;
-            while (q >= s && cs.sorted_idx[q] > key) {
-                cs.sorted_idx[q + 1] = cs.sorted_idx[q];
-                --q;
-            }
-            cs.sorted_idx[q + 1] = key;
-        }
-        occ = e - s;
-        int n = min(occ, M);
-        bins.cnt[c] = n;
-        for (int a = 0; a < n; ++a) {
-            int j = cs.sorted_idx[s + a];
-            uint32_t u[D];
-            load_pos<D>(pos, j, u);
-            store_rec<D>(bins.mem, (uint32_t)(c * M + a), u, j);
-        }
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    int c = cs.cell_of[i];
+    int s = cs.cell_start[c], e = cs.cell_start[c + 1];
+    int rank = 0;
+    for (int a = s; a < e; ++a) rank += cs.sorted_idx[a] < i ? 1 : 0;
+    if (rank < M) {
+        uint32_t u[D];
+        load_pos<D>(pos, i, u);
+        store_rec<D>(bins.mem, (uint32_t)(c * M + rank), u, i);
     }
-    wave_flag(occ > M, &flags[MD_FLAG_CELL_OVERFLOW]);
-    occ = block_max(occ, red);
-    if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCELL], occ);
 }
 
 // Stencil table of particle i at reference position ui: the stencil cells that can hold a neighbor, in
@@ -1461,18 +1485,16 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     hipLaunchKernelGGL(k_cs_zero, dim3(nblk(C)), dim3(kBlock), 0, s, cs.cell_count, C, gate);
     if (dim == 3) {
         hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, C, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_fill_bins<3>, dim3(nblk(C)), dim3(kBlock), 0, s, pos, cs, bins, C, lp.M,
-                           nl->flags, gate);
+        hipLaunchKernelGGL(k_cs_rank_fill<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, gate);
         MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
                                           lp, g, nl->flags, gate));
     } else {
         hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kBlock), 0, s, cs, C, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_fill_bins<2>, dim3(nblk(C)), dim3(kBlock), 0, s, pos, cs, bins, C, lp.M,
-                           nl->flags, gate);
+        hipLaunchKernelGGL(k_cs_rank_fill<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, gate);
         MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
                                           lp, g, nl->flags, gate));
     }

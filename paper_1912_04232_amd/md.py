@@ -764,10 +764,38 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         _run_checked(system, saved, call, n_steps)
         return fire_state_read(state)
 
-    def minimize(max_steps: int = 100000, chunk: int = 200):
+    graphs = {}
+
+    def minimize(max_steps: int = 100000, chunk: int = 200, graph: bool = False):
+        """Run FIRE until converged or max_steps.  With graph=True the launches of `chunk` steps are captured
+        once in a HIP graph and replayed (a step's launches are all device-gated, so replays need no host
+        decisions); the flags are read after every chunk and a chunk that reports a problem is re-run eagerly
+        from its saved state."""
         st = fire_state_read(state)
         while not st["converged"] and st["steps"] < max_steps:
-            st = step_fn(min(chunk, max_steps - st["steps"]))
+            k = min(chunk, max_steps - st["steps"])
+            if not graph or k != chunk:
+                st = step_fn(k)
+                continue
+            tensors = (system.pos, system.vel, system.force, state)
+            saved = tuple(t.clone() for t in tensors)
+            g = graphs.get(chunk)
+            if g is None:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
+                    fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force,
+                              system.species, system.nl, fp, state, chunk, f_tol)
+                graphs[chunk] = g
+            system.nl.clear_flags()
+            g.replay()
+            f = system.nl.read_flags()
+            if f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW] or f[FLAG_STALE] or f[FLAG_NONFINITE]:
+                for t, v in zip(tensors, saved):
+                    t.copy_(v)
+                graphs.clear()  # the list may be regrown (new buffers): capture again afterwards
+                st = step_fn(chunk)
+                continue
+            st = fire_state_read(state)
         return st
 
     return init_fn, step_fn, minimize
