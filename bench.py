@@ -106,6 +106,89 @@ def traffic_from(fetch_dir: str, write_dir: str):
     print(json.dumps(rec))
 
 
+def secondary(progress):
+    """Per-config secondary numbers: the small LJ system (list and dense force evaluations), FIRE on 65536 soft
+    disks, and the 64-replica batched minimizer with its adjoint."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04232_amd import inputs, md
+    out = {}
+    ctx = md.Context()
+    # C1: 3D LJ N=1000, 100 NVE steps over the list; dense and list force evaluations
+    c = inputs.lj_small()
+    box = md.Box(tuple(c["L"]), 3)
+    pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=c["r_cut"])
+    s = md.System(box, pot, c["u"], c["v"], skin=c["skin"], ctx=ctx)
+    init, update = md.nve(s, c["dt"])
+    init()
+    update(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    update(c["steps"])
+    torch.cuda.synchronize()
+    t_nve = time.perf_counter() - t0
+    F = torch.zeros_like(s.force)
+    reps = 200
+    for nl in (s.nl, None):
+        md.pair_energy_force(ctx, box, pot, s.pos, None, nl, F)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        md.pair_energy_force(ctx, box, pot, s.pos, None, s.nl, F)
+    torch.cuda.synchronize()
+    t_nl = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        md.pair_energy_force(ctx, box, pot, s.pos, None, None, F)
+    torch.cuda.synchronize()
+    t_dense = (time.perf_counter() - t0) / reps
+    n_mean = float(s.nl.lengths().mean())
+    out["lj_small_N1000"] = {"nve_steps_per_s": c["steps"] / t_nve, "list_force_evals_per_s": 1.0 / t_nl,
+                             "dense_force_evals_per_s": 1.0 / t_dense,
+                             "list_pair_evals_per_s": n_mean * c["N"] / t_nl,
+                             "dense_pair_evals_per_s": c["N"] * (c["N"] - 1) / t_dense}
+    progress("small LJ done")
+    # C2: FIRE on 65536 bidisperse harmonic disks at phi 0.90
+    c = inputs.ss_fire()
+    box = md.Box(tuple(c["L"][:2]), 2)
+    pot = md.Potential("soft_sphere", c["sigma"], c["epsilon"], alpha=2.0)
+    s = md.System(box, pot, c["u"], None, c["species"], skin=c["skin"], ctx=ctx)
+    init, step, minimize = md.fire_descent(s, f_tol=1e-6)
+    init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = minimize(400000, chunk=500, graph=True)
+    torch.cuda.synchronize()
+    t_fire = time.perf_counter() - t0
+    out["fire_ss_N65536"] = {"converged": bool(st["converged"]), "steps": int(st["steps"]), "fmax": st["fmax"],
+                             "seconds": t_fire, "steps_per_s": st["steps"] / t_fire}
+    progress("FIRE done")
+    # C4: 64 packings of uneven N in one launch, then the adjoint at the minima
+    reps = inputs.ss_batch()
+    bt = md.Batch(reps)
+    d = np.array([1.0, 1.4])
+    spot = md.Potential("soft_sphere", 0.5 * (d[:, None] + d[None, :]), np.ones((2, 2)), alpha=2.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, fmax, steps, status = md.fire_batched(ctx, bt, spot, md.FireParams(), 400000, 1e-6)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    md.envelope_grad(ctx, bt, spot)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    steps = steps.cpu().numpy()
+    sizes = np.asarray(bt.sizes)
+    out["batched_fire_64"] = {"replicas": len(reps), "N_range": [int(sizes.min()), int(sizes.max())],
+                              "converged": int((status.cpu().numpy() == 1).sum()), "seconds": t_b,
+                              "max_steps": int(steps.max()),
+                              "particle_steps_per_s": float((steps * sizes).sum()) / t_b,
+                              "adjoint_seconds": t_g}
+    progress("batched FIRE done")
+    return out
+
+
 def surrogate(progress, nn_steps: int, md_steps: int):
     """The learned part against the plain method on the same GPU: a network trained on plain-engine LJ data
     (2000 snapshots of N = 4000 over T in [0.5, 1.5]), then NVE at N = 65536 with network forces (a HIP graph
@@ -157,6 +240,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the neural-potential comparison")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the small LJ / FIRE / batched numbers")
     ap.add_argument("--nn-train-steps", type=int, default=20000)
     ap.add_argument("--nn-md-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -190,6 +274,12 @@ def main():
     s = md.System(box, pot, cfg["u"], cfg["v"], skin=cfg["skin"], lanes=args.lanes)
     init, update = md.nve(s, cfg["dt"])
     init()
+    tune = None
+    if args.lanes is None:
+        progress("autotuning lanes per particle")
+        tune = md.autotune_lanes(s, cfg["dt"])
+        progress(f"lanes per particle: {tune}")
+        init, update = md.nve(s, cfg["dt"])
     E_init = s.potential_energy() + s.kinetic_energy()
     progress(f"initial list built (capacity {s.nl.capacity}, bins of {s.nl.max_per_cell}); warming up")
     if args.warmup:
@@ -240,6 +330,7 @@ def main():
         "config": {"workload": f"lj_large: 3D Lennard-Jones FCC N={N} rho=0.84 T=1 rc=2.5 skin=0.3 dt=0.005 NVE",
                    "N": N, "dt": cfg["dt"], "r_cut": cfg["r_cut"], "skin": cfg["skin"],
                    "positions": "uint32 torus coordinates", "lanes_per_particle": s.nl.lanes,
+                   "lanes_autotune_us_per_step": None if tune is None else tune["us_per_step"],
                    "parallelism": "single GPU"},
         "extra": {
             "pair_evals_per_s": pair_evals,
@@ -256,6 +347,9 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": kernel_s * 1e6},
         "cpu_baseline": None,
     }
+    if not args.no_secondary:
+        progress("secondary configurations")
+        out["extra"]["secondary"] = secondary(progress)
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

@@ -378,6 +378,10 @@ md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *ve
 md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream);
 /* vel[q] += h force[q] for q < N dim. */
 md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream);
+/* out[0] = the smallest pair distance over the rows of nl at pos (double, device memory; 1e150 if no row has
+ * an entry): with the force RMSE, the check that a configuration stays where a network was trained. */
+md_status md_min_distance(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, const md_nlist *nl,
+                          double *out, void *stream);
 /* out[0] = sqrt(mean over q < n of (a[q] - b[q])^2) in double (device memory), e.g. a force RMSE. */
 md_status md_rms_diff(md_ctx *ctx, const float *a, const float *b, int64_t n, double *out, void *stream);
 

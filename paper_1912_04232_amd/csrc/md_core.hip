@@ -48,6 +48,12 @@ struct Bins {
     uint32_t *mem;  // [C][M][4]
 };
 
+// Member record `slot` (a 32-bit byte offset from the bin base; bins stay below 4 GiB).
+__device__ __forceinline__ uint4 rec16(const uint32_t *mem, uint32_t slot)
+{
+    return *(const uint4 *)((const char *)mem + slot * 16u);
+}
+
 template <int D>
 __device__ __forceinline__ void store_rec(uint32_t *mem, uint32_t slot, const uint32_t *u, int j)
 {
@@ -315,8 +321,8 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
                                          const ListParams &lp, int32_t *__restrict__ idx, const uint32_t *tab, int ts,
                                          int ne, int chunks)
 {
-    const uint4 *mem4 = (const uint4 *)bins.mem;
     const uint32_t M = (uint32_t)lp.M;
+    const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
     // cursor of this lane: entry e, chunk c within it, the entry's first slot cb and count mc
     int e = 0, c = l, mc = 0;
     uint32_t cb = 0;
@@ -339,7 +345,7 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
         uint32_t base = have ? cb + 4u * (uint32_t)c : 0u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            uint4 r = mem4[base + q];
+            uint4 r = rec16(bins.mem, base + q);
             cx[q] = r.x;
             cy[q] = r.y;
             cz[q] = r.z;
@@ -373,14 +379,14 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
             uint32_t base = have2 ? cb2 + 4u * (uint32_t)c2 : 0u;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                uint4 r = mem4[base + q];
+                uint4 r = rec16(bins.mem, base + q);
                 nxx[q] = r.x;
                 nxy[q] = r.y;
                 nxz[q] = r.z;
                 nxj[q] = r.w;
             }
         }
-        int bits = 0;
+        int bits = 0, band = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t uj[3] = {cx[q], cy[q], cz[q]};
@@ -390,19 +396,30 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
                 float d = tdisp(ui[z], uj[z], b.s[z]);
                 r2 = __builtin_fmaf(d, d, r2);
             }
-            bool acc = r2 < lp.rl2f_lo;
-            if (r2 >= lp.rl2f_lo && r2 <= lp.rl2f_hi) {
-                // the defining double expression, evaluated without contraction
-                double r2d = 0.0;
+            bits |= r2 < lp.rl2f_lo ? 1 << q : 0;
+            band |= r2 >= lp.rl2f_lo && r2 <= lp.rl2f_hi ? 1 << q : 0;
+        }
+        // candidates within the float guard band of r_list^2 (rare) take the defining double expression; the
+        // branch is taken by the whole wave or not at all, so the common path carries no double arithmetic
+        if (__ballot(band != 0) != 0) {
 #pragma unroll
-                for (int z = 0; z < D; ++z) {
-                    double d = tdisp_d(ui[z], uj[z], b.sd[z]);
-                    r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+            for (int q = 0; q < 4; ++q) {
+                if (band & (1 << q)) {
+                    const uint32_t uj[3] = {cx[q], cy[q], cz[q]};
+                    double r2d = 0.0;
+#pragma unroll
+                    for (int z = 0; z < D; ++z) {
+                        double d = tdisp_d(ui[z], uj[z], b.sd[z]);
+                        r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                    }
+                    bits |= r2d < lp.rl2 ? 1 << q : 0;
                 }
-                acc = r2d < lp.rl2;
             }
-            acc = acc && have && 4 * c + q < mc && (int)cj[q] != i;
-            bits |= acc ? 1 << q : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bool ok = have && 4 * c + q < mc && (int)cj[q] != i;
+            bits &= ok ? ~0 : ~(1 << q);
         }
         // numbering across the particle's lanes: this round's chunks are in lane order
         int a = __popc(bits);
@@ -417,7 +434,11 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (bits & (1 << q)) {
-                if (slot < lp.cap) idx[((size_t)(slot / W) * lp.N + i) * W + (slot % W)] = (int)cj[q];
+                if (slot < lp.cap) {
+                    // byte offset of entry slot (below 4 GiB, checked on the host)
+                    uint32_t off = (uint32_t)(slot / W) * row_bytes + ((uint32_t)i * W + (uint32_t)(slot % W)) * 4u;
+                    *(int32_t *)((char *)idx + off) = (int)cj[q];
+                }
                 ++slot;
             }
         }
@@ -1254,6 +1275,57 @@ __global__ __launch_bounds__(kBlock) void k_rescale(float *v, int64_t n, const d
         v[q] = (float)((double)v[q] * f);
 }
 
+// Smallest squared pair distance over the list rows of a workgroup's particles (double partials).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_min_r2_partial(DevBox b, const uint32_t *__restrict__ pos, int N,
+                                                           const int32_t *__restrict__ idx,
+                                                           const int32_t *__restrict__ count, int W, int capW,
+                                                           double *partials)
+{
+    __shared__ double red[kBlock];
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    double m = 1e300;
+    if (i < N) {
+        uint32_t ui[D];
+        load_pos<D>(pos, i, ui);
+        for (int l = 0; l < W; ++l) {
+            int n = min(count[(size_t)i * W + l], capW);
+            for (int t = 0; t < n; ++t) {
+                uint32_t uj[D];
+                load_pos<D>(pos, idx[((size_t)t * N + i) * W + l], uj);
+                double r2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    double d = tdisp_d(ui[q], uj[q], b.sd[q]);
+                    r2 += d * d;
+                }
+                m = fmin(m, r2);
+            }
+        }
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_final(const double *partials, int n, double *out)
+{
+    __shared__ double red[kBlock];
+    double m = 1e300;
+    for (int q = threadIdx.x; q < n; q += kBlock) m = fmin(m, partials[q]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
 __global__ void k_sqrt_mean(double *x, double n)
 {
     x[0] = sqrt(x[0] / n);
@@ -1908,6 +1980,29 @@ md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_
     int64_t n = (int64_t)N * dim;
     if (n == 0) return MD_OK;
     hipLaunchKernelGGL(k_kick, dim3(nblk(n)), dim3(kBlock), 0, (hipStream_t)stream, vel, force, n, h);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_min_distance(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, const md_nlist *nl,
+                          double *out, void *stream)
+{
+    md_status st = check_common(ctx, box, N);
+    if (st != MD_OK) return st;
+    if (!pos || !out || !nl_ok(nl, N)) return MD_ERR_ARG;
+    DevBox b;
+    if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
+    if (N == 0) return MD_OK;
+    int grid = nblk(N);
+    if (grid > 4 * kMaxBlocks) return MD_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    int W = nl->lanes, capW = nl->capacity / nl->lanes;
+    if (box->dim == 3)
+        hipLaunchKernelGGL(k_min_r2_partial<3>, dim3(grid), dim3(kBlock), 0, s, b, pos, N, nl->idx, nl->count, W,
+                           capW, ctx->partials);
+    else
+        hipLaunchKernelGGL(k_min_r2_partial<2>, dim3(grid), dim3(kBlock), 0, s, b, pos, N, nl->idx, nl->count, W,
+                           capW, ctx->partials);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, grid, out);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

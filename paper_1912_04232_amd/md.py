@@ -13,6 +13,7 @@ init/update helpers in the style of the paper's ``simulate.nve`` and
 from __future__ import annotations
 
 import ctypes
+import time
 import os
 import re
 from dataclasses import dataclass
@@ -125,6 +126,7 @@ _SIGNATURES = {
     "md_kick": [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
     "md_copy_words": [P, P, P, ctypes.c_int64, P],
+    "md_min_distance": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P, P],
     "md_flags_read": [ctypes.POINTER(c_nlist), P, P],
     "md_flags_clear": [ctypes.POINTER(c_nlist), P],
     "md_version": [],
@@ -388,6 +390,14 @@ def nl_update(ctx: Context, box: Box, pos, nl: NeighborList):
 def kick(ctx: Context, vel, force, h: float):
     N, dim = vel.shape
     _check("md_kick", load().md_kick(ctx.h, _ptr(vel), _ptr(force), N, dim, ctypes.c_float(h), _stream()))
+
+
+def min_distance(ctx: Context, box: Box, pos, nl: NeighborList) -> torch.Tensor:
+    out = torch.zeros(1, dtype=torch.float64, device=pos.device)
+    b, n = box.c(), nl.c()
+    _check("md_min_distance", load().md_min_distance(ctx.h, ctypes.byref(b), _ptr(pos), pos.shape[0], ctypes.byref(n),
+                                                     _ptr(out), _stream()))
+    return out
 
 
 def rms_diff(ctx: Context, a, b) -> torch.Tensor:
@@ -739,6 +749,39 @@ def nve(system: System, dt: float):
         return system
 
     return init_fn, update_fn
+
+
+def autotune_lanes(system: System, dt: float, candidates=(2, 4, 8), steps: int = 60, repeats: int = 2) -> dict:
+    """Choose the lanes per particle (W) of a system's neighbor list by timing NVE steps with each candidate on
+    a copy of its state; the system keeps its state and gets a list with the fastest W.  Returns the timings
+    (us per step) and the choice."""
+    saved = (system.pos.clone(), system.vel.clone(), system.force.clone())
+    nl0 = system.nl
+    res = {}
+    for W in candidates:
+        system.nl = NeighborList(system.N, system.dim, nl0.capacity, nl0.r_list, nl0.skin, system.ctx.device,
+                                 nl0.max_per_cell, W, nl0.segment)
+        init, update = nve(system, dt)
+        best = float("inf")
+        for _ in range(repeats):
+            for t, v in zip((system.pos, system.vel, system.force), saved):
+                t.copy_(v)
+            init()
+            update(5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            update(steps)
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) / steps * 1e6)
+        res[W] = best
+    choice = min(res, key=res.get)
+    for t, v in zip((system.pos, system.vel, system.force), saved):
+        t.copy_(v)
+    system.nl = NeighborList(system.N, system.dim, nl0.capacity, nl0.r_list, nl0.skin, system.ctx.device,
+                             nl0.max_per_cell, choice, nl0.segment)
+    system.build()
+    system.forces()
+    return {"us_per_step": res, "lanes": choice}
 
 
 def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e-6):

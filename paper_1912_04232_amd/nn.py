@@ -251,12 +251,13 @@ class NNMD:
     if their RMSE exceeds `max_rmse` the run continues with plain LJ (md.nve) from that state."""
 
     def __init__(self, ctx: md.Context, net: Network, box: md.Box, u, v, dt=0.005, skin=0.3, r_cut=2.5,
-                 max_rmse=0.5, check_every=100, chunk=20):
+                 max_rmse=1e-2, check_every=100, chunk=20, r_min=0.8):
         self.ctx, self.net, self.box, self.dt = ctx, net, box, dt
         self.lj = md.Potential("lj", [[1.0]], [[1.0]], r_cut=r_cut)
         self.sys = md.System(box, self.lj, u, v, skin=skin, ctx=ctx)
         self.sys.build()
-        self.max_rmse, self.check_every, self.chunk = max_rmse, check_every, chunk
+        self.max_rmse, self.check_every, self.chunk, self.r_min = max_rmse, check_every, chunk, r_min
+        self.min_r_log = []
         self.fallback = False
         self.rmse_log = []
         self.steps = 0
@@ -322,6 +323,10 @@ class NNMD:
         md.pair_energy_force(self.ctx, self.box, self.lj, s.pos, None, s.nl, self.F_lj)
         return float(md.rms_diff(self.ctx, s.force, self.F_lj))
 
+    def min_distance(self) -> float:
+        """Closest pair distance now; below r_min the configuration has left the descriptors' training range."""
+        return float(md.min_distance(self.ctx, self.box, self.sys.pos, self.sys.nl))
+
     def run(self, n_steps: int, graph: bool = True):
         """Advance n_steps; returns the number of steps run with the network before any fallback."""
         done_nn = 0
@@ -332,11 +337,13 @@ class NNMD:
             if f[md.FLAG_OVERFLOW] or f[md.FLAG_CELL_OVERFLOW]:
                 raise RuntimeError(f"neighbor list overflow during network MD: {f.tolist()}")
             rmse = self.judge()
+            rmin = self.min_distance()
             self.rmse_log.append(rmse)
+            self.min_r_log.append(rmin)
             n_steps -= k
             done_nn += k
             self.steps += k
-            if not math.isfinite(rmse) or rmse > self.max_rmse:
+            if not math.isfinite(rmse) or rmse > self.max_rmse or rmin < self.r_min:
                 self.fallback = True
         if n_steps > 0:
             # plain LJ takes over from the current positions and velocities

@@ -452,3 +452,23 @@ def test_lj_large_sampled_parity(md, orc):
         assert np.array_equal(np.sort(got[i]), want[q])
     Fo, _, _ = orc.pair_rows(orc.decode(u, cfg["L"]), cfg["L"], orc_pot(orc, cfg), rows=rows)
     assert rel_l2(s.force.cpu().numpy()[rows], Fo) <= F_TOL
+
+
+def test_min_distance_and_rms_diff(md, orc):
+    """md_min_distance against the brute-force closest pair; md_rms_diff against numpy."""
+    import torch
+    cfg = lj_cfg(1000, 0.8, 4)
+    s = make_system(md, cfg)
+    s.build()
+    x = orc.decode(cfg["u"], cfg["L"])
+    L = np.asarray(cfg["L"], dtype=np.float64)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    got = float(md.min_distance(s.ctx, s.box, s.pos, s.nl))
+    assert got == pytest.approx(r.min(), rel=1e-12)
+    a = torch.linspace(-1, 1, 3001, device="cuda")
+    b = torch.cos(a * 3)
+    want = float(np.sqrt(np.mean((a.cpu().numpy().astype(np.float64) - b.cpu().numpy().astype(np.float64)) ** 2)))
+    assert float(md.rms_diff(s.ctx, a, b)) == pytest.approx(want, rel=1e-12)
