@@ -82,13 +82,18 @@ def check_rows(orc, sysm, cfg, rows=None):
 
 # ------------------------------------------------------------------ neighbor list
 
-@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "ss2d", "tiny_box", "two", "one"])
+@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "lj_blocks6", "lj_blocks7", "ss2d", "tiny_box", "two",
+                                  "one"])
 def test_nl_build_bitexact(md, orc, case):
     say("nl_build", case)
     if case == "lj1000":
         cfg = inputs.lj_small()
     elif case == "lj_ragged":
         cfg = lj_cfg(3333, 0.84, 77)
+    elif case == "lj_blocks6":
+        cfg = lj_cfg(4500, 0.84, 78)                 # 6 cells a side: smallest box of LDS-staged cell blocks
+    elif case == "lj_blocks7":
+        cfg = lj_cfg(8000, 0.84, 79)                 # 7 cells a side: a ragged last cell block
     elif case == "ss2d":
         cfg = ss_cfg(5000, 0.9, 21)
     elif case == "tiny_box":
@@ -174,6 +179,10 @@ def test_forces_energy_virial_vs_oracle(md, orc, case):
         cfg = inputs.lj_small()
     elif case == "lj_ragged":
         cfg = lj_cfg(3333, 0.84, 77)
+    elif case == "lj_blocks6":
+        cfg = lj_cfg(4500, 0.84, 78)                 # 6 cells a side: smallest box of LDS-staged cell blocks
+    elif case == "lj_blocks7":
+        cfg = lj_cfg(8000, 0.84, 79)                 # 7 cells a side: a ragged last cell block
     elif case.startswith("ss2d"):
         cfg = ss_cfg(3000, 0.9, 22)
         if case == "ss2d_alpha25":
