@@ -37,13 +37,14 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_verlet_step launch from the committed rocprofv3 counter runs, if they match this kernel."""
+def measured_traffic(kernel=None):
+    """HBM bytes per k_md_step launch from the committed rocprofv3 counter runs, if they match this kernel source
+    and (when given) the timed variant, e.g. "k_md_step<3,0,false,4>"."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha():
+    if t.get("kernel_sha") != kernel_sha() or (kernel is not None and t.get("kernel") != kernel):
         return None
     return float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
 
@@ -86,16 +87,25 @@ def traffic_from(fetch_dir: str, write_dir: str):
         rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             rows += [r for r in csv.DictReader(open(f)) if r.get("Counter_Name") == counter]
-        step = [float(r["Counter_Value"]) for r in rows if "k_md_step" in r["Kernel_Name"]]
+        # the timed variant (lanes chosen by the autotuner) is the one with the most dispatches
+        by_variant = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            if "k_md_step<" in name:
+                v = name[name.index("k_md_step<"):name.index(">", name.index("k_md_step<")) + 1].replace(" ", "")
+                by_variant.setdefault(v, []).append(float(r["Counter_Value"]))
         copy = [float(r["Counter_Value"]) for r in rows if "k_copy_words" in r["Kernel_Name"]]
-        if not step or not copy:
+        if not by_variant or not copy:
             raise SystemExit(f"no k_md_step / k_copy_words dispatches with {counter} under {d}")
-        return sum(step) / len(step), len(step), max(copy)
+        variant, step = max(by_variant.items(), key=lambda kv: len(kv[1]))
+        return sum(step) / len(step), len(step), max(copy), variant
 
-    f_step, n_f, f_copy = read(fetch_dir, "FETCH_SIZE")
-    w_step, n_w, w_copy = read(write_dir, "WRITE_SIZE")
+    f_step, n_f, f_copy, f_var = read(fetch_dir, "FETCH_SIZE")
+    w_step, n_w, w_copy, w_var = read(write_dir, "WRITE_SIZE")
+    if f_var != w_var:
+        raise SystemExit(f"the two runs timed different variants: {f_var} / {w_var}")
     ref_kib = COPY_BYTES / 1024.0
-    rec = {"kernel": "k_md_step", "kernel_sha": kernel_sha(), "dispatches": [n_f, n_w],
+    rec = {"kernel": f_var, "kernel_sha": kernel_sha(), "dispatches": [n_f, n_w],
            "fetch_kib_per_launch_raw": f_step, "write_kib_per_launch_raw": w_step,
            "copy_fetch_kib": f_copy, "copy_write_kib": w_copy, "copy_bytes": COPY_BYTES,
            "fetch_scale": ref_kib / f_copy, "write_scale": ref_kib / w_copy,
@@ -307,13 +317,13 @@ def main():
     sec = wall
     steps_per_s = args.steps / sec
     pair_evals = mean_n * N * steps_per_s
-    # dominant kernel: one k_verlet_step launch per step; its algorithmic bytes with the implemented layout:
+    # dominant kernel: one k_md_step launch per step; its algorithmic bytes with the implemented layout:
     # own position read 12 B, velocity read+write 24 B, new position write 12 B, reference position read 12 B,
     # row length 4 B, and 4 B per list entry; neighbor positions are gathers served by cache.
     bytes_per_launch = N * (12 + 24 + 12 + 12 + 4) + 4.0 * float(counts.sum())
     kernel_s = gpu_ms * 1e-3 / args.steps
     achieved = bytes_per_launch / kernel_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(f"k_md_step<3,0,false,{s.nl.lanes}>")
     out = {
         "metric": "LJ MD steps/s & pair-evals/s at N=256k; surrogate vs plain at stated force RMSE",
         "value": round(steps_per_s, 2),
