@@ -307,6 +307,31 @@ __device__ __forceinline__ int stencil_table(int i, const uint32_t *ui, const De
     return ne;
 }
 
+// Inclusive prefix sum of x over the W lanes of a particle (W <= 8: groups lie within DPP rows of 16 lanes),
+// by DPP row shifts instead of LDS permutes; tot = the group's sum.  Every lane of a group is active together.
+template <int W>
+__device__ __forceinline__ int group_scan(int x, int l, int &tot)
+{
+    int incl = x;
+    if constexpr (W >= 2) {
+        int v = __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);  // row_shr:1
+        incl += l >= 1 ? v : 0;
+    }
+    if constexpr (W >= 4) {
+        int v = __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);  // row_shr:2
+        incl += l >= 2 ? v : 0;
+    }
+    if constexpr (W >= 8) {
+        int v = __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);  // row_shr:4
+        incl += l >= 4 ? v : 0;
+    }
+    if constexpr (W == 1) tot = incl;
+    else if constexpr (W == 2) tot = __builtin_amdgcn_update_dpp(0, incl, 0xF5, 0xf, 0xf, false);  // quad_perm 1,1,3,3
+    else if constexpr (W == 4) tot = __builtin_amdgcn_update_dpp(0, incl, 0xFF, 0xf, 0xf, false);  // quad_perm 3,3,3,3
+    else tot = __shfl(incl, W - 1, W);
+    return incl;
+}
+
 // Row of particle i (Sec. 3.2.3) built by its W lanes; lane l of the particle calls this with the particle's
 // stencil table (ne entries holding `chunks` chunks of four 16-byte member records, one cache line each).
 //
@@ -416,27 +441,22 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
                 }
             }
         }
+        // records of the chunk that are members (a cell's last chunk may be partial), other than i itself
+        const int left = have ? mc - 4 * c : 0;
+        bits &= left >= 4 ? 15 : (1 << max(left, 0)) - 1;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            bool ok = have && 4 * c + q < mc && (int)cj[q] != i;
-            bits &= ok ? ~0 : ~(1 << q);
-        }
+        for (int q = 0; q < 4; ++q) bits &= (int)cj[q] != i ? 15 : ~(1 << q);
         // numbering across the particle's lanes: this round's chunks are in lane order
-        int a = __popc(bits);
-        int incl = a;
-#pragma unroll
-        for (int o = 1; o < W; o <<= 1) {
-            int v = __shfl_up(incl, o, W);
-            if (l >= o) incl += v;
-        }
-        int tot = __shfl(incl, W - 1, W);
-        int slot = n + incl - a;
+        const int a = __popc(bits);
+        int tot;
+        const int incl = group_scan<W>(a, l, tot);
+        uint32_t slot = (uint32_t)(n + incl - a);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (bits & (1 << q)) {
-                if (slot < lp.cap) {
+                if (slot < (uint32_t)lp.cap) {
                     // byte offset of entry slot (below 4 GiB, checked on the host)
-                    uint32_t off = (uint32_t)(slot / W) * row_bytes + ((uint32_t)i * W + (uint32_t)(slot % W)) * 4u;
+                    uint32_t off = slot / W * row_bytes + ((uint32_t)i * W + slot % W) * 4u;
                     *(int32_t *)((char *)idx + off) = (int)cj[q];
                 }
                 ++slot;

@@ -127,6 +127,23 @@ def test_nl_rows_are_canonical(md):
     assert (cnt1[:, 0] >= cnt1[:, -1]).all()
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_nl_rows_every_lane_count(md, orc, lanes):
+    """Rows built by 1, 2, 4 or 8 lanes per particle (each lane count numbers the neighbors by its own prefix
+    sums across the particle's lanes) are the oracle's rows, dealt round-robin over the sub-rows."""
+    say("nl lanes", lanes)
+    cfg = lj_cfg(3333, 0.84, 81)
+    box = md.Box(tuple(cfg["L"]), 3)
+    pot = md.Potential("lj", cfg["sigma"], cfg["epsilon"], r_cut=cfg["r_cut"])
+    s = md.System(box, pot, cfg["u"], cfg["v"], skin=0.3, lanes=lanes)
+    s.build()
+    assert s.nl.lanes == lanes
+    check_rows(orc, s, cfg)
+    cnt = s.nl.count.cpu().numpy()[: s.N]
+    assert (cnt.max(axis=1) - cnt.min(axis=1)).max() <= 1
+    assert s.nl.read_flags()[md.FLAG_OVERFLOW] == 0
+
+
 def test_segmented_list_matches_per_system_oracle(md, orc):
     """A list over three independent systems of 700 particles each (segment = 700, same box) holds exactly the
     rows of each system on its own, with indices offset by the system's first particle."""
