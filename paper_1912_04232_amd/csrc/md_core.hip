@@ -595,87 +595,145 @@ __device__ __forceinline__ T ld_off(const void *base, uint32_t off)
     return *(const T *)((const char *)base + off);
 }
 
-template <int D>
-__device__ __forceinline__ void ld_pos(const uint32_t *__restrict__ pos, int j, uint32_t *u)
+// Buffer resource over `bytes` bytes at `base` (raw addressing: loads at byte offsets at or past `bytes` return
+// 0 instead of touching memory).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, uint32_t bytes)
 {
-    // j < 2^24 (checked on the host): a 24-bit multiply gives the byte offset
-    const char *p = (const char *)pos + __umul24((uint32_t)j, (uint32_t)(4 * D));
-#pragma unroll
-    for (int q = 0; q < D; ++q) u[q] = ((const uint32_t *)p)[q];
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// Four pairs of one lane: positions pc of neighbors jc against ui; `live` masks slots past the row's end.
-template <int D, int KIND, bool MULTI, bool MASK>
-__device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, const int32_t *__restrict__ species,
+// Position of particle j through a range-checked buffer load: an index read from past the end of a row (a stale
+// or never written entry) cannot fault.  j < 2^24 for real entries (checked on the host).
+template <int D>
+__device__ __forceinline__ void ld_pos(const __amdgpu_buffer_rsrc_t &rp, int j, uint32_t *u)
+{
+    const uint32_t off = __umul24((uint32_t)j & 0xffffffu, (uint32_t)(4 * D));
+    if constexpr (D == 3) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b96(rp, off, 0, 0);
+        u[0] = v[0];
+        u[1] = v[1];
+        u[2] = v[2];
+    } else {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(rp, off, 0, 0);
+        u[0] = v[0];
+        u[1] = v[1];
+    }
+}
+
+// Species of particle j through a range-checked buffer load (0 for an index past the array).
+__device__ __forceinline__ int ld_species(const __amdgpu_buffer_rsrc_t &rs, int j)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, ((uint32_t)j & 0xffffffu) << 2, 0, 0);
+}
+
+// Four pairs of one lane: positions pc of neighbors jc against ui; `live` masks slots past the row's end.  With
+// ISO (LJ in a box with one scale s along every axis) the displacement stays in integer units: r^2 is their
+// squared sum times s^2, and the caller multiplies the summed force by s once.
+template <int D, int KIND, bool MULTI, bool MASK, bool ISO>
+__device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, const __amdgpu_buffer_rsrc_t &rs,
                                            int si, const uint32_t *ui, const int *jc, const uint32_t (*pc)[D],
-                                           int t0, int n, float *F)
+                                           int t0, int n, float s2, float *F)
 {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        float d[D], r2, u;
-        int pt = MULTI ? si * p.S + species[jc[a]] : 0;
-        float fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, pc[a], b.s, b.sd, d, r2, u);
+        float d[D], r2, u, fs;
+        // species of a slot past the row's end come through the range-checked load like its position
+        int pt = MULTI ? si * p.S + ld_species(rs, jc[a]) : 0;
+        if constexpr (ISO) {
+            float r2u = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                d[k] = (float)(int32_t)(ui[k] - pc[a][k]);
+                r2u = __builtin_fmaf(d[k], d[k], r2u);
+            }
+            r2 = r2u * s2;
+            fs = pair_fs<KIND, MULTI, false>(p, pt, r2, u);
+        } else {
+            fs = pair_eval<D, KIND, MULTI, false>(p, pt, ui, pc[a], b.s, b.sd, d, r2, u);
+        }
         if (MASK) fs = t0 + a < n ? fs : 0.0f;
 #pragma unroll
         for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fs, d[q], F[q]);
     }
 }
 
-// Force from lane l's sub-row of particle i (the hot loop), then summed over the W lanes.  Entries go in
-// groups of four, two groups per iteration with the register sets alternating: the indices two groups ahead
-// and the neighbor positions one group ahead are loaded while a group is evaluated.  Loads past the row's end
-// re-read its last entry (always a valid particle) and those slots are masked out.
+// Lane l's sub-row of particle i: entries go in groups of four, two groups per iteration with the register sets
+// alternating; the indices two groups ahead and the neighbor positions one group ahead are loaded while a group
+// is evaluated.  An entry's address is a scalar row base (the same in every lane, clamped to the list's last row)
+// plus the lane's own offset, so the loads carry no per-lane address arithmetic; entries past the row's end may
+// hold anything, their positions come through the range-checked load and their slots are masked out.
+template <int D, int KIND, bool MULTI, int W, bool ISO>
+__device__ __forceinline__ void lane_force_rows(const DevBox &b, const DevPot &p, const __amdgpu_buffer_rsrc_t &rp,
+                                                const __amdgpu_buffer_rsrc_t &rs, int N, int capW,
+                                                const int32_t *__restrict__ idx, int n, int i, int l,
+                                                const uint32_t *ui, int si, float *F)
+{
+    const uint32_t step = (uint32_t)N * W * 4u;  // bytes between consecutive entries of a sub-row
+    const uint32_t off = ((uint32_t)i * W + (uint32_t)l) * 4u;
+    const float s2 = b.s[0] * b.s[0];
+    auto ldj = [&](int t) -> int {
+        const char *row = (const char *)idx + (size_t)min(t, capW - 1) * step;
+        return *(const int32_t *)(row + off);
+    };
+    int jA[4], jB[4];
+    uint32_t pA[4][D], pB[4][D];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        jA[a] = ldj(a);
+        jB[a] = ldj(4 + a);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jA[a], pA[a]);
+    int t = 0;
+    // full pairs of groups: A holds group t/4 (positions loaded), B the next group's indices
+    for (; t + 8 <= n; t += 8) {
+        int jC[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jB[a], pB[a]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) jC[a] = ldj(t + 8 + a);
+        asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
+        quad_force<D, KIND, MULTI, false, ISO>(b, p, rs, si, ui, jA, pA, t, n, s2, F);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jC[a], pA[a]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) jA[a] = ldj(t + 12 + a);
+        asm volatile("" ::: "memory");
+        quad_force<D, KIND, MULTI, false, ISO>(b, p, rs, si, ui, jB, pB, t + 4, n, s2, F);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            int x = jA[a];
+            jA[a] = jC[a];
+            jB[a] = x;
+        }
+    }
+    // at most two groups remain: A (positions loaded) and B (indices loaded)
+    if (t < n) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jB[a], pB[a]);
+        quad_force<D, KIND, MULTI, true, ISO>(b, p, rs, si, ui, jA, pA, t, n, s2, F);
+        if (t + 4 < n) quad_force<D, KIND, MULTI, true, ISO>(b, p, rs, si, ui, jB, pB, t + 4, n, s2, F);
+    }
+    if constexpr (ISO) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) F[q] *= b.s[0];
+    }
+}
+
+// Force from lane l's sub-row of particle i (the hot loop), then summed over the W lanes.
 template <int D, int KIND, bool MULTI, int W>
 __device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, const uint32_t *__restrict__ pos,
-                                           const int32_t *__restrict__ species, int N,
+                                           const int32_t *__restrict__ species, int N, int capW,
                                            const int32_t *__restrict__ idx, int n, int i, int l, const uint32_t *ui,
                                            int si, float *F)
 {
+    const __amdgpu_buffer_rsrc_t rp = raw_rsrc(pos, (uint32_t)N * 4u * D);
+    const __amdgpu_buffer_rsrc_t rs = raw_rsrc(species, MULTI ? (uint32_t)N * 4u : 0u);
     if (n > 0) {
-        const uint32_t step = (uint32_t)N * W * 4u;          // bytes between consecutive entries of a sub-row
-        const uint32_t off = ((uint32_t)i * W + (uint32_t)l) * 4u;
-        const uint32_t olast = off + (uint32_t)(n - 1) * step;
-        // t is the same in every lane, so t * step is scalar; the clamp is one vector min
-        auto ldj = [&](int t) -> int { return ld_off<int32_t>(idx, min(off + (uint32_t)t * step, olast)); };
-        int jA[4], jB[4];
-        uint32_t pA[4][D], pB[4][D];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            jA[a] = ldj(a);
-            jB[a] = ldj(4 + a);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jA[a], pA[a]);
-        int t = 0;
-        // full pairs of groups: A holds group t/4 (positions loaded), B the next group's indices
-        for (; t + 8 <= n; t += 8) {
-            int jC[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jB[a], pB[a]);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) jC[a] = ldj(t + 8 + a);
-            asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
-            quad_force<D, KIND, MULTI, false>(b, p, species, si, ui, jA, pA, t, n, F);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jC[a], pA[a]);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) jA[a] = ldj(t + 12 + a);
-            asm volatile("" ::: "memory");
-            quad_force<D, KIND, MULTI, false>(b, p, species, si, ui, jB, pB, t + 4, n, F);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                int x = jA[a];
-                jA[a] = jC[a];
-                jB[a] = x;
-            }
-        }
-        // at most two groups remain: A (positions loaded) and B (indices loaded)
-        if (t < n) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a) ld_pos<D>(pos, jB[a], pB[a]);
-            quad_force<D, KIND, MULTI, true>(b, p, species, si, ui, jA, pA, t, n, F);
-            if (t + 4 < n) quad_force<D, KIND, MULTI, true>(b, p, species, si, ui, jB, pB, t + 4, n, F);
-        }
+        if (KIND == 0 && b.iso)
+            lane_force_rows<D, KIND, MULTI, W, KIND == 0>(b, p, rp, rs, N, capW, idx, n, i, l, ui, si, F);
+        else
+            lane_force_rows<D, KIND, MULTI, W, false>(b, p, rp, rs, N, capW, idx, n, i, l, ui, si, F);
     }
 #pragma unroll
     for (int o = 1; o < W; o <<= 1) {
@@ -946,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 #pragma unroll
     for (int q = 0; q < D; ++q) F[q] = 0.0f;
     int n = live ? min(g.count[(size_t)ii * W + l], lp.capW) : 0;
-    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos_in, a.species, lp.N, g.idx, n, ii, l, ui, si, F);
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos_in, a.species, lp.N, lp.capW, g.idx, n, ii, l, ui, si, F);
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
@@ -1075,7 +1133,7 @@ __global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p, int
 #pragma unroll
     for (int q = 0; q < D; ++q) F[q] = 0.0f;
     int n = live ? min(a.list.count[(size_t)ii * W + l], lp.capW) : 0;
-    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, a.list.idx, n, ii, l, ui, si, F);
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, lp.capW, a.list.idx, n, ii, l, ui, si, F);
     double P = 0.0, vv = 0.0, ff = 0.0;
     bool bad = false;
     if (live && l == 0) {
@@ -1395,6 +1453,7 @@ static bool make_box(const md_box *box, float r_list, DevBox &b)
             b.nc[k] = 1;
         }
     }
+    b.iso = b.s[0] == b.s[1] && (box->dim == 2 || b.s[1] == b.s[2]);
     return true;
 }
 

@@ -21,6 +21,7 @@ struct DevBox {
     int C;            // total cells
     int lo[3], hi[3]; // stencil offsets per dimension: [-1, 1] or [0, 0]
     float cw[3];      // cell width L_k / nc_k
+    int iso;          // the same scale along every axis
 };
 
 // Per-pair-type coefficients (Sec. 3.3.2).  For LJ with r2i = 1/r^2 and

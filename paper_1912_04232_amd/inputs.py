@@ -56,6 +56,16 @@ def uniform_torus(N: int, dim: int, seed: int) -> np.ndarray:
     return rng.integers(0, 2 ** 32, size=(N, dim), dtype=np.uint64).astype(np.uint32)
 
 
+def jittered_grid_torus(counts, jitter: float, seed: int) -> np.ndarray:
+    """A simple grid of counts[0] x counts[1] (x counts[2]) sites, each moved by a uniform offset of up to
+    +-jitter of its grid spacing along every axis; the box edges may differ per axis."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    axes = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in counts], indexing="ij")
+    frac = np.stack([a.ravel() for a in axes], axis=1)
+    frac = (frac + 0.5 + rng.uniform(-jitter, jitter, size=frac.shape)) / np.asarray(counts, dtype=np.float64)
+    return np.floor(np.mod(frac, 1.0) * 2.0 ** 32).astype(np.uint64).astype(np.uint32)
+
+
 def fcc_torus(n_cells: int, L: float) -> np.ndarray:
     """FCC lattice with n_cells^3 cubic cells (4 sites each) filling a cube of edge L."""
     base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]], dtype=np.float64)
