@@ -660,20 +660,22 @@ __device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, con
 // Lane l's sub-row of particle i: entries go in groups of four, two groups per iteration with the register sets
 // alternating; the indices two groups ahead and the neighbor positions one group ahead are loaded while a group
 // is evaluated.  An entry's address is a scalar row base (the same in every lane, clamped to the list's last row)
-// plus the lane's own offset, so the loads carry no per-lane address arithmetic; entries past the row's end may
-// hold anything, their positions come through the range-checked load and their slots are masked out.
+// plus the lane's own offset, so the loads carry no per-lane address arithmetic.  Rows are clamped to tlast, the
+// last entry any lane of the wave needs, so prefetches past it re-read cached lines; entries past a lane's own
+// row end may hold anything, their positions come through the range-checked load and their slots are masked.
 template <int D, int KIND, bool MULTI, int W, bool ISO>
 __device__ __forceinline__ void lane_force_rows(const DevBox &b, const DevPot &p, const __amdgpu_buffer_rsrc_t &rp,
-                                                const __amdgpu_buffer_rsrc_t &rs, int N, int capW,
+                                                const __amdgpu_buffer_rsrc_t &rs, int N, int tlast,
                                                 const int32_t *__restrict__ idx, int n, int i, int l,
                                                 const uint32_t *ui, int si, float *F)
 {
     const uint32_t step = (uint32_t)N * W * 4u;  // bytes between consecutive entries of a sub-row
     const uint32_t off = ((uint32_t)i * W + (uint32_t)l) * 4u;
     const float s2 = b.s[0] * b.s[0];
+    // the row's byte offset goes in the load's scalar offset; the lane's offset is the only vector operand
+    const __amdgpu_buffer_rsrc_t ri = raw_rsrc(idx, (uint32_t)(tlast + 1) * step);
     auto ldj = [&](int t) -> int {
-        const char *row = (const char *)idx + (size_t)min(t, capW - 1) * step;
-        return *(const int32_t *)(row + off);
+        return __builtin_amdgcn_raw_buffer_load_b32(ri, off, (uint32_t)min(t, tlast) * step, 0);
     };
     int jA[4], jB[4];
     uint32_t pA[4][D], pB[4][D];
@@ -729,11 +731,22 @@ __device__ __forceinline__ void lane_force(const DevBox &b, const DevPot &p, con
 {
     const __amdgpu_buffer_rsrc_t rp = raw_rsrc(pos, (uint32_t)N * 4u * D);
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(species, MULTI ? (uint32_t)N * 4u : 0u);
+    // last entry of the longest sub-row in the wave (every lane of the wave calls this), never past the list
+    int nw = n;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nw = max(nw, __shfl_xor(nw, o));
+    // (scalar instructions on purpose: the compiler otherwise keeps tlast in a vector register and turns every
+    // entry load below into 64-bit vector address arithmetic)
+    int tlast;
+    asm volatile("s_min_i32 %0, %1, %2\n\ts_add_i32 %0, %0, -1"
+                 : "=s"(tlast)
+                 : "s"(__builtin_amdgcn_readfirstlane(nw)), "s"(__builtin_amdgcn_readfirstlane(capW))
+                 : "scc");
     if (n > 0) {
         if (KIND == 0 && b.iso)
-            lane_force_rows<D, KIND, MULTI, W, KIND == 0>(b, p, rp, rs, N, capW, idx, n, i, l, ui, si, F);
+            lane_force_rows<D, KIND, MULTI, W, KIND == 0>(b, p, rp, rs, N, tlast, idx, n, i, l, ui, si, F);
         else
-            lane_force_rows<D, KIND, MULTI, W, false>(b, p, rp, rs, N, capW, idx, n, i, l, ui, si, F);
+            lane_force_rows<D, KIND, MULTI, W, false>(b, p, rp, rs, N, tlast, idx, n, i, l, ui, si, F);
     }
 #pragma unroll
     for (int o = 1; o < W; o <<= 1) {
