@@ -377,21 +377,39 @@ __device__ __forceinline__ void load_x(Pair<L16> &X, const NNDev &p, const float
     }
 }
 
+constexpr int kMlpWaves = 4;  // waves per workgroup of k_nn_mlp, sharing one copy of the weights
+
 struct MlpLds {
     WLds w;
-    Pair<L16> X;
-    Pair<L64> T;
-    float E[kTile];
+    Pair<L16> Xs[kMlpWaves];
+    Pair<L64> Ts[kMlpWaves];
+    float Es[kMlpWaves][kTile];
 };
 
-// Per-atom energies E_i and input gradients e_i = dE_i/dG_i for atoms [0, N), one wave per 32-atom tile.
-__global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict__ G, int N, float *__restrict__ Ei,
-                                               float *__restrict__ e)
+// Orders one wave's LDS writes before its later reads (every lane of the wave takes part).
+__device__ __forceinline__ void wave_sync()
 {
-    __shared__ __align__(16) MlpLds s;
-    int lane = threadIdx.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-atom energies E_i and input gradients e_i = dE_i/dG_i for atoms [0, N), one wave per 32-atom tile; the
+// kMlpWaves waves of a workgroup share the weights staged once in LDS and work on tiles of their own.
+__global__ __launch_bounds__(64 * kMlpWaves) void k_nn_mlp(NNDev p, const float *__restrict__ G, int N,
+                                                           float *__restrict__ Ei, float *__restrict__ e)
+{
+    __shared__ __align__(16) MlpLds sh;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int c32 = lane & 31;
-    load_weights(s.w, p, lane, 64);
+    load_weights(sh.w, p, threadIdx.x, 64 * kMlpWaves);
+    __syncthreads();
+    struct {
+        const WLds &w;
+        Pair<L16> &X;
+        Pair<L64> &T;
+        float *E;
+    } s = {sh.w, sh.Xs[wv], sh.Ts[wv], sh.Es[wv]};
     float b1[2], b2[2], w3[2];
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
@@ -401,11 +419,11 @@ __global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict_
     }
     float b3 = *p.b3;
     int ntiles = (N + kTile - 1) / kTile;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int tile = blockIdx.x * kMlpWaves + wv; tile < ntiles; tile += gridDim.x * kMlpWaves) {
         int a0 = tile * kTile;
-        __syncthreads();
+        wave_sync();
         load_x(s.X, p, G, a0, N, lane);
-        __syncthreads();
+        wave_sync();
         // z1 = X W1^T + b1; h1 = sp(z1) -> T; a1 = sp'(z1)
         float a1[2][16];
 #pragma unroll
@@ -418,7 +436,7 @@ __global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict_
                 put_pair(s.T, acc_row(r, lane), 32 * hf + c32, softplus(z));
             }
         }
-        __syncthreads();
+        wave_sync();
         // z2 = H1 W2^T + b2; E_i = w3 . sp(z2) + b3; d2 = sp'(z2) w3
         float d2[2][16], erow[16];
 #pragma unroll
@@ -444,12 +462,12 @@ __global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) s.E[acc_row(r, lane)] = erow[r];
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
             for (int r = 0; r < 16; ++r) put_pair(s.T, acc_row(r, lane), 32 * hf + c32, d2[hf][r]);
-        __syncthreads();
+        wave_sync();
         if (lane < kTile && a0 + lane < N) Ei[a0 + lane] = s.E[lane] + b3;
         // d1 = a1 * (D2 W2)
         float d1[2][16];
@@ -459,12 +477,12 @@ __global__ __launch_bounds__(64) void k_nn_mlp(NNDev p, const float *__restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) d1[hf][r] = c[r] * a1[hf][r];
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
             for (int r = 0; r < 16; ++r) put_pair(s.T, acc_row(r, lane), 32 * hf + c32, d1[hf][r]);
-        __syncthreads();
+        wave_sync();
         // e = (D1 W1) / s  (columns k < K of the product)
         f32x16 c = mma_split_bcol<kH>(s.T, s.w.W1, L16, 0, kK);
         if (c32 < kK) {
@@ -845,8 +863,9 @@ md_status nn_mlp(md_ctx *ctx, const md_nn_params *q, const float *G, int32_t N, 
     if (!ctx || !make_nn(q, p) || !G || !Ei || !e || N < 0) return MD_ERR_ARG;
     if (N == 0) return MD_OK;
     int ntiles = (N + kTile - 1) / kTile;
-    int grid = ntiles < 8192 ? ntiles : 8192;
-    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(64), 0, (hipStream_t)stream, p, G, N, Ei, e);
+    int blocks = (ntiles + kMlpWaves - 1) / kMlpWaves;
+    int grid = blocks < 2048 ? blocks : 2048;
+    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(64 * kMlpWaves), 0, (hipStream_t)stream, p, G, N, Ei, e);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
