@@ -146,13 +146,6 @@ __device__ __forceinline__ int stencil_size(const DevBox &b)
 // ------------------------------------------------------------------------------------------------
 // counting sort into bins (deterministic); every kernel returns at once when its gate word is 0
 
-__global__ void k_cs_zero(int32_t *cell_count, int C, const int32_t *gate)
-{
-    if (gate_closed(gate)) return;
-    int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c < C) cell_count[c] = 0;
-}
-
 template <int D>
 __global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, DevBox b, CountSort cs,
                            const int32_t *gate)
@@ -170,7 +163,8 @@ __global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, Dev
 constexpr int kScan = 1024;  // threads of the one-workgroup scan
 
 // Exclusive scan of cell_count into cell_start[0..C] by one workgroup (wave shuffles and LDS, no atomics);
-// also the bin counts min(count, M), the cell-overflow flag and the largest occupancy.
+// also the bin counts min(count, M), the cell-overflow flag and the largest occupancy.  It leaves the counts at
+// zero for the next build.
 __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bins, int M, int32_t *flags,
                                                    const int32_t *gate)
 {
@@ -219,6 +213,7 @@ __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bin
     for (int c = lo; c < hi; ++c) {
         cs.cell_start[c] = run;
         int v = cs.cell_count[c];
+        cs.cell_count[c] = 0;  // ready for the next build (the counts start zeroed at allocation)
         bins.cnt[c] = min(v, M);
         run += v;
     }
@@ -1646,7 +1641,6 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     ListGen g = caller_gen(nl);
     int rows_grid = nblk((int64_t)N * lp.W);
     int C = list_cells(b, nl);  // cells over all systems of a segmented list
-    hipLaunchKernelGGL(k_cs_zero, dim3(nblk(C)), dim3(kBlock), 0, s, cs.cell_count, C, gate);
     if (dim == 3) {
         hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
         hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
@@ -1758,6 +1752,8 @@ md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells,
     HIP_OK(hipMalloc(&ctx->cs.slot, sizeof(int32_t) * nn));
     HIP_OK(hipMalloc(&ctx->cs.sorted_idx, sizeof(int32_t) * nn));
     HIP_OK(hipMalloc(&ctx->cs.cell_count, sizeof(int32_t) * (size_t)C));
+    HIP_OK(hipMemset(ctx->cs.cell_count, 0, sizeof(int32_t) * (size_t)C));  // each scan re-zeroes what it read
+    HIP_OK(hipDeviceSynchronize());  // the zeroes land before any stream's first build
     HIP_OK(hipMalloc(&ctx->cs.cell_start, sizeof(int32_t) * ((size_t)C + 1)));
     for (int g = 0; g < 2; ++g) {
         HIP_OK(hipMalloc(&ctx->bin_cnt[g], sizeof(int32_t) * (size_t)C));
