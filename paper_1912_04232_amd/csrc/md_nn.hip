@@ -86,10 +86,11 @@ __device__ __forceinline__ void rbf(const NNDev &p, float r, float *g, float *dg
     float c = __cosf(pi * r / p.r_c);
     float fc = 0.5f * (c + 1.0f);
     float dfc = DERIV ? -0.5f * pi / p.r_c * __sinf(pi * r / p.r_c) : 0.0f;
+    const float nel2 = -p.eta * 1.4426950408889634f;  // -eta log2(e): exp(-eta t^2) = 2^(nel2 t^2)
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
         float t = r - (p.mu0 + k * p.dmu);
-        float gauss = __expf(-p.eta * t * t);
+        float gauss = __builtin_amdgcn_exp2f(nel2 * t * t);
         g[k] = gauss * fc;
         if (DERIV) dg[k] = gauss * (dfc - 2.0f * p.eta * t * fc);
     }
@@ -124,10 +125,19 @@ __global__ __launch_bounds__(kBlock) void k_nn_descriptor(DevBox b, NNDev p, con
     for (int k = 0; k < kK; ++k) acc[k] = 0.0f;
     int n = live ? min(count[(size_t)ii * W + l], capW) : 0;
     float rc2 = p.r_c * p.r_c;
+    // the next entry's index and position are loaded while the current pair is evaluated
+    int jn = n > 0 ? idx[(size_t)ii * W + l] : ii;
+    uint32_t un[D];
+    load_pos<D>(pos, jn, un);
     for (int t = 0; t < n; ++t) {
-        int j = idx[((size_t)t * N + ii) * W + l];
         uint32_t uj[D];
-        load_pos<D>(pos, j, uj);
+#pragma unroll
+        for (int q = 0; q < D; ++q) uj[q] = un[q];
+        if (t + 1 < n) {
+            jn = idx[((size_t)(t + 1) * N + ii) * W + l];
+            load_pos<D>(pos, jn, un);
+        }
+        asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
         float d[D];
         float r2 = pair_r<D>(ui, uj, b, d);
         if (r2 < rc2) {
@@ -169,19 +179,37 @@ __global__ __launch_bounds__(kBlock) void k_nn_force(DevBox b, NNDev p, const ui
     for (int q = 0; q < D; ++q) F[q] = 0.0f;
     int n = live ? min(count[(size_t)ii * W + l], capW) : 0;
     float rc2 = p.r_c * p.r_c;
+    // the next entry's index, position and e row are loaded while the current pair is evaluated
+    int jn = n > 0 ? idx[(size_t)ii * W + l] : ii;
+    uint32_t un[D];
+    load_pos<D>(pos, jn, un);
+    float4 en[kK / 4];
+#pragma unroll
+    for (int k = 0; k < kK / 4; ++k) en[k] = ((const float4 *)(e + (size_t)jn * kK))[k];
     for (int t = 0; t < n; ++t) {
-        int j = idx[((size_t)t * N + ii) * W + l];
         uint32_t uj[D];
-        load_pos<D>(pos, j, uj);
+#pragma unroll
+        for (int q = 0; q < D; ++q) uj[q] = un[q];
+        float4 ej[kK / 4];
+#pragma unroll
+        for (int k = 0; k < kK / 4; ++k) ej[k] = en[k];
+        if (t + 1 < n) {
+            jn = idx[((size_t)(t + 1) * N + ii) * W + l];
+            load_pos<D>(pos, jn, un);
+#pragma unroll
+            for (int k = 0; k < kK / 4; ++k) en[k] = ((const float4 *)(e + (size_t)jn * kK))[k];
+        }
+        asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
         float d[D];
         float r2 = pair_r<D>(ui, uj, b, d);
         if (r2 < rc2) {
             float r = sqrtf(r2);
             float g[kK], dg[kK];
             rbf<true>(p, r, g, dg);
+            const float *ejf = (const float *)ej;
             float coef = 0.0f;
 #pragma unroll
-            for (int k = 0; k < kK; ++k) coef = __builtin_fmaf(ei[k] + e[(size_t)j * kK + k], dg[k], coef);
+            for (int k = 0; k < kK; ++k) coef = __builtin_fmaf(ei[k] + ejf[k], dg[k], coef);
             float fr = -coef / r;
 #pragma unroll
             for (int q = 0; q < D; ++q) F[q] = __builtin_fmaf(fr, d[q], F[q]);
