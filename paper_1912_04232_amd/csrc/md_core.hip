@@ -327,15 +327,67 @@ __device__ __forceinline__ int group_scan(int x, int l, int &tot)
     return incl;
 }
 
+// A lane's place in the stencil table's chunk sequence: entry e, chunk c within it, the entry's first slot cb
+// and member count mc; `have` is false past the last chunk.
+struct ChunkCursor {
+    int e, c, mc;
+    uint32_t cb;
+    bool have;
+};
+
+// The four records of a chunk as separate registers.
+struct Chunk4 {
+    uint32_t x[4], y[4], z[4], j[4];
+};
+
+// The cursor's chunk, W chunks on (entries of the table are ne words apart by ts).
+template <int W>
+__device__ __forceinline__ ChunkCursor chunk_next(ChunkCursor k, const uint32_t *tab, int ts, int ne, uint32_t M)
+{
+    k.c += W;
+    if (k.have) {
+        while (true) {
+            int nch = (k.mc + 3) >> 2;
+            if (k.c < nch) break;
+            k.c -= nch;
+            ++k.e;
+            if (k.e >= ne) {
+                k.have = false;
+                break;
+            }
+            uint32_t en = tab[k.e * ts];
+            k.mc = (int)(en & 255u);
+            k.cb = (en >> 8) * M;
+        }
+    }
+    return k;
+}
+
+// Loads the cursor's chunk (a cursor past the end re-reads slot 0, always mapped): one address, four offsets.
+__device__ __forceinline__ void chunk_load(const ChunkCursor &k, const uint32_t *mem, Chunk4 &r)
+{
+    const uint4 *p = (const uint4 *)mem + (k.have ? k.cb + 4u * (uint32_t)k.c : 0u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint4 v = p[q];
+        r.x[q] = v.x;
+        r.y[q] = v.y;
+        r.z[q] = v.z;
+        r.j[q] = v.w;
+    }
+}
+
 // Row of particle i (Sec. 3.2.3) built by its W lanes; lane l of the particle calls this with the particle's
 // stencil table (ne entries holding `chunks` chunks of four 16-byte member records, one cache line each).
 //
 // The listed cells' records form one flat sequence of chunks; lane l tests chunks l, l + W, l + 2W, ...,
-// loading its next chunk while it tests the current one, so the walk does not stall at cell boundaries.
-// Accepted neighbors are numbered in sequence order (a prefix sum over the W lanes after each round) and
-// dealt round-robin to the interleaved sub-rows: neighbor n goes to sub-row n % W at position n / W, so the
-// W lanes that later share the row differ by at most one entry.  Returns the row length (the same in every
-// lane of the particle; it may exceed the capacity, and only the first `cap` entries are stored).
+// loading its next chunk while it tests the current one (two register sets in turn), so the walk does not
+// stall at cell boundaries.  Accepted neighbors are numbered in sequence order (a prefix sum over the W lanes
+// after each round) and dealt round-robin to the interleaved sub-rows: neighbor n goes to sub-row n % W at
+// position n / W, so the W lanes that later share the row differ by at most one entry.  In a box with one scale
+// s along every axis, r^2 is compared in integer units (the thresholds divided by s^2).  Returns the row length
+// (the same in every lane of the particle; it may exceed the capacity, and only the first `cap` entries are
+// stored).
 template <int D, int W>
 __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
                                          const ListParams &lp, int32_t *__restrict__ idx, const uint32_t *tab, int ts,
@@ -343,81 +395,44 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
 {
     const uint32_t M = (uint32_t)lp.M;
     const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
-    // cursor of this lane: entry e, chunk c within it, the entry's first slot cb and count mc
-    int e = 0, c = l, mc = 0;
-    uint32_t cb = 0;
-    bool have = false;
-    while (e < ne) {
-        uint32_t en = tab[e * ts];
-        mc = (int)(en & 255u);
-        int nch = (mc + 3) >> 2;
-        if (c < nch) {
-            cb = (en >> 8) * M;
-            have = true;
+    const bool iso = b.iso != 0;
+    const float s2 = b.s[0] * b.s[0];
+    const float lo = iso ? lp.rl2f_lo / s2 : lp.rl2f_lo, hi = iso ? lp.rl2f_hi / s2 : lp.rl2f_hi;
+    ChunkCursor ka{0, l, 0, 0u, false};
+    while (ka.e < ne) {
+        uint32_t en = tab[ka.e * ts];
+        ka.mc = (int)(en & 255u);
+        int nch = (ka.mc + 3) >> 2;
+        if (ka.c < nch) {
+            ka.cb = (en >> 8) * M;
+            ka.have = true;
             break;
         }
-        c -= nch;
-        ++e;
+        ka.c -= nch;
+        ++ka.e;
     }
-    // the current chunk's records as separate registers (a chunk past the end re-reads slot 0, always mapped)
-    uint32_t cx[4], cy[4], cz[4], cj[4];
-    {
-        uint32_t base = have ? cb + 4u * (uint32_t)c : 0u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint4 r = rec16(bins.mem, base + q);
-            cx[q] = r.x;
-            cy[q] = r.y;
-            cz[q] = r.z;
-            cj[q] = r.w;
-        }
-    }
-    const int iters = (chunks + W - 1) / W;  // the same in every lane of the particle
     int n = 0;
-    for (int it = 0; it < iters; ++it) {
-        // the lane's next chunk, W chunks on
-        int e2 = e, c2 = c + W, mc2 = mc;
-        uint32_t cb2 = cb;
-        bool have2 = have;
-        if (have2) {
-            while (true) {
-                int nch = (mc2 + 3) >> 2;
-                if (c2 < nch) break;
-                c2 -= nch;
-                ++e2;
-                if (e2 >= ne) {
-                    have2 = false;
-                    break;
-                }
-                uint32_t en = tab[e2 * ts];
-                mc2 = (int)(en & 255u);
-                cb2 = (en >> 8) * M;
-            }
-        }
-        uint32_t nxx[4], nxy[4], nxz[4], nxj[4];
-        {
-            uint32_t base = have2 ? cb2 + 4u * (uint32_t)c2 : 0u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 r = rec16(bins.mem, base + q);
-                nxx[q] = r.x;
-                nxy[q] = r.y;
-                nxz[q] = r.z;
-                nxj[q] = r.w;
-            }
-        }
+    auto test = [&](const Chunk4 &r, const ChunkCursor &k) {
         int bits = 0, band = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const uint32_t uj[3] = {cx[q], cy[q], cz[q]};
+            const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
             float r2 = 0.0f;
+            if (iso) {
 #pragma unroll
-            for (int z = 0; z < D; ++z) {
-                float d = tdisp(ui[z], uj[z], b.s[z]);
-                r2 = __builtin_fmaf(d, d, r2);
+                for (int z = 0; z < D; ++z) {
+                    float d = (float)(int32_t)(ui[z] - uj[z]);
+                    r2 = __builtin_fmaf(d, d, r2);
+                }
+            } else {
+#pragma unroll
+                for (int z = 0; z < D; ++z) {
+                    float d = tdisp(ui[z], uj[z], b.s[z]);
+                    r2 = __builtin_fmaf(d, d, r2);
+                }
             }
-            bits |= r2 < lp.rl2f_lo ? 1 << q : 0;
-            band |= r2 >= lp.rl2f_lo && r2 <= lp.rl2f_hi ? 1 << q : 0;
+            bits |= r2 < lo ? 1 << q : 0;
+            band |= r2 >= lo && r2 <= hi ? 1 << q : 0;
         }
         // candidates within the float guard band of r_list^2 (rare) take the defining double expression; the
         // branch is taken by the whole wave or not at all, so the common path carries no double arithmetic
@@ -425,7 +440,7 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (band & (1 << q)) {
-                    const uint32_t uj[3] = {cx[q], cy[q], cz[q]};
+                    const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
                     double r2d = 0.0;
 #pragma unroll
                     for (int z = 0; z < D; ++z) {
@@ -437,10 +452,10 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
             }
         }
         // records of the chunk that are members (a cell's last chunk may be partial), other than i itself
-        const int left = have ? mc - 4 * c : 0;
+        const int left = k.have ? k.mc - 4 * k.c : 0;
         bits &= left >= 4 ? 15 : (1 << max(left, 0)) - 1;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bits &= (int)cj[q] != i ? 15 : ~(1 << q);
+        for (int q = 0; q < 4; ++q) bits &= (int)r.j[q] != i ? 15 : ~(1 << q);
         // numbering across the particle's lanes: this round's chunks are in lane order
         const int a = __popc(bits);
         int tot;
@@ -452,25 +467,26 @@ __device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const
                 if (slot < (uint32_t)lp.cap) {
                     // byte offset of entry slot (below 4 GiB, checked on the host)
                     uint32_t off = slot / W * row_bytes + ((uint32_t)i * W + slot % W) * 4u;
-                    *(int32_t *)((char *)idx + off) = (int)cj[q];
+                    *(int32_t *)((char *)idx + off) = (int)r.j[q];
                 }
                 ++slot;
             }
         }
         n += tot;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            cx[q] = nxx[q];
-            cy[q] = nxy[q];
-            cz[q] = nxz[q];
-            cj[q] = nxj[q];
-        }
-        e = e2;
-        c = c2;
-        mc = mc2;
-        cb = cb2;
-        have = have2;
+    };
+    const int iters = (chunks + W - 1) / W;  // the same in every lane of the particle
+    Chunk4 A, B;
+    chunk_load(ka, bins.mem, A);
+    int it = 0;
+    for (; it + 2 <= iters; it += 2) {
+        const ChunkCursor kb = chunk_next<W>(ka, tab, ts, ne, M);
+        chunk_load(kb, bins.mem, B);
+        test(A, ka);
+        ka = chunk_next<W>(kb, tab, ts, ne, M);
+        chunk_load(ka, bins.mem, A);
+        test(B, kb);
     }
+    if (it < iters) test(A, ka);
     return n;
 }
 
