@@ -315,6 +315,44 @@ def test_verlet_rectangular_box_vs_oracle(md, orc):
         assert rel_l2(s.force.cpu().numpy(), F) < 1e-4
 
 
+@pytest.mark.parametrize("case", ["2d_square", "2d_rect", "3d_two_species"])
+def test_verlet_lj_variants_vs_oracle(md, orc, case):
+    """LJ through the Verlet step kernel in 2D (square box: integer-unit displacements; rectangular: per-axis
+    scale) and in 3D with two species (species of neighbors through the range-checked loads)."""
+    say("verlet lj", case)
+    if case == "3d_two_species":
+        counts, a = (12, 12, 12), 1.12
+        sigma, eps = [[1.0, 1.05], [1.05, 1.1]], [[1.0, 0.8], [0.8, 1.2]]
+    else:
+        counts = (40, 40) if case == "2d_square" else (44, 34)
+        a = 1.08
+        sigma, eps = [[1.0]], [[1.0]]
+    dim = len(counts)
+    L = [inputs.f32(n * a) for n in counts] + [0.0] * (3 - dim)
+    N = int(np.prod(counts))
+    u = inputs.jittered_grid_torus(counts, 0.12, 95)
+    cfg = dict(N=N, dim=dim, L=L, u=u, v=inputs.maxwell_velocities(N, dim, 0.8, 96), kind="lj", sigma=sigma,
+               epsilon=eps, r_cut=2.5, skin=0.3)
+    if len(sigma) > 1:
+        cfg["species"] = inputs.bidisperse_species(N)
+    s = make_system(md, cfg)
+    init, update = md.nve(s, 0.004)
+    init()
+    x = orc.decode(cfg["u"], cfg["L"][:dim])
+    p = orc_pot(orc, cfg)
+    sp = cfg.get("species")
+    F, _, _ = orc.pair_rows(x, cfg["L"][:dim], p, sp) if sp is not None else orc.pair_rows(x, cfg["L"][:dim], p)
+    assert rel_l2(s.force.cpu().numpy(), F) < F_TOL
+    v = cfg["v"].astype(np.float64)
+    update(3)
+    if sp is not None:
+        x, v, F = orc.verlet(x, v, F, cfg["L"][:dim], p, 0.004, 3, sp)
+    else:
+        x, v, F = orc.verlet(x, v, F, cfg["L"][:dim], p, 0.004, 3)
+    assert rel_l2(s.force.cpu().numpy(), F) < 1e-4
+    assert rel_l2(s.vel.cpu().numpy(), v) < 1e-5
+
+
 def test_verlet_rebuilds_keep_every_pair(md, orc):
     """Over 300 steps with device-side rebuilds the list always contains every pair inside the cutoff and the
     final forces agree with a fresh evaluation from a fresh list (a fresh build orders rows differently, so the
