@@ -880,6 +880,14 @@ __global__ __launch_bounds__(kBlock) void k_pair_dense(DevBox b, DevPot p, const
 // velocity Verlet
 
 // Shift (Sec. 3.2.1) by a real displacement: add its nearest whole number of 2^-32 L units (wraps mod 2^32).
+// Value q of up to three by selects (no dynamic indexing, no address taken).
+template <int D, typename T>
+__device__ __forceinline__ T pick(int q, T v0, T v1, T v2)
+{
+    if constexpr (D == 3) return q == 0 ? v0 : (q == 1 ? v1 : v2);
+    else return q == 0 ? v0 : v1;
+}
+
 __device__ __forceinline__ uint32_t shift_coord(uint32_t u, float dx, float inv_s)
 {
     return u + (uint32_t)__float2int_rn(dx * inv_s);
@@ -1033,6 +1041,46 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 #pragma unroll
     for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
     wave_flag(live && bad, &a.flags[MD_FLAG_NONFINITE]);
+    if constexpr (W >= D) {
+        // every lane of the particle holds the summed force: lane q < D updates coordinate q
+        if (!live) return;
+        const int q = l < D ? l : 0;
+        const float Fq = pick<D>(q, F[0], F[1], F[D - 1]);
+        const float sq = pick<D>(q, a.box.s[0], a.box.s[1], a.box.s[2]);
+        const float isq = pick<D>(q, a.box.inv_s[0], a.box.inv_s[1], a.box.inv_s[2]);
+        const uint32_t uq = pick<D>(q, ui[0], ui[1], ui[D - 1]);
+        const size_t at = (size_t)i * D + q;
+        float dq2 = 0.0f, st2 = 0.0f, f2q = 0.0f;
+        if (l < D) {
+            if (a.last) {
+                a.vel[at] = __builtin_fmaf(0.5f * a.dt, Fq, a.vel[at]);
+                a.force[at] = Fq;
+            } else {
+                const float v = __builtin_fmaf(a.dt, Fq, a.vel[at]);
+                a.vel[at] = v;
+                const float dx = a.dt * v;
+                const uint32_t un = shift_coord(uq, dx, isq);
+                a.pos_out[at] = un;
+                const float d = tdisp(un, g.pos_ref[at], sq);
+                dq2 = d * d;
+                st2 = dx * dx;
+                f2q = Fq * Fq;
+            }
+        }
+        if (a.last || mode != M_IDLE) return;
+        // |r(s+1) - r_ref|^2, |step|^2 and |F|^2 summed over the particle's lanes
+#pragma unroll
+        for (int o = 1; o < W; o <<= 1) {
+            dq2 += __shfl_xor(dq2, o, W);
+            st2 += __shfl_xor(st2, o, W);
+            f2q += __shfl_xor(f2q, o, W);
+        }
+        if (l == 0) {
+            float ahead = sqrtf(st2) + a.dt * a.dt * sqrtf(f2q);
+            if (sqrtf(dq2) + lp.kappa * ahead > lp.half_skin) a.ctl[6 + (a.step + 1) % 3] = 1;
+        }
+        return;
+    }
     if (!live || l != 0) return;
     if (a.last) {
 #pragma unroll
