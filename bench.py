@@ -320,7 +320,14 @@ def main():
     # dominant kernel: one k_md_step launch per step; its algorithmic bytes with the implemented layout:
     # own position read 12 B, velocity read+write 24 B, new position write 12 B, reference position read 12 B,
     # row length 4 B, and 4 B per list entry; neighbor positions are gathers served by cache.
-    bytes_per_launch = N * (12 + 24 + 12 + 12 + 4) + 4.0 * float(counts.sum())
+    step_bytes = N * (12 + 24 + 12 + 12 + 4) + 4.0 * float(counts.sum())
+    # a rebuild (its bin step and build step) adds, once per rebuild: positions read 12 B and previous bin
+    # indices 4 B, bin records written 16 B and read back 16 B, reference positions written 12 B and read 12 B,
+    # row lengths written 4 B per lane, and every list entry written (4 B each); candidate records re-read by
+    # neighboring particles are served by cache.  Amortized over the measured rebuilds of the timed region.
+    rebuilds = int(s.last_flags[md.FLAG_REBUILDS])
+    rebuild_bytes = N * (12 + 4 + 16 + 16 + 12 + 12 + 4 * s.nl.lanes) + 4.0 * float(counts.sum())
+    bytes_per_launch = step_bytes + rebuild_bytes * rebuilds / args.steps
     kernel_s = gpu_ms * 1e-3 / args.steps
     achieved = bytes_per_launch / kernel_s / 1e9
     traffic = measured_traffic(f"k_md_step<3,0,false,{s.nl.lanes}>")
@@ -354,7 +361,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": f"k_md_step<3,0,false,{s.nl.lanes}>",
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": kernel_s * 1e6},
+                     "bytes_per_launch": bytes_per_launch, "step_bytes": step_bytes,
+                     "rebuild_bytes": rebuild_bytes, "rebuilds": rebuilds, "avg_launch_us": kernel_s * 1e6},
         "cpu_baseline": None,
     }
     if not args.no_secondary:
