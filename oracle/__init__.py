@@ -258,3 +258,21 @@ def diameter_grad(x, L, diameters, epsilon, species, alpha: float = 2.0):
             g[a] += 0.5 * gs[a, b]
             g[b] += 0.5 * gs[a, b]
     return g
+
+
+def rescaled_box_grad(u, L, D: float, species, epsilon: float = 1.0, alpha: float = 2.0):
+    """(U, dU/dD) for the bidisperse disks of Sec. 4.2 / App. A: species 0 has diameter D and species 1 diameter 1
+    (sigma_ab = (d_a + d_b)/2), and the square box edge follows the packing-fraction law L(D) ~ sqrt(D^2 + 1), so at
+    fixed fractional positions s = u / 2^32 every distance scales with L.  The derivative at fixed s is the
+    derivative in the diameters at fixed real positions plus the box term (dL/dD)/L * sum_pairs r du/dr, with
+    (dL/dD)/L = D / (D^2 + 1).  L is the box edge at D (the caller's value)."""
+    d = np.array([D, 1.0])
+    x = decode(u, [L, L])
+    sig = 0.5 * (d[:, None] + d[None, :])
+    pot = Potential("soft_sphere", sig, np.full((2, 2), float(epsilon)), alpha=alpha)
+    g = diameter_grad(x, [L, L], d, epsilon, species, alpha)
+    _, e, w = pair_rows(x, [L, L], pot, species)
+    U = math.fsum(e)
+    W = math.fsum(w)   # sum over pairs of -r du/dr
+    return U, float(g[0]) - D / (D * D + 1.0) * W
+

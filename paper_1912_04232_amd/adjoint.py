@@ -10,6 +10,15 @@ R*: at a converged minimum F(R*) = 0, so by the envelope theorem
 which is the derivative the unrolled reverse pass converges to as max |F| -> 0.  Soft-sphere diameters
 enter through sigma_ab = (d_a + d_b) / 2 (App. A), so dE*/dd_s = 1/2 sum_b (G_sb + G_bs) with
 G_ab = dU/dsigma_ab per ordered species pair.  The box is held fixed while the diameters change.
+
+``rescaled_box_sweep`` is the experiment of Sec. 4.2 with the box of App. A: half the disks have diameter D and
+half diameter 1, and the box edge follows the packing fraction, L(D) ~ sqrt(D^2 + 1), so positions are fractional
+and every distance scales with L.  At a minimum s* in fractional coordinates the envelope theorem gives
+
+    dE*/dD = dU/dD (s*; D) = G_AA + (G_AB + G_BA)/2 - D/(D^2 + 1) * W,
+
+where the last term is the box's: W = sum over pairs of -r du/dr.  The harmonic soft sphere depends on r/sigma
+only, so W = sum_ab sigma_ab G_ab and the GPU's parameter-gradient sums give it with no further pass.
 """
 from __future__ import annotations
 
@@ -61,3 +70,39 @@ def minimized_energy(diameters: torch.Tensor, epsilon: torch.Tensor, batch: "md.
     """E*_b for every replica, differentiable w.r.t. the species diameters and epsilon (box fixed)."""
     return FireMinimizedEnergy.apply(diameters, epsilon, batch_u, batch, fp or md.FireParams(), f_tol, max_steps,
                                      md_ctx or md.Context(), alpha)
+
+
+def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: "md.FireParams | None" = None,
+                       f_tol: float = 1e-6, max_steps: int = 200000, epsilon: float = 1.0, alpha: float = 2.0):
+    """For every small-disk diameter D and every start (uint32 fractional positions [N][2], N even; the first N/2
+    disks are the small ones): minimize with batched FIRE in the box of packing fraction phi, then return per D the
+    minimized energies E*, dE*/dD with the box rescaled with D (see the module docstring), max |F|, the FIRE step
+    counts and the status words, as numpy arrays [len(D)][len(starts)]; also the batches (minimized positions)."""
+    from . import inputs
+    fp = fp or md.FireParams()
+    out = {k: [] for k in ("energy", "dEdD", "fmax", "steps", "status")}
+    batches = []
+    for D in diameters:
+        D = float(D)
+        reps = []
+        for u in starts:
+            N = int(u.shape[0])
+            L = inputs.box_for_packing([D, 1.0], [N // 2, N - N // 2], phi, 2)
+            reps.append(dict(N=N, L=[L, L, 0.0], u=u, species=inputs.bidisperse_species(N)))
+        bt = md.Batch(reps)
+        d = np.array([D, 1.0])
+        sig = sigma_from_diameters(d)
+        pot = md.Potential("soft_sphere", sig, np.full((2, 2), float(epsilon)), alpha=alpha)
+        e, fmax, steps, status = md.fire_batched(md_ctx, bt, pot, fp, max_steps, f_tol)
+        gs, _, _ = md.envelope_grad(md_ctx, bt, pot)
+        G = gs.cpu().numpy()
+        dsig = np.array([[1.0, 0.5], [0.5, 0.0]])   # d sigma_ab / dD
+        W = (G * sig[None]).sum(axis=(1, 2))
+        out["energy"].append(e.cpu().numpy())
+        out["dEdD"].append((G * dsig[None]).sum(axis=(1, 2)) - D / (D * D + 1.0) * W)
+        out["fmax"].append(fmax.cpu().numpy())
+        out["steps"].append(steps.cpu().numpy())
+        out["status"].append(status.cpu().numpy())
+        batches.append(bt)
+    return {k: np.array(v) for k, v in out.items()}, batches
+

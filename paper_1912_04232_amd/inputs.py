@@ -189,6 +189,13 @@ def ss_batch(B: int = 64, seed: int = 4001, n_lo: int = 256, n_hi: int = 4096, p
     return reps
 
 
+def rescaled_box_starts(count: int = 100, N: int = 128, seed: int = 7001):
+    """Random starts for the small-disk-diameter sweep (Sec. 4.2, App. A): `count` configurations of N disks,
+    fractional positions uniform in the unit square (as uint32 torus coordinates, so one start serves every box)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.integers(0, 2 ** 32, size=(N, 2), dtype=np.uint64).astype(np.uint32) for _ in range(count)]
+
+
 def lj_train_box(N: int = 4000, rho: float = 0.84) -> float:
     return box_for_density(N, rho)
 

@@ -168,3 +168,60 @@ def test_batch_of_uneven_sizes_full_range(md):
         "converged", int((status == 1).sum()))
     assert (status == 1).all()
     assert (fmax < 1e-6).all()
+
+
+# ------------------------------------------------------------ box rescaled with the small-disk diameter
+
+def fig3_starts(n, count, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64).astype(np.uint32) for _ in range(count)]
+
+
+def test_rescaled_box_grad_matches_oracle(md, orc):
+    """dE*/dD with the box rescaled with D (App. A) at the GPU's minima against the FP64 oracle at the same
+    positions, for several D around the disorder maximum."""
+    from paper_1912_04232_amd import adjoint
+    ctx = md.Context()
+    starts = fig3_starts(64, 4, 5101)
+    Ds = [0.6, 0.8, 1.0]
+    res, batches = adjoint.rescaled_box_sweep(ctx, Ds, starts, 0.9)
+    assert (res["status"] == 1).all() and (res["fmax"] < 1e-6).all()
+    for k, D in enumerate(Ds):
+        for b in range(len(starts)):
+            u = batches[k].replica_positions(b)
+            L = float(batches[k].boxes[b][0])
+            U, g = orc.rescaled_box_grad(u, L, D, inputs.bidisperse_species(64))
+            say("D", D, "b", b, "E", res["energy"][k][b], U, "dE/dD", res["dEdD"][k][b], g)
+            assert abs(res["energy"][k][b] - U) <= 1e-6 * max(abs(U), 1e-12) + 1e-12
+            assert abs(res["dEdD"][k][b] - g) <= 1e-5 * max(abs(g), 1e-3)
+
+
+def test_rescaled_box_grad_matches_fd_through_minimization(md, orc):
+    """The GPU's envelope gradient at its minimum s* equals the central difference of the minimized energy
+    E*(D +- h), each minimized by the oracle's FP64 FIRE from s* in the box of D +- h (so it follows that minimum;
+    a float32 re-minimization resolves E* only to ~1e-7, too coarse for h = 1e-5 at 64 disks)."""
+    import math
+
+    from paper_1912_04232_amd import adjoint
+    ctx = md.Context()
+    N, phi = 64, 0.9
+    starts = fig3_starts(N, 3, 5202)
+    sp = inputs.bidisperse_species(N)
+    D, h = 0.8, 1e-5
+    res, batches = adjoint.rescaled_box_sweep(ctx, [D], starts, phi, f_tol=1e-7)
+
+    def e_star(u, Dx):
+        L = math.sqrt((N // 2) * math.pi * (Dx * Dx + 1.0) / 4.0 / phi)
+        d = np.array([Dx, 1.0])
+        pot = orc.Potential("soft_sphere", 0.5 * (d[:, None] + d[None, :]), np.ones((2, 2)), alpha=2.0)
+        r = orc.fire(orc.decode(u, [L, L]), [L, L], pot, sp, max_steps=400000, f_tol=1e-10)
+        assert r["converged"]
+        return orc.energy(r["x"], [L, L], pot, sp)
+
+    for b in range(len(starts)):
+        u = batches[0].replica_positions(b)
+        fd = (e_star(u, D + h) - e_star(u, D - h)) / (2 * h)
+        g = res["dEdD"][0][b]
+        say("b", b, "fd", fd, "envelope", g, "E", res["energy"][0][b])
+        assert res["energy"][0][b] > 0
+        assert abs(fd - g) <= 1e-4 * abs(g) + 1e-7

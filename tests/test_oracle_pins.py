@@ -458,6 +458,26 @@ def test_param_grad_identities(orc):
     assert math.isclose(float(g @ d), math.fsum(w), rel_tol=1e-12)
 
 
+def test_rescaled_box_grad_matches_fd(orc):
+    """dU/dD at fixed fractional positions for the bidisperse disks whose box follows the packing-fraction law
+    (App. A): central differences of U with the box edge and sigma both recomputed at D +- h."""
+    rng = np.random.default_rng(12)
+    N, phi = 64, 0.9
+    u = rng.integers(0, 2 ** 32, size=(N, 2), dtype=np.uint64).astype(np.uint32)
+    sp = inputs.bidisperse_species(N)
+
+    def box(D):  # the packing-fraction law in float64: N/2 disks of each diameter
+        return math.sqrt((N // 2) * math.pi * (D * D + 1.0) / 4.0 / phi)
+
+    for D in (0.6, 0.8, 1.0, 1.3):
+        U, g = orc.rescaled_box_grad(u, box(D), D, sp)
+        h = 1e-6
+        Up, _ = orc.rescaled_box_grad(u, box(D + h), D + h, sp)
+        Um, _ = orc.rescaled_box_grad(u, box(D - h), D - h, sp)
+        assert U > 0
+        assert math.isclose(g, (Up - Um) / (2 * h), rel_tol=1e-6, abs_tol=1e-9), (D, g, (Up - Um) / (2 * h))
+
+
 # ----------------------------------------------------------------------- inputs
 
 def test_workload_boxes():
