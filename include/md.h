@@ -297,6 +297,55 @@ md_status envelope_grad(md_ctx *ctx, const md_batch *batch, const md_potential *
                         double *g_eps, double *energy, int32_t *status, void *stream);
 
 /*
+ * Bytes of device workspace fire_unrolled_grad needs for B replicas holding
+ * total_n particles in all and K steps: 40 K B bytes of step records
+ * (rounded up to a multiple of 256), then 24 (K + 1) total_n bytes of
+ * particle records.  0 for a negative argument.
+ */
+uint64_t fire_unrolled_workspace_bytes(int32_t B, int64_t total_n, int32_t K);
+
+/*
+ * Reverse mode through K FIRE steps.  Sec. 4.2 differentiates the minimized
+ * energy by differentiating through the minimizer; App. A does so for a fixed
+ * 300 FIRE steps on 128 disks whose box is rescaled with the small diameter.
+ * For every replica of the batch: K steps with the rules of fire_batched
+ * (v = 0, dt_start, alpha_start at the start; no convergence test) from the
+ * batch positions, then E_K = U(x_K) and its derivatives by transposing the
+ * steps in reverse order.  The branch decisions (P > 0) and the dt / alpha
+ * schedule are held fixed, as automatic differentiation of the loop does.
+ * Outputs, all device arrays:
+ *   energy [B]             E_K
+ *   g_sigma, g_eps [B][S*S] dE_K / d entry (a,c) of the ordered species
+ *                          matrices; a symmetric parameter is the (a,c) plus
+ *                          the (c,a) value, and sigma_ab = (d_a + d_b)/2 turns
+ *                          them into per-species diameter derivatives
+ *   g_lnc [B]              dE_K / d ln c for the box scaled to c L at fixed
+ *                          fractional start positions u / 2^32 and fixed time
+ *                          parameters (App. A's rescaled box)
+ *   rbar0 [offset[B]][2]   dE_K / dR_0 in fractional coordinates R = u / 2^32,
+ *                          or NULL
+ *   mixed [B][K]           1 where step k had P > 0, else 0; or NULL
+ *   status [B]             1 done, -1 replica above 256 particles, -2 the
+ *                          workspace is too small for the replica; or NULL
+ * The batch positions are left at R_K.  workspace is caller-owned device
+ * memory of fire_unrolled_workspace_bytes(B, offset[B], K) bytes.  It
+ * receives the trajectory: for replica b, K records of 5 doubles (dt, alpha,
+ * |w|, |F'|, P > 0) at byte 40 K b, and from byte
+ * round256(40 K B) + 24 (K + 1) offset[b], one block of 24 n_b bytes per
+ * state k = 0..K: positions u_k [n_b][2] uint32, forces F_k [n_b][2] float,
+ * pre-mixing velocities w_k [n_b][2] float.
+ * One wavefront per replica, dense pair sums over the nearest image.  Soft
+ * sphere or LJ with S <= 4 and symmetric positive sigma / epsilon
+ * (MD_ERR_ARG otherwise); max_n <= 256 (MD_ERR_CAPACITY otherwise).  Pair
+ * arithmetic is single precision (the soft-sphere overlap from the double
+ * distance); reductions, step scalars and parameter sums are double.
+ */
+md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const md_fire_params *fp,
+                             int32_t K, void *workspace, uint64_t workspace_bytes, double *energy, double *g_sigma,
+                             double *g_eps, double *g_lnc, float *rbar0, uint8_t *mixed, int32_t *status,
+                             void *stream);
+
+/*
  * Neural pair potential (Sec. 3.2.4 featurizations, Sec. 4.1 per-atom networks, forces as -grad E by
  * Sec. 3.3.2): K = 16 radial basis functions
  *   G_i^k = sum_{j != i, r_ij < r_c} exp(-eta (r_ij - mu_k)^2) (cos(pi r_ij / r_c) + 1)/2,

@@ -105,6 +105,9 @@ _SIGNATURES = {
     "fire_batched": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
                      ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
     "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
+    "fire_unrolled_workspace_bytes": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32],
+    "fire_unrolled_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
+                           ctypes.c_int32, P, ctypes.c_uint64, P, P, P, P, P, P, P, P],
     "nn_descriptors": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32,
                        ctypes.POINTER(c_nlist), P, P],
     "nn_mlp": [P, ctypes.POINTER(c_nn_params), P, ctypes.c_int32, P, P, P],
@@ -133,11 +136,14 @@ _SIGNATURES = {
 }
 
 
+_RESTYPES = {"md_version": ctypes.c_char_p, "fire_unrolled_workspace_bytes": ctypes.c_uint64}
+
+
 def header_functions(path: str = HEADER):
     """Names of the functions declared in include/md.h."""
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:md_status|int32_t|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", text,
+    return sorted(set(re.findall(r"^\s*(?:md_status|int32_t|uint64_t|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", text,
                                  flags=re.M)))
 
 
@@ -151,7 +157,7 @@ def load(path: str = LIB_PATH):
         for name, args in _SIGNATURES.items():
             f = getattr(lib, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name == "md_version" else ctypes.c_int
+            f.restype = _RESTYPES.get(name, ctypes.c_int)
         _lib = lib
     return _lib
 
@@ -519,6 +525,47 @@ def envelope_grad(ctx: Context, batch: Batch, pot: Potential):
     _check("envelope_grad", load().envelope_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(gs), _ptr(ge),
                                                  _ptr(e), None, _stream()))
     return gs[: batch.B], ge[: batch.B], e[: batch.B]
+
+
+def fire_unrolled_grad(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, K: int, rbar0: bool = False,
+                       mixed: bool = False, workspace=None):
+    """K FIRE steps on every replica, then dE_K/dtheta by reverse mode through the steps (one launch).
+
+    Returns a dict of device tensors: energy [B] f64, g_sigma and g_eps [B][S][S] f64 (ordered entries),
+    g_lnc [B] f64 (box scale at fixed fractional start), status [B] i32, and when asked rbar0 [total][2] f32
+    (dE_K/dR_0, fractional) and mixed [B][K] u8 (P > 0 per step).  The batch positions end at R_K.  The
+    trajectory workspace is allocated here unless a uint8 device tensor of at least
+    fire_unrolled_workspace_bytes bytes is passed; it is returned as "workspace".
+    """
+    lib = load()
+    dev = batch.pos.device
+    total = int(sum(batch.sizes))
+    need = int(lib.fire_unrolled_workspace_bytes(batch.B, total, int(K)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    S = pot.n_species
+    B1 = max(batch.B, 1)
+    out = {
+        "energy": torch.zeros(B1, dtype=torch.float64, device=dev),
+        "g_sigma": torch.zeros((B1, S, S), dtype=torch.float64, device=dev),
+        "g_eps": torch.zeros((B1, S, S), dtype=torch.float64, device=dev),
+        "g_lnc": torch.zeros(B1, dtype=torch.float64, device=dev),
+        "status": torch.zeros(B1, dtype=torch.int32, device=dev),
+    }
+    rb = torch.zeros((max(total, 1), 2), dtype=torch.float32, device=dev) if rbar0 else None
+    mx = torch.zeros((B1, max(int(K), 1)), dtype=torch.uint8, device=dev) if mixed else None
+    b, p, f = batch.c(pot.cutoff()), pot.c(), fp.c()
+    _check("fire_unrolled_grad", lib.fire_unrolled_grad(
+        ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f), int(K), _ptr(workspace), workspace.numel(),
+        _ptr(out["energy"]), _ptr(out["g_sigma"]), _ptr(out["g_eps"]), _ptr(out["g_lnc"]), _ptr(rb), _ptr(mx),
+        _ptr(out["status"]), _stream()))
+    res = {k: v[: batch.B] for k, v in out.items()}
+    if rb is not None:
+        res["rbar0"] = rb[:total]
+    if mx is not None:
+        res["mixed"] = mx[: batch.B, : int(K)]
+    res["workspace"] = workspace
+    return res
 
 
 class NNParams:

@@ -53,3 +53,20 @@ def test_argument_errors_are_returned_synchronously():
     assert lib.nl_build(None, ctypes.byref(b), None, 0, None, None) == -1
     assert lib.md_ctx_reserve(None, 10, 3, 1, 1, 1, 1) == -1
     assert lib.md_sum(None, None, 0, None, None) == -1
+
+
+def test_unrolled_fire_workspace_size_and_argument_errors():
+    lib = md.load()
+    B, total, K = 3, 300, 10
+    rec = (40 * K * B + 255) // 256 * 256
+    assert lib.fire_unrolled_workspace_bytes(B, total, K) == rec + 24 * (K + 1) * total
+    assert lib.fire_unrolled_workspace_bytes(0, 0, 0) == 0
+    assert lib.fire_unrolled_workspace_bytes(-1, 5, 5) == 0
+    pot = md.Potential("soft_sphere", ((1.0,),), ((1.0,),), alpha=2.0).c()
+    fp = md.FireParams().c()
+    b = md.c_batch()
+    b.B, b.dim, b.max_n = 1, 2, 10
+    args = [ctypes.byref(b), ctypes.byref(pot), ctypes.byref(fp), 5, None, 0] + [None] * 7 + [None]
+    assert lib.fire_unrolled_grad(None, *args) == -1           # no context
+    b.dim = 3
+    assert lib.fire_unrolled_grad(None, *args) == -1

@@ -1,0 +1,308 @@
+"""Reverse mode through fixed-K FIRE on the GPU (fire_unrolled_grad) against the FP64 oracle on the same
+seeded inputs: final energies, every parameter derivative, dE_K/dR_0 and the branch record."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_04232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1912_04232_amd import md as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def un():
+    from oracle import unrolled
+    return unrolled
+
+
+def sigma_of(d):
+    d = np.asarray(d, dtype=np.float64)
+    return 0.5 * (d[:, None] + d[None, :])
+
+
+def pots(md, orc, kind="soft_sphere", d=(1.0, 1.4), eps=((1.0, 0.8), (0.8, 1.2))):
+    if kind == "lj":
+        s, e = np.array([[1.0, 0.9], [0.9, 0.8]]), np.array([[1.0, 1.5], [1.5, 0.5]])
+        return (md.Potential("lj", s, e, r_cut=2.5, shift=True), orc.Potential("lj", s, e, r_cut=2.5, shift=True))
+    s, e = sigma_of(d), np.asarray(eps, dtype=np.float64)
+    return md.Potential("soft_sphere", s, e, alpha=2.0), orc.Potential("soft_sphere", s, e, alpha=2.0)
+
+
+def disks(N, phi, seed, d=(1.0, 1.4), stretch=1.0):
+    L = inputs.box_for_packing(list(d), [N // 2, N - N // 2], phi, 2) if N > 0 else 5.0
+    return dict(N=N, L=np.array([L, L * stretch, 0.0]), u=inputs.uniform_torus(N, 2, seed),
+                species=inputs.bidisperse_species(N))
+
+
+def fire_params(orc, dt_start=0.1, dt_max=0.4):
+    """The oracle's FIRE parameters at exactly the values the kernel receives (md_fire_params holds floats)."""
+    f = lambda x: float(np.float32(x))
+    p = orc.FireParams(dt_start=dt_start, dt_max=dt_max)
+    return orc.FireParams(dt_start=f(p.dt_start), dt_max=f(p.dt_max), n_min=p.n_min, f_inc=f(p.f_inc),
+                          f_dec=f(p.f_dec), alpha_start=f(p.alpha_start), f_alpha=f(p.f_alpha))
+
+
+def run(md, reps, pot, K, dt=(0.1, 0.4), **kw):
+    ctx = md.Context()
+    bt = md.Batch(reps)
+    res = md.fire_unrolled_grad(ctx, bt, pot, md.FireParams(dt_start=dt[0], dt_max=dt[1]), K, rbar0=True,
+                                mixed=True, **kw)
+    out = {k: v.cpu().numpy() for k, v in res.items()}
+    out["uK"] = [bt.replica_positions(b) for b in range(len(reps))]
+    out["offset"] = bt.offset.cpu().numpy()
+    return out
+
+
+def gpu_state_positions(out, B, K, b, n):
+    """Positions u_k [K+1][n][2] the kernel recorded for replica b (workspace layout of include/md.h)."""
+    ws = out["workspace"]
+    base = (40 * K * B + 255) // 256 * 256 + 24 * (K + 1) * int(out["offset"][b])
+    return np.stack([ws[base + 24 * n * k: base + 24 * n * k + 8 * n].view(np.uint32).reshape(n, 2)
+                     for k in range(K + 1)])
+
+
+def contact_sets(R_states, L, cut):
+    """Boolean [K+1][n][n]: r_ij < cut (the pair is inside the range where u'' is the smooth branch)."""
+    Lv = np.asarray(L, dtype=np.float64)
+    out = []
+    for R in R_states:
+        d = (R[:, None, :] - R[None, :, :])
+        d -= np.round(d)
+        r = np.sqrt(((d * Lv) ** 2).sum(-1))
+        np.fill_diagonal(r, np.inf)
+        out.append(r < cut)
+    return np.array(out)
+
+
+def compare(un, opot, orc, reps, out, K, tol, min_strict=1, band=None, dt=(0.1, 0.4), branch_noise=False):
+    """Element-wise comparison with the oracle on the same seeded inputs.
+
+    E_K, R_K and the branch record are continuous (or integer) functions of the run and are compared for every
+    replica.  The parameter derivatives also depend on which pairs are in contact at each state (u'' jumps at
+    r = sigma, the force at an LJ cutoff): where a pair sits closer to contact than the float32 and float64
+    trajectories differ, the two runs take different branches of a piecewise-smooth function and both are
+    correct.  The gradients are compared where the contact sets of the recorded GPU states and of the oracle's
+    states agree at every step, and at least `min_strict` replicas must qualify.  With `band`, the gradients are
+    instead held to a band set by linear response: the oracle is run again from a start moved by one position
+    quantum (2^-32 of the box, the GPU's resolution); the change of its gradient, scaled by how much further the
+    GPU's final positions lie from the oracle's than the moved run's do, times `band`, plus tol.  With
+    `branch_noise`, a replica whose P > 0 record differs (a decision taken inside float32 noise) is compared on
+    E_K and R_K only, at 1e-3, and does not count towards `min_strict`.
+    """
+    worst = {}
+    strict = 0
+    off = 0
+    fp = fire_params(orc, *dt)
+    B = len(out["energy"])
+    for b, r in enumerate(reps):
+        n = r["N"]
+        L = r["L"][:2]
+        R0 = un.torus_to_frac(r["u"])
+        o = un.fire_unrolled_grad(R0, L, opot, r["species"], K, fp)
+        assert out["status"][b] == 1
+        dR = un.torus_to_frac(out["uK"][b]) - o["traj"]["R"][K]
+        dR -= np.round(dR)
+        errs = {"E": abs(out["energy"][b] - o["E"]) / max(abs(o["E"]), 1e-9), "R_K": np.abs(dR).max()}
+        if not np.array_equal(out["mixed"][b].astype(bool), o["traj"]["mixed"]):
+            first = int(np.argmax(out["mixed"][b].astype(bool) != o["traj"]["mixed"]))
+            say("replica", b, "N", n, "K", K, "P > 0 record differs from step", first, errs)
+            assert branch_noise, (b, first)
+            assert errs["E"] <= 1e-3 and errs["R_K"] <= 1e-3, (b, errs)
+            off += n
+            continue
+        _, sig, _ = un._pair_table(opot, r["species"], n)
+        cut = sig if opot.kind == "soft_sphere" else opot.r_cut
+        R_gpu = gpu_state_positions(out, B, K, b, n).astype(np.float64) / 2.0 ** 32
+        same = np.array_equal(contact_sets(R_gpu, L, cut), contact_sets(o["traj"]["R"], L, cut))
+        if band is not None:
+            rng = np.random.Generator(np.random.PCG64(9000 + b))
+            kick = rng.choice([-1.0, 1.0], size=R0.shape) / 2.0 ** 32
+            o2 = un.fire_unrolled_grad(R0 + kick, L, opot, r["species"], K, fp)
+            assert np.array_equal(o2["traj"]["mixed"], o["traj"]["mixed"])
+            dk = o2["traj"]["R"][K] - o["traj"]["R"][K]
+            dk -= np.round(dk)
+            resp = max(1.0, errs["R_K"] / max(np.abs(dk).max(), 1e-30))
+            for k in ("g_sigma", "g_eps"):
+                spread = np.abs(o2[k] - o[k]).max() * resp
+                diff = np.abs(out[k][b] - o[k]).max()
+                scale = np.abs(o[k]).max()
+                say("  ", k, "gpu-oracle %.2e" % (diff / scale), "scaled spread %.2e" % (spread / scale),
+                    "response x%.1f" % resp)
+                assert diff <= band * spread + tol[k] * scale, (b, k, diff, spread)
+            spread = abs(o2["g_lnc"] - o["g_lnc"]) * resp
+            diff = abs(out["g_lnc"][b] - o["g_lnc"])
+            say("   g_lnc gpu-oracle %.2e" % (diff / abs(o["g_lnc"])), "scaled spread %.2e" % (spread / abs(o["g_lnc"])))
+            assert diff <= band * spread + tol["g_lnc"] * abs(o["g_lnc"]), (b, diff, spread)
+            strict += 1
+        elif same:
+            strict += 1
+            errs.update({
+                "g_sigma": np.abs(out["g_sigma"][b] - o["g_sigma"]).max() / max(np.abs(o["g_sigma"]).max(), 1e-9),
+                "g_eps": np.abs(out["g_eps"][b] - o["g_eps"]).max() / max(np.abs(o["g_eps"]).max(), 1e-9),
+                "g_lnc": abs(out["g_lnc"][b] - o["g_lnc"]) / max(abs(o["g_lnc"]), 1e-9),
+                "rbar0": np.abs(out["rbar0"][off:off + n] - o["Rbar0"]).max() / max(np.abs(o["Rbar0"]).max(), 1e-9),
+            })
+        say("replica", b, "N", n, "K", K, "same contacts" if same else "contact event inside float32 noise",
+            {k: float("%.2e" % v) for k, v in errs.items()})
+        for k, v in errs.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+            assert v <= tol[k], (b, k, v)
+        off += n
+    assert strict >= min_strict, strict
+    return worst
+
+
+# float32 pair arithmetic and positions on a 2^-32 grid against FP64 with the same float-valued parameters: one
+# step agrees to a few ulp of the sums; the trajectories then separate slowly (FIRE's mixing and resets feed
+# rounding back), so the bound is set per horizon.
+TOL_SHORT = dict(E=2e-5, g_sigma=5e-5, g_eps=5e-5, g_lnc=5e-5, rbar0=5e-5, R_K=1e-6)
+TOL_LONG = dict(E=1e-3, g_sigma=3e-3, g_eps=3e-3, g_lnc=3e-3, rbar0=1e-2, R_K=1e-4)
+
+
+@pytest.mark.parametrize("K", [0, 1, 10, 60])
+def test_unrolled_matches_oracle_ragged_batch(md, orc, un, K):
+    """Uneven replicas (128 = App. A's size, 100, 37, 1 and an empty one) in one launch."""
+    reps = [disks(128, 0.9, 7001 + K), disks(100, 0.85, 7002 + K), disks(37, 0.9, 7003 + K, stretch=1.2),
+            disks(1, 0.5, 7004), disks(0, 0.5, 7005)]
+    reps[3]["species"] = np.array([1], dtype=np.int32)
+    reps[4]["species"] = np.zeros(0, dtype=np.int32)
+    mpot, opot = pots(md, orc)
+    out = run(md, reps, mpot, K)
+    assert out["status"][4] == 1 and out["energy"][4] == 0.0 and out["energy"][3] == 0.0
+    assert np.all(out["g_sigma"][3:] == 0.0)
+    compare(un, opot, orc, reps[:3], out, K, TOL_SHORT if K <= 10 else TOL_LONG, min_strict=2)
+
+
+def test_unrolled_app_a_shape_300_steps(md, orc, un):
+    """App. A's minimization: 128 disks 50:50 with diameters D and 1, 300 steps.  E_K, R_K and the branch record
+    are compared element-wise.  At this size FIRE has not converged after 300 steps and the float32 and float64
+    trajectories separate by about 2 % per step, so one sample's dE_K/dtheta is only defined to within what a
+    start moved by one position quantum gives; the gradients are held to a band of that size, measured by the
+    oracle for each replica."""
+    D = 0.8
+    reps = [disks(128, 0.9, 7101 + s, d=(D, 1.0)) for s in range(4)]
+    mpot, opot = pots(md, orc, d=(D, 1.0), eps=((1.0, 1.0), (1.0, 1.0)))
+    out = run(md, reps, mpot, 300)
+    compare(un, opot, orc, reps, out, 300, TOL_LONG, band=4.0)
+
+
+def test_unrolled_300_steps_converging_system(md, orc, un):
+    """Smaller packings that come close to a minimum within the 300 steps (|F| ~ 1e-3, far above float32 force
+    noise, so every P > 0 decision has a clear sign): final energies and positions agree element-wise to ~1e-6,
+    and the derivatives to the linear-response band (FIRE's mixing scales the adjoint by 1/|F|, so near a
+    minimum the derivative responds strongly to the trajectory).  A system that reaches |F| ~ 1e-8 inside the
+    loop keeps stepping on rounding noise; its late decisions are arbitrary on either side."""
+    reps = [disks(32, 0.85, 7476, d=(0.8, 1.0)), disks(32, 0.85, 7477, d=(0.8, 1.0)),
+            disks(48, 0.9, 7630, d=(0.8, 1.0)), disks(48, 0.9, 7634, d=(0.8, 1.0)),
+            disks(48, 0.9, 7635, d=(0.8, 1.0))]
+    mpot, opot = pots(md, orc, d=(0.8, 1.0), eps=((1.0, 1.0), (1.0, 1.0)))
+    out = run(md, reps, mpot, 300)
+    compare(un, opot, orc, reps, out, 300, dict(TOL_LONG, E=1e-5, R_K=1e-5), band=4.0, min_strict=3,
+            branch_noise=True)
+
+
+def test_unrolled_lj_and_largest_replica(md, orc, un):
+    """Lennard-Jones pairs in a rectangular box from jittered lattices (time steps for LJ stiffness), and a
+    256-particle replica (four particles per lane)."""
+    reps = []
+    for (nx, ny), seed in (((16, 16), 7201), ((10, 9), 7202)):
+        N = nx * ny
+        L = math.sqrt(N / 0.7 / 0.8)
+        reps.append(dict(N=N, L=np.array([L, 0.8 * L, 0.0]), u=inputs.jittered_grid_torus((nx, ny), 0.2, seed),
+                         species=inputs.bidisperse_species(N)))
+    mpot, opot = pots(md, orc, kind="lj")
+    out = run(md, reps, mpot, 20, dt=(0.002, 0.01))
+    compare(un, opot, orc, reps, out, 20, dt=(0.002, 0.01), tol=dict(TOL_SHORT, E=1e-4, g_sigma=2e-4, g_eps=2e-4, g_lnc=2e-4, rbar0=2e-4))
+
+
+def test_unrolled_rescaled_box_derivative(md, orc, un):
+    """dE_K/dD with the box rescaled with D at fixed fractional start (App. A): sigma_AA = D, sigma_AB = (D+1)/2
+    and L ~ sqrt(D^2 + 1), so dE/dD = G_AA + (G_AB + G_BA)/2 + D/(D^2+1) dE/dln c; against central differences
+    of the oracle's E_K(D) over the same steps."""
+    N, K, D, phi = 64, 40, 0.8, 0.9
+    u = inputs.uniform_torus(N, 2, 7301)
+    sp = inputs.bidisperse_species(N)
+
+    def box(Dx):
+        return math.sqrt((N // 2) * math.pi * (Dx * Dx + 1.0) / 4.0 / phi)
+
+    L = box(D)
+    mpot, opot = pots(md, orc, d=(D, 1.0), eps=((1.0, 1.0), (1.0, 1.0)))
+    out = run(md, [dict(N=N, L=np.array([L, L, 0.0]), u=u, species=sp)], mpot, K)
+    gs = out["g_sigma"][0]
+    g = gs[0, 0] + 0.5 * (gs[0, 1] + gs[1, 0]) + D / (D * D + 1.0) * out["g_lnc"][0]
+    R0 = un.torus_to_frac(u)
+    h = 1e-6
+
+    def E(Dx):
+        Lx = box(Dx)
+        e, mixed = un.final_energy(R0, [Lx, Lx], orc.Potential("soft_sphere", sigma_of([Dx, 1.0]), np.ones((2, 2)),
+                                                                alpha=2.0), sp, K, fire_params(orc))
+        assert np.array_equal(mixed, out["mixed"][0].astype(bool))
+        return e
+    fd = (E(D + h) - E(D - h)) / (2 * h)
+    say("dE/dD gpu", g, "oracle fd", fd)
+    assert g == pytest.approx(fd, rel=1e-4)
+
+
+def test_unrolled_tends_to_gpu_envelope_gradient(md):
+    """After enough steps that FIRE has converged inside the loop, the unrolled derivative equals the envelope
+    derivative envelope_grad computes at the same final positions (two HIP paths, Sec. 4.2's two routes)."""
+    reps = [disks(64, 0.8, 7401 + s) for s in range(3)]
+    mpot = md.Potential("soft_sphere", sigma_of([1.0, 1.4]), np.ones((2, 2)), alpha=2.0)
+    ctx = md.Context()
+    bt = md.Batch(reps)
+    res = md.fire_unrolled_grad(ctx, bt, mpot, md.FireParams(), 3000)
+    gs_env, _, e_env = md.envelope_grad(ctx, bt, mpot)
+    gu = res["g_sigma"].cpu().numpy()
+    ge = gs_env.cpu().numpy()
+    say("unrolled", gu.reshape(3, -1), "envelope", ge.reshape(3, -1))
+    assert np.allclose(gu, ge, rtol=1e-4, atol=1e-7)
+    assert np.allclose(res["energy"].cpu().numpy(), e_env.cpu().numpy(), rtol=1e-6, atol=1e-12)
+
+
+def test_unrolled_is_deterministic_and_reuses_workspace(md):
+    reps = [disks(128, 0.9, 7501), disks(77, 0.9, 7502)]
+    mpot = md.Potential("soft_sphere", sigma_of([1.0, 1.4]), np.ones((2, 2)), alpha=2.0)
+    ctx = md.Context()
+    a = md.fire_unrolled_grad(ctx, md.Batch(reps), mpot, md.FireParams(), 50, rbar0=True)
+    b = md.fire_unrolled_grad(ctx, md.Batch(reps), mpot, md.FireParams(), 50, rbar0=True, workspace=a["workspace"])
+    for k in ("energy", "g_sigma", "g_eps", "g_lnc", "rbar0"):
+        assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), k
+
+
+def test_unrolled_rejects_small_workspace_and_large_replicas(md):
+    import torch
+    reps = [disks(64, 0.9, 7601)]
+    mpot = md.Potential("soft_sphere", sigma_of([1.0, 1.4]), np.ones((2, 2)), alpha=2.0)
+    ctx = md.Context()
+    small = torch.empty(1100, dtype=torch.uint8, device="cuda")   # records need 1024 bytes
+    bt = md.Batch(reps)
+    lib = md.load()
+    b, p, f = bt.c(mpot.cutoff()), mpot.c(), md.FireParams().c()
+    out = [torch.zeros(4, dtype=torch.float64, device="cuda") for _ in range(4)]
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    import ctypes
+    rc = lib.fire_unrolled_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f), 20, md._ptr(small), 1100,
+                                *[md._ptr(t) for t in out], None, None, md._ptr(st), md._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(st[0]) == -2      # the records fit, the particle block does not
+    with pytest.raises(RuntimeError):
+        md.fire_unrolled_grad(ctx, md.Batch([disks(300, 0.9, 7602)]), mpot, md.FireParams(), 5)
