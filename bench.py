@@ -197,30 +197,13 @@ def secondary(progress):
                               "adjoint_seconds": t_g}
     progress("batched FIRE done")
     # Sec. 4.2 with the box of App. A: 128 disks, half of diameter D and half 1, box rescaled with D at packing
-    # fraction 1; 100 random starts per D, each minimized (batched FIRE), dE*/dD at the minima
-    from paper_1912_04232_amd import adjoint
-    Ds = np.round(np.arange(0.5, 1.2001, 0.05), 2)
-    starts = inputs.rescaled_box_starts()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res, _ = adjoint.rescaled_box_sweep(ctx, Ds, starts, 1.0, f_tol=1e-7)
-    torch.cuda.synchronize()
-    t_s = time.perf_counter() - t0
-    mE, sE = res["energy"].mean(axis=1), res["energy"].std(axis=1)
-    mG = res["dEdD"].mean(axis=1)
-    eG = res["dEdD"].std(axis=1) / np.sqrt(res["dEdD"].shape[1])
-    k_max = int(np.argmax(mE))
-    k_cross = next((k for k in range(1, len(Ds)) if mG[k - 1] > 0 >= mG[k]), None)
-    k1 = int(np.argmin(np.abs(Ds - 1.0)))
-    out["rescaled_box_sweep"] = {
-        "N": 128, "packing_fraction": 1.0, "starts_per_D": len(starts), "D": Ds.tolist(),
-        "mean_E": mE.tolist(), "std_E": sE.tolist(), "mean_dEdD": mG.tolist(), "stderr_dEdD": eG.tolist(),
-        "converged": int((res["status"] == 1).sum()), "replicas": int(res["status"].size), "seconds": t_s,
-        "particle_steps_per_s": float(res["steps"].sum()) * 128 / t_s,
-        "D_energy_max": float(Ds[k_max]), "D_gradient_zero_crossing": None if k_cross is None else float(Ds[k_cross]),
-        "dEdD_positive_below_energy_max": bool((mG[:k_max] > 0).all()),
-        "dEdD_at_D1_within_2_stderr": bool(abs(mG[k1]) <= 2 * eG[k1])}
+    # fraction 1, 100 random starts per D; dE*/dD at minima (batched FIRE + envelope_grad), then the way App. A
+    # computes it: 300 FIRE steps and dE_300/dD by reverse mode through the steps, all 1500 replicas in one launch
+    from paper_1912_04232_amd import sweep
+    out["rescaled_box_sweep"] = sweep.run_envelope(ctx)
     progress("rescaled-box sweep done")
+    out["unrolled_box_sweep"] = sweep.run_unrolled(ctx)
+    progress("unrolled sweep done")
     return out
 
 

@@ -313,6 +313,10 @@ uint64_t fire_unrolled_workspace_bytes(int32_t B, int64_t total_n, int32_t K);
  * batch positions, then E_K = U(x_K) and its derivatives by transposing the
  * steps in reverse order.  The branch decisions (P > 0) and the dt / alpha
  * schedule are held fixed, as automatic differentiation of the loop does.
+ * sigma: NULL, or a device array [B][S*S] giving each replica its own sigma
+ * matrix (symmetric, positive; e.g. one diameter per replica, as the paper
+ * vectorizes the minimization over diameters and random keys); epsilon,
+ * alpha, r_cut and shift come from pot.
  * Outputs, all device arrays:
  *   energy [B]             E_K
  *   g_sigma, g_eps [B][S*S] dE_K / d entry (a,c) of the ordered species
@@ -340,8 +344,8 @@ uint64_t fire_unrolled_workspace_bytes(int32_t B, int64_t total_n, int32_t K);
  * arithmetic is single precision (the soft-sphere overlap from the double
  * distance); reductions, step scalars and parameter sums are double.
  */
-md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const md_fire_params *fp,
-                             int32_t K, void *workspace, uint64_t workspace_bytes, double *energy, double *g_sigma,
+md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const double *sigma,
+                             const md_fire_params *fp, int32_t K, void *workspace, uint64_t workspace_bytes, double *energy, double *g_sigma,
                              double *g_eps, double *g_lnc, float *rbar0, uint8_t *mixed, int32_t *status,
                              void *stream);
 

@@ -19,6 +19,16 @@ and every distance scales with L.  At a minimum s* in fractional coordinates the
 
 where the last term is the box's: W = sum over pairs of -r du/dr.  The harmonic soft sphere depends on r/sigma
 only, so W = sum_ab sigma_ab G_ab and the GPU's parameter-gradient sums give it with no further pass.
+
+``unrolled_box_sweep`` is the same experiment the way App. A computes it: a fixed number of FIRE steps (300) from
+each start, and the derivative of the final energy E_K through those steps (``fire_unrolled_grad``, reverse mode
+through the loop).  Every diameter and every start is one replica of a single launch (the paper's two nested
+vmaps), each with its own sigma matrix and box, and
+
+    dE_K/dD = G_AA + (G_AB + G_BA)/2 + D/(D^2 + 1) * dE_K/dln c
+
+with dE_K/dln c the derivative for the box scaled at fixed fractional start.  Unlike E*, E_K is not at a minimum
+when K is too short to converge, so the two sweeps agree only where FIRE has converged.
 """
 from __future__ import annotations
 
@@ -106,3 +116,43 @@ def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: 
         batches.append(bt)
     return {k: np.array(v) for k, v in out.items()}, batches
 
+
+
+def unrolled_box_batch(diameters, starts, phi: float, epsilon: float = 1.0, alpha: float = 2.0):
+    """(Batch, Potential, sigma [B][2][2]) for the rescaled-box sweep: replica (D, start) in D-major order, box of
+    packing fraction phi at diameters (D, 1), species 0 = the first N/2 disks (diameter D)."""
+    from . import inputs
+    reps, sig = [], []
+    for D in diameters:
+        D = float(D)
+        for u in starts:
+            N = int(u.shape[0])
+            L = inputs.box_for_packing([D, 1.0], [N // 2, N - N // 2], phi, 2)
+            reps.append(dict(N=N, L=[L, L, 0.0], u=u, species=inputs.bidisperse_species(N)))
+            sig.append(sigma_from_diameters([D, 1.0]))
+    pot = md.Potential("soft_sphere", sigma_from_diameters([1.0, 1.0]), np.full((2, 2), float(epsilon)), alpha=alpha)
+    return md.Batch(reps), pot, np.array(sig)
+
+
+def unrolled_box_grad(diameters, n_starts: int, res):
+    """dE_K/dD [len(D)][n_starts] from a fire_unrolled_grad result on an unrolled_box_batch."""
+    nD = len(diameters)
+    G = res["g_sigma"].cpu().numpy().reshape(nD, n_starts, 2, 2)
+    gl = res["g_lnc"].cpu().numpy().reshape(nD, n_starts)
+    Dv = np.asarray(diameters, dtype=np.float64)[:, None]
+    return G[..., 0, 0] + 0.5 * (G[..., 0, 1] + G[..., 1, 0]) + Dv / (Dv * Dv + 1.0) * gl
+
+
+def unrolled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, K: int = 300,
+                       fp: "md.FireParams | None" = None, epsilon: float = 1.0, alpha: float = 2.0, workspace=None):
+    """E_K and dE_K/dD after K FIRE steps for every small-disk diameter D and every start (uint32 fractional
+    positions [N][2], N even, the first N/2 disks small), box at packing fraction phi rescaled with D, all in one
+    launch.  Returns (dict of numpy arrays [len(D)][len(starts)]: energy, dEdD, g_lnc, status; the raw result
+    of fire_unrolled_grad, whose "workspace" can be passed back in to reuse the trajectory buffer)."""
+    bt, pot, sig = unrolled_box_batch(diameters, starts, phi, epsilon, alpha)
+    res = md.fire_unrolled_grad(md_ctx, bt, pot, fp or md.FireParams(), K, workspace=workspace, sigma=sig)
+    nD, ns = len(diameters), len(starts)
+    out = {"energy": res["energy"].cpu().numpy().reshape(nD, ns), "dEdD": unrolled_box_grad(diameters, ns, res),
+           "g_lnc": res["g_lnc"].cpu().numpy().reshape(nD, ns),
+           "status": res["status"].cpu().numpy().reshape(nD, ns)}
+    return out, res

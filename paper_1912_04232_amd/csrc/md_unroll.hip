@@ -38,24 +38,26 @@ constexpr int kUMaxN = 256;     // particles per replica
 constexpr int kUS = 4;          // species
 constexpr int kRec = 5;         // doubles per step record: dt, alpha, |w|, |F'|, P > 0
 constexpr int kAcc = 2 * kUS * kUS;
+constexpr int kNb = 32;         // candidate partners per particle kept for one pair pass
 
 struct UPot {
-    int kind, S, alpha_is_2, pad;
-    float alpha, rc2;
+    int kind, S, alpha_is_2, shift;
+    float alpha, rc2, rc, pad;
     float sig[kUS * kUS], eps[kUS * kUS], inv_eps[kUS * kUS];
     float ushift[kUS * kUS], ushift_s[kUS * kUS];  // LJ: u(r_c) and its sigma derivative when shifted
     double sigd[kUS * kUS];
 };
 
 struct UWave {
+    UPot pot;  // the replica's pair table (sigma may differ per replica)
     uint32_t u[kUMaxN][2];
     float z[kUMaxN][2];
     int8_t sp[kUMaxN];
-    double acc[kAcc];  // sigma entries, then eps entries
+    uint8_t nb[kUMaxN][kNb];  // candidate partners of each particle in the current pass, ascending
+    double acc[kAcc];         // sigma entries, then eps entries
 };
 
 struct ULds {
-    UPot pot;
     UWave w[kUW];
 };
 
@@ -65,6 +67,7 @@ struct UnrollArgs {
     const float *box;
     uint32_t *pos;
     const int32_t *species;
+    const double *rep_sigma;  // [B][S*S] or null
     uint8_t *ws;
     uint64_t ws_bytes, part_base;  // byte offset of the particle records inside ws
     double *energy, *g_sigma, *g_eps, *g_lnc;
@@ -175,38 +178,94 @@ __device__ __forceinline__ void own_load(Own<P> &o, const UWave &W, int n, int l
     }
 }
 
-// F_i for the wave's own particles at the positions in W.u.
-template <int KIND, int P>
-__device__ void wave_forces(const UPot &p, const UWave &W, const Own<P> &o, int n, int lane, const float *s,
-                            const double *sd, float (&F)[P][2])
+// The cheap first test of pair_terms (float distance against the cutoff, with the soft-sphere guard band).
+template <int KIND>
+__device__ __forceinline__ bool near_pair(const UPot &p, int pt, const uint32_t *ui, const uint32_t *uj,
+                                          const float *s)
 {
-#pragma unroll
-    for (int q = 0; q < P; ++q) F[q][0] = F[q][1] = 0.0f;
+    float dx = (float)(int32_t)(ui[0] - uj[0]) * s[0], dy = (float)(int32_t)(ui[1] - uj[1]) * s[1];
+    float r2 = __builtin_fmaf(dx, dx, dy * dy);
+    if (KIND == 0) return r2 < p.rc2;
+    float sig = p.sig[pt];
+    return r2 < sig * sig * 1.00001f;
+}
+
+// Calls f(q, j, uj, sj) for every own particle q and every partner j != i_q that passes near_pair, in
+// ascending j for each q (the order of a plain loop over j, so sums come out the same).  A cheap scan over all
+// j writes each particle's candidates to its LDS row first; the expensive pair terms then run over the rows
+// only.  A pass in which some particle has more than kNb candidates runs the plain loop instead.
+template <int KIND, int P, class Fn>
+__device__ __forceinline__ void wave_pairs(UWave &W, const Own<P> &o, int n, int lane, const float *s, Fn &&f)
+{
+    const UPot &p = W.pot;
     const int S = p.S;
+    int cnt[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) cnt[q] = 0;
     for (int j = 0; j < n; ++j) {
         uint32_t uj[2] = {W.u[j][0], W.u[j][1]};
         int sj = W.sp[j];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            PairT t;
-            if (o.on[q] && j != lane + 64 * q &&
-                pair_terms<KIND, false>(p, o.sp[q] * S + sj, o.u[q], uj, s, sd, t)) {
-                float c = -t.u1 / t.r;
-                F[q][0] = __builtin_fmaf(c, t.dx, F[q][0]);
-                F[q][1] = __builtin_fmaf(c, t.dy, F[q][1]);
+            if (o.on[q] && j != lane + 64 * q && near_pair<KIND>(p, o.sp[q] * S + sj, o.u[q], uj, s)) {
+                if (cnt[q] < kNb) W.nb[lane + 64 * q][cnt[q]] = (uint8_t)j;
+                ++cnt[q];
             }
         }
     }
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < P; ++q) over |= cnt[q] > kNb;
+    if (__any(over)) {
+        for (int j = 0; j < n; ++j) {
+            uint32_t uj[2] = {W.u[j][0], W.u[j][1]};
+            int sj = W.sp[j];
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                if (o.on[q] && j != lane + 64 * q) f(q, j, uj, sj);
+        }
+        return;
+    }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        for (int m = 0; __any(m < cnt[q]); ++m) {
+            if (m < cnt[q]) {
+                int j = W.nb[lane + 64 * q][m];
+                uint32_t uj[2] = {W.u[j][0], W.u[j][1]};
+                f(q, j, uj, (int)W.sp[j]);
+            }
+        }
+    }
+}
+
+// F_i for the wave's own particles at the positions in W.u.
+template <int KIND, int P>
+__device__ void wave_forces(UWave &W, const Own<P> &o, int n, int lane, const float *s, const double *sd,
+                            float (&F)[P][2])
+{
+    const UPot &p = W.pot;
+#pragma unroll
+    for (int q = 0; q < P; ++q) F[q][0] = F[q][1] = 0.0f;
+    const int S = p.S;
+    wave_pairs<KIND, P>(W, o, n, lane, s, [&](int q, int, const uint32_t *uj, int sj) {
+        PairT t;
+        if (pair_terms<KIND, false>(p, o.sp[q] * S + sj, o.u[q], uj, s, sd, t)) {
+            float c = -t.u1 / t.r;
+            F[q][0] = __builtin_fmaf(c, t.dx, F[q][0]);
+            F[q][1] = __builtin_fmaf(c, t.dy, F[q][1]);
+        }
+    });
 }
 
 // One reverse pair pass at the positions in W.u with the vector z = W.z: jv = (dF/dx) z for the own
 // particles, and per own particle the parameter contractions by species of the partner (gs, ge) and the
 // box-scale contraction gl.
 template <int KIND, int P>
-__device__ void wave_adjoint(const UPot &p, const UWave &W, const Own<P> &o, int n, int lane, const float *s,
-                             const double *sd, float (&jv)[P][2], float (&gs)[P][kUS], float (&ge)[P][kUS],
-                             float &gl)
+__device__ void wave_adjoint(UWave &W, const Own<P> &o, int n, int lane, const float *s, const double *sd,
+                             float (&jv)[P][2], float (&gs)[P][kUS], float (&ge)[P][kUS], float &gl)
 {
+    const UPot &p = W.pot;
     float zi[P][2];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -219,65 +278,55 @@ __device__ void wave_adjoint(const UPot &p, const UWave &W, const Own<P> &o, int
     }
     gl = 0.0f;
     const int S = p.S;
-    for (int j = 0; j < n; ++j) {
-        uint32_t uj[2] = {W.u[j][0], W.u[j][1]};
-        int sj = W.sp[j];
-        float zj0 = W.z[j][0], zj1 = W.z[j][1];
+    wave_pairs<KIND, P>(W, o, n, lane, s, [&](int q, int j, const uint32_t *uj, int sj) {
+        PairT t;
+        int pt = o.sp[q] * S + sj;
+        if (pair_terms<KIND, false>(p, pt, o.u[q], uj, s, sd, t)) {
+            float ri = 1.0f / t.r;
+            float hx = t.dx * ri, hy = t.dy * ri;
+            float z0 = zi[q][0] - W.z[j][0], z1 = zi[q][1] - W.z[j][1];
+            float sh = __builtin_fmaf(hx, z0, hy * z1);   // rhat . z_ij
+            float a = t.u1 * ri;
+            float b = (t.u2 - a) * sh;
+            jv[q][0] -= __builtin_fmaf(a, z0, b * hx);
+            jv[q][1] -= __builtin_fmaf(a, z1, b * hy);
+            float vs = -0.5f * t.u1s * sh;
+            float ve = -0.5f * t.u1 * p.inv_eps[pt] * sh;
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            PairT t;
-            int pt = o.sp[q] * S + sj;
-            if (o.on[q] && j != lane + 64 * q && pair_terms<KIND, false>(p, pt, o.u[q], uj, s, sd, t)) {
-                float ri = 1.0f / t.r;
-                float hx = t.dx * ri, hy = t.dy * ri;
-                float z0 = zi[q][0] - zj0, z1 = zi[q][1] - zj1;
-                float sh = __builtin_fmaf(hx, z0, hy * z1);   // rhat . z_ij
-                float a = t.u1 * ri;
-                float b = (t.u2 - a) * sh;
-                jv[q][0] -= __builtin_fmaf(a, z0, b * hx);
-                jv[q][1] -= __builtin_fmaf(a, z1, b * hy);
-                float vs = -0.5f * t.u1s * sh;
-                float ve = -0.5f * t.u1 * p.inv_eps[pt] * sh;
-#pragma unroll
-                for (int c = 0; c < kUS; ++c) {
-                    gs[q][c] += sj == c ? vs : 0.0f;
-                    ge[q][c] += sj == c ? ve : 0.0f;
-                }
-                gl = __builtin_fmaf(-0.5f * t.u2 * t.r, sh, gl);
+            for (int c = 0; c < kUS; ++c) {
+                gs[q][c] += sj == c ? vs : 0.0f;
+                ge[q][c] += sj == c ? ve : 0.0f;
             }
+            gl = __builtin_fmaf(-0.5f * t.u2 * t.r, sh, gl);
         }
-    }
+    });
 }
 
 // Energy and its own parameter derivatives at the positions in W.u (1/2 per ordered pair).
 template <int KIND, int P>
-__device__ void wave_energy(const UPot &p, const UWave &W, const Own<P> &o, int n, int lane, const float *s,
-                            const double *sd, float &e, float (&gs)[P][kUS], float (&ge)[P][kUS], float &gl)
+__device__ void wave_energy(UWave &W, const Own<P> &o, int n, int lane, const float *s, const double *sd,
+                            float &e, float (&gs)[P][kUS], float (&ge)[P][kUS], float &gl)
 {
+    const UPot &p = W.pot;
 #pragma unroll
     for (int q = 0; q < P; ++q)
 #pragma unroll
         for (int c = 0; c < kUS; ++c) gs[q][c] = ge[q][c] = 0.0f;
     e = gl = 0.0f;
     const int S = p.S;
-    for (int j = 0; j < n; ++j) {
-        uint32_t uj[2] = {W.u[j][0], W.u[j][1]};
-        int sj = W.sp[j];
+    wave_pairs<KIND, P>(W, o, n, lane, s, [&](int q, int, const uint32_t *uj, int sj) {
+        PairT t;
+        int pt = o.sp[q] * S + sj;
+        if (pair_terms<KIND, true>(p, pt, o.u[q], uj, s, sd, t)) {
+            e += 0.5f * t.u;
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            PairT t;
-            int pt = o.sp[q] * S + sj;
-            if (o.on[q] && j != lane + 64 * q && pair_terms<KIND, true>(p, pt, o.u[q], uj, s, sd, t)) {
-                e += 0.5f * t.u;
-#pragma unroll
-                for (int c = 0; c < kUS; ++c) {
-                    gs[q][c] += sj == c ? 0.5f * t.us : 0.0f;
-                    ge[q][c] += sj == c ? 0.5f * t.u * p.inv_eps[pt] : 0.0f;
-                }
-                gl = __builtin_fmaf(0.5f * t.u1, t.r, gl);
+            for (int c = 0; c < kUS; ++c) {
+                gs[q][c] += sj == c ? 0.5f * t.us : 0.0f;
+                ge[q][c] += sj == c ? 0.5f * t.u * p.inv_eps[pt] : 0.0f;
             }
+            gl = __builtin_fmaf(0.5f * t.u1, t.r, gl);
         }
-    }
+    });
 }
 
 // Adds the wave's per-lane parameter contractions into the replica's double accumulators (lane 0 writes).
@@ -307,14 +356,29 @@ template <int KIND, int P>
 __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot pin)
 {
     __shared__ ULds L;
-    if (threadIdx.x == 0) L.pot = pin;
-    __syncthreads();
-    const UPot &pot = L.pot;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = blockIdx.x * kUW + wv;
     if (b >= a.B) return;
     UWave &W = L.w[wv];
-    const int off = a.offset[b], n = a.offset[b + 1] - off, K = a.K, S = pot.S;
+    if (lane == 0) W.pot = pin;
+    wave_sync();
+    const int S = pin.S;
+    if (a.rep_sigma && lane < S * S) {
+        double sg = a.rep_sigma[(size_t)b * S * S + lane];
+        W.pot.sig[lane] = (float)sg;
+        W.pot.sigd[lane] = sg;
+        if (KIND == 0 && pin.shift) {
+            double qc = sg / (double)pin.rc;
+            qc = qc * qc * qc;
+            qc = qc * qc;
+            double ep = (double)pin.eps[lane];
+            W.pot.ushift[lane] = (float)(4.0 * ep * (qc * qc - qc));
+            W.pot.ushift_s[lane] = (float)(4.0 * ep / sg * (12.0 * qc * qc - 6.0 * qc));
+        }
+    }
+    wave_sync();
+    const UPot &pot = W.pot;
+    const int off = a.offset[b], n = a.offset[b + 1] - off, K = a.K;
     if (n < 0 || n > 64 * P) {
         if (lane == 0 && a.status) a.status[b] = -1;
         return;
@@ -364,7 +428,7 @@ __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot p
     float V[P][2], F[P][2];
 #pragma unroll
     for (int q = 0; q < P; ++q) V[q][0] = V[q][1] = 0.0f;
-    wave_forces<KIND, P>(pot, W, o, n, lane, s, sd, F);
+    wave_forces<KIND, P>(W, o, n, lane, s, sd, F);
     store_state(0, F);
     double dt = a.dt_start, al = a.alpha_start;
     int n_pos = 0;
@@ -385,7 +449,7 @@ __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot p
         }
         wave_sync();
         float Fn[P][2], w[P][2];
-        wave_forces<KIND, P>(pot, W, o, n, lane, s, sd, Fn);
+        wave_forces<KIND, P>(W, o, n, lane, s, sd, Fn);
         double Pw = 0.0, vv = 0.0, ff = 0.0;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -452,7 +516,7 @@ __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot p
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     wave_sync();
     float gs[P][kUS], ge[P][kUS], gl_l, e_l;
-    wave_energy<KIND, P>(pot, W, o, n, lane, s, sd, e_l, gs, ge, gl_l);
+    wave_energy<KIND, P>(W, o, n, lane, s, sd, e_l, gs, ge, gl_l);
     fold(W, o, S, lane, gs, ge);
     double E = wsum((double)e_l);
     double g_lnc = wsum((double)gl_l);
@@ -531,7 +595,7 @@ __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot p
         }
         wave_sync();
         float jv[P][2];
-        wave_adjoint<KIND, P>(pot, W, o, n, lane, s, sd, jv, gs, ge, gl_l);
+        wave_adjoint<KIND, P>(W, o, n, lane, s, sd, jv, gs, ge, gl_l);
         fold(W, o, S, lane, gs, ge);
         double gd = 0.0;
 #pragma unroll
@@ -574,7 +638,7 @@ __global__ __launch_bounds__(64 * kUW) void k_fire_unrolled(UnrollArgs a, UPot p
     wave_sync();
     {
         float jv[P][2];
-        wave_adjoint<KIND, P>(pot, W, o, n, lane, s, sd, jv, gs, ge, gl_l);
+        wave_adjoint<KIND, P>(W, o, n, lane, s, sd, jv, gs, ge, gl_l);
         fold(W, o, S, lane, gs, ge);
         g_lnc += wsum((double)gl_l);
 #pragma unroll
@@ -616,6 +680,8 @@ bool make_upot(const md_potential *pot, UPot &u)
     if (pot->kind == MD_SOFT_SPHERE && !(pot->alpha >= 1.0f)) return false;
     if (pot->kind == MD_LJ && !(pot->r_cut > 0.0f)) return false;
     u.rc2 = pot->r_cut * pot->r_cut;
+    u.rc = pot->r_cut;
+    u.shift = pot->kind == MD_LJ && pot->shift;
     for (int q = 0; q < S * S; ++q) {
         double sg = pot->sigma[q], ep = pot->epsilon[q];
         int qt = (q % S) * S + q / S;
@@ -649,8 +715,8 @@ uint64_t fire_unrolled_workspace_bytes(int32_t B, int64_t total_n, int32_t K)
     return rec_region(B, K) + 24ull * (uint64_t)(K + 1) * (uint64_t)total_n;
 }
 
-md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *bt, const md_potential *pot, const md_fire_params *fp,
-                             int32_t K, void *workspace, uint64_t workspace_bytes, double *energy, double *g_sigma,
+md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *bt, const md_potential *pot, const double *sigma,
+                             const md_fire_params *fp, int32_t K, void *workspace, uint64_t workspace_bytes, double *energy, double *g_sigma,
                              double *g_eps, double *g_lnc, float *rbar0, uint8_t *mixed, int32_t *status,
                              void *stream)
 {
@@ -672,6 +738,7 @@ md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *bt, const md_potential
     a.box = bt->box;
     a.pos = bt->pos;
     a.species = bt->species;
+    a.rep_sigma = sigma;
     a.ws = (uint8_t *)workspace;
     a.ws_bytes = workspace_bytes;
     a.part_base = rec_region(bt->B, K);

@@ -106,7 +106,7 @@ _SIGNATURES = {
                      ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
     "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
     "fire_unrolled_workspace_bytes": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32],
-    "fire_unrolled_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
+    "fire_unrolled_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, ctypes.POINTER(c_fire_params),
                            ctypes.c_int32, P, ctypes.c_uint64, P, P, P, P, P, P, P, P],
     "nn_descriptors": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_nn_params), P, ctypes.c_int32,
                        ctypes.POINTER(c_nlist), P, P],
@@ -528,14 +528,15 @@ def envelope_grad(ctx: Context, batch: Batch, pot: Potential):
 
 
 def fire_unrolled_grad(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, K: int, rbar0: bool = False,
-                       mixed: bool = False, workspace=None):
+                       mixed: bool = False, workspace=None, sigma=None):
     """K FIRE steps on every replica, then dE_K/dtheta by reverse mode through the steps (one launch).
 
     Returns a dict of device tensors: energy [B] f64, g_sigma and g_eps [B][S][S] f64 (ordered entries),
     g_lnc [B] f64 (box scale at fixed fractional start), status [B] i32, and when asked rbar0 [total][2] f32
     (dE_K/dR_0, fractional) and mixed [B][K] u8 (P > 0 per step).  The batch positions end at R_K.  The
     trajectory workspace is allocated here unless a uint8 device tensor of at least
-    fire_unrolled_workspace_bytes bytes is passed; it is returned as "workspace".
+    fire_unrolled_workspace_bytes bytes is passed; it is returned as "workspace".  sigma: optional per-replica
+    sigma matrices [B][S][S] (float64 device tensor); the potential's own sigma is used when it is None.
     """
     lib = load()
     dev = batch.pos.device
@@ -554,9 +555,14 @@ def fire_unrolled_grad(ctx: Context, batch: Batch, pot: Potential, fp: FireParam
     }
     rb = torch.zeros((max(total, 1), 2), dtype=torch.float32, device=dev) if rbar0 else None
     mx = torch.zeros((B1, max(int(K), 1)), dtype=torch.uint8, device=dev) if mixed else None
-    b, p, f = batch.c(pot.cutoff()), pot.c(), fp.c()
+    if sigma is not None:
+        sigma = torch.as_tensor(sigma, dtype=torch.float64, device=dev).contiguous()
+        if tuple(sigma.shape) != (batch.B, S, S):
+            raise ValueError("sigma must be [B][S][S]")
+    rng = pot.cutoff() if sigma is None or pot.kind == "lj" else max(pot.cutoff(), float(sigma.max()))
+    b, p, f = batch.c(rng), pot.c(), fp.c()
     _check("fire_unrolled_grad", lib.fire_unrolled_grad(
-        ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f), int(K), _ptr(workspace), workspace.numel(),
+        ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(sigma), ctypes.byref(f), int(K), _ptr(workspace), workspace.numel(),
         _ptr(out["energy"]), _ptr(out["g_sigma"]), _ptr(out["g_eps"]), _ptr(out["g_lnc"]), _ptr(rb), _ptr(mx),
         _ptr(out["status"]), _stream()))
     res = {k: v[: batch.B] for k, v in out.items()}

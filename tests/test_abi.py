@@ -66,7 +66,7 @@ def test_unrolled_fire_workspace_size_and_argument_errors():
     fp = md.FireParams().c()
     b = md.c_batch()
     b.B, b.dim, b.max_n = 1, 2, 10
-    args = [ctypes.byref(b), ctypes.byref(pot), ctypes.byref(fp), 5, None, 0] + [None] * 7 + [None]
+    args = [ctypes.byref(b), ctypes.byref(pot), None, ctypes.byref(fp), 5, None, 0] + [None] * 7 + [None]
     assert lib.fire_unrolled_grad(None, *args) == -1           # no context
     b.dim = 3
     assert lib.fire_unrolled_grad(None, *args) == -1

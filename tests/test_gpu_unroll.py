@@ -299,10 +299,38 @@ def test_unrolled_rejects_small_workspace_and_large_replicas(md):
     out = [torch.zeros(4, dtype=torch.float64, device="cuda") for _ in range(4)]
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     import ctypes
-    rc = lib.fire_unrolled_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f), 20, md._ptr(small), 1100,
+    rc = lib.fire_unrolled_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), None, ctypes.byref(f), 20, md._ptr(small), 1100,
                                 *[md._ptr(t) for t in out], None, None, md._ptr(st), md._stream())
     assert rc == 0
     torch.cuda.synchronize()
     assert int(st[0]) == -2      # the records fit, the particle block does not
     with pytest.raises(RuntimeError):
         md.fire_unrolled_grad(ctx, md.Batch([disks(300, 0.9, 7602)]), mpot, md.FireParams(), 5)
+
+
+def test_unrolled_per_replica_sigma_equals_separate_launches(md, orc, un):
+    """One launch over several diameters (per-replica sigma, as the paper vmaps over diameters and keys) gives
+    bitwise the results of one launch per diameter, and matches the oracle for each diameter."""
+    import torch
+    Ds = [0.6, 0.8, 1.0]
+    u = [inputs.uniform_torus(64, 2, 7701 + s) for s in range(2)]
+    reps, sig = [], []
+    for D in Ds:
+        for uu in u:
+            L = inputs.box_for_packing([D, 1.0], [32, 32], 0.9, 2)
+            reps.append(dict(N=64, L=np.array([L, L, 0.0]), u=uu, species=inputs.bidisperse_species(64)))
+            sig.append(sigma_of([D, 1.0]))
+    base = md.Potential("soft_sphere", sigma_of([1.0, 1.0]), np.ones((2, 2)), alpha=2.0)
+    ctx = md.Context()
+    allr = md.fire_unrolled_grad(ctx, md.Batch(reps), base, md.FireParams(), 40, sigma=np.array(sig))
+    for k, D in enumerate(Ds):
+        pot = md.Potential("soft_sphere", sigma_of([D, 1.0]), np.ones((2, 2)), alpha=2.0)
+        one = md.fire_unrolled_grad(ctx, md.Batch(reps[2 * k: 2 * k + 2]), pot, md.FireParams(), 40)
+        for key in ("energy", "g_sigma", "g_eps", "g_lnc"):
+            assert torch.equal(allr[key][2 * k: 2 * k + 2], one[key]), (D, key)
+    opot = orc.Potential("soft_sphere", sigma_of([0.6, 1.0]), np.ones((2, 2)), alpha=2.0)
+    o = un.fire_unrolled_grad(un.torus_to_frac(u[0]), reps[0]["L"][:2], opot, reps[0]["species"], 40,
+                              fire_params(orc))
+    g = allr["g_sigma"][0].cpu().numpy()
+    say("D=0.6 gpu", g.ravel(), "oracle", o["g_sigma"].ravel())
+    assert np.abs(g - o["g_sigma"]).max() <= 1e-4 * np.abs(o["g_sigma"]).max()
