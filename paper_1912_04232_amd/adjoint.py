@@ -82,6 +82,15 @@ def minimized_energy(diameters: torch.Tensor, epsilon: torch.Tensor, batch: "md.
                                      md_ctx or md.Context(), alpha)
 
 
+def rescaled_box_dEdD(G, D: float) -> np.ndarray:
+    """dU/dD at fixed fractional positions for every replica, from its dU/dsigma_ab G [B][2][2] at diameters (D, 1):
+    G_AA + (G_AB + G_BA)/2 - D/(D^2 + 1) W with W = sum_ab sigma_ab G_ab (harmonic soft spheres)."""
+    sig = sigma_from_diameters([D, 1.0])
+    dsig = np.array([[1.0, 0.5], [0.5, 0.0]])   # d sigma_ab / dD
+    W = (G * sig[None]).sum(axis=(1, 2))
+    return (G * dsig[None]).sum(axis=(1, 2)) - D / (D * D + 1.0) * W
+
+
 def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: "md.FireParams | None" = None,
                        f_tol: float = 1e-6, max_steps: int = 200000, epsilon: float = 1.0, alpha: float = 2.0):
     """For every small-disk diameter D and every start (uint32 fractional positions [N][2], N even; the first N/2
@@ -105,11 +114,8 @@ def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: 
         pot = md.Potential("soft_sphere", sig, np.full((2, 2), float(epsilon)), alpha=alpha)
         e, fmax, steps, status = md.fire_batched(md_ctx, bt, pot, fp, max_steps, f_tol)
         gs, _, _ = md.envelope_grad(md_ctx, bt, pot)
-        G = gs.cpu().numpy()
-        dsig = np.array([[1.0, 0.5], [0.5, 0.0]])   # d sigma_ab / dD
-        W = (G * sig[None]).sum(axis=(1, 2))
         out["energy"].append(e.cpu().numpy())
-        out["dEdD"].append((G * dsig[None]).sum(axis=(1, 2)) - D / (D * D + 1.0) * W)
+        out["dEdD"].append(rescaled_box_dEdD(gs.cpu().numpy(), D))
         out["fmax"].append(fmax.cpu().numpy())
         out["steps"].append(steps.cpu().numpy())
         out["status"].append(status.cpu().numpy())

@@ -76,6 +76,15 @@ def fcc_torus(n_cells: int, L: float) -> np.ndarray:
     return to_torus(pts * L, [L, L, L])
 
 
+def jittered_torus(u: np.ndarray, L, amplitude: float, seed: int) -> np.ndarray:
+    """Torus coordinates u moved by independent uniform offsets of up to +-amplitude (length units) per axis."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = np.asarray(L, dtype=np.float64)[: u.shape[1]]
+    off = rng.uniform(-amplitude, amplitude, size=u.shape) / L * TWO32
+    q = u.astype(np.int64) + np.rint(off).astype(np.int64)
+    return (q & 0xFFFFFFFF).astype(np.uint32)
+
+
 def triangular_torus(nx: int, ny: int, a: float):
     """2D triangular lattice nx x ny (ny even) with spacing a; returns (u, Lx, Ly)."""
     Lx = f32(nx * a)

@@ -34,6 +34,24 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def bf16_round(a):
+    """Nearest bfloat16 of the float32 value (ties to even), as float64: the weights the model holds."""
+    a32 = np.ascontiguousarray(a, dtype=np.float32)
+    b = a32.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def model_params(nn_oracle, W1, b1, W2, b2, w3, b3, m, s):
+    """The oracle's copy of the seeded network: BF16 weight matrices and float32 vectors, rounded here."""
+    return nn_oracle.NNParams(W1=bf16_round(W1), b1=f32(b1), W2=bf16_round(W2), b2=f32(b2), w3=f32(w3),
+                              b3=float(np.float32(b3)), m=f32(m), s=f32(s))
+
+
 def setup(md, nn_oracle, orc, N=2000, seed=12):
     L = inputs.box_for_density(N, 0.84)
     u = inputs.random_insertion_torus(N, L, 3, 0.85, seed)
@@ -44,9 +62,10 @@ def setup(md, nn_oracle, orc, N=2000, seed=12):
     P.b1 = np.random.default_rng(1).normal(0, 0.2, 64)
     P.b2 = np.random.default_rng(2).normal(0, 0.2, 64)
     nn = md.NNParams(P.W1, P.b1, P.W2, P.b2, P.w3, P.b3, P.m, P.s)
-    h = nn.host()   # the oracle uses the BF16-rounded weights, upcast exactly
-    Q = nn_oracle.NNParams(W1=h["W1"], b1=h["b1"], W2=h["W2"], b2=h["b2"], w3=h["w3"], b3=h["b3"], m=h["m"],
-                           s=h["s"])
+    Q = model_params(nn_oracle, P.W1, P.b1, P.W2, P.b2, P.w3, P.b3, P.m, P.s)
+    h = nn.host()   # the device copy holds exactly those values
+    for k in ("W1", "W2", "b1", "b2", "w3", "m", "s"):
+        assert np.array_equal(h[k], getattr(Q, k)), k
     box = md.Box((L, L, L), 3)
     s = md.System(box, md.Potential("lj", [[1.0]], [[1.0]], r_cut=2.5), u, skin=0.3)
     s.build()
@@ -67,9 +86,13 @@ def test_mlp_matches_oracle(md):
     from oracle import nn_oracle
     import oracle as orc
     s, nn, Q, spec, x, L = setup(md, nn_oracle, orc)
-    G = md.nn_descriptors(s.ctx, s.box, nn, s.pos, s.nl)
+    import torch
+    # both networks read the same descriptor matrix: the oracle's, from the seeded positions, in float32
+    Go, _ = nn_oracle.descriptors(x, L, spec)
+    G32 = Go.astype(np.float32)
+    G = torch.as_tensor(G32, device="cuda").contiguous()
     Ei, e = md.nn_mlp(s.ctx, nn, G)
-    Eo, eo, _ = nn_oracle.mlp(G.cpu().numpy().astype(np.float64), Q, spec)
+    Eo, eo, _ = nn_oracle.mlp(G32.astype(np.float64), Q, spec)
     say("Ei rel-L2", rel_l2(Ei.cpu().numpy(), Eo), "e rel-L2", rel_l2(e.cpu().numpy(), eo))
     assert rel_l2(Ei.cpu().numpy(), Eo) < 1e-4
     assert rel_l2(e.cpu().numpy(), eo) < 1e-4
@@ -113,14 +136,16 @@ def train_setup(md, S=3, n=400, seed=21):
     net = nnmod.Network(ctx, w, G0.mean(0), G0.std(0) + 1e-3)
     box = md.Box((L, L, L), 3)
     pos = torch.as_tensor(np.concatenate(us).view(np.int32), device="cuda").contiguous()
-    E_ref = torch.as_tensor(rng.normal(-5.0 * n, 30.0, S), dtype=torch.float64, device="cuda")
-    F_ref = torch.as_tensor(rng.normal(0, 3.0, (S * n, 3)).astype(np.float32), device="cuda")
+    E_np = rng.normal(-5.0 * n, 30.0, S)
+    F_np = rng.normal(0, 3.0, (S * n, 3)).astype(np.float32)
+    E_ref = torch.as_tensor(E_np, dtype=torch.float64, device="cuda")
+    F_ref = torch.as_tensor(F_np, device="cuda")
     batch = nnmod.Batch(ctx, box, net, pos, E_ref, F_ref, n, 2.5)
-    h = net.host()
-    Q = nn_oracle.NNParams(W1=h["W1"], b1=h["b1"], W2=h["W2"], b2=h["b2"], w3=h["w3"], b3=h["b3"], m=h["m"],
-                           s=h["s"])
-    snaps = [(xs[k], [L] * 3, float(E_ref[k]), F_ref[k * n:(k + 1) * n].cpu().numpy().astype(np.float64))
-             for k in range(S)]
+    Q = model_params(nn_oracle, w["W1"], w["b1"], w["W2"], w["b2"], w["w3"], w["b3"], G0.mean(0), G0.std(0) + 1e-3)
+    h = net.host()   # the device copy (float32 master values, BF16 matrices from the cast kernel) holds them exactly
+    for k in ("W1", "W2", "b1", "b2", "w3", "m", "s"):
+        assert np.array_equal(h[k], getattr(Q, k)), k
+    snaps = [(xs[k], [L] * 3, float(E_np[k]), F_np[k * n:(k + 1) * n].astype(np.float64)) for k in range(S)]
     return ctx, box, net, batch, Q, spec, snaps, xs, [L] * 3, nnmod
 
 
@@ -133,10 +158,13 @@ def test_loss_and_pair_adjoint_match_oracle(md):
     lo, _ = nn_oracle.loss_and_grad(snaps, Q, spec)
     say("loss", float(loss), lo)
     assert abs(float(loss) - lo) / lo < 1e-4
-    # the pair adjoint of the GPU's own lam against the oracle's adjoint of the same lam
-    ebar = nnmod.pair_adjoint(ctx, box, net, batch.pos, batch.nl, lam).cpu().numpy()
-    lam_h = lam.cpu().numpy().astype(np.float64)
+    # the pair adjoint is linear in lam: both sides transpose the same seeded vector
+    import torch
     n = batch.n
+    lam_h = np.random.default_rng(77).normal(0.0, 1.0, (len(xs) * n, 3)).astype(np.float32)
+    lam_d = torch.as_tensor(lam_h, device="cuda").contiguous()
+    ebar = nnmod.pair_adjoint(ctx, box, net, batch.pos, batch.nl, lam_d).cpu().numpy()
+    lam_h = lam_h.astype(np.float64)
     want = np.concatenate([nn_oracle.pair_adjoint(xs[k], L, spec, lam_h[k * n:(k + 1) * n]) for k in range(len(xs))])
     say("ebar rel-L2", rel_l2(ebar, want))
     assert rel_l2(ebar, want) < 1e-5

@@ -116,7 +116,7 @@ def compare(un, opot, orc, reps, out, K, tol, min_strict=1, band=None, dt=(0.1, 
         R0 = un.torus_to_frac(r["u"])
         o = un.fire_unrolled_grad(R0, L, opot, r["species"], K, fp)
         assert out["status"][b] == 1
-        dR = un.torus_to_frac(out["uK"][b]) - o["traj"]["R"][K]
+        dR = out["uK"][b].astype(np.float64) / 2.0 ** 32 - o["traj"]["R"][K]
         dR -= np.round(dR)
         errs = {"E": abs(out["energy"][b] - o["E"]) / max(abs(o["E"]), 1e-9), "R_K": np.abs(dR).max()}
         if not np.array_equal(out["mixed"][b].astype(bool), o["traj"]["mixed"]):

@@ -478,6 +478,34 @@ def test_rescaled_box_grad_matches_fd(orc):
         assert math.isclose(g, (Up - Um) / (2 * h), rel_tol=1e-6, abs_tol=1e-9), (D, g, (Up - Um) / (2 * h))
 
 
+def test_rescaled_box_envelope_matches_fd_through_minimization(orc):
+    """At an FP64 FIRE minimum s* of the rescaled-box disks, dU/dD(s*) equals the central difference of the
+    minimized energy E*(D +- h), each minimized from s* in the box of D +- h (envelope theorem, Sec. 4.2)."""
+    N, phi, D, h = 32, 0.9, 0.8, 1e-5
+    u0 = np.random.default_rng(21).integers(0, 2 ** 32, size=(N, 2), dtype=np.uint64).astype(np.uint32)
+    sp = inputs.bidisperse_species(N)
+
+    def box(Dx):
+        return math.sqrt((N // 2) * math.pi * (Dx * Dx + 1.0) / 4.0 / phi)
+
+    def pot(Dx):
+        d = np.array([Dx, 1.0])
+        return orc.Potential("soft_sphere", 0.5 * (d[:, None] + d[None, :]), np.ones((2, 2)), alpha=2.0)
+
+    def minimize(s, Dx):
+        L = box(Dx)
+        r = orc.fire(s * L, [L, L], pot(Dx), sp, f_tol=1e-11, max_steps=400000)
+        assert r["converged"]
+        return r["x"] / L, orc.energy(r["x"], [L, L], pot(Dx), sp)
+
+    s_star, E = minimize(u0.astype(np.float64) / 2.0 ** 32, D)
+    u_star = inputs.to_torus(s_star, [1.0, 1.0])
+    _, g = orc.rescaled_box_grad(u_star, box(D), D, sp)
+    fd = (minimize(s_star, D + h)[1] - minimize(s_star, D - h)[1]) / (2 * h)
+    assert E > 0
+    assert math.isclose(g, fd, rel_tol=1e-4, abs_tol=1e-7), (g, fd)
+
+
 # ----------------------------------------------------------------------- inputs
 
 def test_workload_boxes():
