@@ -431,6 +431,53 @@ md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *ve
 md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, md_nlist *nl, void *stream);
 /* vel[q] += h force[q] for q < N dim. */
 md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream);
+
+/*
+ * Constant temperature and gradient descent (Sec. 3.3.1 names Nose-Hoover, Langevin and Brownian NVT and a
+ * gradient-descent minimizer beside NVE and FIRE; the discretizations are published schemes, unit masses).
+ * Each step, like md_kick_drift, moves positions by the shift of Sec. 3.2.1 and marks on the device when a
+ * particle has moved more than skin/2 from nl->pos_ref; the caller then runs nl_update and new forces.
+ * Noise: xi for particle i at step s is Philox4x64-10 (Salmon et al., SC'11) at counter (i, s, 0, 0) with key
+ * (seed, 0); the top 24 bits of each output word plus half a unit, over 2^24, are uniforms in (0, 1) and
+ * Box-Muller turns (u0, u1), (u2, u3) into four standard normals, the first dim used.  *step is a device
+ * counter the call reads and then advances by one (so captured graphs replay with fresh noise).
+ *
+ * Langevin (BAOAB, Leimkuhler and Matthews 2013): one step is
+ *   md_langevin_baoa (v += dt/2 F; x += dt/2 v; v = c1 v + c2 xi; x += dt/2 v) -> nl_update -> new forces F
+ *   -> md_kick (v += dt/2 F),   c1 = exp(-gamma dt), c2 = sqrt((1 - c1^2) kT).
+ */
+md_status md_langevin_baoa(md_ctx *ctx, const md_box *box, uint32_t *pos, float *vel, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, float gamma, float kT, uint64_t seed, uint64_t *step,
+                           void *stream);
+/* Brownian dynamics (overdamped Langevin, Euler-Maruyama): x += (dt/gamma) F + sqrt(2 kT dt / gamma) xi, then
+ * nl_update and new forces.  gamma > 0; with kT = 0 no noise is drawn and step may be NULL. */
+md_status md_brownian_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, float gamma, float kT, uint64_t seed, uint64_t *step,
+                           void *stream);
+/* Gradient descent (steepest descent): x += dt F, then nl_update and new forces. */
+md_status md_gradient_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, void *stream);
+
+/* Nose-Hoover chain state (Martyna, Klein and Tuckerman 1992), kept in DEVICE memory by the caller. */
+typedef struct {
+    double p[8];      /* thermostat momenta p_k = Q_k xi_k */
+    double eta[8];    /* thermostat positions */
+    double Q[8];      /* thermostat masses, k < M */
+    double kT;        /* target temperature */
+    double scale;     /* velocity factor applied by the last md_nhc_half */
+    int32_t M;        /* chain length, 1..8 */
+    int32_t n_dof;    /* degrees of freedom n_f (N dim) */
+} md_nhc_state;
+
+/*
+ * Half step of the chain over time h (Martyna, Tuckerman, Tobias and Klein 1996, one stage): thermostat
+ * forces G_1 = 2K - n_f kT, G_k = p_{k-1}^2 / Q_{k-1} - kT; momenta down the chain (each scaled by
+ * exp(-h/4 p_{k+1}/Q_{k+1}) around its h/2 kick), eta += h p / Q, velocities scaled by exp(-h p_1 / Q_1), momenta
+ * back up.  A Nose-Hoover step is md_nhc_half(dt/2) -> md_kick_drift -> nl_update -> forces -> md_kick(dt/2)
+ * -> md_nhc_half(dt/2); H' = K + U + sum_k p_k^2 / (2 Q_k) + n_f kT eta_1 + kT sum_{k>1} eta_k is conserved.
+ * K is summed in double in a fixed order; the chain update runs on the device (no host round trip).
+ */
+md_status md_nhc_half(md_ctx *ctx, float *vel, int32_t N, int32_t dim, md_nhc_state *state, double h, void *stream);
 /* out[0] = the smallest pair distance over the rows of nl at pos (double, device memory; 1e150 if no row has
  * an entry): with the force RMSE, the check that a configuration stays where a network was trained. */
 md_status md_min_distance(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t N, const md_nlist *nl,

@@ -1321,6 +1321,147 @@ __global__ __launch_bounds__(kBlock) void k_kick(float *vel, const float *force,
     if (q < n) vel[q] = __builtin_fmaf(h, force[q], vel[q]);
 }
 
+// ------------------------------------------------------------------------------------------------
+// constant-temperature steps and gradient descent (the caller computes forces between launches)
+
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): the counter c is replaced by the output block.
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(m0, c[0]), lo0 = m0 * c[0];
+        uint64_t hi1 = __umul64hi(m1, c[2]), lo1 = m1 * c[2];
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += w0;
+        k1 += w1;
+    }
+}
+
+// Four standard normals of particle i at step s: the top 24 bits of each Philox word plus half a unit give a
+// uniform in (0, 1), exact in float; Box-Muller turns (u0, u1) and (u2, u3) into normals.
+__device__ __forceinline__ void normals4(uint64_t i, uint64_t s, uint64_t seed, float z[4])
+{
+    uint64_t c[4] = {i, s, 0, 0};
+    philox4x64(c, seed, 0);
+    float u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = ((float)(uint32_t)(c[q] >> 40) + 0.5f) * (1.0f / 16777216.0f);
+    float r0 = sqrtf(-2.0f * logf(u[0])), r1 = sqrtf(-2.0f * logf(u[2]));
+    float s0, c0, s1, c1;
+    sincospif(2.0f * u[1], &s0, &c0);
+    sincospif(2.0f * u[3], &s1, &c1);
+    z[0] = r0 * c0;
+    z[1] = r0 * s0;
+    z[2] = r1 * c1;
+    z[3] = r1 * s1;
+}
+
+// BAOA of a BAOAB Langevin step (Leimkuhler and Matthews): v += dt/2 F, x += dt/2 v, v = c1 v + c2 xi,
+// x += dt/2 v (both drifts applied as one shift), and the rebuild trigger of k_kick_drift.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_langevin_baoa(uint32_t *pos, float *vel, const float *force, int N,
+                                                          DevBox b, const uint32_t *pos_ref, float half_skin,
+                                                          float dt, float c1, float c2, uint64_t seed,
+                                                          const uint64_t *step, int32_t *ctl)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < N) {
+        float z[4];
+        normals4((uint64_t)i, step[0], seed, z);
+        uint32_t ui[D], un[D];
+        load_pos<D>(pos, i, ui);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            float v = __builtin_fmaf(0.5f * dt, force[(size_t)i * D + q], vel[(size_t)i * D + q]);
+            float vo = __builtin_fmaf(c1, v, c2 * z[q]);
+            vel[(size_t)i * D + q] = vo;
+            un[q] = shift_coord(ui[q], 0.5f * dt * (v + vo), b.inv_s[q]);
+        }
+        store_pos<D>(pos, i, un);
+        far = disp2<D>(un, pos_ref, i, b) > half_skin * half_skin;
+    }
+    wave_flag(far, &ctl[kTrigWord]);
+}
+
+// Overdamped step x += a_f F (+ a_n xi): Brownian dynamics (Euler-Maruyama) or, without noise, gradient descent.
+template <int D, bool NOISE>
+__global__ __launch_bounds__(kBlock) void k_overdamped(uint32_t *pos, const float *force, int N, DevBox b,
+                                                       const uint32_t *pos_ref, float half_skin, float a_f, float a_n,
+                                                       uint64_t seed, const uint64_t *step, int32_t *ctl)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < N) {
+        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (NOISE) normals4((uint64_t)i, step[0], seed, z);
+        uint32_t ui[D], un[D];
+        load_pos<D>(pos, i, ui);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            float dx = a_f * force[(size_t)i * D + q];
+            if (NOISE) dx = __builtin_fmaf(a_n, z[q], dx);
+            un[q] = shift_coord(ui[q], dx, b.inv_s[q]);
+        }
+        store_pos<D>(pos, i, un);
+        far = disp2<D>(un, pos_ref, i, b) > half_skin * half_skin;
+    }
+    wave_flag(far, &ctl[kTrigWord]);
+}
+
+__global__ void k_step_advance(uint64_t *step)
+{
+    if (threadIdx.x == 0) step[0] += 1;
+}
+
+// Half step of a Nose-Hoover chain over time h (Martyna, Tuckerman, Tobias and Klein 1996, one stage): 2K from
+// the kinetic-energy partials (fixed order), thermostat momenta down the chain, positions, the velocity factor,
+// momenta back up.  One workgroup; thread 0 updates the chain.
+__global__ __launch_bounds__(kBlock) void k_nhc_chain(const double *partials, int n, md_nhc_state *st, double h)
+{
+    __shared__ double red[kBlock];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += kBlock) s += partials[q];
+    s = block_sum(s, red);
+    if (threadIdx.x != 0) return;
+    const int M = st->M;
+    if (M < 1 || M > 8) {  // not a chain: leave the velocities as they are
+        st->scale = 1.0;
+        return;
+    }
+    const double kT = st->kT, nf = (double)st->n_dof;
+    double K2 = 2.0 * s;
+    double *p = st->p, *Q = st->Q;
+    auto G = [&](int k) { return k == 0 ? K2 - nf * kT : p[k - 1] * p[k - 1] / Q[k - 1] - kT; };
+    p[M - 1] += 0.5 * h * G(M - 1);
+    for (int k = M - 2; k >= 0; --k) {
+        double f = exp(-0.25 * h * p[k + 1] / Q[k + 1]);
+        p[k] = (p[k] * f + 0.5 * h * G(k)) * f;
+    }
+    for (int k = 0; k < M; ++k) st->eta[k] += h * p[k] / Q[k];
+    double sc = exp(-h * p[0] / Q[0]);
+    K2 *= sc * sc;
+    for (int k = 0; k < M - 1; ++k) {
+        double f = exp(-0.25 * h * p[k + 1] / Q[k + 1]);
+        p[k] = (p[k] * f + 0.5 * h * G(k)) * f;
+    }
+    p[M - 1] += 0.5 * h * G(M - 1);
+    st->scale = sc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_by(float *v, int64_t n, const md_nhc_state *st)
+{
+    double f = st->scale;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)gridDim.x * kBlock)
+        v[q] = (float)((double)v[q] * f);
+}
+
 __global__ void k_clear_trigger(int32_t *ctl)
 {
     if (threadIdx.x == 0) ctl[kTrigWord] = 0;
@@ -2107,6 +2248,95 @@ md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *ve
     else
         hipLaunchKernelGGL(k_kick_drift<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, N, b, nl->pos_ref,
                            0.5f * nl->skin, dt, ctx->ctl);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+static md_status step_common(md_ctx *ctx, const md_box *box, const uint32_t *pos, const float *force, int32_t N,
+                             const md_nlist *nl, DevBox &b)
+{
+    md_status st = check_common(ctx, box, N);
+    if (st != MD_OK) return st;
+    if (!pos || !force || !nl_ok(nl, N) || nl->segment != 0) return MD_ERR_ARG;
+    if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
+    return MD_OK;
+}
+
+md_status md_langevin_baoa(md_ctx *ctx, const md_box *box, uint32_t *pos, float *vel, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, float gamma, float kT, uint64_t seed, uint64_t *step,
+                           void *stream)
+{
+    DevBox b;
+    md_status st = step_common(ctx, box, pos, force, N, nl, b);
+    if (st != MD_OK) return st;
+    if (!vel || !step || !isfinite(dt) || !(gamma >= 0.0f) || !(kT >= 0.0f)) return MD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (N > 0) {
+        double c1 = exp(-(double)gamma * (double)dt);
+        float c2 = (float)sqrt((1.0 - c1 * c1) * (double)kT);
+        if (box->dim == 3)
+            hipLaunchKernelGGL(k_langevin_baoa<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, N, b,
+                               nl->pos_ref, 0.5f * nl->skin, dt, (float)c1, c2, seed, step, ctx->ctl);
+        else
+            hipLaunchKernelGGL(k_langevin_baoa<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, N, b,
+                               nl->pos_ref, 0.5f * nl->skin, dt, (float)c1, c2, seed, step, ctx->ctl);
+    }
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+static md_status overdamped(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
+                            const md_nlist *nl, float a_f, float a_n, uint64_t seed, uint64_t *step, void *stream)
+{
+    DevBox b;
+    md_status st = step_common(ctx, box, pos, force, N, nl, b);
+    if (st != MD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool noise = a_n > 0.0f;
+    if (N > 0) {
+        if (box->dim == 3) {
+            if (noise)
+                hipLaunchKernelGGL((k_overdamped<3, true>), dim3(nblk(N)), dim3(kBlock), 0, s, pos, force, N, b,
+                                   nl->pos_ref, 0.5f * nl->skin, a_f, a_n, seed, step, ctx->ctl);
+            else
+                hipLaunchKernelGGL((k_overdamped<3, false>), dim3(nblk(N)), dim3(kBlock), 0, s, pos, force, N, b,
+                                   nl->pos_ref, 0.5f * nl->skin, a_f, a_n, seed, step, ctx->ctl);
+        } else {
+            if (noise)
+                hipLaunchKernelGGL((k_overdamped<2, true>), dim3(nblk(N)), dim3(kBlock), 0, s, pos, force, N, b,
+                                   nl->pos_ref, 0.5f * nl->skin, a_f, a_n, seed, step, ctx->ctl);
+            else
+                hipLaunchKernelGGL((k_overdamped<2, false>), dim3(nblk(N)), dim3(kBlock), 0, s, pos, force, N, b,
+                                   nl->pos_ref, 0.5f * nl->skin, a_f, a_n, seed, step, ctx->ctl);
+        }
+    }
+    if (noise) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status md_brownian_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, float gamma, float kT, uint64_t seed, uint64_t *step,
+                           void *stream)
+{
+    if (!isfinite(dt) || !(gamma > 0.0f) || !(kT >= 0.0f) || (kT > 0.0f && !step)) return MD_ERR_ARG;
+    float a_n = (float)sqrt(2.0 * (double)kT * (double)dt / (double)gamma);
+    return overdamped(ctx, box, pos, force, N, nl, dt / gamma, a_n, seed, step, stream);
+}
+
+md_status md_gradient_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
+                           const md_nlist *nl, float dt, void *stream)
+{
+    if (!isfinite(dt)) return MD_ERR_ARG;
+    return overdamped(ctx, box, pos, force, N, nl, dt, 0.0f, 0, nullptr, stream);
+}
+
+md_status md_nhc_half(md_ctx *ctx, float *vel, int32_t N, int32_t dim, md_nhc_state *state, double h, void *stream)
+{
+    if (!ctx || !vel || !state || N < 0 || (dim != 2 && dim != 3) || !isfinite(h)) return MD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t n = (int64_t)N * dim;
+    hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, n, ctx->partials);
+    hipLaunchKernelGGL(k_nhc_chain, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, state, h);
+    hipLaunchKernelGGL(k_scale_by, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, n, state);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -68,6 +68,11 @@ class c_fire_state(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("n_pos", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
+class c_nhc_state(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double * 8), ("eta", ctypes.c_double * 8), ("Q", ctypes.c_double * 8),
+                ("kT", ctypes.c_double), ("scale", ctypes.c_double), ("M", ctypes.c_int32), ("n_dof", ctypes.c_int32)]
+
+
 class c_batch(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int32), ("dim", ctypes.c_int32), ("max_n", ctypes.c_int32),
                 ("max_cells", ctypes.c_int32), ("offset", ctypes.c_void_p), ("box", ctypes.c_void_p),
@@ -127,6 +132,12 @@ _SIGNATURES = {
     "md_kick_drift": [P, ctypes.POINTER(c_box), P, P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
     "nl_update": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P],
     "md_kick": [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P],
+    "md_langevin_baoa": [P, ctypes.POINTER(c_box), P, P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float,
+                         ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P],
+    "md_brownian_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float,
+                         ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P],
+    "md_gradient_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
+    "md_nhc_half": [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
     "md_copy_words": [P, P, P, ctypes.c_int64, P],
     "md_min_distance": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P, P],
@@ -396,6 +407,53 @@ def nl_update(ctx: Context, box: Box, pos, nl: NeighborList):
 def kick(ctx: Context, vel, force, h: float):
     N, dim = vel.shape
     _check("md_kick", load().md_kick(ctx.h, _ptr(vel), _ptr(force), N, dim, ctypes.c_float(h), _stream()))
+
+
+def langevin_baoa(ctx: Context, box: Box, pos, vel, force, nl: NeighborList, dt: float, gamma: float, kT: float,
+                  seed: int, step: torch.Tensor):
+    b, n = box.c(), nl.c()
+    _check("md_langevin_baoa", load().md_langevin_baoa(
+        ctx.h, ctypes.byref(b), _ptr(pos), _ptr(vel), _ptr(force), pos.shape[0], ctypes.byref(n), ctypes.c_float(dt),
+        ctypes.c_float(gamma), ctypes.c_float(kT), ctypes.c_uint64(seed), _ptr(step), _stream()))
+
+
+def brownian_step(ctx: Context, box: Box, pos, force, nl: NeighborList, dt: float, gamma: float, kT: float,
+                  seed: int, step: torch.Tensor | None):
+    b, n = box.c(), nl.c()
+    _check("md_brownian_step", load().md_brownian_step(
+        ctx.h, ctypes.byref(b), _ptr(pos), _ptr(force), pos.shape[0], ctypes.byref(n), ctypes.c_float(dt),
+        ctypes.c_float(gamma), ctypes.c_float(kT), ctypes.c_uint64(seed), _ptr(step), _stream()))
+
+
+def gradient_step(ctx: Context, box: Box, pos, force, nl: NeighborList, dt: float):
+    b, n = box.c(), nl.c()
+    _check("md_gradient_step", load().md_gradient_step(ctx.h, ctypes.byref(b), _ptr(pos), _ptr(force), pos.shape[0],
+                                                       ctypes.byref(n), ctypes.c_float(dt), _stream()))
+
+
+def nhc_state_tensor(Q, kT: float, n_dof: int, device=None) -> torch.Tensor:
+    """A Nose-Hoover chain state (md_nhc_state) in device memory: masses Q (chain length len(Q) <= 8), momenta and
+    positions zero."""
+    Q = [float(q) for q in Q]
+    if not 1 <= len(Q) <= 8 or min(Q) <= 0.0:
+        raise ValueError("chain of 1..8 positive masses")
+    st = c_nhc_state()
+    for k, q in enumerate(Q):
+        st.Q[k] = q
+    st.kT, st.scale, st.M, st.n_dof = float(kT), 1.0, len(Q), int(n_dof)
+    raw = np.frombuffer(bytes(st), dtype=np.uint8).copy()
+    return torch.as_tensor(raw, device=device or _dev())
+
+
+def nhc_state_read(state: torch.Tensor) -> dict:
+    s = c_nhc_state.from_buffer_copy(state.cpu().numpy().tobytes())
+    return dict(p=np.array(s.p[: s.M]), eta=np.array(s.eta[: s.M]), Q=np.array(s.Q[: s.M]), kT=s.kT, scale=s.scale,
+                M=s.M, n_dof=s.n_dof)
+
+
+def nhc_half(ctx: Context, vel, state: torch.Tensor, h: float):
+    N, dim = vel.shape
+    _check("md_nhc_half", load().md_nhc_half(ctx.h, _ptr(vel), N, dim, _ptr(state), ctypes.c_double(h), _stream()))
 
 
 def min_distance(ctx: Context, box: Box, pos, nl: NeighborList) -> torch.Tensor:
@@ -802,6 +860,112 @@ def nve(system: System, dt: float):
         return system
 
     return init_fn, update_fn
+
+
+def _stepper(system: System, step_once, state_tensors, chunk: int = 20):
+    """update_fn(n, graph=False) for an integrator whose step is a fixed sequence of launches (step_once).  The
+    device decides every rebuild (nl_update), so `chunk` steps can be captured once in a HIP graph and replayed;
+    flags are read after every run, and a run that reports an overflow is re-run eagerly from its saved state."""
+    graphs = {}
+
+    def eager(n):
+        for _ in range(n):
+            step_once()
+
+    def update_fn(n_steps: int = 1, graph: bool = False):
+        done = 0
+        while done < n_steps:
+            k = min(chunk, n_steps - done) if graph else n_steps - done
+            saved = (state_tensors, tuple(t.clone() for t in state_tensors))
+            if graph and k == chunk:
+                g = graphs.get(chunk)
+                if g is None:
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
+                        eager(chunk)
+                    graphs[chunk] = g
+                system.nl.clear_flags()
+                g.replay()
+                f = system.nl.read_flags()
+                if f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW] or f[FLAG_STALE]:
+                    for t, v in zip(saved[0], saved[1]):
+                        t.copy_(v)
+                    graphs.clear()
+                    system.last_flags = _run_checked(system, saved, eager, k)
+                elif f[FLAG_NONFINITE]:
+                    raise FloatingPointError("non-finite force")
+                else:
+                    system.last_flags = f
+            else:
+                system.last_flags = _run_checked(system, saved, eager, k)
+            done += k
+        return system
+
+    return update_fn
+
+
+def _init_forces(system: System):
+    def init_fn():
+        system.build()
+        system.forces()
+        return system
+    return init_fn
+
+
+def nvt_langevin(system: System, dt: float, gamma: float, kT: float, seed: int = 0):
+    """init_fn / update_fn for Langevin dynamics at temperature kT (Sec. 3.3.1 ``simulate.nvt_langevin``; BAOAB
+    with friction gamma, unit masses).  The step counter that indexes the noise lives on the device."""
+    step = torch.zeros(1, dtype=torch.int64, device=system.ctx.device)
+
+    def once():
+        langevin_baoa(system.ctx, system.box, system.pos, system.vel, system.force, system.nl, dt, gamma, kT, seed,
+                      step)
+        nl_update(system.ctx, system.box, system.pos, system.nl)
+        system.forces()
+        kick(system.ctx, system.vel, system.force, 0.5 * dt)
+
+    return _init_forces(system), _stepper(system, once, (system.pos, system.vel, system.force, step))
+
+
+def brownian(system: System, dt: float, gamma: float, kT: float, seed: int = 0):
+    """init_fn / update_fn for Brownian (overdamped Langevin) dynamics at temperature kT, friction gamma
+    (Sec. 3.3.1 ``simulate.brownian``; Euler-Maruyama)."""
+    step = torch.zeros(1, dtype=torch.int64, device=system.ctx.device)
+
+    def once():
+        brownian_step(system.ctx, system.box, system.pos, system.force, system.nl, dt, gamma, kT, seed, step)
+        nl_update(system.ctx, system.box, system.pos, system.nl)
+        system.forces()
+
+    return _init_forces(system), _stepper(system, once, (system.pos, system.force, step))
+
+
+def gradient_descent(system: System, dt: float):
+    """init_fn / update_fn for steepest descent x += dt F (Sec. 3.3.1 ``minimize.gradient_descent``)."""
+
+    def once():
+        gradient_step(system.ctx, system.box, system.pos, system.force, system.nl, dt)
+        nl_update(system.ctx, system.box, system.pos, system.nl)
+        system.forces()
+
+    return _init_forces(system), _stepper(system, once, (system.pos, system.force))
+
+
+def nvt_nose_hoover(system: System, dt: float, kT: float, Q=(1.0,)):
+    """init_fn / update_fn for a Nose-Hoover chain at temperature kT with thermostat masses Q (Sec. 3.3.1
+    ``simulate.nvt_nose_hoover``, Martyna et al.).  The chain state (md_nhc_state) is returned as the third
+    element; nhc_state_read decodes it."""
+    state = nhc_state_tensor(Q, kT, system.N * system.dim, system.ctx.device)
+
+    def once():
+        nhc_half(system.ctx, system.vel, state, 0.5 * dt)
+        kick_drift(system.ctx, system.box, system.pos, system.vel, system.force, system.nl, dt)
+        nl_update(system.ctx, system.box, system.pos, system.nl)
+        system.forces()
+        kick(system.ctx, system.vel, system.force, 0.5 * dt)
+        nhc_half(system.ctx, system.vel, state, 0.5 * dt)
+
+    return _init_forces(system), _stepper(system, once, (system.pos, system.vel, system.force, state)), state
 
 
 def autotune_lanes(system: System, dt: float, candidates=(2, 4, 8), steps: int = 60, repeats: int = 2) -> dict:
