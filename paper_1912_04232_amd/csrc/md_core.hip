@@ -1321,6 +1321,38 @@ __global__ __launch_bounds__(kBlock) void k_kick(float *vel, const float *force,
     if (q < n) vel[q] = __builtin_fmaf(h, force[q], vel[q]);
 }
 
+// Forces from a list with W lanes per particle (the loop of the step kernel), for calls that need no energies:
+// the lanes of a particle split its sub-rows and combine through shuffles; lane 0 writes the force.
+template <int D, int KIND, bool MULTI, int W>
+__global__ __launch_bounds__(kBlock) void k_force_lanes(DevBox b, DevPot p, const uint32_t *__restrict__ pos,
+                                                        const int32_t *__restrict__ species, int N, int capW,
+                                                        const int32_t *__restrict__ idx,
+                                                        const int32_t *__restrict__ count, float *__restrict__ force,
+                                                        int32_t *flags)
+{
+    int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    int i = gt / W, l = gt % W;
+    bool live = i < N;
+    int ii = live ? i : N - 1;  // dead lanes shadow the last particle so the lane reduction stays uniform
+    uint32_t ui[D];
+    load_pos<D>(pos, ii, ui);
+    int si = MULTI ? species[ii] : 0;
+    float F[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) F[q] = 0.0f;
+    int n = live ? min(count[(size_t)ii * W + l], capW) : 0;
+    lane_force<D, KIND, MULTI, W>(b, p, pos, species, N, capW, idx, n, ii, l, ui, si, F);
+    bool bad = false;
+    if (live && l == 0) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            bad = bad || !isfinite(F[q]);
+            force[(size_t)i * D + q] = F[q];
+        }
+    }
+    wave_flag(bad, &flags[MD_FLAG_NONFINITE]);
+}
+
 // ------------------------------------------------------------------------------------------------
 // constant-temperature steps and gradient descent (the caller computes forces between launches)
 
@@ -2046,11 +2078,13 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
                         hipLaunchKernelGGL((k_pair_nl<D, KIND, MULTI, true>), dim3(grid), dim3(kBlock), 0, s, b, p,
                                            pos, species, N, nl->idx, nl->count, W, capW, force, energy, virial,
                                            flags));
-        } else {
+        } else if (force) {
+            // forces only: W lanes per particle over the balanced sub-rows
+            int lgrid = nblk((int64_t)N * W);
             MD_DISPATCH(box->dim, pot->kind, multi,
-                        hipLaunchKernelGGL((k_pair_nl<D, KIND, MULTI, false>), dim3(grid), dim3(kBlock), 0, s, b, p,
-                                           pos, species, N, nl->idx, nl->count, W, capW, force, energy, virial,
-                                           flags));
+                        MD_LANES(W, hipLaunchKernelGGL((k_force_lanes<D, KIND, MULTI, W>), dim3(lgrid), dim3(kBlock),
+                                                       0, s, b, p, pos, species, N, capW, nl->idx, nl->count, force,
+                                                       flags)));
         }
     } else {
         if (ew) {
