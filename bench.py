@@ -212,37 +212,11 @@ def integrators(ctx, progress, steps: int = 1000):
     """The constant-temperature steps and gradient descent on the benchmark system (3D LJ N = 256000, FCC start,
     T = 1): one step is the integrator's kernel, the device-gated rebuild, the list force pass and (for the
     inertial schemes) the closing kick, replayed from HIP graphs of 20 steps."""
-    import torch
-
-    from paper_1912_04232_amd import inputs, md
-    c = inputs.lj_large()
-    box = md.Box(tuple(c["L"]), 3)
-    pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=c["r_cut"])
-    makers = (
-        ("langevin", "BAOAB, gamma 1, kT 1, dt 0.005", lambda s: md.nvt_langevin(s, c["dt"], 1.0, 1.0, 1)),
-        ("nose_hoover", "chain Q = (100, 10), kT 1, dt 0.005",
-         lambda s: md.nvt_nose_hoover(s, c["dt"], 1.0, (100.0, 10.0))[:2]),
-        ("brownian", "gamma 1, kT 1, dt 1e-4", lambda s: md.brownian(s, 1e-4, 1.0, 1.0, 1)),
-        ("gradient_descent", "dt 1e-4", lambda s: md.gradient_descent(s, 1e-4)),
-    )
+    from paper_1912_04232_amd import simulate
     out = {}
-    for name, what, make in makers:
-        s = md.System(box, pot, c["u"], c["v"], skin=c["skin"], ctx=ctx)
-        init, update = make(s)
-        init()
-        update(100, graph=True)
-        torch.cuda.synchronize()
-        s.nl.clear_flags()
-        t0 = time.perf_counter()
-        update(steps, graph=True)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        f = s.nl.read_flags()
-        out[name] = {"scheme": what, "steps": steps, "steps_per_s": steps / t, "us_per_step": 1e6 * t / steps,
-                     "rebuilds": int(f[md.FLAG_REBUILDS]),
-                     "kinetic_T": float((s.vel.double() ** 2).sum()) / (3 * s.N) if name in ("langevin", "nose_hoover")
-                     else None}
-        progress(f"{name}: {out[name]['steps_per_s']:.0f} steps/s")
+    for m in simulate.METHODS:
+        out[m] = simulate.run(ctx, m, steps)
+        progress(f"{m}: {out[m]['steps_per_s']:.0f} steps/s")
     return out
 
 
