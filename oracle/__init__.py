@@ -85,7 +85,7 @@ def default_threads() -> int:
 @dataclass
 class Potential:
     """Pair potential parameters (paper Sec. 3.3.2; species matrices as App. A)."""
-    kind: str = "lj"                      # "lj" or "soft_sphere"
+    kind: str = "lj"                      # "lj", "soft_sphere" or "morse"
     sigma: np.ndarray = field(default_factory=lambda: np.ones((1, 1)))
     epsilon: np.ndarray = field(default_factory=lambda: np.ones((1, 1)))
     alpha: float = 2.0
@@ -97,7 +97,7 @@ class Potential:
         e = np.atleast_2d(np.asarray(self.epsilon, dtype=np.float64))
         S = s.shape[0]
         p = _Pot()
-        p.kind = 0 if self.kind == "lj" else 1
+        p.kind = {"lj": 0, "soft_sphere": 1, "morse": 2}[self.kind]
         p.n_species = S
         for q in range(S * S):
             p.sigma[q] = float(s.reshape(-1)[q])

@@ -20,6 +20,8 @@
  *     soft sphere    u = (eps/alpha) (1 - r/s)^alpha for r < s, else 0; the
  *                    same functional form the paper prints for its flocking
  *                    cutoff function (App. B, eq. "cutoff")
+ *     Morse          u = eps [(1 - exp(-alpha (r - s)))^2 - 1] (- u(r_c) if
+ *                    shifted), 0 for r >= r_c: well depth eps at r = s
  *   species mixing : s_ab, eps_ab given as S x S matrices (App. A builds
  *                    s_ab = (d_a + d_b)/2)
  *   neighbor set   : all ordered pairs with r^2 < r_list^2 (Sec. 3.2.3)
@@ -34,13 +36,13 @@
 #include <string.h>
 
 typedef struct {
-    int32_t kind;        /* 0 = Lennard-Jones, 1 = soft sphere */
+    int32_t kind;        /* 0 = Lennard-Jones, 1 = soft sphere, 2 = Morse */
     int32_t n_species;   /* S, 1..8 */
     double sigma[64];    /* S x S, row-major */
     double epsilon[64];  /* S x S, row-major */
-    double alpha;        /* soft-sphere exponent */
-    double r_cut;        /* Lennard-Jones cutoff distance */
-    int32_t shift;       /* Lennard-Jones: subtract u(r_cut) from the energy */
+    double alpha;        /* soft-sphere exponent; Morse range parameter */
+    double r_cut;        /* Lennard-Jones / Morse cutoff distance */
+    int32_t shift;       /* Lennard-Jones / Morse: subtract u(r_cut) from the energy */
 } orc_pot;
 
 typedef struct {
@@ -90,6 +92,16 @@ static void pair_u(const orc_pot *p, double r, double s, double e, double *u, do
             *u -= 4.0 * e * (sc6 * sc6 - sc6);
         }
         *f = 24.0 * e * (2.0 * sr12 - sr6) / r;
+    } else if (p->kind == 2) {
+        /* Morse: u = e [(1 - exp(-a (r - s)))^2 - 1], minimum -e at r = s */
+        if (r >= p->r_cut) return;
+        double x = exp(-p->alpha * (r - s));
+        *u = e * ((1.0 - x) * (1.0 - x) - 1.0);
+        if (p->shift) {
+            double xc = exp(-p->alpha * (p->r_cut - s));
+            *u -= e * ((1.0 - xc) * (1.0 - xc) - 1.0);
+        }
+        *f = -2.0 * p->alpha * e * x * (1.0 - x);
     } else {
         if (r >= s) return;
         double t = 1.0 - r / s;
@@ -415,6 +427,7 @@ int orc_fire(int dim, const double *L, int64_t N, double *x, double *v, double *
 int orc_param_grad(int dim, const double *L, int64_t N, const double *x, const int32_t *species,
                    const orc_pot *pot, double *g_sigma, double *g_eps)
 {
+    if (pot->kind == 2) return -3; /* parameter derivatives are written for Lennard-Jones and soft spheres */
     int S = pot->n_species;
     for (int q = 0; q < S * S; ++q) {
         g_sigma[q] = 0.0;

@@ -542,3 +542,47 @@ def test_envelope_theorem_through_fire(orc):
             E.append(orc.energy(r["x"], [L, L], ss_pot(orc, d=dd), sp))
         fd = (E[0] - E[1]) / (2 * h)
         assert math.isclose(g[s], fd, rel_tol=1e-5, abs_tol=1e-10), (s, g[s], fd)
+
+
+# ------------------------------------------------------------------------ Morse
+
+def morse_pot(orc, shift=True):
+    return orc.Potential("morse", np.array([[1.1, 1.2], [1.2, 1.3]]), np.array([[1.0, 0.7], [0.7, 1.4]]), alpha=3.0,
+                         r_cut=2.8, shift=shift)
+
+
+def test_morse_dimer_closed_form(orc):
+    """Two particles of species (0, 1): u(r) = eps [(1 - exp(-a (r - s)))^2 - 1], minimum -eps at r = s, zero force
+    there, and the energy shift is u(r_c)."""
+    L = [30.0, 30.0, 30.0]
+    for r, shift in ((1.2, False), (1.0, False), (2.0, True), (2.79, True)):
+        x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+        F, e, _ = orc.pair_rows(x, L, morse_pot(orc, shift), [0, 1])
+        t = math.exp(-3.0 * (r - 1.2))
+        u = 0.7 * ((1 - t) ** 2 - 1)
+        if shift:
+            tc = math.exp(-3.0 * (2.8 - 1.2))
+            u -= 0.7 * ((1 - tc) ** 2 - 1)
+        fr = -2.0 * 3.0 * 0.7 * t * (1 - t)          # force on particle 1 along +x
+        assert math.isclose(e.sum(), u, rel_tol=1e-13, abs_tol=1e-15)
+        assert math.isclose(F[1, 0], fr, rel_tol=1e-13, abs_tol=1e-13) and F[0, 0] == pytest.approx(-fr, abs=1e-13)
+    x = np.array([[5.0, 5.0, 5.0], [6.2, 5.0, 5.0]])
+    F, e, _ = orc.pair_rows(x, L, morse_pot(orc, False), [0, 1])
+    assert math.isclose(e.sum(), -0.7, rel_tol=1e-14) and abs(F).max() < 1e-13
+    x = np.array([[5.0, 5.0, 5.0], [7.85, 5.0, 5.0]])       # beyond the cutoff
+    F, e, _ = orc.pair_rows(x, L, morse_pot(orc), [0, 1])
+    assert e.sum() == 0.0 and abs(F).max() == 0.0
+
+
+def test_morse_forces_are_minus_energy_gradient(orc):
+    N = 60
+    L = [5.5, 5.0, 4.8]
+    x = inputs.uniform_torus(N, 3, 19).astype(np.float64) * (np.array(L) / 2.0 ** 32)
+    sp = np.arange(N) % 2
+    pot = morse_pot(orc)
+    F, _, _ = orc.pair_rows(x, L, pot, sp)
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal(x.shape)
+    h = 1e-6
+    fd = -(orc.energy(x + h * z, L, pot, sp) - orc.energy(x - h * z, L, pot, sp)) / (2 * h)
+    assert (F * z).sum() == pytest.approx(fd, rel=1e-7, abs=1e-9)
