@@ -205,6 +205,33 @@ def secondary(progress):
     out["unrolled_box_sweep"] = sweep.run_unrolled(ctx)
     progress("unrolled sweep done")
     out["integrators_lj256k"] = integrators(ctx, progress)
+    out["morse_nve_256k"] = morse_nve(ctx, progress)
+    return out
+
+
+def morse_nve(ctx, progress, steps: int = 2000):
+    """Fused velocity-Verlet steps with the Morse potential on the benchmark's lattice (N = 256000 FCC, density
+    0.84, T = 1): eps 1, minimum at 2^(1/6), alpha 5, cutoff 2.5 with the energy shifted."""
+    import torch
+
+    from paper_1912_04232_amd import inputs, md
+    c = inputs.lj_large()
+    box = md.Box(tuple(c["L"]), 3)
+    pot = md.Potential("morse", [[2.0 ** (1.0 / 6.0)]], [[1.0]], alpha=5.0, r_cut=c["r_cut"], shift=True)
+    s = md.System(box, pot, c["u"], c["v"], skin=c["skin"], ctx=ctx)
+    init, update = md.nve(s, c["dt"])
+    init()
+    update(100)
+    torch.cuda.synchronize()
+    s.nl.clear_flags()
+    t0 = time.perf_counter()
+    update(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    f = s.nl.read_flags()
+    out = {"N": s.N, "steps": steps, "steps_per_s": steps / t, "us_per_step": 1e6 * t / steps,
+           "rebuilds": int(f[md.FLAG_REBUILDS]), "mean_row": float(s.nl.lengths().mean())}
+    progress(f"morse NVE: {out['steps_per_s']:.0f} steps/s")
     return out
 
 

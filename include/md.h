@@ -63,13 +63,17 @@ typedef struct {
     float L[3];    /* edge lengths; L[2] ignored when dim == 2 */
 } md_box;
 
-enum { MD_LJ = 0, MD_SOFT_SPHERE = 1 };
+enum { MD_LJ = 0, MD_SOFT_SPHERE = 1, MD_MORSE = 2 };
 
 /*
  * Pair potential with S species (Sec. 3.3.2; species matrices as in App. A).
  *   MD_LJ          u = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] for r < r_cut,
  *                  minus u(r_cut) when shift != 0; 0 beyond r_cut.
  *   MD_SOFT_SPHERE u = eps_ab/alpha (1 - r/sigma_ab)^alpha for r < sigma_ab, else 0.
+ *   MD_MORSE       u = eps_ab [(1 - exp(-alpha (r - sigma_ab)))^2 - 1] for r < r_cut (well depth eps_ab at
+ *                  r = sigma_ab, range alpha > 0), minus u(r_cut) when shift != 0; 0 beyond r_cut.
+ *                  Accepted by the list, dense and step entry points; the replica entry points
+ *                  (fire_batched, envelope_grad, fire_unrolled_grad) take MD_LJ and MD_SOFT_SPHERE only.
  * sigma and epsilon are S x S row-major (entry a*S+b), symmetric, S <= 8.
  */
 typedef struct {

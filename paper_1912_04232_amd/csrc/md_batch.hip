@@ -474,6 +474,7 @@ md_status batch_check(md_ctx *ctx, const md_batch *bt, const md_potential *pot, 
 {
     if (!ctx || !bt || !pot || bt->B < 0 || bt->dim != 2 || !bt->offset || !bt->box || !bt->pos) return MD_ERR_ARG;
     if (!md_make_pot(pot, p)) return MD_ERR_ARG;
+    if (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE) return MD_ERR_ARG;  // the replica kernels know these two
     if (pot->n_species > 1 && !bt->species) return MD_ERR_ARG;
     if (bt->max_n > kMaxRepN || bt->max_cells > kMaxRepCells) return MD_ERR_CAPACITY;
     return MD_OK;

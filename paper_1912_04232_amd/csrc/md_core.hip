@@ -1704,7 +1704,7 @@ static bool make_box(const md_box *box, float r_list, DevBox &b)
 
 bool md_make_pot(const md_potential *pot, DevPot &p)
 {
-    if (!pot || (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE)) return false;
+    if (!pot || (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE && pot->kind != MD_MORSE)) return false;
     int S = pot->n_species;
     if (S < 1 || S > kMaxSpecies) return false;
     memset(&p, 0, sizeof(p));
@@ -1715,6 +1715,8 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
     p.rc2 = pot->r_cut * pot->r_cut;
     if (pot->kind == MD_SOFT_SPHERE && !(pot->alpha >= 1.0f)) return false;
     if (pot->kind == MD_LJ && !(pot->r_cut > 0.0f)) return false;
+    if (pot->kind == MD_MORSE && !(pot->r_cut > 0.0f && pot->alpha > 0.0f)) return false;
+    p.mk = (float)((double)pot->alpha * 1.4426950408889634);  // alpha log2(e)
     for (int a = 0; a < S; ++a)
         for (int c = 0; c < S; ++c) {
             int q = a * S + c;
@@ -1733,6 +1735,12 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
             p.inv_sig[q] = (float)(1.0 / s);
             p.eps_over_sig[q] = (float)(e / s);
             p.eps_over_alpha[q] = (float)(e / pot->alpha);
+            if (pot->kind == MD_MORSE) {
+                double xc = exp(-(double)pot->alpha * (rc - s));
+                p.a12[q] = (float)(2.0 * pot->alpha * e);
+                p.c12[q] = (float)e;
+                p.ushift[q] = pot->shift ? (float)(e * xc * (xc - 2.0)) : 0.0f;
+            }
         }
     return true;
 }
@@ -1744,7 +1752,7 @@ int md_partials_blocks()
 
 float md_max_cutoff(const md_potential *pot)
 {
-    if (pot->kind == MD_LJ) return pot->r_cut;
+    if (pot->kind == MD_LJ || pot->kind == MD_MORSE) return pot->r_cut;
     float m = 0.0f;
     for (int q = 0; q < pot->n_species * pot->n_species; ++q) m = fmaxf(m, (float)pot->sigma[q]);
     return m;
@@ -1790,6 +1798,10 @@ static inline int nblk(int64_t n)
                 constexpr int KIND = 0;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
                 else { constexpr bool MULTI = false; __VA_ARGS__; }          \
+            } else if (KIND_ == 2) {                                         \
+                constexpr int KIND = 2;                                      \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \
                 constexpr int KIND = 1;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
@@ -1799,6 +1811,10 @@ static inline int nblk(int64_t n)
             constexpr int D = 2;                                             \
             if (KIND_ == 0) {                                                \
                 constexpr int KIND = 0;                                      \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
+            } else if (KIND_ == 2) {                                         \
+                constexpr int KIND = 2;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
                 else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \

@@ -29,13 +29,13 @@ struct DevBox {
 // For soft spheres: f/r = (eps/sig) t^(alpha-1) / r, u = eps/alpha t^alpha,
 // t = 1 - r/sig.
 struct DevPot {
-    int kind;          // 0 LJ, 1 soft sphere
+    int kind;          // 0 LJ, 1 soft sphere, 2 Morse
     int S;
-    float rc2;         // LJ cutoff squared
+    float rc2;         // LJ / Morse cutoff squared
     float alpha;
     int alpha_is_2;
-    int pad;
-    float a12[64], a6[64], c12[64], c6[64], ushift[64];  // LJ
+    float mk;          // Morse: alpha log2(e)
+    float a12[64], a6[64], c12[64], c6[64], ushift[64];  // LJ; Morse keeps 2 alpha eps in a12, eps in c12
     float sig[64], inv_sig[64], eps_over_sig[64], eps_over_alpha[64];  // soft sphere
     double sigd[64];                                                    // sigma in double (overlap)
 };
@@ -78,12 +78,30 @@ __device__ __forceinline__ float ss_fs(float r2, float sig, float inv_sig, float
     return in ? fs : 0.0f;
 }
 
+// Morse, u = eps [(1 - x)^2 - 1] with x = exp(-alpha (r - r0)): returns f/r = 2 alpha eps x (x - 1) / r (0 beyond
+// the cutoff); u = eps x (x - 2) - u(r_c) when WANT_U.
+template <bool WANT_U>
+__device__ __forceinline__ float morse_fs(float r2, float rc2, float r0, float mk, float eps, float two_ae,
+                                          float ushift, float &u)
+{
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float r = r2 * ri;
+    float x = __builtin_exp2f(mk * (r0 - r));
+    float fs = two_ae * x * (x - 1.0f) * ri;
+    bool in = r2 < rc2;
+    if (WANT_U) u = in ? eps * x * (x - 2.0f) - ushift : 0.0f;
+    return in ? fs : 0.0f;
+}
+
 template <int KIND, bool MULTI, bool WANT_U>
 __device__ __forceinline__ float pair_fs(const DevPot &p, int pt, float r2, float &u)
 {
     if (KIND == 0) {
         int q = MULTI ? pt : 0;
         return lj_fs<WANT_U>(r2, p.rc2, p.a12[q], p.a6[q], p.c12[q], p.c6[q], p.ushift[q], u);
+    } else if (KIND == 2) {
+        int q = MULTI ? pt : 0;
+        return morse_fs<WANT_U>(r2, p.rc2, p.sig[q], p.mk, p.c12[q], p.a12[q], p.ushift[q], u);
     } else {
         int q = MULTI ? pt : 0;
         return ss_fs<WANT_U>(r2, p.sig[q], p.inv_sig[q], p.eps_over_sig[q], p.eps_over_alpha[q], p.alpha,
@@ -122,7 +140,7 @@ __device__ __forceinline__ float pair_eval(const DevPot &p, int pt, const uint32
         d[k] = tdisp(ui[k], uj[k], s[k]);
         r2 = __builtin_fmaf(d[k], d[k], r2);
     }
-    if (KIND == 0) return pair_fs<KIND, MULTI, WANT_U>(p, pt, r2, u);
+    if (KIND != 1) return pair_fs<KIND, MULTI, WANT_U>(p, pt, r2, u);
     double dd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) dd[k] = tdisp_d(ui[k], uj[k], sd[k]);

@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmdcore.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
 
-MD_LJ, MD_SOFT_SPHERE = 0, 1
+MD_LJ, MD_SOFT_SPHERE, MD_MORSE = 0, 1, 2
 FLAG_OVERFLOW, FLAG_MAXCOUNT, FLAG_NONFINITE, FLAG_REBUILDS = 0, 1, 2, 3
 FLAG_CELL_OVERFLOW, FLAG_STALE, FLAG_MAXCELL, FLAG_STEPS, NFLAGS = 4, 5, 6, 7, 8
 
@@ -212,7 +212,8 @@ class Box:
 
 @dataclass
 class Potential:
-    """Pair potential (paper Sec. 3.3.2): kind 'lj' or 'soft_sphere', S x S sigma / epsilon."""
+    """Pair potential (paper Sec. 3.3.2): kind 'lj', 'soft_sphere' or 'morse', S x S sigma / epsilon (Morse: sigma
+    is the minimum position, epsilon the well depth, alpha the range)."""
     kind: str = "lj"
     sigma: object = ((1.0,),)
     epsilon: object = ((1.0,),)
@@ -225,7 +226,7 @@ class Potential:
         return int(np.atleast_2d(np.asarray(self.sigma)).shape[0])
 
     def cutoff(self) -> float:
-        if self.kind == "lj":
+        if self.kind in ("lj", "morse"):
             return float(self.r_cut)
         return float(np.max(np.asarray(self.sigma, dtype=np.float64)))
 
@@ -236,7 +237,7 @@ class Potential:
         if e.shape != (S, S) or S > 8:
             raise ValueError("sigma / epsilon must be S x S with S <= 8")
         p = c_potential()
-        p.kind = MD_LJ if self.kind == "lj" else MD_SOFT_SPHERE
+        p.kind = {"lj": MD_LJ, "soft_sphere": MD_SOFT_SPHERE, "morse": MD_MORSE}[self.kind]
         p.n_species = S
         for q in range(S * S):
             p.sigma[q] = float(s.reshape(-1)[q])
