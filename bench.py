@@ -206,6 +206,50 @@ def secondary(progress):
     progress("unrolled sweep done")
     out["integrators_lj256k"] = integrators(ctx, progress)
     out["morse_nve_256k"] = morse_nve(ctx, progress)
+    out["half_vs_full_list_256k"] = half_vs_full(ctx, progress)
+    return out
+
+
+def half_vs_full(ctx, progress, reps: int = 50):
+    """The list force pass over the full list (W lanes per particle, no atomics) against the Newton's-third-law pass
+    over a half list (each pair once, atomics for the partner), on the benchmark's 256k LJ lattice after 200
+    steps; HIP events around `reps` launches of each."""
+    import torch
+
+    from paper_1912_04232_amd import inputs, md
+    c = inputs.lj_large()
+    box = md.Box(tuple(c["L"]), 3)
+    pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=c["r_cut"])
+    s = md.System(box, pot, c["u"], c["v"], skin=c["skin"], ctx=ctx)
+    init, update = md.nve(s, c["dt"])
+    init()
+    update(200)
+    s.build()
+    h = md.HalfList(ctx, s.nl)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    F = torch.zeros_like(s.force)
+    s.forces()
+    h.update()
+    h.forces(box, pot, s.pos, s.species, F)
+    ev[0].record()
+    for _ in range(reps):
+        s.forces()
+    ev[1].record()
+    for _ in range(reps):
+        h.update()
+    ev[2].record()
+    for _ in range(reps):
+        h.forces(box, pot, s.pos, s.species, F)
+    ev[3].record()
+    torch.cuda.synchronize()
+    full_us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    compact_us = ev[1].elapsed_time(ev[2]) * 1e3 / reps
+    half_us = ev[2].elapsed_time(ev[3]) * 1e3 / reps
+    dF = float(torch.linalg.norm((F - s.force).double()) / torch.linalg.norm(s.force.double()))
+    out = {"full_list_us": full_us, "half_list_us": half_us, "half_list_build_us": compact_us,
+           "mean_full_row": float(s.nl.lengths().mean()), "mean_half_row": float(h.hcount.double().mean()),
+           "half_vs_full_force_rel_l2": dF}
+    progress(f"force pass: full list {full_us:.1f} us, half list {half_us:.1f} us")
     return out
 
 

@@ -437,6 +437,24 @@ md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t
 md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream);
 
 /*
+ * Half list (each pair once) from a full list, for comparing the Newton's-third-law force pass with the
+ * full-list pass (Sec. 3.2.3 lists): hidx [hcap][N] and hcount [N] (caller-owned device arrays) receive each
+ * pair of nl once, in row i when (i < j) differs from (i + j odd) (so rows hold about half their neighbors);
+ * any lane count, segment 0.  *overflow (device int32) is set to 1 when a row has more than hcap entries (the
+ * row is then truncated).
+ */
+md_status nl_half(md_ctx *ctx, const md_nlist *nl, int32_t *hidx, int32_t *hcount, int32_t hcap, int32_t *overflow,
+                  void *stream);
+/*
+ * Forces from a half list: every pair evaluated once, F_i += f_ij and F_j -= f_ij through float atomics, so the
+ * summation order (and the last bits of the forces) varies between runs.  force [N][dim] is overwritten.  The
+ * half list must come from a list valid for pos (the caller checks, e.g. with nl_update).
+ */
+md_status pair_force_half(md_ctx *ctx, const md_box *box, const md_potential *pot, const uint32_t *pos,
+                          const int32_t *species, int32_t N, const int32_t *hidx, const int32_t *hcount, int32_t hcap,
+                          float *force, void *stream);
+
+/*
  * Constant temperature and gradient descent (Sec. 3.3.1 names Nose-Hoover, Langevin and Brownian NVT and a
  * gradient-descent minimizer beside NVE and FIRE; the discretizations are published schemes, unit masses).
  * Each step, like md_kick_drift, moves positions by the shift of Sec. 3.2.1 and marks on the device when a

@@ -138,6 +138,9 @@ _SIGNATURES = {
                          ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P],
     "md_gradient_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
     "md_nhc_half": [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P],
+    "nl_half": [P, ctypes.POINTER(c_nlist), P, P, ctypes.c_int32, P, P],
+    "pair_force_half": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, ctypes.c_int32, P, P,
+                        ctypes.c_int32, P, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
     "md_copy_words": [P, P, P, ctypes.c_int64, P],
     "md_min_distance": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P, P],
@@ -455,6 +458,30 @@ def nhc_state_read(state: torch.Tensor) -> dict:
 def nhc_half(ctx: Context, vel, state: torch.Tensor, h: float):
     N, dim = vel.shape
     _check("md_nhc_half", load().md_nhc_half(ctx.h, _ptr(vel), N, dim, _ptr(state), ctypes.c_double(h), _stream()))
+
+
+class HalfList:
+    """Each pair of a full list once (row i keeps j when (i < j) differs from (i + j odd)): hidx [hcap][N],
+    hcount [N], for the Newton's-third-law pass."""
+
+    def __init__(self, ctx: Context, nl: NeighborList, hcap: int | None = None):
+        self.ctx, self.nl = ctx, nl
+        self.hcap = int(hcap or max(8, nl.capacity // 2 + 8))
+        dev = ctx.device
+        self.hidx = torch.zeros((self.hcap, nl.N), dtype=torch.int32, device=dev)
+        self.hcount = torch.zeros(nl.N, dtype=torch.int32, device=dev)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def update(self):
+        n = self.nl.c()
+        _check("nl_half", load().nl_half(self.ctx.h, ctypes.byref(n), _ptr(self.hidx), _ptr(self.hcount), self.hcap,
+                                         _ptr(self.overflow), _stream()))
+
+    def forces(self, box: Box, pot: Potential, pos, species, force):
+        b, p = box.c(), pot.c()
+        _check("pair_force_half", load().pair_force_half(
+            self.ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(species), pos.shape[0], _ptr(self.hidx),
+            _ptr(self.hcount), self.hcap, _ptr(force), _stream()))
 
 
 def min_distance(ctx: Context, box: Box, pos, nl: NeighborList) -> torch.Tensor:

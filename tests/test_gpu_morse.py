@@ -99,3 +99,41 @@ def test_replica_paths_refuse_morse(md):
         md.envelope_grad(ctx, md.Batch(reps), pot)
     with pytest.raises(md.MDError):
         md.fire_unrolled_grad(ctx, md.Batch(reps), pot, md.FireParams(), 5)
+
+
+@pytest.mark.parametrize("kind", ["lj", "morse", "soft_sphere"])
+def test_half_list_forces_match_full_list_and_oracle(md, orc, kind):
+    """Newton's-third-law pass over a half list (each pair in one row): the same forces as the full-list pass and
+    the oracle (to
+    float rounding; the atomic scatter makes the last bits order-dependent)."""
+    import torch
+    if kind == "soft_sphere":
+        N = 3000
+        L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], 0.88, 2)
+        d = np.array([1.0, 1.4])
+        sig = 0.5 * (d[:, None] + d[None, :])
+        u = inputs.uniform_torus(N, 2, 151)
+        sp = inputs.bidisperse_species(N)
+        mpot = md.Potential("soft_sphere", sig, np.ones((2, 2)), alpha=2.0)
+        opot = orc.Potential("soft_sphere", sig, np.ones((2, 2)), alpha=2.0)
+        s = md.System(md.Box((L, L), 2), mpot, u, None, sp, skin=0.3)
+        Lv = np.array([L, L])
+    else:
+        s, opot, u, v, sp, Lv = case(md, orc, seed=152)
+        if kind == "lj":
+            s = md.System(s.box, md.Potential("lj", SIG, EPS, r_cut=2.6), u, v, sp, skin=0.3)
+            opot = orc.Potential("lj", SIG, EPS, r_cut=2.6)
+    s.build()
+    s.forces()
+    full = s.force.clone()
+    h = md.HalfList(s.ctx, s.nl)
+    h.update()
+    F = torch.zeros_like(s.force)
+    h.forces(s.box, s.pot, s.pos, s.species, F)
+    assert int(h.overflow.item()) == 0
+    assert int(h.hcount.sum().item()) * 2 == int(s.nl.lengths().sum())
+    x = u.astype(np.float64) * (Lv / 2.0 ** 32)
+    Fo, _, _ = orc.pair_rows(x, Lv, opot, sp)
+    say(kind, "half vs full", rel_l2(F.cpu().numpy(), full.cpu().numpy()), "half vs oracle", rel_l2(F.cpu().numpy(), Fo))
+    assert rel_l2(F.cpu().numpy(), full.cpu().numpy()) <= 1e-5
+    assert rel_l2(F.cpu().numpy(), Fo) <= 1e-5
