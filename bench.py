@@ -207,6 +207,18 @@ def secondary(progress):
     out["integrators_lj256k"] = integrators(ctx, progress)
     out["morse_nve_256k"] = morse_nve(ctx, progress)
     out["half_vs_full_list_256k"] = half_vs_full(ctx, progress)
+    out["flocking_65536"] = flocking(ctx, progress)
+    return out
+
+
+def flocking(ctx, progress, steps: int = 2000):
+    """The flocking model of Sec. 4.3 / App. B at tens of thousands of boids: 65536 boids, uniform start in a
+    512 x 512 periodic box (density 0.25), 16 disk obstacles of radius 2 to 6, the default parameters (J_align 1,
+    R_align 3, J_avoid 25, R_avoid 1, J_coh 0.05, R_coh 3, J_obs 10, alpha 3, v 1, dt 0.05), list skin 0.5.  One
+    step is flock_step (three launches) and the device-gated rebuild, replayed from HIP graphs of 20 steps."""
+    from paper_1912_04232_amd import simulate
+    out = simulate.run_flocking(ctx, steps)
+    progress(f"flocking: {out['steps_per_s']:.0f} steps/s")
     return out
 
 

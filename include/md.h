@@ -480,6 +480,42 @@ md_status md_brownian_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const 
 md_status md_gradient_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,
                            const md_nlist *nl, float dt, void *stream);
 
+/*
+ * Flocking energy model (Sec. 4.3, App. B): boids with positions R_i (uint32 torus coordinates, [N][2]) and
+ * headings theta_i (float [N]), N_i = (cos theta_i, sin theta_i), rho(r; Rc) = (1/alpha)(1 - r/Rc)^alpha below Rc.
+ *   E_align    = 1/2 sum_{i != j} J_align rho(r_ij; R_align)(1 - N_i . N_j)^2, its position gradient stopped
+ *   E_avoid    = 1/2 sum_{i != j} J_avoid rho(r_ij; R_avoid)
+ *   E_cohesion = sum_i 1/2 J_coh (1 - hat(dR_i) . N_i)^2, dR_i = mean over j with r_ij < R_coh of (R_j - R_i)
+ *                (a boid with no such neighbor, or dR_i = 0, adds nothing)
+ *   E_obstacle = sum_i sum_o J_obs rho(|R_i - C_o|; D_o)(1 - N_i . hat(R_i - C_o))^2 (disk o: center C_o, radius D_o)
+ * Displacements are nearest images; obstacle centers are plain coordinates in [0, L).  Predators (App. B) are
+ * not part of this call.
+ */
+typedef struct {
+    float J_align, R_align;
+    float J_avoid, R_avoid;
+    float J_coh, R_coh;
+    float J_obs;
+    float alpha;        /* exponent of rho, >= 1 */
+    float v;            /* speed along N_i */
+    float dt;
+    int32_t n_obstacles;  /* 0..16 */
+    int32_t reserved;
+    float obstacles[16][3];  /* (C_x, C_y, D) */
+} md_flock_params;
+
+/*
+ * One forward-Euler step of the flocking dynamics (App. B): R_i += dt (v N_i - dE/dR_i), theta_i -= dt dE/dtheta_i,
+ * both from the state at the start of the step.  nl must be a full list (segment 0, any lane count) with
+ * r_list >= max(R_align, R_avoid, R_coh), valid for pos (nl_update after each step keeps it so: the call marks on
+ * the device when a boid has moved more than skin/2 from nl->pos_ref).  work is device scratch of 6 N floats owned
+ * by the caller; after the call work[6i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step.  box->dim must
+ * be 2.  Errors: MD_ERR_ARG (missing pointer, dim, list or parameters out of range), MD_ERR_BOX (an edge not above
+ * 2 r_list).
+ */
+md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta, int32_t N, const md_nlist *nl,
+                     const md_flock_params *fp, float *work, void *stream);
+
 /* Nose-Hoover chain state (Martyna, Klein and Tuckerman 1992), kept in DEVICE memory by the caller. */
 typedef struct {
     double p[8];      /* thermostat momenta p_k = Q_k xi_k */

@@ -87,9 +87,8 @@ enum { M_IDLE = 0, M_BIN = 1, M_BUILD = 2 };
 // slot s % 3, written by workgroup 0 of step s-1; ctl[6 + slot] = rebuild request for step s, written
 // by any workgroup of step s-1; ctl[kGenWord] = generation to use after the last step that ran.
 // FIRE: ctl[kTrigWord] = rebuild needed before this step's forces.
-constexpr int kCtlWords = 16;
+// (kCtlWords and kTrigWord come from md_host.h)
 constexpr int kGenWord = 9;
-constexpr int kTrigWord = 10;
 
 // Raise *addr to v.  Every workgroup calls this with its own maximum; atomics on one address from thousands
 // of workgroups serialize (~0.1 us each), so only a workgroup that exceeds the value already there issues one.

@@ -20,6 +20,12 @@ struct CountSort {
     int32_t *cell_start;
 };
 
+// Control words of the context (device memory, kCtlWords int32).  ctl[kTrigWord] is the rebuild trigger: a
+// kernel that moves positions sets it when a particle has moved more than skin/2 from the list's reference
+// positions, and nl_update rebuilds (on the device) and clears it.
+constexpr int kCtlWords = 16;
+constexpr int kTrigWord = 10;
+
 struct md_ctx {
     int device = 0;
     int32_t N_cap = 0, dim_cap = 0, C_cap = 0, cap_cap = 0, M_cap = 0, W_cap = 0;

@@ -135,6 +135,18 @@ def random_insertion_torus(N: int, L: float, dim: int, r_min: float, seed: int, 
     return to_torus(pts, [L] * dim)
 
 
+def boids(N: int, L: float, seed: int, n_obstacles: int = 0, D_lo: float = 2.0, D_hi: float = 6.0):
+    """Flocking start: uniform positions on the 2D torus (uint32), headings uniform in [-pi, pi) (float32 values),
+    and n_obstacles disks (C_x, C_y, D) with centers uniform in [0, L) and radii uniform in [D_lo, D_hi), all
+    float32-representable so that every consumer sees the same numbers."""
+    u = uniform_torus(N, 2, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    theta = rng.uniform(-np.pi, np.pi, N).astype(np.float32)
+    obs = np.stack([rng.uniform(0.0, L, n_obstacles), rng.uniform(0.0, L, n_obstacles),
+                    rng.uniform(D_lo, D_hi, n_obstacles)], 1).astype(np.float32).reshape(-1, 3)
+    return u, theta, obs
+
+
 def maxwell_velocities(N: int, dim: int, T: float, seed: int) -> np.ndarray:
     """Gaussian velocities (unit mass), net momentum removed, rescaled so sum v^2 = dim (N-1) T."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -86,6 +86,13 @@ class c_nn_params(ctypes.Structure):
                 ("b3", ctypes.c_void_p), ("m", ctypes.c_void_p), ("s", ctypes.c_void_p)]
 
 
+class c_flock_params(ctypes.Structure):
+    _fields_ = [("J_align", ctypes.c_float), ("R_align", ctypes.c_float), ("J_avoid", ctypes.c_float),
+                ("R_avoid", ctypes.c_float), ("J_coh", ctypes.c_float), ("R_coh", ctypes.c_float),
+                ("J_obs", ctypes.c_float), ("alpha", ctypes.c_float), ("v", ctypes.c_float), ("dt", ctypes.c_float),
+                ("n_obstacles", ctypes.c_int32), ("reserved", ctypes.c_int32), ("obstacles", ctypes.c_float * 48)]
+
+
 FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
 _lib = None
 
@@ -139,6 +146,8 @@ _SIGNATURES = {
     "md_gradient_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
     "md_nhc_half": [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P],
     "nl_half": [P, ctypes.POINTER(c_nlist), P, P, ctypes.c_int32, P, P],
+    "flock_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist),
+                   ctypes.POINTER(c_flock_params), P, P],
     "pair_force_half": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, ctypes.c_int32, P, P,
                         ctypes.c_int32, P, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
@@ -458,6 +467,12 @@ def nhc_state_read(state: torch.Tensor) -> dict:
 def nhc_half(ctx: Context, vel, state: torch.Tensor, h: float):
     N, dim = vel.shape
     _check("md_nhc_half", load().md_nhc_half(ctx.h, _ptr(vel), N, dim, _ptr(state), ctypes.c_double(h), _stream()))
+
+
+def flock_step(ctx: Context, box: Box, pos, theta, nl: NeighborList, fp: c_flock_params, work):
+    b, n = box.c(), nl.c()
+    _check("flock_step", load().flock_step(ctx.h, ctypes.byref(b), _ptr(pos), _ptr(theta), pos.shape[0],
+                                           ctypes.byref(n), ctypes.byref(fp), _ptr(work), _stream()))
 
 
 class HalfList:
@@ -1087,3 +1102,48 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         return st
 
     return init_fn, step_fn, minimize
+
+
+FLOCK_DEFAULTS = dict(J_align=1.0, R_align=3.0, J_avoid=25.0, R_avoid=1.0, J_coh=0.05, R_coh=3.0, J_obs=10.0,
+                      alpha=3.0, v=1.0, dt=0.05)
+
+
+class Flock(System):
+    """Boids of the flocking model (Sec. 4.3, App. B): positions pos (uint32 torus, [N][2]), headings theta [N],
+    and a full neighbor list of radius max(R_align, R_avoid, R_coh) + skin.  ``params`` overrides FLOCK_DEFAULTS;
+    ``obstacles`` is a list of disks (C_x, C_y, D), at most 16."""
+
+    def __init__(self, box: Box, u: np.ndarray, theta, params: dict | None = None, obstacles=(), skin: float = 0.5,
+                 capacity: int | None = None, ctx: Context | None = None, max_per_cell: int | None = None):
+        if box.dim != 2:
+            raise ValueError("the flocking model is two-dimensional")
+        p = dict(FLOCK_DEFAULTS, **(params or {}))
+        obstacles = np.asarray(obstacles, dtype=np.float64).reshape(-1, 3)
+        if len(obstacles) > 16:
+            raise ValueError("at most 16 obstacles")
+        self.fp = c_flock_params(**{k: float(v) for k, v in p.items()})
+        self.fp.n_obstacles = len(obstacles)
+        for o, (cx, cy, D) in enumerate(obstacles):
+            self.fp.obstacles[3 * o: 3 * o + 3] = (float(cx), float(cy), float(D))
+        self.params = p
+        r = max(p["R_align"], p["R_avoid"], p["R_coh"])
+        # the list radius is r + skin; the stand-in potential only carries the range r and is never evaluated
+        super().__init__(box, Potential("soft_sphere", [[r]], [[1.0]], alpha=2.0), u, None, None, skin, capacity, ctx,
+                         max_per_cell, 1)
+        self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32), device=self.ctx.device).contiguous()
+        self.work = torch.zeros((self.N, 6), dtype=torch.float32, device=self.ctx.device)
+
+
+def flocking(flock: Flock):
+    """init_fn / update_fn for the forward-Euler flocking dynamics: each step is flock_step then nl_update (the
+    rebuild decided on the device), so update_fn(n, graph=True) replays chunks of 20 steps from a HIP graph."""
+
+    def init_fn():
+        flock.build()
+        return flock
+
+    def once():
+        flock_step(flock.ctx, flock.box, flock.pos, flock.theta, flock.nl, flock.fp, flock.work)
+        nl_update(flock.ctx, flock.box, flock.pos, flock.nl)
+
+    return init_fn, _stepper(flock, once, (flock.pos, flock.theta))

@@ -1,11 +1,13 @@
-"""Constant-temperature dynamics and gradient descent on the benchmark system, as a command.
+"""Constant-temperature dynamics, gradient descent and flocking, as a command.
 
-    python -m paper_1912_04232_amd.simulate [--method langevin|nose_hoover|brownian|gradient_descent|all]
-                                            [--steps 1000] [--n-cells 40]
+    python -m paper_1912_04232_amd.simulate [--method langevin|nose_hoover|brownian|gradient_descent|all|flocking]
+                                            [--steps 1000] [--n-cells 40] [--boids 65536]
 
-3D Lennard-Jones, 4 n^3 particles on an FCC lattice at density 0.84 (N = 256000 for n = 40), Maxwell velocities at
-T = 1, cutoff 2.5, skin 0.3.  Each method runs 100 steps (graph capture and warm-up), then `steps` timed steps
-replayed from HIP graphs of 20 steps; one JSON line per run with steps/s and the final kinetic temperature.
+The integrators run on 3D Lennard-Jones, 4 n^3 particles on an FCC lattice at density 0.84 (N = 256000 for
+n = 40), Maxwell velocities at T = 1, cutoff 2.5, skin 0.3.  Flocking (Sec. 4.3, App. B) runs the boid model with
+its default parameters: boids uniform in a square box at density 0.25 with 16 disk obstacles, skin 0.5.  Each run
+takes 100 steps (graph capture and warm-up), then `steps` timed steps replayed from HIP graphs of 20 steps; one
+JSON line per run.
 """
 from __future__ import annotations
 
@@ -14,6 +16,7 @@ import json
 import sys
 import time
 
+import numpy as np
 import torch
 
 from . import inputs, md
@@ -47,16 +50,38 @@ def run(ctx, method: str, steps: int = 1000, n_cells: int = 40) -> dict:
             "kinetic_T": float((s.vel.double() ** 2).sum()) / (3 * s.N) if inertial else None}
 
 
+def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, seed: int = 29) -> dict:
+    L = float(np.float32(np.sqrt(N / 0.25)))
+    u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
+    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, ctx=ctx)
+    init, update = md.flocking(f)
+    init()
+    update(100, graph=True)
+    torch.cuda.synchronize()
+    f.nl.clear_flags()
+    t0 = time.perf_counter()
+    update(steps, graph=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"method": "flocking", "N": f.N, "L": L, "obstacles": n_obstacles, "steps": steps,
+            "steps_per_s": steps / t, "boid_steps_per_s": f.N * steps / t, "us_per_step": 1e6 * t / steps,
+            "mean_row": float(f.nl.lengths().mean())}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--method", choices=tuple(METHODS) + ("all",), default="all")
+    ap.add_argument("--method", choices=tuple(METHODS) + ("all", "flocking"), default="all")
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--n-cells", type=int, default=40)
+    ap.add_argument("--boids", type=int, default=65536)
     a = ap.parse_args(argv)
     md.load()
     if not torch.cuda.is_available():
         sys.exit("no GPU visible")
     ctx = md.Context()
+    if a.method == "flocking":
+        print(json.dumps(run_flocking(ctx, a.steps, a.boids)), flush=True)
+        return
     for m in (METHODS if a.method == "all" else (a.method,)):
         print(json.dumps(run(ctx, m, a.steps, a.n_cells)), flush=True)
 
