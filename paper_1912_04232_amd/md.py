@@ -876,6 +876,7 @@ def _run_checked(system: System, saved, call, n_steps: int):
                 done += k
             return f
         system.grow(f)
+        system.build()  # a step may read the list before any rebuild (flocking does): build it for the restored state
     raise RuntimeError("neighbor list kept overflowing")
 
 
@@ -934,6 +935,9 @@ def _stepper(system: System, step_once, state_tensors, chunk: int = 20):
                     for t, v in zip(saved[0], saved[1]):
                         t.copy_(v)
                     graphs.clear()
+                    if f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW]:
+                        system.grow(f)
+                        system.build()  # the grown list must be valid for the restored positions
                     system.last_flags = _run_checked(system, saved, eager, k)
                 elif f[FLAG_NONFINITE]:
                     raise FloatingPointError("non-finite force")

@@ -67,9 +67,9 @@ def oracle_params(fl, md, flock):
     return fl.FlockParams(**{k: float(np.float32(v)) for k, v in flock.params.items()})
 
 
-def make(md, N, L, seed, n_obstacles, params=None):
+def make(md, N, L, seed, n_obstacles, params=None, capacity=None):
     u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
-    f = md.Flock(md.Box((L, L), 2), u, theta, params, obs)
+    f = md.Flock(md.Box((L, L), 2), u, theta, params, obs, capacity=capacity)
     return f, u, theta.astype(np.float64), obs.astype(np.float64)
 
 
@@ -164,11 +164,11 @@ def test_flock_sampled_boids_at_full_size(md, fl):
 
 def test_flock_graph_replay_matches_eager(md):
     """120 steps (several device-decided list rebuilds) replayed from HIP graphs equal the same steps launched
-    eagerly, bit for bit."""
+    eagerly, bit for bit (rows with room for any clumping, so that no regrow moves a rebuild)."""
     import torch
     L = 64.0
-    a = make(md, 2000, L, 31, 2)[0]
-    b = make(md, 2000, L, 31, 2)[0]
+    a = make(md, 2000, L, 31, 2, capacity=400)[0]
+    b = make(md, 2000, L, 31, 2, capacity=400)[0]
     ia, ua = md.flocking(a)
     ib, ub = md.flocking(b)
     ia()
@@ -178,4 +178,30 @@ def test_flock_graph_replay_matches_eager(md):
         ub(40, graph=False)
         torch.cuda.synchronize()
         assert torch.equal(a.pos, b.pos) and torch.equal(a.theta, b.theta)
-    assert a.last_flags[md.FLAG_REBUILDS] > 0
+    assert a.last_flags[md.FLAG_REBUILDS] > 0 and a.nl.capacity == 400
+
+
+def test_flock_regrow_rebuilds_before_the_rerun(md):
+    """Rows that outgrow the list during a run: the run is repeated from its start with a larger list built for
+    the restored state, and ends bit for bit where a run whose list never overflowed ends (the same rebuild
+    steps, the same row order)."""
+    import torch
+    L = 40.0
+    clump = {"J_avoid": 0.0, "J_coh": 2.0, "J_align": 0.2}   # boids gather: the longest row grows from 60 to ~95
+    u, theta, _ = inputs.boids(1600, L, 37, 0)
+    a = md.Flock(md.Box((L, L), 2), u, theta, clump, capacity=400, max_per_cell=252)
+    b = md.Flock(md.Box((L, L), 2), u, theta, clump, max_per_cell=252)
+    ia, ua = md.flocking(a)
+    ib, ub = md.flocking(b)
+    ia()
+    ib()
+    tight = int(b.nl.lengths().max())
+    b.nl = md.NeighborList(b.N, 2, tight, b.nl.r_list, b.nl.skin, b.ctx.device, b.nl.max_per_cell, 1)
+    b.build()
+    assert b.nl.capacity == tight
+    ua(60)
+    ub(60)
+    torch.cuda.synchronize()
+    say("capacity", tight, "->", b.nl.capacity, "max row", int(a.nl.lengths().max()))
+    assert b.nl.capacity > tight
+    assert torch.equal(a.pos, b.pos) and torch.equal(a.theta, b.theta)
