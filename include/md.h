@@ -508,10 +508,11 @@ typedef struct {
  * One forward-Euler step of the flocking dynamics (App. B): R_i += dt (v N_i - dE/dR_i), theta_i -= dt dE/dtheta_i,
  * both from the state at the start of the step.  nl must be a full list (segment 0, any lane count) with
  * r_list >= max(R_align, R_avoid, R_coh), valid for pos (nl_update after each step keeps it so: the call marks on
- * the device when a boid has moved more than skin/2 from nl->pos_ref).  work is device scratch of 6 N floats owned
- * by the caller; after the call work[6i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step.  box->dim must
- * be 2.  Errors: MD_ERR_ARG (missing pointer, dim, list or parameters out of range), MD_ERR_BOX (an edge not above
- * 2 r_list).
+ * the device when a boid has moved more than skin/2 from nl->pos_ref).  The list's lanes (W) set how many GPU
+ * lanes share a boid.  work is device scratch of 8 N floats owned by the caller (8-byte aligned); after the call
+ * work[8i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step and work[8i + 6..7] the heading N_i it used.  box->dim must
+ * be 2.  Errors: MD_ERR_ARG (missing pointer, dim, list or parameters out of range, 8 N >= 2^31), MD_ERR_BOX (an
+ * edge not above 2 r_list).
  */
 md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta, int32_t N, const md_nlist *nl,
                      const md_flock_params *fp, float *work, void *stream);

@@ -159,64 +159,85 @@ __global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, Dev
     cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: the totals do not depend on order
 }
 
-constexpr int kScan = 1024;  // threads of the one-workgroup scan
+constexpr int kScan = 1024;      // threads of the one-workgroup scan
+constexpr int kScanTile = 4096;  // cells per LDS tile (4 per thread)
 
 // Exclusive scan of cell_count into cell_start[0..C] by one workgroup (wave shuffles and LDS, no atomics);
 // also the bin counts min(count, M), the cell-overflow flag and the largest occupancy.  It leaves the counts at
-// zero for the next build.
+// zero for the next build.  The cells go through LDS in tiles of kScanTile: coalesced loads, each thread scans
+// 4 adjacent cells from LDS, the workgroup scans the thread sums, coalesced stores, and a carry between tiles.
 __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bins, int M, int32_t *flags,
                                                    const int32_t *gate)
 {
+    constexpr int kPer = kScanTile / kScan;
+    __shared__ int cnt[kScanTile];
+    __shared__ int start[kScanTile];
     __shared__ int wsum[kScan / 64];
     __shared__ int wmax[kScan / 64];
+    __shared__ int tile_end;
     if (gate_closed(gate)) return;
-    int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    int chunk = (C + kScan - 1) / kScan;
-    int lo = min(C, t * chunk), hi = min(C, lo + chunk);
-    int local = 0, mx = 0;
-    for (int c = lo; c < hi; ++c) {
-        int v = cs.cell_count[c];
-        local += v;
-        mx = max(mx, v);
-    }
-    int incl = local;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int carry = 0, mx = 0;
+    for (int base = 0; base < C; base += kScanTile) {
+        const int n = min(kScanTile, C - base);
+        for (int k = t; k < kScanTile; k += kScan) cnt[k] = k < n ? cs.cell_count[base + k] : 0;
+        __syncthreads();
+        int local = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
+        for (int k = 0; k < kPer; ++k) {
+            int v = cnt[t * kPer + k];
+            local += v;
+            mx = max(mx, v);
+        }
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        if (w == 0) {
+            int x = lane < kScan / 64 ? wsum[lane] : 0;
+            int xi = x;
+#pragma unroll
+            for (int o = 1; o < kScan / 64; o <<= 1) {
+                int v = __shfl_up(xi, o);
+                if (lane >= o) xi += v;
+            }
+            if (lane < kScan / 64) wsum[lane] = xi - x;
+        }
+        __syncthreads();
+        int run = carry + incl - local + wsum[w];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            start[t * kPer + k] = run;
+            run += cnt[t * kPer + k];
+        }
+        if (t == kScan - 1) tile_end = run;
+        __syncthreads();
+        for (int k = t; k < n; k += kScan) {
+            cs.cell_start[base + k] = start[k];
+            cs.cell_count[base + k] = 0;  // ready for the next build (the counts start zeroed at allocation)
+            bins.cnt[base + k] = min(cnt[k], M);
+        }
+        carry = tile_end;
+        __syncthreads();  // the next tile overwrites cnt, start and tile_end
     }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o));
-    if (lane == 63) wsum[w] = incl;
     if (lane == 0) wmax[w] = mx;
     __syncthreads();
     if (w == 0) {
-        int x = lane < kScan / 64 ? wsum[lane] : 0;
-        int xi = x;
-#pragma unroll
-        for (int o = 1; o < kScan / 64; o <<= 1) {
-            int v = __shfl_up(xi, o);
-            if (lane >= o) xi += v;
-        }
         int m2 = lane < kScan / 64 ? wmax[lane] : 0;
 #pragma unroll
         for (int o = 1; o < kScan / 64; o <<= 1) m2 = max(m2, __shfl_xor(m2, o));
-        if (lane < kScan / 64) wsum[lane] = xi - x;
         if (lane == 0) {
             raise_max(&flags[MD_FLAG_MAXCELL], m2);
             if (m2 > M) flags[MD_FLAG_CELL_OVERFLOW] = 1;
+            cs.cell_start[C] = carry;
         }
     }
-    __syncthreads();
-    int run = incl - local + wsum[w];
-    for (int c = lo; c < hi; ++c) {
-        cs.cell_start[c] = run;
-        int v = cs.cell_count[c];
-        cs.cell_count[c] = 0;  // ready for the next build (the counts start zeroed at allocation)
-        bins.cnt[c] = min(v, M);
-        run += v;
-    }
-    if (t == kScan - 1) cs.cell_start[C] = run;
 }
 
 __global__ void k_cs_place(CountSort cs, int N, const int32_t *gate)

@@ -1,6 +1,9 @@
 // The flocking energy model of App. B on a neighbor list (Sec. 4.3: boids interact with their local
-// neighborhood only, so a list scales the model to tens of thousands of agents), 2D, one thread per boid:
+// neighborhood only, so a list scales the model to tens of thousands of agents), 2D.  W lanes per boid walk
+// the W sub-rows of its list row and their sums are combined across the lanes (more waves in flight to hide the
+// neighbor gathers than one thread per boid gives):
 //
+//   k_flock_heading N_i = (cos theta_i, sin theta_i), once per boid and step;
 //   k_flock_terms   per boid i over its list row: avoidance dE/dR_i, alignment dE/dtheta_i, the obstacle terms,
 //                   and cohesion: dR_i = mean over neighbors within R_coh of (R_j - R_i), its energy
 //                   1/2 J (1 - hat(dR_i) . N_i)^2, the gradient g_i of that energy with respect to dR_i, the
@@ -24,68 +27,113 @@ using namespace md;
 
 namespace {
 
-constexpr int kWork = 6;  // floats per boid in the work array: dE/dR (2), dE/dtheta, g / n (2), pad
+constexpr int kWork = 8;  // floats per boid in the work array: dE/dR (2), dE/dtheta, pad, g / n (2), N (2)
 
 struct FlockArgs {
     const uint32_t *pos;
     float *theta;
-    int N, W, capW;
+    int N, capW;
     const int32_t *idx, *count;
     float s[2], inv_s[2], L[2];
     md_flock_params fp;
+    float inv_R_align, inv_R_avoid, inv_alpha;
+    int ialpha;  // alpha when it is an integer in [1, 8] (powers by multiplication), else 0
     float *work;
 };
 
-__device__ __forceinline__ float rho_t(float t, float a)  // (1/a) t^a, t in (0, 1]
+// t^e for t in (0, 1]: repeated products when the exponent is a small integer, else exp2(e log2 t)
+__device__ __forceinline__ float tpow(float t, int ie, float e)
 {
-    return __builtin_exp2f(a * __builtin_log2f(t)) / a;
-}
-
-__device__ __forceinline__ float drho_t(float t, float a, float Rc)  // d rho / dr = -(1/Rc) t^(a-1)
-{
-    return -__builtin_exp2f((a - 1.0f) * __builtin_log2f(t)) / Rc;
-}
-
-template <class Fn>
-__device__ __forceinline__ void for_row(const FlockArgs &a, int i, Fn &&f)
-{
-    for (int l = 0; l < a.W; ++l) {
-        int n = min(a.count[(size_t)i * a.W + l], a.capW);
-        for (int t = 0; t < n; ++t) f(a.idx[((size_t)t * a.N + i) * a.W + l]);
+    if (ie > 0) {
+        float p = 1.0f;
+        for (int k = 0; k < ie; ++k) p *= t;
+        return p;
     }
+    return __builtin_exp2f(e * __builtin_log2f(t));
 }
 
-__global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
+__device__ __forceinline__ float rho_t(const FlockArgs &a, float t)  // (1/alpha) t^alpha
+{
+    return tpow(t, a.ialpha, a.fp.alpha) * a.inv_alpha;
+}
+
+__device__ __forceinline__ float drho_t(const FlockArgs &a, float t, float inv_Rc)  // d rho / dr = -(1/Rc) t^(alpha-1)
+{
+    return -tpow(t, a.ialpha - 1, a.fp.alpha - 1.0f) * inv_Rc;
+}
+
+// Sum over the W lanes of one boid (adjacent lanes of a wave), a fixed tree: deterministic.
+template <int W>
+__device__ __forceinline__ float lane_sum(float v)
+{
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int lane_sum_i(int v)
+{
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flock_heading(FlockArgs a)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.N) return;
-    const md_flock_params &p = a.fp;
-    uint32_t ui[2] = {a.pos[2 * (size_t)i], a.pos[2 * (size_t)i + 1]};
     float th = a.theta[i];
-    const float Nx = cosf(th), Ny = sinf(th);
+    a.work[(size_t)i * kWork + 6] = cosf(th);
+    a.work[(size_t)i * kWork + 7] = sinf(th);
+}
+
+// W lanes per boid: lane l walks sub-row l of the list, the lane sums are combined, and lane 0 finishes.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int i = t / W, l = t % W;
+    const bool live = i < a.N;
+    const md_flock_params &p = a.fp;
+    const int ic = live ? i : 0;
+    uint32_t ui[2] = {a.pos[2 * (size_t)ic], a.pos[2 * (size_t)ic + 1]};
+    const float2 Ni = *reinterpret_cast<const float2 *>(a.work + (size_t)ic * kWork + 6);
     float gx = 0.0f, gy = 0.0f, gt = 0.0f, Sx = 0.0f, Sy = 0.0f;
     int n = 0;
-    for_row(a, i, [&](int j) {
+    const int len = live ? min(a.count[(size_t)i * W + l], a.capW) : 0;
+    const float R2coh = p.R_coh * p.R_coh;
+    for (int q = 0; q < len; ++q) {
+        int j = a.idx[((size_t)q * a.N + i) * W + l];
         float dx = tdisp(ui[0], a.pos[2 * (size_t)j], a.s[0]);      // R_i - R_j
         float dy = tdisp(ui[1], a.pos[2 * (size_t)j + 1], a.s[1]);
         float r2 = __builtin_fmaf(dx, dx, dy * dy);
         float r = sqrtf(r2);
         if (r < p.R_avoid) {
-            float c = p.J_avoid * drho_t(1.0f - r / p.R_avoid, p.alpha, p.R_avoid) / r;
+            float c = p.J_avoid * drho_t(a, 1.0f - r * a.inv_R_avoid, a.inv_R_avoid) / r;
             gx = __builtin_fmaf(c, dx, gx);
             gy = __builtin_fmaf(c, dy, gy);
         }
         if (r < p.R_align) {
-            float dth = th - a.theta[j];
-            float cc = cosf(dth), ss = sinf(dth);
-            gt += p.J_align * rho_t(1.0f - r / p.R_align, p.alpha) * 2.0f * (1.0f - cc) * ss;
+            const float2 Nj = *reinterpret_cast<const float2 *>(a.work + (size_t)j * kWork + 6);
+            float cc = __builtin_fmaf(Ni.x, Nj.x, Ni.y * Nj.y);       // cos(theta_i - theta_j)
+            float ss = __builtin_fmaf(Ni.y, Nj.x, -Ni.x * Nj.y);      // sin(theta_i - theta_j)
+            gt += p.J_align * rho_t(a, 1.0f - r * a.inv_R_align) * 2.0f * (1.0f - cc) * ss;
         }
-        if (r2 < p.R_coh * p.R_coh) {
+        if (r2 < R2coh) {
             Sx -= dx;
             Sy -= dy;
             ++n;
         }
-    });
+    }
+    gx = lane_sum<W>(gx);
+    gy = lane_sum<W>(gy);
+    gt = lane_sum<W>(gt);
+    Sx = lane_sum<W>(Sx);
+    Sy = lane_sum<W>(Sy);
+    n = lane_sum_i<W>(n);
+    if (!live || l != 0) return;
+    const float Nx = Ni.x, Ny = Ni.y;
     const float xi = (float)ui[0] * a.s[0], yi = (float)ui[1] * a.s[1];
     for (int o = 0; o < p.n_obstacles; ++o) {
         float cx = xi - p.obstacles[o][0], cy = yi - p.obstacles[o][1], D = p.obstacles[o][2];
@@ -95,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
         if (ro < D && ro > 0.0f) {
             float hx = cx / ro, hy = cy / ro;
             float am = __builtin_fmaf(Nx, hx, Ny * hy);
-            float t = 1.0f - ro / D;
-            float w = rho_t(t, p.alpha), dw = drho_t(t, p.alpha, D);
+            float tt = 1.0f - ro / D;
+            float w = rho_t(a, tt), dw = drho_t(a, tt, 1.0f / D);
             float om = 1.0f - am;
             gx += p.J_obs * (dw * hx * om * om - 2.0f * w * om * (Nx - am * hx) / ro);
             gy += p.J_obs * (dw * hy * om * om - 2.0f * w * om * (Ny - am * hy) / ro);
@@ -123,25 +171,35 @@ __global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
     w[0] = gx;
     w[1] = gy;
     w[2] = gt;
-    w[3] = Gx;
-    w[4] = Gy;
+    w[3] = 0.0f;
+    w[4] = Gx;
+    w[5] = Gy;
 }
 
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_flock_gather(FlockArgs a)
 {
-    int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= a.N) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int k = t / W, l = t % W;
+    const bool live = k < a.N;
     const float R2 = a.fp.R_coh * a.fp.R_coh;
-    uint32_t uk[2] = {a.pos[2 * (size_t)k], a.pos[2 * (size_t)k + 1]};
+    const int kc = live ? k : 0;
+    uint32_t uk[2] = {a.pos[2 * (size_t)kc], a.pos[2 * (size_t)kc + 1]};
     float gx = 0.0f, gy = 0.0f;
-    for_row(a, k, [&](int i) {
+    const int len = live ? min(a.count[(size_t)k * W + l], a.capW) : 0;
+    for (int q = 0; q < len; ++q) {
+        int i = a.idx[((size_t)q * a.N + k) * W + l];
         float dx = tdisp(uk[0], a.pos[2 * (size_t)i], a.s[0]);
         float dy = tdisp(uk[1], a.pos[2 * (size_t)i + 1], a.s[1]);
         if (__builtin_fmaf(dx, dx, dy * dy) < R2) {   // the same test as k_flock_terms, from the other end
-            gx += a.work[(size_t)i * kWork + 3];
-            gy += a.work[(size_t)i * kWork + 4];
+            const float2 G = *reinterpret_cast<const float2 *>(a.work + (size_t)i * kWork + 4);
+            gx += G.x;
+            gy += G.y;
         }
-    });
+    }
+    gx = lane_sum<W>(gx);
+    gy = lane_sum<W>(gy);
+    if (!live || l != 0) return;
     a.work[(size_t)k * kWork + 0] += gx;
     a.work[(size_t)k * kWork + 1] += gy;
 }
@@ -153,14 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_flock_move(FlockArgs a, uint32_t *po
     bool far = false;
     if (i < a.N) {
         const float *w = a.work + (size_t)i * kWork;
-        float th = a.theta[i];
         float dt = a.fp.dt, v = a.fp.v;
-        float dx = dt * (v * cosf(th) - w[0]), dy = dt * (v * sinf(th) - w[1]);
+        float dx = dt * (v * w[6] - w[0]), dy = dt * (v * w[7] - w[1]);
         uint32_t u0 = pos[2 * (size_t)i] + (uint32_t)__float2int_rn(dx * a.inv_s[0]);
         uint32_t u1 = pos[2 * (size_t)i + 1] + (uint32_t)__float2int_rn(dy * a.inv_s[1]);
         pos[2 * (size_t)i] = u0;
         pos[2 * (size_t)i + 1] = u1;
-        a.theta[i] = th - dt * w[2];
+        a.theta[i] -= dt * w[2];
         float ex = tdisp(u0, pos_ref[2 * (size_t)i], a.s[0]), ey = tdisp(u1, pos_ref[2 * (size_t)i + 1], a.s[1]);
         far = __builtin_fmaf(ex, ex, ey * ey) > half_skin * half_skin;
     }
@@ -168,9 +225,9 @@ __global__ __launch_bounds__(kBlock) void k_flock_move(FlockArgs a, uint32_t *po
     if (m != 0 && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) ctl[kTrigWord] = 1;
 }
 
-int nblocks(int n)
+int nblocks(int64_t n)
 {
-    return (n + kBlock - 1) / kBlock;
+    return (int)((n + kBlock - 1) / kBlock);
 }
 
 }  // namespace
@@ -187,7 +244,7 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         !(fp->R_avoid > 0.0f) || !(fp->R_coh > 0.0f) || !isfinite(fp->dt))
         return MD_ERR_ARG;
     float rmax = fmaxf(fp->R_align, fmaxf(fp->R_avoid, fp->R_coh));
-    if (nl->r_list < rmax) return MD_ERR_ARG;
+    if (nl->r_list < rmax || (int64_t)N * 8 >= ((int64_t)1 << 31)) return MD_ERR_ARG;
     int W = nl->lanes;
     if (W != 1 && W != 2 && W != 4 && W != 8) return MD_ERR_ARG;
     FlockArgs a{};
@@ -202,17 +259,37 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
     a.pos = pos;
     a.theta = theta;
     a.N = N;
-    a.W = W;
     a.capW = nl->capacity / W;
     a.idx = nl->idx;
     a.count = nl->count;
     a.fp = *fp;
+    a.inv_R_align = 1.0f / fp->R_align;
+    a.inv_R_avoid = 1.0f / fp->R_avoid;
+    a.inv_alpha = 1.0f / fp->alpha;
+    a.ialpha = (fp->alpha == floorf(fp->alpha) && fp->alpha <= 8.0f) ? (int)fp->alpha : 0;
     a.work = work;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_flock_terms, dim3(nblocks(N)), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_flock_gather, dim3(nblocks(N)), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_flock_move, dim3(nblocks(N)), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin,
-                       ctx->ctl);
+    const int g1 = nblocks(N), gW = nblocks((int64_t)N * W);
+    hipLaunchKernelGGL(k_flock_heading, dim3(g1), dim3(kBlock), 0, s, a);
+    switch (W) {
+    case 1:
+        hipLaunchKernelGGL(k_flock_terms<1>, dim3(gW), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flock_gather<1>, dim3(gW), dim3(kBlock), 0, s, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_flock_terms<2>, dim3(gW), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flock_gather<2>, dim3(gW), dim3(kBlock), 0, s, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_flock_terms<4>, dim3(gW), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flock_gather<4>, dim3(gW), dim3(kBlock), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_flock_terms<8>, dim3(gW), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flock_gather<8>, dim3(gW), dim3(kBlock), 0, s, a);
+        break;
+    }
+    hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

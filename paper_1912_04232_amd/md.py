@@ -1115,10 +1115,11 @@ FLOCK_DEFAULTS = dict(J_align=1.0, R_align=3.0, J_avoid=25.0, R_avoid=1.0, J_coh
 class Flock(System):
     """Boids of the flocking model (Sec. 4.3, App. B): positions pos (uint32 torus, [N][2]), headings theta [N],
     and a full neighbor list of radius max(R_align, R_avoid, R_coh) + skin.  ``params`` overrides FLOCK_DEFAULTS;
-    ``obstacles`` is a list of disks (C_x, C_y, D), at most 16."""
+    ``obstacles`` is a list of disks (C_x, C_y, D), at most 16; ``lanes`` GPU lanes share each boid."""
 
     def __init__(self, box: Box, u: np.ndarray, theta, params: dict | None = None, obstacles=(), skin: float = 0.5,
-                 capacity: int | None = None, ctx: Context | None = None, max_per_cell: int | None = None):
+                 capacity: int | None = None, ctx: Context | None = None, max_per_cell: int | None = None,
+                 lanes: int = 4):
         if box.dim != 2:
             raise ValueError("the flocking model is two-dimensional")
         p = dict(FLOCK_DEFAULTS, **(params or {}))
@@ -1133,9 +1134,9 @@ class Flock(System):
         r = max(p["R_align"], p["R_avoid"], p["R_coh"])
         # the list radius is r + skin; the stand-in potential only carries the range r and is never evaluated
         super().__init__(box, Potential("soft_sphere", [[r]], [[1.0]], alpha=2.0), u, None, None, skin, capacity, ctx,
-                         max_per_cell, 1)
+                         max_per_cell, lanes)
         self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32), device=self.ctx.device).contiguous()
-        self.work = torch.zeros((self.N, 6), dtype=torch.float32, device=self.ctx.device)
+        self.work = torch.zeros((self.N, 8), dtype=torch.float32, device=self.ctx.device)
 
 
 def flocking(flock: Flock):

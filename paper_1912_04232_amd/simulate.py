@@ -50,10 +50,11 @@ def run(ctx, method: str, steps: int = 1000, n_cells: int = 40) -> dict:
             "kinetic_T": float((s.vel.double() ** 2).sum()) / (3 * s.N) if inertial else None}
 
 
-def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, seed: int = 29) -> dict:
+def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, seed: int = 29, skin: float = 0.5,
+                 lanes: int = 4) -> dict:
     L = float(np.float32(np.sqrt(N / 0.25)))
     u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
-    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, ctx=ctx)
+    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, skin=skin, ctx=ctx, lanes=lanes)
     init, update = md.flocking(f)
     init()
     update(100, graph=True)
@@ -63,9 +64,10 @@ def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, 
     update(steps, graph=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    return {"method": "flocking", "N": f.N, "L": L, "obstacles": n_obstacles, "steps": steps,
-            "steps_per_s": steps / t, "boid_steps_per_s": f.N * steps / t, "us_per_step": 1e6 * t / steps,
-            "mean_row": float(f.nl.lengths().mean())}
+    return {"method": "flocking", "N": f.N, "L": L, "obstacles": n_obstacles, "skin": skin, "lanes": lanes,
+            "steps": steps, "steps_per_s": steps / t, "boid_steps_per_s": f.N * steps / t,
+            "us_per_step": 1e6 * t / steps, "mean_row": float(f.nl.lengths().mean()),
+            "rebuilds_in_last_20_steps": int(f.last_flags[md.FLAG_REBUILDS])}
 
 
 def main(argv=None):
@@ -74,13 +76,15 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--n-cells", type=int, default=40)
     ap.add_argument("--boids", type=int, default=65536)
+    ap.add_argument("--skin", type=float, default=0.5, help="flocking list skin")
+    ap.add_argument("--lanes", type=int, default=4, help="GPU lanes per boid")
     a = ap.parse_args(argv)
     md.load()
     if not torch.cuda.is_available():
         sys.exit("no GPU visible")
     ctx = md.Context()
     if a.method == "flocking":
-        print(json.dumps(run_flocking(ctx, a.steps, a.boids)), flush=True)
+        print(json.dumps(run_flocking(ctx, a.steps, a.boids, skin=a.skin, lanes=a.lanes)), flush=True)
         return
     for m in (METHODS if a.method == "all" else (a.method,)):
         print(json.dumps(run(ctx, m, a.steps, a.n_cells)), flush=True)

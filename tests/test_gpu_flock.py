@@ -67,17 +67,18 @@ def oracle_params(fl, md, flock):
     return fl.FlockParams(**{k: float(np.float32(v)) for k, v in flock.params.items()})
 
 
-def make(md, N, L, seed, n_obstacles, params=None, capacity=None):
+def make(md, N, L, seed, n_obstacles, params=None, capacity=None, lanes=4):
     u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
-    f = md.Flock(md.Box((L, L), 2), u, theta, params, obs, capacity=capacity)
+    f = md.Flock(md.Box((L, L), 2), u, theta, params, obs, capacity=capacity, lanes=lanes)
     return f, u, theta.astype(np.float64), obs.astype(np.float64)
 
 
-def test_flock_gradients_and_steps_match_oracle(md, fl):
-    """2000 boids at density 0.5 with 4 obstacles: the gradients of the first step (work array) and the state
-    after 1 and 4 steps."""
+@pytest.mark.parametrize("lanes", [1, 4, 8])
+def test_flock_gradients_and_steps_match_oracle(md, fl, lanes):
+    """2000 boids at density 0.5 with 4 obstacles, 1, 4 or 8 GPU lanes per boid: the gradients of the first step
+    (work array) and the state after 1 and 4 steps."""
     L = 64.0
-    f, u, theta, obs = make(md, 2000, L, 17, 4)
+    f, u, theta, obs = make(md, 2000, L, 17, 4, lanes=lanes)
     p = oracle_params(fl, md, f)
     init, update = md.flocking(f)
     init()
@@ -195,10 +196,11 @@ def test_flock_regrow_rebuilds_before_the_rerun(md):
     ib, ub = md.flocking(b)
     ia()
     ib()
-    tight = int(b.nl.lengths().max())
-    b.nl = md.NeighborList(b.N, 2, tight, b.nl.r_list, b.nl.skin, b.ctx.device, b.nl.max_per_cell, 1)
+    W = b.nl.lanes
+    tight = (int(b.nl.lengths().max()) + W - 1) // W * W
+    b.nl = md.NeighborList(b.N, 2, tight, b.nl.r_list, b.nl.skin, b.ctx.device, b.nl.max_per_cell, W)
     b.build()
-    assert b.nl.capacity == tight
+    assert b.nl.capacity == tight and a.nl.lanes == W
     ua(60)
     ub(60)
     torch.cuda.synchronize()
