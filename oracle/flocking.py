@@ -15,9 +15,11 @@ and one step of the dynamics is forward Euler,
 Readings (the printed forms disagree with the behavior the text describes): dR_i points from the boid to its
 neighbors' center of mass, and the obstacle term vanishes when the boid faces away from the obstacle; the
 obstacle's range is its radius D_o.  Displacements are nearest images.
+Predators (the two-player extension of App. B) follow at the end of the file.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -134,3 +136,117 @@ def step(R, theta, L, p: FlockParams, centers=None, radii=None, n_steps: int = 1
         R -= L * np.floor(R / L)
         theta = theta - p.dt * gT
     return R, theta
+
+
+# ----------------------------------------------------------------------------------------------- predators
+# App. B adds predators, each with a position and a heading, and makes the simulation a two-player game: boids
+# minimize E_boid = (the four terms above) + E_boid-predator, predators minimize E_predator = E_predator-boid +
+# E_obstacle.  The boid-predator term is the obstacle term with the predator in the obstacle's place (range
+# R_flee, strength J_flee); the predator-boid term is the cohesion term of a predator over the boids within
+# R_chase (strength J_chase).  Each side takes the forward-Euler step of its own energy in its own variables
+# (predators at speed v_pred); both steps start from the same state.  The predators' occasional sprint is not
+# modeled (the text gives no rule for it).
+
+@dataclass
+class PredatorParams:
+    J_flee: float = 10.0
+    R_flee: float = 4.0
+    J_chase: float = 1.0
+    R_chase: float = 8.0
+    v: float = 1.2
+
+
+def _wrap(x, L):
+    return x - L * np.round(x / L)
+
+
+def _facing_term(X, N, C, D, J, alpha, L):
+    """sum_i J rho(|X_i - C|; D)(1 - N_i . hat(X_i - C))^2 and its gradients in X_i and in the heading angle."""
+    x = _wrap(X - C, L)
+    ro = np.sqrt((x * x).sum(1))
+    xh = x / np.where(ro > 0, ro, 1.0)[:, None]
+    a = (N * xh).sum(1)
+    w = rho(ro, D, alpha)
+    dw = drho(ro, D, alpha)
+    Np = np.stack([-N[:, 1], N[:, 0]], 1)
+    e = (J * w * (1.0 - a) ** 2).sum()
+    dadX = (N - a[:, None] * xh) / np.where(ro > 0, ro, 1.0)[:, None]
+    gX = J * (dw[:, None] * xh * ((1.0 - a) ** 2)[:, None] - (w * 2.0 * (1.0 - a))[:, None] * dadX)
+    gT = J * w * 2.0 * (1.0 - a) * (-(Np * xh).sum(1))
+    return e, gX, gT
+
+
+def predator_terms(R, theta, Rp, thp, L, p: FlockParams, q: PredatorParams, centers=None, radii=None):
+    """(E_boid-predator, E_predator-boid, E_obstacle of the predators)."""
+    L = np.asarray(L, dtype=np.float64)
+    N = np.stack([np.cos(theta), np.sin(theta)], 1)
+    Np_ = np.stack([np.cos(thp), np.sin(thp)], 1)
+    e_flee = sum(_facing_term(R, N, c, q.R_flee, q.J_flee, p.alpha, L)[0] for c in Rp)
+    e_chase = 0.0
+    for k in range(len(Rp)):
+        d = _wrap(R - Rp[k], L)                       # R_j - R_p
+        m = (d * d).sum(1) < q.R_chase ** 2
+        if m.any():
+            dR = d[m].mean(0)
+            dn = math.sqrt((dR * dR).sum())
+            if dn > 0:
+                e_chase += 0.5 * q.J_chase * (1.0 - (dR / dn) @ Np_[k]) ** 2
+    e_obs = 0.0
+    if centers is not None:
+        for C, D in zip(np.asarray(centers, np.float64), np.asarray(radii, np.float64)):
+            e_obs += _facing_term(Rp, Np_, C, D, p.J_obs, p.alpha, L)[0]
+    return e_flee, e_chase, e_obs
+
+
+def predator_gradients(R, theta, Rp, thp, L, p: FlockParams, q: PredatorParams, centers=None, radii=None):
+    """Gradients of each side's own energy in its own variables: (dE_boid-predator/dR [N,2], d/dtheta [N],
+    dE_predator/dR_p [P,2], d/dtheta_p [P])."""
+    L = np.asarray(L, dtype=np.float64)
+    N = np.stack([np.cos(theta), np.sin(theta)], 1)
+    gR, gT = np.zeros_like(R), np.zeros_like(theta)
+    for c in Rp:
+        _, a, b = _facing_term(R, N, c, q.R_flee, q.J_flee, p.alpha, L)
+        gR += a
+        gT += b
+    Np_ = np.stack([np.cos(thp), np.sin(thp)], 1)
+    gRp, gTp = np.zeros_like(Rp), np.zeros_like(thp)
+    for k in range(len(Rp)):
+        d = _wrap(R - Rp[k], L)
+        m = (d * d).sum(1) < q.R_chase ** 2
+        if not m.any():
+            continue
+        dR = d[m].mean(0)
+        dn = math.sqrt((dR * dR).sum())
+        if dn == 0:
+            continue
+        h = dR / dn
+        c = h @ Np_[k]
+        g = -q.J_chase * (1.0 - c) * (Np_[k] - c * h) / dn      # dE/d(dR)
+        gRp[k] += -g                                           # dR moves by -dR_p
+        gTp[k] += -q.J_chase * (1.0 - c) * (h @ np.array([-Np_[k, 1], Np_[k, 0]]))
+    if centers is not None:
+        for C, D in zip(np.asarray(centers, np.float64), np.asarray(radii, np.float64)):
+            _, a, b = _facing_term(Rp, Np_, C, D, p.J_obs, p.alpha, L)
+            gRp += a
+            gTp += b
+    return gR, gT, gRp, gTp
+
+
+def step_with_predators(R, theta, Rp, thp, L, p: FlockParams, q: PredatorParams, centers=None, radii=None,
+                        n_steps: int = 1):
+    """n_steps of the two-player forward-Euler dynamics.  Returns (R, theta, Rp, thp)."""
+    L = np.asarray(L, dtype=np.float64)
+    R, theta = np.array(R, dtype=np.float64), np.array(theta, dtype=np.float64)
+    Rp, thp = np.array(Rp, dtype=np.float64), np.array(thp, dtype=np.float64)
+    for _ in range(n_steps):
+        gR, gT = gradients(R, theta, L, p, centers, radii)
+        fR, fT, gRp, gTp = predator_gradients(R, theta, Rp, thp, L, p, q, centers, radii)
+        N = np.stack([np.cos(theta), np.sin(theta)], 1)
+        Np_ = np.stack([np.cos(thp), np.sin(thp)], 1)
+        R = R + p.dt * (p.v * N - gR - fR)
+        theta = theta - p.dt * (gT + fT)
+        Rp = Rp + p.dt * (q.v * Np_ - gRp)
+        thp = thp - p.dt * gTp
+        R -= L * np.floor(R / L)
+        Rp -= L * np.floor(Rp / L)
+    return R, theta, Rp, thp
