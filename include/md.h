@@ -488,8 +488,8 @@ md_status md_gradient_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const 
  *   E_cohesion = sum_i 1/2 J_coh (1 - hat(dR_i) . N_i)^2, dR_i = mean over j with r_ij < R_coh of (R_j - R_i)
  *                (a boid with no such neighbor, or dR_i = 0, adds nothing)
  *   E_obstacle = sum_i sum_o J_obs rho(|R_i - C_o|; D_o)(1 - N_i . hat(R_i - C_o))^2 (disk o: center C_o, radius D_o)
- * Displacements are nearest images; obstacle centers are plain coordinates in [0, L).  Predators (App. B) are
- * not part of this call.
+ * Displacements are nearest images; obstacle centers are plain coordinates in [0, L).  Predators: see
+ * md_flock_predators.
  */
 typedef struct {
     float J_align, R_align;
@@ -505,17 +505,36 @@ typedef struct {
 } md_flock_params;
 
 /*
+ * Predators (App. B): a two-player game.  Boids add E_boid-predator = sum_{i,p} J_flee rho(|R_i - R_p|; R_flee)
+ * (1 - N_i . hat(R_i - R_p))^2 (the obstacle form with predator p as the disk center) to the energy they step on;
+ * predator p steps on its own energy E_p = 1/2 J_chase (1 - hat(dR_p) . N_p)^2, dR_p = mean over boids within
+ * R_chase of (R_j - R_p) (the cohesion form; nothing when no boid is in range), plus the obstacle terms with
+ * J_obs, at speed v.  Both sides step from the state at the start of the step.  The predators' occasional sprint
+ * is not part of this call.  pos [P][2] (uint32 torus coordinates) and theta [P] are device memory, updated in
+ * place; each predator scans all N boids (P workgroups), so P is meant to be small.
+ */
+typedef struct {
+    int32_t P;           /* number of predators, 0..4096 */
+    float J_flee, R_flee;
+    float J_chase, R_chase;
+    float v;
+    uint32_t *pos;
+    float *theta;
+} md_flock_predators;
+
+/*
  * One forward-Euler step of the flocking dynamics (App. B): R_i += dt (v N_i - dE/dR_i), theta_i -= dt dE/dtheta_i,
  * both from the state at the start of the step.  nl must be a full list (segment 0, any lane count) with
  * r_list >= max(R_align, R_avoid, R_coh), valid for pos (nl_update after each step keeps it so: the call marks on
  * the device when a boid has moved more than skin/2 from nl->pos_ref).  The list's lanes (W) set how many GPU
  * lanes share a boid.  work is device scratch of 8 N floats owned by the caller (8-byte aligned); after the call
  * work[8i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step and work[8i + 6..7] the heading N_i it used.  box->dim must
- * be 2.  Errors: MD_ERR_ARG (missing pointer, dim, list or parameters out of range, 8 N >= 2^31), MD_ERR_BOX (an
- * edge not above 2 r_list).
+ * be 2.  pred may be NULL (no predators); with predators, work[8i + 0..2] includes the flee term.  Errors:
+ * MD_ERR_ARG (missing pointer, dim, list or parameters out of range, 8 N >= 2^31), MD_ERR_BOX (an edge not above
+ * 2 r_list, or not above 2 R_flee or 2 R_chase).
  */
 md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta, int32_t N, const md_nlist *nl,
-                     const md_flock_params *fp, float *work, void *stream);
+                     const md_flock_params *fp, const md_flock_predators *pred, float *work, void *stream);
 
 /* Nose-Hoover chain state (Martyna, Klein and Tuckerman 1992), kept in DEVICE memory by the caller. */
 typedef struct {

@@ -9,6 +9,7 @@
 //                   1/2 J (1 - hat(dR_i) . N_i)^2, the gradient g_i of that energy with respect to dR_i, the
 //                   heading part, and the boid's own position part -g_i;
 //   k_flock_gather  per boid k: adds g_i / n_i of every neighbor i within R_coh (dR_i moves with R_k);
+//   k_pred_step     (with predators) each predator's step on its own energy;
 //   k_flock_move    forward Euler, R += dt (v N - dE/dR), theta -= dt dE/dtheta, and the rebuild trigger.
 //
 // With rho(r; Rc) = (1/alpha)(1 - r/Rc)^alpha the pair terms are J_avoid rho(r; R_avoid) and J_align rho(r;
@@ -39,7 +40,13 @@ struct FlockArgs {
     float inv_R_align, inv_R_avoid, inv_alpha;
     int ialpha;  // alpha when it is an integer in [1, 8] (powers by multiplication), else 0
     float *work;
+    int P;                 // predators (0: none)
+    uint32_t *ppos;        // [P][2]
+    float *pth;            // [P]
+    float J_flee, R_flee, J_chase, R_chase, v_pred;
 };
+
+
 
 // t^e for t in (0, 1]: repeated products when the exponent is a small integer, else exp2(e log2 t)
 __device__ __forceinline__ float tpow(float t, int ie, float e)
@@ -60,6 +67,23 @@ __device__ __forceinline__ float rho_t(const FlockArgs &a, float t)  // (1/alpha
 __device__ __forceinline__ float drho_t(const FlockArgs &a, float t, float inv_Rc)  // d rho / dr = -(1/Rc) t^(alpha-1)
 {
     return -tpow(t, a.ialpha - 1, a.fp.alpha - 1.0f) * inv_Rc;
+}
+
+// J rho(|x|; D)(1 - N . hat x)^2 (the obstacle form; x = X - C) added to the gradients in X and in the angle.
+__device__ __forceinline__ void facing_grad(const FlockArgs &a, float cx, float cy, float Nx, float Ny, float D,
+                                            float J, float &gx, float &gy, float &gt)
+{
+    float ro = sqrtf(__builtin_fmaf(cx, cx, cy * cy));
+    if (!(ro < D && ro > 0.0f)) return;
+    float hx = cx / ro, hy = cy / ro;
+    float am = __builtin_fmaf(Nx, hx, Ny * hy);
+    float tt = 1.0f - ro / D;
+    float w = tpow(tt, a.ialpha, a.fp.alpha) * a.inv_alpha;
+    float dw = -tpow(tt, a.ialpha - 1, a.fp.alpha - 1.0f) / D;
+    float om = 1.0f - am;
+    gx += J * (dw * hx * om * om - 2.0f * w * om * (Nx - am * hx) / ro);
+    gy += J * (dw * hy * om * om - 2.0f * w * om * (Ny - am * hy) / ro);
+    gt += J * w * 2.0f * om * (Ny * hx - Nx * hy);      // -(N_perp . hat) with N_perp = (-sin, cos)
 }
 
 // Sum over the W lanes of one boid (adjacent lanes of a wave), a fixed tree: deterministic.
@@ -136,21 +160,14 @@ __global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
     const float Nx = Ni.x, Ny = Ni.y;
     const float xi = (float)ui[0] * a.s[0], yi = (float)ui[1] * a.s[1];
     for (int o = 0; o < p.n_obstacles; ++o) {
-        float cx = xi - p.obstacles[o][0], cy = yi - p.obstacles[o][1], D = p.obstacles[o][2];
+        float cx = xi - p.obstacles[o][0], cy = yi - p.obstacles[o][1];
         cx -= a.L[0] * rintf(cx / a.L[0]);
         cy -= a.L[1] * rintf(cy / a.L[1]);
-        float ro = sqrtf(__builtin_fmaf(cx, cx, cy * cy));
-        if (ro < D && ro > 0.0f) {
-            float hx = cx / ro, hy = cy / ro;
-            float am = __builtin_fmaf(Nx, hx, Ny * hy);
-            float tt = 1.0f - ro / D;
-            float w = rho_t(a, tt), dw = drho_t(a, tt, 1.0f / D);
-            float om = 1.0f - am;
-            gx += p.J_obs * (dw * hx * om * om - 2.0f * w * om * (Nx - am * hx) / ro);
-            gy += p.J_obs * (dw * hy * om * om - 2.0f * w * om * (Ny - am * hy) / ro);
-            gt += p.J_obs * w * 2.0f * om * (Ny * hx - Nx * hy);      // -(N_perp . hat) with N_perp = (-sin, cos)
-        }
+        facing_grad(a, cx, cy, Nx, Ny, p.obstacles[o][2], p.J_obs, gx, gy, gt);
     }
+    for (int q = 0; q < a.P; ++q)  // fleeing: the obstacle form with the predator as the disk center
+        facing_grad(a, tdisp(ui[0], a.ppos[2 * q], a.s[0]), tdisp(ui[1], a.ppos[2 * q + 1], a.s[1]), Nx, Ny,
+                    a.R_flee, a.J_flee, gx, gy, gt);
     float Gx = 0.0f, Gy = 0.0f;
     if (n > 0) {
         float dRx = Sx / n, dRy = Sy / n;
@@ -204,6 +221,67 @@ __global__ __launch_bounds__(kBlock) void k_flock_gather(FlockArgs a)
     a.work[(size_t)k * kWork + 1] += gy;
 }
 
+// One workgroup per predator: the cohesion form over the boids within R_chase (dR_p = mean of R_j - R_p, which
+// moves by -dR_p), the obstacle terms, then the predator's own forward-Euler step.  Runs after k_flock_terms has
+// read the predators and before the boids move, so both sides step from the same state.
+__global__ __launch_bounds__(kBlock) void k_pred_step(FlockArgs a)
+{
+    __shared__ float sx[kBlock], sy[kBlock];
+    __shared__ int sn[kBlock];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const uint32_t u0 = a.ppos[2 * k], u1 = a.ppos[2 * k + 1];
+    const float R2 = a.R_chase * a.R_chase;
+    float Sx = 0.0f, Sy = 0.0f;
+    int n = 0;
+    for (int j = t; j < a.N; j += kBlock) {
+        float dx = tdisp(a.pos[2 * (size_t)j], u0, a.s[0]), dy = tdisp(a.pos[2 * (size_t)j + 1], u1, a.s[1]);
+        if (__builtin_fmaf(dx, dx, dy * dy) < R2) {
+            Sx += dx;
+            Sy += dy;
+            ++n;
+        }
+    }
+    sx[t] = Sx;
+    sy[t] = Sy;
+    sn[t] = n;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {  // fixed tree: deterministic
+        if (t < off) {
+            sx[t] += sx[t + off];
+            sy[t] += sy[t + off];
+            sn[t] += sn[t + off];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const float th = a.pth[k], Nx = cosf(th), Ny = sinf(th);
+    float gx = 0.0f, gy = 0.0f, gt = 0.0f;
+    n = sn[0];
+    if (n > 0) {
+        float dRx = sx[0] / n, dRy = sy[0] / n;
+        float dn = sqrtf(__builtin_fmaf(dRx, dRx, dRy * dRy));
+        if (dn > 0.0f) {
+            float hx = dRx / dn, hy = dRy / dn;
+            float ci = __builtin_fmaf(hx, Nx, hy * Ny);
+            float kk = -a.J_chase * (1.0f - ci) / dn;
+            gx -= kk * (Nx - ci * hx);
+            gy -= kk * (Ny - ci * hy);
+            gt += -a.J_chase * (1.0f - ci) * (Nx * hy - Ny * hx);
+        }
+    }
+    const float xp = (float)u0 * a.s[0], yp = (float)u1 * a.s[1];
+    for (int o = 0; o < a.fp.n_obstacles; ++o) {
+        float cx = xp - a.fp.obstacles[o][0], cy = yp - a.fp.obstacles[o][1];
+        cx -= a.L[0] * rintf(cx / a.L[0]);
+        cy -= a.L[1] * rintf(cy / a.L[1]);
+        facing_grad(a, cx, cy, Nx, Ny, a.fp.obstacles[o][2], a.fp.J_obs, gx, gy, gt);
+    }
+    const float dt = a.fp.dt;
+    a.ppos[2 * k] = u0 + (uint32_t)__float2int_rn(dt * (a.v_pred * Nx - gx) * a.inv_s[0]);
+    a.ppos[2 * k + 1] = u1 + (uint32_t)__float2int_rn(dt * (a.v_pred * Ny - gy) * a.inv_s[1]);
+    a.pth[k] = th - dt * gt;
+}
+
 __global__ __launch_bounds__(kBlock) void k_flock_move(FlockArgs a, uint32_t *pos, const uint32_t *pos_ref,
                                                        float half_skin, int32_t *ctl)
 {
@@ -235,7 +313,7 @@ int nblocks(int64_t n)
 extern "C" {
 
 md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta, int32_t N, const md_nlist *nl,
-                     const md_flock_params *fp, float *work, void *stream)
+                     const md_flock_params *fp, const md_flock_predators *pred, float *work, void *stream)
 {
     if (!ctx || !box || box->dim != 2 || !pos || !theta || !nl || !fp || !work || N < 0 || nl->N != N ||
         nl->segment != 0 || !nl->idx || !nl->count || !nl->pos_ref)
@@ -254,6 +332,21 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         a.s[k] = L / 4294967296.0f;
         a.inv_s[k] = 4294967296.0f / L;
         a.L[k] = L;
+    }
+    if (pred && pred->P > 0) {
+        if (pred->P > 4096 || !pred->pos || !pred->theta || !(pred->R_flee > 0.0f) || !(pred->R_chase > 0.0f) ||
+            !isfinite(pred->J_flee) || !isfinite(pred->J_chase) || !isfinite(pred->v))
+            return MD_ERR_ARG;
+        if (!(pred->R_flee < 0.5f * fminf(a.L[0], a.L[1])) || !(pred->R_chase < 0.5f * fminf(a.L[0], a.L[1])))
+            return MD_ERR_BOX;
+        a.P = pred->P;
+        a.ppos = pred->pos;
+        a.pth = pred->theta;
+        a.J_flee = pred->J_flee;
+        a.R_flee = pred->R_flee;
+        a.J_chase = pred->J_chase;
+        a.R_chase = pred->R_chase;
+        a.v_pred = pred->v;
     }
     if (N == 0) return MD_OK;
     a.pos = pos;
@@ -289,6 +382,7 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         hipLaunchKernelGGL(k_flock_gather<8>, dim3(gW), dim3(kBlock), 0, s, a);
         break;
     }
+    if (a.P > 0) hipLaunchKernelGGL(k_pred_step, dim3(a.P), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }

@@ -93,6 +93,12 @@ class c_flock_params(ctypes.Structure):
                 ("n_obstacles", ctypes.c_int32), ("reserved", ctypes.c_int32), ("obstacles", ctypes.c_float * 48)]
 
 
+class c_flock_predators(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("J_flee", ctypes.c_float), ("R_flee", ctypes.c_float),
+                ("J_chase", ctypes.c_float), ("R_chase", ctypes.c_float), ("v", ctypes.c_float),
+                ("pos", ctypes.c_void_p), ("theta", ctypes.c_void_p)]
+
+
 FIRE_STATE_BYTES = ctypes.sizeof(c_fire_state)
 _lib = None
 
@@ -147,7 +153,7 @@ _SIGNATURES = {
     "md_nhc_half": [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P],
     "nl_half": [P, ctypes.POINTER(c_nlist), P, P, ctypes.c_int32, P, P],
     "flock_step": [P, ctypes.POINTER(c_box), P, P, ctypes.c_int32, ctypes.POINTER(c_nlist),
-                   ctypes.POINTER(c_flock_params), P, P],
+                   ctypes.POINTER(c_flock_params), ctypes.POINTER(c_flock_predators), P, P],
     "pair_force_half": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, ctypes.c_int32, P, P,
                         ctypes.c_int32, P, P],
     "md_rms_diff": [P, P, P, ctypes.c_int64, P, P],
@@ -469,10 +475,12 @@ def nhc_half(ctx: Context, vel, state: torch.Tensor, h: float):
     _check("md_nhc_half", load().md_nhc_half(ctx.h, _ptr(vel), N, dim, _ptr(state), ctypes.c_double(h), _stream()))
 
 
-def flock_step(ctx: Context, box: Box, pos, theta, nl: NeighborList, fp: c_flock_params, work):
+def flock_step(ctx: Context, box: Box, pos, theta, nl: NeighborList, fp: c_flock_params, work,
+               pred: c_flock_predators | None = None):
     b, n = box.c(), nl.c()
     _check("flock_step", load().flock_step(ctx.h, ctypes.byref(b), _ptr(pos), _ptr(theta), pos.shape[0],
-                                           ctypes.byref(n), ctypes.byref(fp), _ptr(work), _stream()))
+                                           ctypes.byref(n), ctypes.byref(fp),
+                                           ctypes.byref(pred) if pred is not None else None, _ptr(work), _stream()))
 
 
 class HalfList:
@@ -1110,16 +1118,19 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
 
 FLOCK_DEFAULTS = dict(J_align=1.0, R_align=3.0, J_avoid=25.0, R_avoid=1.0, J_coh=0.05, R_coh=3.0, J_obs=10.0,
                       alpha=3.0, v=1.0, dt=0.05)
+PREDATOR_DEFAULTS = dict(J_flee=10.0, R_flee=4.0, J_chase=1.0, R_chase=8.0, v=1.2)
 
 
 class Flock(System):
     """Boids of the flocking model (Sec. 4.3, App. B): positions pos (uint32 torus, [N][2]), headings theta [N],
     and a full neighbor list of radius max(R_align, R_avoid, R_coh) + skin.  ``params`` overrides FLOCK_DEFAULTS;
-    ``obstacles`` is a list of disks (C_x, C_y, D), at most 16; ``lanes`` GPU lanes share each boid."""
+    ``obstacles`` is a list of disks (C_x, C_y, D), at most 16; ``lanes`` GPU lanes share each boid.
+    ``predators`` = (uint32 positions [P][2], headings [P]) adds the predators of App. B (``predator_params``
+    overrides PREDATOR_DEFAULTS); they live in ``ppos`` and ``ptheta``."""
 
     def __init__(self, box: Box, u: np.ndarray, theta, params: dict | None = None, obstacles=(), skin: float = 0.5,
                  capacity: int | None = None, ctx: Context | None = None, max_per_cell: int | None = None,
-                 lanes: int = 4):
+                 lanes: int = 4, predators=None, predator_params: dict | None = None):
         if box.dim != 2:
             raise ValueError("the flocking model is two-dimensional")
         p = dict(FLOCK_DEFAULTS, **(params or {}))
@@ -1137,6 +1148,15 @@ class Flock(System):
                          max_per_cell, lanes)
         self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32), device=self.ctx.device).contiguous()
         self.work = torch.zeros((self.N, 8), dtype=torch.float32, device=self.ctx.device)
+        self.pred = None
+        if predators is not None:
+            up, thp = predators
+            self.ppos = to_device_u32(np.asarray(up, np.uint32).reshape(-1, 2), self.ctx.device)
+            self.ptheta = torch.as_tensor(np.asarray(thp, dtype=np.float32), device=self.ctx.device).contiguous()
+            q = dict(PREDATOR_DEFAULTS, **(predator_params or {}))
+            self.predator_params = q
+            self.pred = c_flock_predators(P=self.ppos.shape[0], **{k: float(v) for k, v in q.items()})
+            self.pred.pos, self.pred.theta = self.ppos.data_ptr(), self.ptheta.data_ptr()
 
 
 def flocking(flock: Flock):
@@ -1148,7 +1168,8 @@ def flocking(flock: Flock):
         return flock
 
     def once():
-        flock_step(flock.ctx, flock.box, flock.pos, flock.theta, flock.nl, flock.fp, flock.work)
+        flock_step(flock.ctx, flock.box, flock.pos, flock.theta, flock.nl, flock.fp, flock.work, flock.pred)
         nl_update(flock.ctx, flock.box, flock.pos, flock.nl)
 
-    return init_fn, _stepper(flock, once, (flock.pos, flock.theta))
+    state = (flock.pos, flock.theta) + ((flock.ppos, flock.ptheta) if flock.pred is not None else ())
+    return init_fn, _stepper(flock, once, state)

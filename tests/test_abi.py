@@ -31,6 +31,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(md.c_fire_params) == 32
     assert ctypes.sizeof(md.c_fire_state) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(md.c_flock_params) == 10 * 4 + 2 * 4 + 16 * 3 * 4
+    assert ctypes.sizeof(md.c_flock_predators) == 6 * 4 + 2 * 8
 
 
 def test_host_side_helpers_without_gpu():
@@ -56,7 +57,7 @@ def test_argument_errors_are_returned_synchronously():
     assert lib.md_sum(None, None, 0, None, None) == -1
     fp = md.c_flock_params()
     b.dim = 2
-    assert lib.flock_step(None, ctypes.byref(b), None, None, 0, None, ctypes.byref(fp), None, None) == -1
+    assert lib.flock_step(None, ctypes.byref(b), None, None, 0, None, ctypes.byref(fp), None, None, None) == -1
 
 
 def test_unrolled_fire_workspace_size_and_argument_errors():

@@ -207,3 +207,62 @@ def test_flock_regrow_rebuilds_before_the_rerun(md):
     say("capacity", tight, "->", b.nl.capacity, "max row", int(a.nl.lengths().max()))
     assert b.nl.capacity > tight
     assert torch.equal(a.pos, b.pos) and torch.equal(a.theta, b.theta)
+
+
+def make_with_predators(md, N, L, seed, n_obstacles, P, lanes=4):
+    u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
+    up, thp, _ = inputs.boids(P, L, seed + 100, 0)
+    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, lanes=lanes, predators=(up, thp))
+    return f, u, theta.astype(np.float64), obs.astype(np.float64), up, thp.astype(np.float64)
+
+
+def test_flock_with_predators_matches_oracle(md, fl):
+    """1500 boids, 2 obstacles and 4 predators (App. B's two-player game): the boids' gradients of the first step
+    (flee term included), the predators after one step, and both sides after 4 steps."""
+    L = 56.0
+    f, u, theta, obs, up, thp = make_with_predators(md, 1500, L, 47, 2, 4)
+    p = oracle_params(fl, md, f)
+    q = fl.PredatorParams(**{k: float(np.float32(v)) for k, v in f.predator_params.items()})
+    init, update = md.flocking(f)
+    init()
+    update(1)
+    x, xp, LL = positions(u, L), positions(up, L), np.array([L, L])
+    gR, gT = fl.gradients(x, theta, LL, p, obs[:, :2], obs[:, 2])
+    fR, fT, _, _ = fl.predator_gradients(x, theta, xp, thp, LL, p, q, obs[:, :2], obs[:, 2])
+    w = f.work.cpu().numpy().astype(np.float64)
+    scale = max(np.abs(gR + fR).max(), np.abs(gT + fT).max())
+    e = grad_err(w, gR + fR, gT + fT, cohesion_dn(x, L, p.R_coh), p.J_coh, scale)
+    say("boid gradient err / bound", e, "flee part", np.abs(fR).max())
+    assert e < 1.0 and np.abs(fR).max() > 0
+    R, T, Rp, Tp = x, theta, xp, thp
+    done = 0
+    for n in (1, 3):
+        if done:
+            update(n)
+        R, T, Rp, Tp = fl.step_with_predators(R, T, Rp, Tp, LL, p, q, obs[:, :2], obs[:, 2], n_steps=n)
+        done += n
+        dR = image_diff(positions(md.from_device_u32(f.pos), L), R, L).max()
+        dT = np.abs(f.theta.cpu().numpy().astype(np.float64) - T).max()
+        dRp = image_diff(positions(md.from_device_u32(f.ppos), L), Rp, L).max()
+        dTp = np.abs(f.ptheta.cpu().numpy().astype(np.float64) - Tp).max()
+        say("steps", done, "boids dR", dR, "dtheta", dT, "predators dR", dRp, "dtheta", dTp)
+        if done == 1:
+            assert dRp < 1e-5 and dTp < 1e-5
+        assert dR < 1e-3 and dT < 1e-3 and dRp < 1e-3 and dTp < 1e-3
+
+
+def test_flock_with_predators_graph_replay_matches_eager(md):
+    import torch
+    L = 56.0
+    a = make_with_predators(md, 1500, L, 53, 2, 4)[0]
+    b = make_with_predators(md, 1500, L, 53, 2, 4)[0]
+    ia, ua = md.flocking(a)
+    ib, ub = md.flocking(b)
+    ia()
+    ib()
+    for _ in range(2):
+        ua(40, graph=True)
+        ub(40, graph=False)
+        torch.cuda.synchronize()
+        assert torch.equal(a.pos, b.pos) and torch.equal(a.theta, b.theta)
+        assert torch.equal(a.ppos, b.ppos) and torch.equal(a.ptheta, b.ptheta)
