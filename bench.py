@@ -215,10 +215,13 @@ def flocking(ctx, progress, steps: int = 2000):
     """The flocking model of Sec. 4.3 / App. B at tens of thousands of boids: 65536 boids, uniform start in a
     512 x 512 periodic box (density 0.25), 16 disk obstacles of radius 2 to 6, the default parameters (J_align 1,
     R_align 3, J_avoid 25, R_avoid 1, J_coh 0.05, R_coh 3, J_obs 10, alpha 3, v 1, dt 0.05), list skin 0.5.  One
-    step is flock_step (three launches) and the device-gated rebuild, replayed from HIP graphs of 20 steps."""
+    step is flock_step (four launches, five with predators) and the device-gated rebuild, replayed from HIP graphs
+    of 20 steps; measured without predators and with 16."""
     from paper_1912_04232_amd import simulate
     out = simulate.run_flocking(ctx, steps)
     progress(f"flocking: {out['steps_per_s']:.0f} steps/s")
+    out["with_16_predators"] = simulate.run_flocking(ctx, steps, predators=16)
+    progress(f"flocking with 16 predators: {out['with_16_predators']['steps_per_s']:.0f} steps/s")
     return out
 
 

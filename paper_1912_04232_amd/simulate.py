@@ -5,7 +5,8 @@
 
 The integrators run on 3D Lennard-Jones, 4 n^3 particles on an FCC lattice at density 0.84 (N = 256000 for
 n = 40), Maxwell velocities at T = 1, cutoff 2.5, skin 0.3.  Flocking (Sec. 4.3, App. B) runs the boid model with
-its default parameters: boids uniform in a square box at density 0.25 with 16 disk obstacles, skin 0.5.  Each run
+its default parameters: boids uniform in a square box at density 0.25 with 16 disk obstacles, skin 0.5, and
+optionally predators (App. B's two-player extension).  Each run
 takes 100 steps (graph capture and warm-up), then `steps` timed steps replayed from HIP graphs of 20 steps; one
 JSON line per run.
 """
@@ -51,10 +52,11 @@ def run(ctx, method: str, steps: int = 1000, n_cells: int = 40) -> dict:
 
 
 def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, seed: int = 29, skin: float = 0.5,
-                 lanes: int = 4) -> dict:
+                 lanes: int = 4, predators: int = 0) -> dict:
     L = float(np.float32(np.sqrt(N / 0.25)))
     u, theta, obs = inputs.boids(N, L, seed, n_obstacles)
-    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, skin=skin, ctx=ctx, lanes=lanes)
+    pred = inputs.boids(predators, L, seed + 100, 0)[:2] if predators else None
+    f = md.Flock(md.Box((L, L), 2), u, theta, None, obs, skin=skin, ctx=ctx, lanes=lanes, predators=pred)
     init, update = md.flocking(f)
     init()
     update(100, graph=True)
@@ -64,7 +66,8 @@ def run_flocking(ctx, steps: int = 1000, N: int = 65536, n_obstacles: int = 16, 
     update(steps, graph=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    return {"method": "flocking", "N": f.N, "L": L, "obstacles": n_obstacles, "skin": skin, "lanes": lanes,
+    return {"method": "flocking", "N": f.N, "L": L, "obstacles": n_obstacles, "predators": predators, "skin": skin,
+            "lanes": lanes,
             "steps": steps, "steps_per_s": steps / t, "boid_steps_per_s": f.N * steps / t,
             "us_per_step": 1e6 * t / steps, "mean_row": float(f.nl.lengths().mean()),
             "rebuilds_in_last_20_steps": int(f.last_flags[md.FLAG_REBUILDS])}
@@ -78,13 +81,15 @@ def main(argv=None):
     ap.add_argument("--boids", type=int, default=65536)
     ap.add_argument("--skin", type=float, default=0.5, help="flocking list skin")
     ap.add_argument("--lanes", type=int, default=4, help="GPU lanes per boid")
+    ap.add_argument("--predators", type=int, default=0, help="flocking predators")
     a = ap.parse_args(argv)
     md.load()
     if not torch.cuda.is_available():
         sys.exit("no GPU visible")
     ctx = md.Context()
     if a.method == "flocking":
-        print(json.dumps(run_flocking(ctx, a.steps, a.boids, skin=a.skin, lanes=a.lanes)), flush=True)
+        print(json.dumps(run_flocking(ctx, a.steps, a.boids, skin=a.skin, lanes=a.lanes,
+                                                 predators=a.predators)), flush=True)
         return
     for m in (METHODS if a.method == "all" else (a.method,)):
         print(json.dumps(run(ctx, m, a.steps, a.n_cells)), flush=True)
