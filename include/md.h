@@ -511,7 +511,8 @@ typedef struct {
  * R_chase of (R_j - R_p) (the cohesion form; nothing when no boid is in range), plus the obstacle terms with
  * J_obs, at speed v.  Both sides step from the state at the start of the step.  The predators' occasional sprint
  * is not part of this call.  pos [P][2] (uint32 torus coordinates) and theta [P] are device memory, updated in
- * place; each predator scans all N boids (P workgroups), so P is meant to be small.
+ * place; each predator scans all N boids (its sums split over up to 64 workgroups and combined in a fixed order in
+ * the context's reduction buffer), so P is meant to be small.
  */
 typedef struct {
     int32_t P;           /* number of predators, 0..4096 */

@@ -9,7 +9,7 @@
 //                   1/2 J (1 - hat(dR_i) . N_i)^2, the gradient g_i of that energy with respect to dR_i, the
 //                   heading part, and the boid's own position part -g_i;
 //   k_flock_gather  per boid k: adds g_i / n_i of every neighbor i within R_coh (dR_i moves with R_k);
-//   k_pred_step     (with predators) each predator's step on its own energy;
+//   k_pred_partial, k_pred_finish  (with predators) each predator's step on its own energy;
 //   k_flock_move    forward Euler, R += dt (v N - dE/dR), theta -= dt dE/dtheta, and the rebuild trigger.
 //
 // With rho(r; Rc) = (1/alpha)(1 - r/Rc)^alpha the pair terms are J_avoid rho(r; R_avoid) and J_align rho(r;
@@ -17,6 +17,7 @@
 // J_obs rho(|R_i - C|; D)(1 - N_i . hat(R_i - C))^2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -221,19 +222,24 @@ __global__ __launch_bounds__(kBlock) void k_flock_gather(FlockArgs a)
     a.work[(size_t)k * kWork + 1] += gy;
 }
 
-// One workgroup per predator: the cohesion form over the boids within R_chase (dR_p = mean of R_j - R_p, which
-// moves by -dR_p), the obstacle terms, then the predator's own forward-Euler step.  Runs after k_flock_terms has
-// read the predators and before the boids move, so both sides step from the same state.
-__global__ __launch_bounds__(kBlock) void k_pred_step(FlockArgs a)
+// Predators, in two launches.  k_pred_partial: workgroup (b, k) sums R_j - R_p and the count over the boids
+// within R_chase of predator k among the b-th of B equal slices of the boids (a fixed LDS tree), into
+// partials[(k B + b) 3 + 0..2] (double).  k_pred_finish: one thread per predator adds the B partials in order
+// (deterministic), forms the cohesion-form gradient (dR_p moves by -dR_p) and the obstacle terms, and takes the
+// predator's forward-Euler step.  Both run after k_flock_terms has read the predators and before the boids move,
+// so both sides step from the same state.
+__global__ __launch_bounds__(kBlock) void k_pred_partial(FlockArgs a, double *partials, int B)
 {
     __shared__ float sx[kBlock], sy[kBlock];
     __shared__ int sn[kBlock];
-    const int k = blockIdx.x, t = threadIdx.x;
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
     const uint32_t u0 = a.ppos[2 * k], u1 = a.ppos[2 * k + 1];
     const float R2 = a.R_chase * a.R_chase;
+    const int chunk = (a.N + B - 1) / B;
+    const int lo = b * chunk, hi = min(a.N, lo + chunk);
     float Sx = 0.0f, Sy = 0.0f;
     int n = 0;
-    for (int j = t; j < a.N; j += kBlock) {
+    for (int j = lo + t; j < hi; j += kBlock) {
         float dx = tdisp(a.pos[2 * (size_t)j], u0, a.s[0]), dy = tdisp(a.pos[2 * (size_t)j + 1], u1, a.s[1]);
         if (__builtin_fmaf(dx, dx, dy * dy) < R2) {
             Sx += dx;
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_pred_step(FlockArgs a)
     sy[t] = Sy;
     sn[t] = n;
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {  // fixed tree: deterministic
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (t < off) {
             sx[t] += sx[t + off];
             sy[t] += sy[t + off];
@@ -253,12 +259,30 @@ __global__ __launch_bounds__(kBlock) void k_pred_step(FlockArgs a)
         }
         __syncthreads();
     }
-    if (t != 0) return;
+    if (t == 0) {
+        double *o = partials + ((size_t)k * B + b) * 3;
+        o[0] = sx[0];
+        o[1] = sy[0];
+        o[2] = sn[0];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_pred_finish(FlockArgs a, const double *partials, int B)
+{
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= a.P) return;
+    double Sx = 0.0, Sy = 0.0, n = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double *o = partials + ((size_t)k * B + b) * 3;
+        Sx += o[0];
+        Sy += o[1];
+        n += o[2];
+    }
+    const uint32_t u0 = a.ppos[2 * k], u1 = a.ppos[2 * k + 1];
     const float th = a.pth[k], Nx = cosf(th), Ny = sinf(th);
     float gx = 0.0f, gy = 0.0f, gt = 0.0f;
-    n = sn[0];
-    if (n > 0) {
-        float dRx = sx[0] / n, dRy = sy[0] / n;
+    if (n > 0.0) {
+        float dRx = (float)(Sx / n), dRy = (float)(Sy / n);
         float dn = sqrtf(__builtin_fmaf(dRx, dRx, dRy * dRy));
         if (dn > 0.0f) {
             float hx = dRx / dn, hy = dRy / dn;
@@ -382,7 +406,13 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         hipLaunchKernelGGL(k_flock_gather<8>, dim3(gW), dim3(kBlock), 0, s, a);
         break;
     }
-    if (a.P > 0) hipLaunchKernelGGL(k_pred_step, dim3(a.P), dim3(kBlock), 0, s, a);
+    if (a.P > 0) {
+        // slices per predator: enough workgroups to fill the chip, within the context's partials buffer
+        const int64_t cap = (int64_t)4 * md_partials_blocks() / (3 * (int64_t)a.P);
+        const int B = (int)std::max<int64_t>(1, std::min<int64_t>({64, cap, (int64_t)(N + kBlock - 1) / kBlock}));
+        hipLaunchKernelGGL(k_pred_partial, dim3(B, a.P), dim3(kBlock), 0, s, a, ctx->partials, B);
+        hipLaunchKernelGGL(k_pred_finish, dim3((a.P + 63) / 64), dim3(64), 0, s, a, (const double *)ctx->partials, B);
+    }
     hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
