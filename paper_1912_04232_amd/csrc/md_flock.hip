@@ -224,9 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_flock_gather(FlockArgs a)
 
 // Predators, in two launches.  k_pred_partial: workgroup (b, k) sums R_j - R_p and the count over the boids
 // within R_chase of predator k among the b-th of B equal slices of the boids (a fixed LDS tree), into
-// partials[(k B + b) 3 + 0..2] (double).  k_pred_finish: one thread per predator adds the B partials in order
-// (deterministic), forms the cohesion-form gradient (dR_p moves by -dR_p) and the obstacle terms, and takes the
-// predator's forward-Euler step.  Both run after k_flock_terms has read the predators and before the boids move,
+// partials[(k B + b) 3 + 0..2] (double).  k_pred_finish: one wave per predator adds the B partials in a fixed
+// xor tree (deterministic); its first lane forms the cohesion-form gradient (dR_p moves by -dR_p) and the
+// obstacle terms, and takes the predator's forward-Euler step.  Both run after k_flock_terms has read the predators and before the boids move,
 // so both sides step from the same state.
 __global__ __launch_bounds__(kBlock) void k_pred_partial(FlockArgs a, double *partials, int B)
 {
@@ -269,15 +269,21 @@ __global__ __launch_bounds__(kBlock) void k_pred_partial(FlockArgs a, double *pa
 
 __global__ __launch_bounds__(64) void k_pred_finish(FlockArgs a, const double *partials, int B)
 {
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= a.P) return;
+    const int k = blockIdx.x, lane = threadIdx.x;  // one wave per predator, lane b holds partial b (B <= 64)
     double Sx = 0.0, Sy = 0.0, n = 0.0;
-    for (int b = 0; b < B; ++b) {
-        const double *o = partials + ((size_t)k * B + b) * 3;
-        Sx += o[0];
-        Sy += o[1];
-        n += o[2];
+    if (lane < B) {
+        const double *o = partials + ((size_t)k * B + lane) * 3;
+        Sx = o[0];
+        Sy = o[1];
+        n = o[2];
     }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {  // fixed xor tree: deterministic
+        Sx += __shfl_xor(Sx, m, 64);
+        Sy += __shfl_xor(Sy, m, 64);
+        n += __shfl_xor(n, m, 64);
+    }
+    if (lane != 0) return;
     const uint32_t u0 = a.ppos[2 * k], u1 = a.ppos[2 * k + 1];
     const float th = a.pth[k], Nx = cosf(th), Ny = sinf(th);
     float gx = 0.0f, gy = 0.0f, gt = 0.0f;
@@ -411,7 +417,7 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         const int64_t cap = (int64_t)4 * md_partials_blocks() / (3 * (int64_t)a.P);
         const int B = (int)std::max<int64_t>(1, std::min<int64_t>({64, cap, (int64_t)(N + kBlock - 1) / kBlock}));
         hipLaunchKernelGGL(k_pred_partial, dim3(B, a.P), dim3(kBlock), 0, s, a, ctx->partials, B);
-        hipLaunchKernelGGL(k_pred_finish, dim3((a.P + 63) / 64), dim3(64), 0, s, a, (const double *)ctx->partials, B);
+        hipLaunchKernelGGL(k_pred_finish, dim3(a.P), dim3(64), 0, s, a, (const double *)ctx->partials, B);
     }
     hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
