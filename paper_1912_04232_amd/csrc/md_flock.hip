@@ -151,6 +151,18 @@ __global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
             ++n;
         }
     }
+    // obstacles and predators, dealt round-robin to the boid's W lanes
+    const float Nx = Ni.x, Ny = Ni.y;
+    const float xi = (float)ui[0] * a.s[0], yi = (float)ui[1] * a.s[1];
+    for (int o = l; o < p.n_obstacles; o += W) {
+        float cx = xi - p.obstacles[o][0], cy = yi - p.obstacles[o][1];
+        cx -= a.L[0] * rintf(cx / a.L[0]);
+        cy -= a.L[1] * rintf(cy / a.L[1]);
+        facing_grad(a, cx, cy, Nx, Ny, p.obstacles[o][2], p.J_obs, gx, gy, gt);
+    }
+    for (int q = l; q < a.P; q += W)  // fleeing: the obstacle form with the predator as the disk center
+        facing_grad(a, tdisp(ui[0], a.ppos[2 * q], a.s[0]), tdisp(ui[1], a.ppos[2 * q + 1], a.s[1]), Nx, Ny,
+                    a.R_flee, a.J_flee, gx, gy, gt);
     gx = lane_sum<W>(gx);
     gy = lane_sum<W>(gy);
     gt = lane_sum<W>(gt);
@@ -158,17 +170,6 @@ __global__ __launch_bounds__(kBlock) void k_flock_terms(FlockArgs a)
     Sy = lane_sum<W>(Sy);
     n = lane_sum_i<W>(n);
     if (!live || l != 0) return;
-    const float Nx = Ni.x, Ny = Ni.y;
-    const float xi = (float)ui[0] * a.s[0], yi = (float)ui[1] * a.s[1];
-    for (int o = 0; o < p.n_obstacles; ++o) {
-        float cx = xi - p.obstacles[o][0], cy = yi - p.obstacles[o][1];
-        cx -= a.L[0] * rintf(cx / a.L[0]);
-        cy -= a.L[1] * rintf(cy / a.L[1]);
-        facing_grad(a, cx, cy, Nx, Ny, p.obstacles[o][2], p.J_obs, gx, gy, gt);
-    }
-    for (int q = 0; q < a.P; ++q)  // fleeing: the obstacle form with the predator as the disk center
-        facing_grad(a, tdisp(ui[0], a.ppos[2 * q], a.s[0]), tdisp(ui[1], a.ppos[2 * q + 1], a.s[1]), Nx, Ny,
-                    a.R_flee, a.J_flee, gx, gy, gt);
     float Gx = 0.0f, Gy = 0.0f;
     if (n > 0) {
         float dRx = Sx / n, dRy = Sy / n;
