@@ -531,7 +531,7 @@ typedef struct {
  * lanes share a boid.  work is device scratch of 8 N floats owned by the caller (8-byte aligned); after the call
  * work[8i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step and work[8i + 6..7] the heading N_i it used.  box->dim must
  * be 2.  pred may be NULL (no predators); with predators, work[8i + 0..2] includes the flee term.  With N = 0 nothing
- * is enqueued (predators do not move either).  Errors:
+ * is enqueued (predators do not move either) and the boid arrays may be NULL.  Errors:
  * MD_ERR_ARG (missing pointer, dim, list or parameters out of range, 8 N >= 2^31), MD_ERR_BOX (an edge not above
  * 2 r_list, or not above 2 R_flee or 2 R_chase).
  */

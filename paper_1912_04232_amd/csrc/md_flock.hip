@@ -346,8 +346,8 @@ extern "C" {
 md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta, int32_t N, const md_nlist *nl,
                      const md_flock_params *fp, const md_flock_predators *pred, float *work, void *stream)
 {
-    if (!ctx || !box || box->dim != 2 || !pos || !theta || !nl || !fp || !work || N < 0 || nl->N != N ||
-        nl->segment != 0 || !nl->idx || !nl->count || !nl->pos_ref)
+    if (!ctx || !box || box->dim != 2 || !nl || !fp || N < 0 || nl->N != N || nl->segment != 0 ||
+        (N > 0 && (!pos || !theta || !work || !nl->idx || !nl->count || !nl->pos_ref)))
         return MD_ERR_ARG;
     if (fp->n_obstacles < 0 || fp->n_obstacles > 16 || !(fp->alpha >= 1.0f) || !(fp->R_align > 0.0f) ||
         !(fp->R_avoid > 0.0f) || !(fp->R_coh > 0.0f) || !isfinite(fp->dt))

@@ -266,3 +266,21 @@ def test_flock_with_predators_graph_replay_matches_eager(md):
         torch.cuda.synchronize()
         assert torch.equal(a.pos, b.pos) and torch.equal(a.theta, b.theta)
         assert torch.equal(a.ppos, b.ppos) and torch.equal(a.ptheta, b.ptheta)
+
+
+def test_flock_step_without_boids_is_a_no_op(md):
+    """N = 0: the call succeeds with empty (NULL) boid arrays and enqueues nothing; predators stay put."""
+    import torch
+    ctx = md.Context()
+    box = md.Box((32.0, 32.0), 2)
+    nl = md.NeighborList(0, 2, 8, 3.5, 0.5, ctx.device, 8, 4)
+    fp = md.c_flock_params(**{k: float(v) for k, v in md.FLOCK_DEFAULTS.items()})
+    up = torch.tensor([[123, 456]], dtype=torch.int32, device=ctx.device)
+    thp = torch.tensor([0.5], dtype=torch.float32, device=ctx.device)
+    pred = md.c_flock_predators(P=1, **{k: float(v) for k, v in md.PREDATOR_DEFAULTS.items()})
+    pred.pos, pred.theta = up.data_ptr(), thp.data_ptr()
+    empty_u = torch.empty((0, 2), dtype=torch.int32, device=ctx.device)
+    empty_f = torch.empty(0, dtype=torch.float32, device=ctx.device)
+    md.flock_step(ctx, box, empty_u, empty_f, nl, fp, torch.empty((0, 8), device=ctx.device), pred)
+    torch.cuda.synchronize()
+    assert up.tolist() == [[123, 456]] and thp.tolist() == [0.5]
