@@ -176,7 +176,9 @@ md_status nl_build(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t 
  *   energy[i] = 1/2 sum_j u(r_ij)                        (double [N] or NULL)
  *   virial[i] = 1/2 sum_j r_ij f(r_ij),  f = -du/dr      (double [N] or NULL)
  * over the neighbor list when nl != NULL (its pairs beyond the cutoff add
- * nothing), or over all N(N-1) ordered pairs when nl == NULL (dense).
+ * nothing), or over all N(N-1) ordered pairs when nl == NULL (dense).  A list must have
+ * r_list - skin >= the potential's range (MD_ERR_ARG otherwise): it is used while particles stay
+ * within skin/2 of pos_ref, so only pairs within r_list - skin are sure to be in it.
  * Pair arithmetic is single precision; energy and virial sums are double.
  * species may be NULL when pot->n_species == 1.  force may be NULL.
  */
@@ -378,7 +380,8 @@ typedef struct {
 
 /* Number of network parameters (the length of theta). */
 int32_t nn_param_count(void);
-/* G[i][k] (float [N][K]) over a neighbor list with r_list >= r_c (3D; a segmented list gives each system's). */
+/* G[i][k] (float [N][K]) over a neighbor list with r_list - skin >= r_c (3D; a segmented list gives each
+ * system's; MD_ERR_ARG for a list that does not cover r_c). */
 md_status nn_descriptors(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,
                          const md_nlist *nl, float *G, void *stream);
 /*
@@ -526,12 +529,13 @@ typedef struct {
 /*
  * One forward-Euler step of the flocking dynamics (App. B): R_i += dt (v N_i - dE/dR_i), theta_i -= dt dE/dtheta_i,
  * both from the state at the start of the step.  nl must be a full list (segment 0, any lane count) with
- * r_list >= max(R_align, R_avoid, R_coh), valid for pos (nl_update after each step keeps it so: the call marks on
+ * r_list - skin >= max(R_align, R_avoid, R_coh), valid for pos (nl_update after each step keeps it so: the call marks on
  * the device when a boid has moved more than skin/2 from nl->pos_ref).  The list's lanes (W) set how many GPU
  * lanes share a boid.  work is device scratch of 8 N floats owned by the caller (8-byte aligned); after the call
  * work[8i + 0..2] holds (dE/dx_i, dE/dy_i, dE/dtheta_i) of the step and work[8i + 6..7] the heading N_i it used.  box->dim must
  * be 2.  pred may be NULL (no predators); with predators, work[8i + 0..2] includes the flee term.  With N = 0 nothing
- * is enqueued (predators do not move either) and the boid arrays may be NULL.  Errors:
+ * is enqueued for boids (their arrays may be NULL) and the predators still take their step: they swim at speed v
+ * and descend their obstacle terms, with empty chase sums.  Errors:
  * MD_ERR_ARG (missing pointer, dim, list or parameters out of range, 8 N >= 2^31), MD_ERR_BOX (an edge not above
  * 2 r_list, or not above 2 R_flee or 2 R_chase).
  */

@@ -2097,7 +2097,7 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
     bool multi = pot->n_species > 1;
     if (multi && !species) return MD_ERR_ARG;
     if (nl && !nl_ok(nl, N)) return MD_ERR_ARG;
-    if (nl && nl->r_list < md_max_cutoff(pot)) return MD_ERR_ARG;
+    if (nl && !md_list_covers(nl, md_max_cutoff(pot))) return MD_ERR_ARG;
     if (!box_ok(box, nl ? nl->r_list : md_max_cutoff(pot))) return MD_ERR_BOX;
     DevBox b;
     if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
@@ -2145,7 +2145,7 @@ static md_status run_checks(md_ctx *ctx, const md_box *box, const md_potential *
     if (pot->n_species > 1 && !species) return MD_ERR_ARG;
     st = check_list(ctx, box, nl, N, b);
     if (st != MD_OK) return st;
-    if (nl->r_list < md_max_cutoff(pot)) return MD_ERR_ARG;
+    if (!md_list_covers(nl, md_max_cutoff(pot))) return MD_ERR_ARG;
     if (nl->capacity > ctx->cap_cap || nl->lanes > ctx->W_cap) return MD_ERR_CAPACITY;
     return MD_OK;
 }

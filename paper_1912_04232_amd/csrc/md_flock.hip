@@ -39,7 +39,7 @@ struct FlockArgs {
     float s[2], inv_s[2], L[2];
     md_flock_params fp;
     float inv_R_align, inv_R_avoid, inv_alpha;
-    int ialpha;  // alpha when it is an integer in [1, 8] (powers by multiplication), else 0
+    int ialpha;  // alpha when it is an integer in [1, 8] (powers by multiplication), else -1
     float *work;
     int P;                 // predators (0: none)
     uint32_t *ppos;        // [P][2]
@@ -49,10 +49,11 @@ struct FlockArgs {
 
 
 
-// t^e for t in (0, 1]: repeated products when the exponent is a small integer, else exp2(e log2 t)
+// t^e for t in [0, 1]: repeated products when the exponent is a small integer (ie >= 0; t^0 = 1 even at t = 0),
+// else exp2(e log2 t) for a non-integer e > 0 (ie < 0), which is 0 at t = 0
 __device__ __forceinline__ float tpow(float t, int ie, float e)
 {
-    if (ie > 0) {
+    if (ie >= 0) {
         float p = 1.0f;
         for (int k = 0; k < ie; ++k) p *= t;
         return p;
@@ -352,8 +353,10 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
     if (fp->n_obstacles < 0 || fp->n_obstacles > 16 || !(fp->alpha >= 1.0f) || !(fp->R_align > 0.0f) ||
         !(fp->R_avoid > 0.0f) || !(fp->R_coh > 0.0f) || !isfinite(fp->dt))
         return MD_ERR_ARG;
+    // between rebuilds a boid moves up to skin/2 from its reference position, so the list holds every pair within
+    // r_list - skin; that must cover the longest interaction range
     float rmax = fmaxf(fp->R_align, fmaxf(fp->R_avoid, fp->R_coh));
-    if (nl->r_list < rmax || (int64_t)N * 8 >= ((int64_t)1 << 31)) return MD_ERR_ARG;
+    if (!md_list_covers(nl, rmax) || (int64_t)N * 8 >= ((int64_t)1 << 31)) return MD_ERR_ARG;
     int W = nl->lanes;
     if (W != 1 && W != 2 && W != 4 && W != 8) return MD_ERR_ARG;
     FlockArgs a{};
@@ -379,7 +382,6 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         a.R_chase = pred->R_chase;
         a.v_pred = pred->v;
     }
-    if (N == 0) return MD_OK;
     a.pos = pos;
     a.theta = theta;
     a.N = N;
@@ -390,10 +392,12 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
     a.inv_R_align = 1.0f / fp->R_align;
     a.inv_R_avoid = 1.0f / fp->R_avoid;
     a.inv_alpha = 1.0f / fp->alpha;
-    a.ialpha = (fp->alpha == floorf(fp->alpha) && fp->alpha <= 8.0f) ? (int)fp->alpha : 0;
+    a.ialpha = (fp->alpha == floorf(fp->alpha) && fp->alpha <= 8.0f) ? (int)fp->alpha : -1;
     a.work = work;
     hipStream_t s = (hipStream_t)stream;
     const int g1 = nblocks(N), gW = nblocks((int64_t)N * W);
+    // with no boids only the predators step: they still swim and feel the obstacles (their chase sums are empty)
+    if (N > 0) {
     hipLaunchKernelGGL(k_flock_heading, dim3(g1), dim3(kBlock), 0, s, a);
     switch (W) {
     case 1:
@@ -413,6 +417,7 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         hipLaunchKernelGGL(k_flock_gather<8>, dim3(gW), dim3(kBlock), 0, s, a);
         break;
     }
+    }
     if (a.P > 0) {
         // slices per predator: enough workgroups to fill the chip, within the context's partials buffer
         const int64_t cap = (int64_t)4 * md_partials_blocks() / (3 * (int64_t)a.P);
@@ -420,7 +425,8 @@ md_status flock_step(md_ctx *ctx, const md_box *box, uint32_t *pos, float *theta
         hipLaunchKernelGGL(k_pred_partial, dim3(B, a.P), dim3(kBlock), 0, s, a, ctx->partials, B);
         hipLaunchKernelGGL(k_pred_finish, dim3(a.P), dim3(64), 0, s, a, (const double *)ctx->partials, B);
     }
-    hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
+    if (N > 0)
+        hipLaunchKernelGGL(k_flock_move, dim3(g1), dim3(kBlock), 0, s, a, pos, nl->pos_ref, 0.5f * nl->skin, ctx->ctl);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

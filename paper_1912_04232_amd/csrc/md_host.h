@@ -54,3 +54,9 @@ int md_partials_blocks();
 bool md_make_pot(const md_potential *pot, md::DevPot &p);
 // Largest interaction range of the potential (LJ cutoff, or the largest soft-sphere sigma).
 float md_max_cutoff(const md_potential *pot);
+// A list is used while every particle stays within skin/2 of its reference position, so it holds every pair
+// within r_list - skin: true when that covers `range` (up to float rounding of r_list and skin).
+inline bool md_list_covers(const md_nlist *nl, float range)
+{
+    return (double)nl->r_list - (double)nl->skin >= (double)range * (1.0 - 1e-6);
+}

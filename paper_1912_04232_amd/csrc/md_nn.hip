@@ -854,7 +854,7 @@ static md_status nn_checks(md_ctx *ctx, const md_box *box, const md_nn_params *q
     if (!nl || nl->N != N || !nl->idx || !nl->count || !(nl->lanes == 1 || nl->lanes == 2 || nl->lanes == 4 ||
                                                          nl->lanes == 8))
         return MD_ERR_ARG;
-    if (nl->r_list < q->r_c) return MD_ERR_ARG;
+    if (!md_list_covers(nl, q->r_c)) return MD_ERR_ARG;
     for (int k = 0; k < 3; ++k)
         if (!(nl->r_list < 0.5f * box->L[k])) return MD_ERR_BOX;
     memset(&b, 0, sizeof(b));

@@ -268,14 +268,21 @@ def test_flock_with_predators_graph_replay_matches_eager(md):
         assert torch.equal(a.ppos, b.ppos) and torch.equal(a.ptheta, b.ptheta)
 
 
-def test_flock_step_without_boids_is_a_no_op(md):
-    """N = 0: the call succeeds with empty (NULL) boid arrays and enqueues nothing; predators stay put."""
+def test_flock_step_without_boids_moves_predators_like_the_oracle(md, fl):
+    """N = 0: the call succeeds with empty (NULL) boid arrays; a predator still swims at its speed and descends its
+    obstacle terms (its chase sums are empty), as the oracle's two-player step does with no boids."""
     import torch
     ctx = md.Context()
-    box = md.Box((32.0, 32.0), 2)
+    L = 32.0
+    box = md.Box((L, L), 2)
     nl = md.NeighborList(0, 2, 8, 3.5, 0.5, ctx.device, 8, 4)
     fp = md.c_flock_params(**{k: float(v) for k, v in md.FLOCK_DEFAULTS.items()})
-    up = torch.tensor([[123, 456]], dtype=torch.int32, device=ctx.device)
+    # one obstacle of radius 5 centred 2 units from the predator, so the obstacle term acts
+    fp.n_obstacles = 1
+    u0 = np.array([[1 << 31, 1 << 30]], dtype=np.uint32)
+    x0 = positions(u0, L)
+    fp.obstacles[0:3] = (float(x0[0, 0] + 2.0), float(x0[0, 1] + 1.0), 5.0)
+    up = md.to_device_u32(u0, ctx.device)
     thp = torch.tensor([0.5], dtype=torch.float32, device=ctx.device)
     pred = md.c_flock_predators(P=1, **{k: float(v) for k, v in md.PREDATOR_DEFAULTS.items()})
     pred.pos, pred.theta = up.data_ptr(), thp.data_ptr()
@@ -283,4 +290,34 @@ def test_flock_step_without_boids_is_a_no_op(md):
     empty_f = torch.empty(0, dtype=torch.float32, device=ctx.device)
     md.flock_step(ctx, box, empty_u, empty_f, nl, fp, torch.empty((0, 8), device=ctx.device), pred)
     torch.cuda.synchronize()
-    assert up.tolist() == [[123, 456]] and thp.tolist() == [0.5]
+    p = fl.FlockParams(**{k: float(np.float32(v)) for k, v in md.FLOCK_DEFAULTS.items()})
+    q = fl.PredatorParams(**{k: float(np.float32(v)) for k, v in md.PREDATOR_DEFAULTS.items()})
+    obs = np.array([fp.obstacles[0:3]], dtype=np.float64)
+    _, _, Rp, Tp = fl.step_with_predators(np.zeros((0, 2)), np.zeros(0), x0, np.array([0.5]), np.array([L, L]), p, q,
+                                          obs[:, :2], obs[:, 2])
+    got = positions(md.from_device_u32(up), L)
+    moved = image_diff(got, x0, L).max()
+    say("predator moved", moved, "dR", image_diff(got, Rp, L).max(), "dtheta", abs(float(thp[0]) - Tp[0]))
+    assert moved > 0.01
+    assert image_diff(got, Rp, L).max() < 1e-5 and abs(float(thp[0]) - Tp[0]) < 1e-5
+
+
+def test_flock_alpha_one_matches_oracle(md, fl):
+    """alpha = 1 (the cutoff function is linear): t^(alpha - 1) = 1 even where t rounds to 0, no NaN reaches the
+    positions; gradients of the first step and the state after one step against the oracle."""
+    L = 48.0
+    f, u, theta, obs = make(md, 900, L, 31, 2, {"alpha": 1.0})
+    p = oracle_params(fl, md, f)
+    init, update = md.flocking(f)
+    init()
+    update(1)
+    gR, gT = fl.gradients(positions(u, L), theta, np.array([L, L]), p, obs[:, :2], obs[:, 2])
+    w = f.work.cpu().numpy().astype(np.float64)
+    assert np.isfinite(w).all()
+    scale = max(np.abs(gR).max(), np.abs(gT).max())
+    e = grad_err(w, gR, gT, cohesion_dn(positions(u, L), L, p.R_coh), p.J_coh, scale)
+    say("alpha 1: gradient err / bound", e)
+    assert e < 1.0
+    R, T = fl.step(positions(u, L), theta, np.array([L, L]), p, obs[:, :2], obs[:, 2])
+    dR = image_diff(positions(md.from_device_u32(f.pos), L), R, L).max()
+    assert dR < 1e-3

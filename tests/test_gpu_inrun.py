@@ -1,0 +1,167 @@
+"""The benchmarked velocity-Verlet path through its device-side rebuilds, against the FP64 oracle.
+
+Inside a verlet_step call the list is rebuilt on the device (bins refreshed from the previous bins, rows of a
+second list generation built from them) whenever a particle gets close to moving skin/2.  These tests run that
+path through several rebuilds and compare what it leaves behind with the oracle:
+
+- the rows of the list in use are the brute-force r_list sets at the list's own reference positions, bit for bit;
+- the forces at the final positions are the oracle's pair sums (rel-L2 <= 1e-5);
+- the total energy over 100 steps from a relaxed FCC start stays within 1e-4 eps per particle (Sec. 3.3.1).
+
+Inputs are seeded (jittered lattices and random insertion with Maxwell velocities); the oracle is handed the
+positions the GPU state holds at that point, which is how a checker of a GPU result is used here: the oracle's
+own arithmetic takes nothing else from the HIP path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_04232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1912_04232_amd import md as m
+    m.load()
+    return m
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def lj_system(md, u, v, L, skin=0.3):
+    box = md.Box((L, L, L), 3)
+    pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=2.5)
+    return md.System(box, pot, u, v, skin=skin)
+
+
+def lj_oracle_pot(orc):
+    return orc.Potential("lj", np.ones((1, 1)), np.ones((1, 1)), r_cut=2.5)
+
+
+def check_list_in_use(md, orc, s, L, rows=None):
+    """Rows of the list the system holds now against the brute-force set at its reference positions."""
+    ref = md.from_device_u32(s.nl.pos_ref)
+    got = s.nl.rows()
+    want = orc.neighbors(ref, [L, L, L], s.nl.r_list, rows=rows)
+    ids = range(s.N) if rows is None else rows
+    for q, i in enumerate(ids):
+        g = np.sort(got[i])
+        assert np.array_equal(g, want[q]), (int(i), g[:8], want[q][:8])
+    return ref
+
+
+def check_forces(md, orc, s, L, rows=None):
+    u = md.from_device_u32(s.pos)
+    Fo, _, _ = orc.pair_rows(orc.decode(u, [L, L, L]), [L, L, L], lj_oracle_pot(orc), rows=rows)
+    F = s.force.cpu().numpy()
+    if rows is not None:
+        F = F[rows]
+    err = rel_l2(F, Fo)
+    assert err <= F_TOL, err
+    return err
+
+
+def run_and_check(md, orc, s, L, calls, steps, rows=None):
+    """Run `calls` verlet_step calls of `steps` steps; after each, compare the list in use and the forces with the
+    oracle.  Returns how many of the checked lists were built inside a run (reference positions equal to neither
+    the start of that call nor any earlier list's)."""
+    init, update = md.nve(s, 0.005)
+    init()
+    seen = {md.from_device_u32(s.nl.pos_ref).tobytes()}
+    inrun = 0
+    rebuilds = 0
+    for c in range(calls):
+        start = md.from_device_u32(s.pos).tobytes()
+        update(steps)
+        f = s.last_flags
+        rebuilds += int(f[md.FLAG_REBUILDS])
+        ref = check_list_in_use(md, orc, s, L, rows)
+        key = ref.tobytes()
+        if key != start and key not in seen:
+            inrun += 1
+        seen.add(key)
+        err = check_forces(md, orc, s, L, rows)
+        say(f"call {c}: rebuild launches {int(f[md.FLAG_REBUILDS])}, in-run lists checked so far {inrun}, "
+            f"force rel-L2 {err:.2e}")
+    return inrun, rebuilds
+
+
+@pytest.mark.parametrize("case", ["lj2000", "lj3333_ragged"])
+def test_inrun_rebuilt_rows_and_forces_match_oracle(md, orc, case):
+    """Small systems, every row: N = 2000 at density 0.84 and a ragged N = 3333 (cells hold uneven counts), random
+    insertion with Maxwell velocities at T = 1, five calls of 40 steps through several device-side rebuilds."""
+    N, seed = (2000, 51) if case == "lj2000" else (3333, 77)
+    L = inputs.box_for_density(N, 0.84)
+    u = inputs.random_insertion_torus(N, L, 3, 0.8, seed)
+    v = inputs.maxwell_velocities(N, 3, 1.0, seed + 1)
+    s = lj_system(md, u, v, L)
+    say("in-run rebuild parity", case)
+    inrun, rebuilds = run_and_check(md, orc, s, L, 5, 40)
+    assert inrun >= 2 and rebuilds >= 4, (inrun, rebuilds)
+
+
+def test_inrun_rebuilt_rows_and_forces_match_oracle_256k(md, orc):
+    """The benchmark's size and launch configuration: N = 256000 FCC at density 0.84 moved by seeded offsets of up to
+    0.1, Maxwell velocities at T = 1, lanes chosen as the benchmark's default; three calls of 25 steps, each through
+    device-side rebuilds.  600 sampled rows bit-exact at the list's reference positions and the sampled forces at
+    the final positions within 1e-5."""
+    cfg = inputs.lj_large()
+    L = cfg["L"][0]
+    u = inputs.jittered_torus(cfg["u"], cfg["L"], 0.1, 3101)
+    s = lj_system(md, u, cfg["v"], L)
+    rows = np.sort(np.random.default_rng(5).choice(cfg["N"], 600, replace=False))
+    say("in-run rebuild parity at N = 256000, lanes", s.nl.lanes)
+    inrun, rebuilds = run_and_check(md, orc, s, L, 3, 25, rows)
+    assert inrun >= 2 and rebuilds >= 6, (inrun, rebuilds)
+
+
+def test_verlet_energy_conservation_relaxed_fcc(md):
+    """NVE from a relaxed start (FCC at density 0.84, every force zero; Maxwell velocities at T = 1): over 100 steps
+    at dt = 0.005 the total energy stays within 1e-4 eps per particle of its start (the bound the FP64 oracle is
+    pinned to), checked after every 10 steps."""
+    cfg = inputs.lj_large(n_cells=8)   # 2048 particles
+    L = cfg["L"][0]
+    s = lj_system(md, cfg["u"], cfg["v"], L)
+    init, update = md.nve(s, 0.005)
+    init()
+    E0 = s.potential_energy() + s.kinetic_energy()
+    worst = 0.0
+    for _ in range(10):
+        update(10)
+        worst = max(worst, abs(s.potential_energy() + s.kinetic_energy() - E0))
+    say("relaxed FCC, 100 steps: max |dE|/N", worst / s.N)
+    assert worst / s.N < 1e-4
+
+
+def test_kinetic_energy_and_sum_against_numpy(md):
+    """md_kinetic_energy = 1/2 sum v^2 and md_sum against numpy's float64 sums (math.fsum order-free reference)."""
+    import math
+
+    import torch
+    ctx = md.Context()
+    rng = np.random.default_rng(11)
+    for n, dim in ((1, 3), (1000, 3), (65537, 2), (300001, 3)):
+        v = rng.standard_normal((n, dim)).astype(np.float32)
+        out = torch.zeros(1, dtype=torch.float64, device=ctx.device)
+        md.kinetic_energy(ctx, torch.as_tensor(v, device=ctx.device), out)
+        want = 0.5 * math.fsum((v.astype(np.float64) ** 2).ravel().tolist())
+        assert float(out.item()) == pytest.approx(want, rel=1e-12, abs=1e-300)
+        x = rng.standard_normal(n * dim)
+        md.md_sum(ctx, torch.as_tensor(x, device=ctx.device), out)
+        assert float(out.item()) == pytest.approx(math.fsum(x.tolist()), rel=1e-10, abs=1e-9)
