@@ -54,6 +54,13 @@ __device__ __forceinline__ uint4 rec16(const uint32_t *mem, uint32_t slot)
     return *(const uint4 *)((const char *)mem + slot * 16u);
 }
 
+// Buffer resource over `bytes` bytes at `base` (raw addressing: loads at byte offsets at or past `bytes` return
+// 0 and stores there are dropped, instead of touching memory).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 template <int D>
 __device__ __forceinline__ void store_rec(uint32_t *mem, uint32_t slot, const uint32_t *u, int j)
 {
@@ -74,13 +81,20 @@ struct ListGen {
 struct ListParams {
     int32_t N, cap, W, capW, M;
     int32_t seg;             // 0, or particles per independent system (cells of system s are s*C .. s*C + C-1)
+    int32_t cells;           // cells of the list (C per system times the systems of a segmented list)
+    int32_t pk;              // 1: candidates are tested on packed 16-bit coordinates (isotropic boxes)
+    int32_t pk_lo, pk_hi;    // packed test: R16 < pk_lo is a neighbor, R16 >= pk_hi is not, else the double test
     float rl2f_lo, rl2f_hi;  // float guard band around r_list^2
     double rl2;              // (double)r_list * (double)r_list
-    float cull2;             // a stencil cell farther than this (squared) from the particle holds no neighbor
     float half_skin;         // skin / 2
     float kappa;             // pipelined rebuild starts when disp + kappa * (last step + dt^2 |F|) > skin/2
 };
 
+
+// Running row lengths a building wave keeps in LDS: one per member of a bin (bins hold at most 252).
+constexpr int kMaxPerCellPad = 256;
+// Predicates of the lane-mask compare builtins (LLVM's numbering).
+constexpr int kFCmpOLT = 4, kFCmpOLE = 5, kICmpNE = 33, kICmpSGE = 39, kICmpSLT = 40;
 
 enum { M_IDLE = 0, M_BIN = 1, M_BUILD = 2 };
 // Control words (device).  Verlet: ctl[2*slot] = mode and ctl[2*slot+1] = generation of step s at
@@ -248,10 +262,11 @@ __global__ void k_cs_place(CountSort cs, int N, const int32_t *gate)
 }
 
 // Bin records in index order without sorting: particle i's rank in its cell is the number of members with a
-// smaller index, which makes the bins (and so the rows built from them) deterministic.
+// smaller index, which makes the bins (and so the rows built from them) deterministic.  A particle that does not
+// fit its bin (the cell-overflow flag is raised) gets empty sub-rows, so no row length is left undefined.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_cs_rank_fill(const uint32_t *__restrict__ pos, int N, CountSort cs,
-                                                         Bins bins, int M, const int32_t *gate)
+                                                         Bins bins, int M, int32_t *count, int W, const int32_t *gate)
 {
     if (gate_closed(gate)) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
@@ -264,250 +279,50 @@ __global__ __launch_bounds__(kBlock) void k_cs_rank_fill(const uint32_t *__restr
         uint32_t u[D];
         load_pos<D>(pos, i, u);
         store_rec<D>(bins.mem, (uint32_t)(c * M + rank), u, i);
+    } else {
+        for (int l = 0; l < W; ++l) count[(size_t)i * W + l] = 0;
     }
 }
 
-// Stencil table of particle i at reference position ui: the stencil cells that can hold a neighbor, in
-// stencil order, packed as (cell << 8) | count at tab[e * ts].  A cell is left out when its slab distance
-// from the particle (the distance to the faces it lies beyond) already exceeds r_list, or when it is empty.
-// Every lane of the particle computes the table; only lanes with `write` store it.  Returns the number of
-// entries; `chunks` receives the number of 4-record chunks they hold.
-template <int D>
-__device__ __forceinline__ int stencil_table(int i, const uint32_t *ui, const DevBox &b, const Bins &bins,
-                                             const ListParams &lp, uint32_t *tab, int ts, bool write, int &chunks)
-{
-    constexpr int NST = D == 3 ? 27 : 9;
-    int cc[3][3];
-    float lo2[3], hi2[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        cc[q][0] = cc[q][1] = cc[q][2] = 0;
-        lo2[q] = hi2[q] = 0.0f;
-    }
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-        uint64_t pr = (uint64_t)ui[q] * (uint64_t)b.nc[q];
-        int c = (int)(pr >> 32);
-        float f = (float)(uint32_t)pr * 2.3283064365386963e-10f;  // position within the cell, [0, 1)
-        float dl = f * b.cw[q], dh = (1.0f - f) * b.cw[q];
-        lo2[q] = dl * dl;
-        hi2[q] = dh * dh;
-        cc[q][0] = wrapc(c - 1, b.nc[q]);
-        cc[q][1] = c;
-        cc[q][2] = wrapc(c + 1, b.nc[q]);
-    }
-    const int cbase = lp.seg > 0 ? (i / lp.seg) * b.C : 0;  // first cell of the particle's system
-    int cell[NST], m[NST];
-#pragma unroll
-    for (int t = 0; t < NST; ++t) {
-        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = D == 3 ? t / 9 - 1 : 0;
-        bool ok = ox >= b.lo[0] && ox <= b.hi[0] && oy >= b.lo[1] && oy <= b.hi[1];
-        if (D == 3) ok = ok && oz >= b.lo[2] && oz <= b.hi[2];
-        float g = (ox < 0 ? lo2[0] : ox > 0 ? hi2[0] : 0.0f) + (oy < 0 ? lo2[1] : oy > 0 ? hi2[1] : 0.0f) +
-                  (oz < 0 ? lo2[2] : oz > 0 ? hi2[2] : 0.0f);
-        ok = ok && g <= lp.cull2;
-        cell[t] = cbase + cc[0][ox + 1] + b.nc[0] * (cc[1][oy + 1] + b.nc[1] * cc[2][oz + 1]);
-        m[t] = ok ? bins.cnt[cell[t]] : 0;
-    }
-    int ne = 0;
-    chunks = 0;
-#pragma unroll
-    for (int t = 0; t < NST; ++t) {
-        if (m[t] > 0) {
-            if (write) tab[ne * ts] = ((uint32_t)cell[t] << 8) | (uint32_t)m[t];
-            ++ne;
-            chunks += (m[t] + 3) >> 2;
-        }
-    }
-    return ne;
-}
-
-// Inclusive prefix sum of x over the W lanes of a particle (W <= 8: groups lie within DPP rows of 16 lanes),
-// by DPP row shifts instead of LDS permutes; tot = the group's sum.  Every lane of a group is active together.
-template <int W>
-__device__ __forceinline__ int group_scan(int x, int l, int &tot)
-{
-    int incl = x;
-    if constexpr (W >= 2) {
-        int v = __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);  // row_shr:1
-        incl += l >= 1 ? v : 0;
-    }
-    if constexpr (W >= 4) {
-        int v = __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);  // row_shr:2
-        incl += l >= 2 ? v : 0;
-    }
-    if constexpr (W >= 8) {
-        int v = __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);  // row_shr:4
-        incl += l >= 4 ? v : 0;
-    }
-    if constexpr (W == 1) tot = incl;
-    else if constexpr (W == 2) tot = __builtin_amdgcn_update_dpp(0, incl, 0xF5, 0xf, 0xf, false);  // quad_perm 1,1,3,3
-    else if constexpr (W == 4) tot = __builtin_amdgcn_update_dpp(0, incl, 0xFF, 0xf, 0xf, false);  // quad_perm 3,3,3,3
-    else tot = __shfl(incl, W - 1, W);
-    return incl;
-}
-
-// A lane's place in the stencil table's chunk sequence: entry e, chunk c within it, the entry's first slot cb
-// and member count mc; `have` is false past the last chunk.
-struct ChunkCursor {
-    int e, c, mc;
-    uint32_t cb;
-    bool have;
-};
-
-// The four records of a chunk as separate registers.
-struct Chunk4 {
-    uint32_t x[4], y[4], z[4], j[4];
-};
-
-// The cursor's chunk, W chunks on (entries of the table are ne words apart by ts).
-template <int W>
-__device__ __forceinline__ ChunkCursor chunk_next(ChunkCursor k, const uint32_t *tab, int ts, int ne, uint32_t M)
-{
-    k.c += W;
-    if (k.have) {
-        while (true) {
-            int nch = (k.mc + 3) >> 2;
-            if (k.c < nch) break;
-            k.c -= nch;
-            ++k.e;
-            if (k.e >= ne) {
-                k.have = false;
-                break;
-            }
-            uint32_t en = tab[k.e * ts];
-            k.mc = (int)(en & 255u);
-            k.cb = (en >> 8) * M;
-        }
-    }
-    return k;
-}
-
-// Loads the cursor's chunk (a cursor past the end re-reads slot 0, always mapped): one address, four offsets.
-__device__ __forceinline__ void chunk_load(const ChunkCursor &k, const uint32_t *mem, Chunk4 &r)
-{
-    const uint4 *p = (const uint4 *)mem + (k.have ? k.cb + 4u * (uint32_t)k.c : 0u);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint4 v = p[q];
-        r.x[q] = v.x;
-        r.y[q] = v.y;
-        r.z[q] = v.z;
-        r.j[q] = v.w;
-    }
-}
-
-// Row of particle i (Sec. 3.2.3) built by its W lanes; lane l of the particle calls this with the particle's
-// stencil table (ne entries holding `chunks` chunks of four 16-byte member records, one cache line each).
+// ------------------------------------------------------------------------------------------------
+// neighbor rows (Sec. 3.2.3): one wave per cell
 //
-// The listed cells' records form one flat sequence of chunks; lane l tests chunks l, l + W, l + 2W, ...,
-// loading its next chunk while it tests the current one (two register sets in turn), so the walk does not
-// stall at cell boundaries.  Accepted neighbors are numbered in sequence order (a prefix sum over the W lanes
-// after each round) and dealt round-robin to the interleaved sub-rows: neighbor n goes to sub-row n % W at
-// position n / W, so the W lanes that later share the row differ by at most one entry.  In a box with one scale
-// s along every axis, r^2 is compared in integer units (the thresholds divided by s^2).  Returns the row length
-// (the same in every lane of the particle; it may exceed the capacity, and only the first `cap` entries are
-// stored).
-template <int D, int W>
-__device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
-                                         const ListParams &lp, int32_t *__restrict__ idx, const uint32_t *tab, int ts,
-                                         int ne, int chunks)
+// A wave takes one cell c at a time.  The candidates of every particle of c are the same: the members of c's stencil
+// cells, numbered in stencil order (x fastest, then y, then z) and then in bin order.  The wave holds up to
+// kSlots x 64 of them in registers, one per lane and slot, and walks the particles of c one after the other, the
+// particle's own record in scalar registers.  Per particle and slot the test is a few vector instructions whose
+// comparison writes a lane mask directly; accepted candidates are numbered in sequence order by counting the mask
+// bits of the lanes below (mbcnt) and dealt round-robin to the W interleaved sub-rows (neighbor n to sub-row n % W at
+// position n / W), so rows are deterministic and the W lanes that later walk a row differ by at most one entry.
+//
+// Filter.  In a box with one scale along every axis the candidate test runs on the upper 16 bits of each torus
+// coordinate, two coordinates packed per register: a packed 16-bit subtraction wraps modulo 2^16, which is the
+// nearest image in units of u = L / 2^16, and a 16-bit dot product with 32-bit saturating accumulation gives
+// R16 = sum d_k^2.  With e_k the exact displacement in units of u, |d_k - e_k| < 1 while |e_k| < 32767, so
+// |R16 - R| < 2 sqrt(D R) + D for R = sum e_k^2.  ListParams.pk_lo / pk_hi bound that error around
+// T = r_list^2 / u^2 (host, double): R16 < pk_lo means the pair is in the list, R16 >= pk_hi that it is not, and
+// the rare candidates in between take the defining double expression.  Other boxes use single-precision
+// displacements with a relative guard band of 1e-5 around r_list^2, again with the double expression in the band.
+
+// Candidates a wave holds at once are NS x 64 (registers per lane: about 5 per slot).  The standalone build holds 8
+// slots with the packed filter; the step kernel holds 4, which keeps it within the registers of its force loop.
+
+__device__ __forceinline__ uint32_t pack_hi16(uint32_t a, uint32_t b)
 {
-    const uint32_t M = (uint32_t)lp.M;
-    const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
-    const bool iso = b.iso != 0;
-    const float s2 = b.s[0] * b.s[0];
-    const float lo = iso ? lp.rl2f_lo / s2 : lp.rl2f_lo, hi = iso ? lp.rl2f_hi / s2 : lp.rl2f_hi;
-    ChunkCursor ka{0, l, 0, 0u, false};
-    while (ka.e < ne) {
-        uint32_t en = tab[ka.e * ts];
-        ka.mc = (int)(en & 255u);
-        int nch = (ka.mc + 3) >> 2;
-        if (ka.c < nch) {
-            ka.cb = (en >> 8) * M;
-            ka.have = true;
-            break;
-        }
-        ka.c -= nch;
-        ++ka.e;
-    }
-    int n = 0;
-    auto test = [&](const Chunk4 &r, const ChunkCursor &k) {
-        int bits = 0, band = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
-            float r2 = 0.0f;
-            if (iso) {
-#pragma unroll
-                for (int z = 0; z < D; ++z) {
-                    float d = (float)(int32_t)(ui[z] - uj[z]);
-                    r2 = __builtin_fmaf(d, d, r2);
-                }
-            } else {
-#pragma unroll
-                for (int z = 0; z < D; ++z) {
-                    float d = tdisp(ui[z], uj[z], b.s[z]);
-                    r2 = __builtin_fmaf(d, d, r2);
-                }
-            }
-            bits |= r2 < lo ? 1 << q : 0;
-            band |= r2 >= lo && r2 <= hi ? 1 << q : 0;
-        }
-        // candidates within the float guard band of r_list^2 (rare) take the defining double expression; the
-        // branch is taken by the whole wave or not at all, so the common path carries no double arithmetic
-        if (__ballot(band != 0) != 0) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (band & (1 << q)) {
-                    const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
-                    double r2d = 0.0;
-#pragma unroll
-                    for (int z = 0; z < D; ++z) {
-                        double d = tdisp_d(ui[z], uj[z], b.sd[z]);
-                        r2d = __dadd_rn(r2d, __dmul_rn(d, d));
-                    }
-                    bits |= r2d < lp.rl2 ? 1 << q : 0;
-                }
-            }
-        }
-        // records of the chunk that are members (a cell's last chunk may be partial), other than i itself
-        const int left = k.have ? k.mc - 4 * k.c : 0;
-        bits &= left >= 4 ? 15 : (1 << max(left, 0)) - 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bits &= (int)r.j[q] != i ? 15 : ~(1 << q);
-        // numbering across the particle's lanes: this round's chunks are in lane order
-        const int a = __popc(bits);
-        int tot;
-        const int incl = group_scan<W>(a, l, tot);
-        uint32_t slot = (uint32_t)(n + incl - a);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (bits & (1 << q)) {
-                if (slot < (uint32_t)lp.cap) {
-                    // byte offset of entry slot (below 4 GiB, checked on the host)
-                    uint32_t off = slot / W * row_bytes + ((uint32_t)i * W + slot % W) * 4u;
-                    *(int32_t *)((char *)idx + off) = (int)r.j[q];
-                }
-                ++slot;
-            }
-        }
-        n += tot;
-    };
-    const int iters = (chunks + W - 1) / W;  // the same in every lane of the particle
-    Chunk4 A, B;
-    chunk_load(ka, bins.mem, A);
-    int it = 0;
-    for (; it + 2 <= iters; it += 2) {
-        const ChunkCursor kb = chunk_next<W>(ka, tab, ts, ne, M);
-        chunk_load(kb, bins.mem, B);
-        test(A, ka);
-        ka = chunk_next<W>(kb, tab, ts, ne, M);
-        chunk_load(ka, bins.mem, A);
-        test(B, kb);
-    }
-    if (it < iters) test(A, ka);
-    return n;
+    return (a >> 16) | (b & 0xffff0000u);
+}
+
+// R16 of a packed candidate (cxy, cz) against the particle's packed (pxy, pz): two wrapping 16-bit subtractions and
+// two saturating 16-bit dot products.  cz / pz hold z in 3D and 0 in 2D, and the candidate's spare component (the
+// upper half in 3D, the lower half in 2D) marks a lane past the last candidate.
+__device__ __forceinline__ int r2_packed(uint32_t cxy, uint32_t cz, uint32_t pxy, uint32_t pz)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    typedef short i16x2 __attribute__((ext_vector_type(2)));
+    const u16x2 dxy = __builtin_bit_cast(u16x2, cxy) - __builtin_bit_cast(u16x2, pxy);
+    const u16x2 dz = __builtin_bit_cast(u16x2, cz) - __builtin_bit_cast(u16x2, pz);
+    const int r2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, dxy), __builtin_bit_cast(i16x2, dxy), 0, true);
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, dz), __builtin_bit_cast(i16x2, dz), r2, true);
 }
 
 // Sub-row length of lane l for a row of n entries dealt round-robin over W sub-rows.
@@ -517,36 +332,197 @@ __device__ __forceinline__ int sub_count(int n, int l)
     return (n + W - 1 - l) / W;
 }
 
-// Rows of every particle from the bins, W lanes per particle; pos_ref = the positions the rows were built from.
-template <int D, int W>
+// Rows of every particle of cell gc (a global cell number: system gc / C of a segmented list, cell gc % C in it)
+// from the bins, by the calling wave.  ncnt is the wave's LDS array of running row lengths (used when the stencil
+// holds more candidates than the wave's slots).  Returns the longest row of the cell.
+template <int D, int W, bool PK, int NS, bool SMALL_ROWS>
+__device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListParams &lp, int32_t *__restrict__ idx,
+                          int32_t *__restrict__ count, int *ncnt)
+{
+    const int lane = threadIdx.x & 63;
+    const int sys = gc / b.C, c = gc - sys * b.C, cbase = sys * b.C;
+    const int cx = c % b.nc[0], cy = (c / b.nc[0]) % b.nc[1], cz = D == 3 ? c / (b.nc[0] * b.nc[1]) : 0;
+    const int nst = stencil_size<D>(b);
+    int src = 0, m = 0;
+    if (lane < nst) {
+        src = cbase + stencil_cell<D>(b, cx, cy, cz, lane);
+        m = bins.cnt[src];
+    }
+    int incl = m;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    const int excl = incl - m;
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, nst - 1));
+    const int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1;
+    const int tc = -b.lo[0] + n0 * (-b.lo[1] + n1 * (D == 3 ? -b.lo[2] : 0));  // the cell itself in stencil order
+    const int mc = __builtin_amdgcn_readfirstlane(__shfl(m, tc));
+    if (mc == 0) return 0;
+    const uint32_t M = (uint32_t)lp.M;
+    const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
+    // list entries through a range-checked buffer: an entry past the capacity (position >= capacity / W) lies past
+    // the end of the array, and the store is dropped (N * capacity * 4 < 2^32, checked on the host)
+    const __amdgpu_buffer_rsrc_t ridx = raw_rsrc(idx, (uint32_t)lp.N * (uint32_t)lp.cap * 4u);
+    const bool iso = b.iso != 0;
+    const float s2 = b.s[0] * b.s[0];
+    const float flo = iso ? lp.rl2f_lo / s2 : lp.rl2f_lo, fhi = iso ? lp.rl2f_hi / s2 : lp.rl2f_hi;
+    int longest = 0;
+    for (int base = 0; base < total; base += NS * 64) {
+        const bool last_batch = base + NS * 64 >= total;
+        const int nslots = min(NS, (total - base + 63) >> 6);
+        uint32_t ca[NS], cb[NS], cc[NS], crec[NS];
+        int cj[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = base + s * 64 + lane;
+            // stencil cell holding candidate q: the largest t with excl_t <= q
+            int t = 0;
+#pragma unroll
+            for (int st = 16; st > 0; st >>= 1) {
+                const int cand = t + st;
+                const int e = __shfl(excl, cand < nst ? cand : nst - 1);
+                if (cand < nst && e <= q) t = cand;
+            }
+            const bool ok = q < total;
+            // the shuffles run in every lane: a lane reads another lane's register only while that lane is active
+            const int t_src = __shfl(src, t), t_ex = __shfl(excl, t);
+            const uint32_t slot = ok ? (uint32_t)t_src * M + (uint32_t)(q - t_ex) : 0u;
+            const uint4 r = rec16(bins.mem, slot);  // slot 0 is always mapped
+            crec[s] = slot;
+            cj[s] = ok ? (int)r.w : -1;
+            if constexpr (PK) {
+                // a lane past the last candidate carries -32768 in a spare 16-bit component, so its R16 >= 2^30
+                // lies above pk_hi for every particle: it never passes and never enters the uncertain band
+                ca[s] = pack_hi16(r.x, r.y);
+                cb[s] = D == 3 ? (r.z >> 16) | (ok ? 0u : 0x80000000u) : (ok ? 0u : 0x8000u);
+                cc[s] = 0u;
+            } else {
+                ca[s] = r.x;
+                cb[s] = r.y;
+                cc[s] = r.z;
+            }
+            // at most four records in flight: the slots' registers, not the loads, set the register budget
+            if (s % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        uint4 rn = rec16(bins.mem, (uint32_t)gc * M);
+        for (int p = 0; p < mc; ++p) {
+            const uint4 ri = rn;
+            rn = rec16(bins.mem, (uint32_t)gc * M + (uint32_t)min(p + 1, mc - 1));  // the next member's record
+            const uint32_t ui[3] = {(uint32_t)__builtin_amdgcn_readfirstlane(ri.x),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(ri.y),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(ri.z)};
+            const int i = __builtin_amdgcn_readfirstlane((int)ri.w);
+            const uint32_t pxy = pack_hi16(ui[0], ui[1]), pz = D == 3 ? ui[2] >> 16 : 0u;
+            const uint32_t iw4 = (uint32_t)i * W * 4u;
+            int n = base > 0 ? __builtin_amdgcn_readfirstlane(ncnt[p]) : 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (s >= nslots) break;
+                // lane masks straight from the compares (no per-lane booleans): acc = surely in the list and not the
+                // particle itself (the one candidate with its own index), band = undecided by the filter
+                uint64_t acc, band;
+                if constexpr (PK) {
+                    const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
+                    const uint64_t lo = __builtin_amdgcn_sicmp(r2, lp.pk_lo, kICmpSLT);
+                    const uint64_t hi = __builtin_amdgcn_sicmp(r2, lp.pk_hi, kICmpSLT);
+                    acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                    band = hi & ~lo;
+                } else {
+                    const uint32_t uj[3] = {ca[s], cb[s], cc[s]};
+                    float r2 = 0.0f;
+#pragma unroll
+                    for (int z = 0; z < D; ++z) {
+                        const float d = iso ? (float)(int32_t)(ui[z] - uj[z]) : tdisp(ui[z], uj[z], b.s[z]);
+                        r2 = __builtin_fmaf(d, d, r2);
+                    }
+                    const uint64_t ok = __builtin_amdgcn_sicmp(cj[s], 0, kICmpSGE);
+                    const uint64_t lo = __builtin_amdgcn_fcmpf(r2, flo, kFCmpOLT) & ok;
+                    const uint64_t hi = __builtin_amdgcn_fcmpf(r2, fhi, kFCmpOLE) & ok;
+                    acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                    band = hi & ~lo;
+                }
+                // candidates near r_list take the defining double expression (rare: the whole wave skips this)
+                if (band != 0) {
+                    bool take = false;
+                    if (__builtin_amdgcn_inverse_ballot_w64(band)) {
+                        uint32_t uj[3] = {ca[s], cb[s], cc[s]};
+                        if constexpr (PK) {
+                            // re-read the full record (the packed copy kept only 16 bits); the empty asm keeps the
+                            // compiler from holding every slot's full record in registers instead
+                            uint32_t slot = crec[s];
+                            asm volatile("" : "+v"(slot));
+                            const uint4 r = rec16(bins.mem, slot);
+                            uj[0] = r.x;
+                            uj[1] = r.y;
+                            uj[2] = r.z;
+                        }
+                        double r2d = 0.0;
+#pragma unroll
+                        for (int z = 0; z < D; ++z) {
+                            const double d = tdisp_d(ui[z], uj[z], b.sd[z]);
+                            r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                        }
+                        take = r2d < lp.rl2;
+                    }
+                    acc |= __builtin_amdgcn_ballot_w64(take);
+                }
+                if (__builtin_amdgcn_inverse_ballot_w64(acc)) {
+                    // entry k = n + (accepted lanes below this one) goes to sub-row k % W at position k / W
+                    const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(acc >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)acc, (uint32_t)n));
+                    const uint32_t lo4 = ((k << 2) & (uint32_t)(4 * W - 4)) | iw4;
+                    const uint32_t off = SMALL_ROWS ? __umul24(k / W, row_bytes) + lo4 : k / W * row_bytes + lo4;
+                    __builtin_amdgcn_raw_buffer_store_b32(cj[s], ridx, off, 0, 0);
+                }
+                n += __popcll(acc);
+            }
+            if (!last_batch) {
+                if (lane == 0) ncnt[p] = n;
+            } else {
+                if (lane < W) count[(size_t)i * W + lane] = sub_count<W>(n, lane);
+                longest = max(longest, n);
+            }
+        }
+    }
+    return longest;
+}
+
+// Cells of the list handed to the waves of a launch: wave w (blocks remapped so that one XCD's workgroups are one
+// contiguous range) takes cells w, w + nwaves, ...  The longest row and the overflow flag go to flags.
+template <int D, int W, bool PK, int NS>
+__device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bins, const ListParams &lp,
+                                                 int32_t *__restrict__ idx, int32_t *__restrict__ count,
+                                                 int32_t *flags, int *ncnt_all, int *red)
+{
+    const int wave = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int nwaves = gridDim.x * (kBlock / 64);
+    int *ncnt = ncnt_all + (threadIdx.x >> 6) * kMaxPerCellPad;
+    int longest = 0;
+    if ((uint64_t)lp.N * W * 4u < (1u << 24)) {  // row stride fits the 24-bit multiplier
+        for (int gc = wave; gc < lp.cells; gc += nwaves)
+            longest = max(longest, build_cell<D, W, PK, NS, true>(gc, b, bins, lp, idx, count, ncnt));
+    } else {
+        for (int gc = wave; gc < lp.cells; gc += nwaves)
+            longest = max(longest, build_cell<D, W, PK, NS, false>(gc, b, bins, lp, idx, count, ncnt));
+    }
+    wave_flag(longest > lp.cap, &flags[MD_FLAG_OVERFLOW]);
+    longest = block_max(longest, red);
+    if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCOUNT], (longest + W - 1) / W * W);
+}
+
+// Standalone build: rows of every particle from the bins, and pos_ref = the positions they were built from.
+template <int D, int W, bool PK>
 __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restrict__ pos, DevBox b, Bins bins,
                                                        ListParams lp, ListGen g, int32_t *flags, const int32_t *gate)
 {
-    constexpr int TS = kBlock / W;
-    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * TS];
+    __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     __shared__ int red[kBlock];
     if (gate_closed(gate)) return;
-    int gt = blockIdx.x * kBlock + threadIdx.x;
-    int i = gt / W, l = gt % W;
-    bool live = i < lp.N;
-    uint32_t ui[D];
-    int ne = 0, chunks = 0, n = 0;
-    if (live) {
-        load_pos<D>(pos, i, ui);
-        ne = stencil_table<D>(i, ui, b, bins, lp, tab + threadIdx.x / W, TS, l == 0, chunks);
-    }
-    __syncthreads();
-    if (live) {
-        n = build_row<D, W>(i, l, ui, b, bins, lp, g.idx, tab + threadIdx.x / W, TS, ne, chunks);
-        g.count[(size_t)i * W + l] = sub_count<W>(n, l);
-        if (l == 0) store_pos<D>(g.pos_ref, i, ui);
-    }
-    wave_flag(n > lp.cap, &flags[MD_FLAG_OVERFLOW]);
-    n = block_max(n, red);
-    if (threadIdx.x == 0) {
-        raise_max(&flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
-        if (blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
-    }
+    build_rows_cells<D, W, PK, PK ? 8 : 4>(b, bins, lp, g.idx, g.count, flags, ncnt, red);
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < lp.N * D; q += gridDim.x * kBlock) g.pos_ref[q] = pos[q];
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -624,13 +600,6 @@ template <typename T>
 __device__ __forceinline__ T ld_off(const void *base, uint32_t off)
 {
     return *(const T *)((const char *)base + off);
-}
-
-// Buffer resource over `bytes` bytes at `base` (raw addressing: loads at byte offsets at or past `bytes` return
-// 0 instead of touching memory).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
 // Position of particle j through a range-checked buffer load: an index read from past the end of a row (a stale
@@ -1002,7 +971,7 @@ template <int D, int KIND, bool MULTI, int W>
 __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 {
     __shared__ int red[kBlock];
-    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * (kBlock / W)];
+    __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     if (frozen(a.flags)) return;
     int mode, gen;
     step_control(a.ctl, a.flags, a.step, mode, gen);
@@ -1020,27 +989,12 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
             store_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
         }
     } else if (mode == M_BUILD) {
-        // rows of the other generation from those bins, W lanes per particle as in the force pass
-        int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-        int i = gt / W, l = gt % W;
-        bool live = i < lp.N;
-        uint32_t ui[D];
-        int ne = 0, chunks = 0, n = 0;
+        // rows of the other generation from those bins, one wave per cell
         const ListGen &g1 = a.gen[gen ^ 1];
-        if (live) {
-            load_pos<D>(g1.pos_ref, i, ui);
-            ne = stencil_table<D>(i, ui, a.box, a.bins[gen ^ 1], lp, tab + threadIdx.x / W, kBlock / W, l == 0,
-                                  chunks);
-        }
-        __syncthreads();
-        if (live) {
-            n = build_row<D, W>(i, l, ui, a.box, a.bins[gen ^ 1], lp, g1.idx, tab + threadIdx.x / W, kBlock / W, ne,
-                                chunks);
-            g1.count[(size_t)i * W + l] = sub_count<W>(n, l);
-        }
-        wave_flag(n > lp.cap, &a.flags[MD_FLAG_OVERFLOW]);
-        n = block_max(n, red);
-        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
+        if (lp.pk)
+            build_rows_cells<D, W, true, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, ncnt, red);
+        else
+            build_rows_cells<D, W, false, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, ncnt, red);
     }
     const ListGen &g = a.gen[gen];
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -1785,7 +1739,20 @@ static bool box_ok(const md_box *box, float r)
     return true;
 }
 
-static ListParams make_lp(const md_nlist *nl, int M)
+// Cells of the whole list: C per system times the number of systems of a segmented list.
+static int list_cells(const DevBox &b, const md_nlist *nl)
+{
+    return nl->segment > 0 ? b.C * (nl->N / nl->segment) : b.C;
+}
+
+// List parameters for the kernels.  The packed 16-bit candidate test (isotropic boxes) bounds the error of
+// R16 = sum d_k^2 (d_k the wrapped difference of the upper 16 bits of the coordinates, unit u = L / 2^16) against the
+// exact R = sum e_k^2 by |R16 - R| < 2 sqrt(D R) + D, valid while |e_k| < 32767.  With T = r_list^2 / u^2 and
+// T1, T2 = T (1 -+ 1e-9) (room for the rounding of the defining double expression, relative error below 1e-15):
+// R16 < floor(T1 - 2 sqrt(D T1) - D) implies R < T1, and R16 >= ceil(T2 + 2 sqrt(D T2) + D) implies R >= T2.  A
+// displacement with |e_k| >= 32767 gives R16 >= 32767^2 (saturating sums), so pk_hi <= 32767^2 rejects it, as it
+// must.  The packed test is used only when the uncertain band is within 10 % of T.
+static ListParams make_lp(const md_nlist *nl, int M, const DevBox &b, int dim)
 {
     ListParams v;
     v.N = nl->N;
@@ -1794,13 +1761,26 @@ static ListParams make_lp(const md_nlist *nl, int M)
     v.capW = nl->capacity / nl->lanes;
     v.M = M;
     v.seg = nl->segment;
+    v.cells = list_cells(b, nl);
     float rl2 = nl->r_list * nl->r_list;
     v.rl2f_lo = rl2 * (1.0f - 1e-5f);
     v.rl2f_hi = rl2 * (1.0f + 1e-5f);
     v.rl2 = (double)nl->r_list * (double)nl->r_list;
-    v.cull2 = rl2 * (1.0f + 1e-4f);
     v.half_skin = 0.5f * nl->skin;
     v.kappa = kKappa;
+    v.pk = 0;
+    v.pk_lo = v.pk_hi = 0;
+    if (b.iso) {
+        const double u = (double)b.s[0] * 65536.0;  // exact: b.s[0] = L / 2^32
+        const double T = v.rl2 / (u * u), T1 = T * (1.0 - 1e-9), T2 = T * (1.0 + 1e-9);
+        const double lo = floor(T1 - 2.0 * sqrt(dim * T1) - dim);
+        const double hi = ceil(T2 + 2.0 * sqrt(dim * T2) + dim);
+        if (lo >= 0.9 * T && hi <= 1.1 * T && hi <= 32767.0 * 32767.0) {
+            v.pk = 1;
+            v.pk_lo = (int32_t)lo;
+            v.pk_hi = (int32_t)hi;
+        }
+    }
     return v;
 }
 
@@ -1885,12 +1865,6 @@ static md_status check_common(md_ctx *ctx, const md_box *box, int32_t N)
     return MD_OK;
 }
 
-// Cells of the whole list: C per system times the number of systems of a segmented list.
-static int list_cells(const DevBox &b, const md_nlist *nl)
-{
-    return nl->segment > 0 ? b.C * (nl->N / nl->segment) : b.C;
-}
-
 static md_status check_list(md_ctx *ctx, const md_box *box, const md_nlist *nl, int32_t N, DevBox &b)
 {
     if (!nl_ok(nl, N)) return MD_ERR_ARG;
@@ -1910,24 +1884,37 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
 {
     CountSort cs = ctx->cs;
     Bins bins = ctx_bins(ctx, 0);
-    ListParams lp = make_lp(nl, ctx->M_cap);
+    ListParams lp = make_lp(nl, ctx->M_cap, b, dim);
     ListGen g = caller_gen(nl);
-    int rows_grid = nblk((int64_t)N * lp.W);
-    int C = list_cells(b, nl);  // cells over all systems of a segmented list
+    int C = lp.cells;  // cells over all systems of a segmented list
+    // one wave per cell (four per workgroup); enough workgroups to copy the reference positions when cells are few
+    int64_t want = ((int64_t)C + 3) / 4, copy = (int64_t)N * dim / (4 * kBlock);
+    if (copy > want) want = copy;
+    int rows_grid = (int)(want < 1 ? 1 : (want > kMaxBlocks ? kMaxBlocks : want));
     if (dim == 3) {
         hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
         hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_rank_fill<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, gate);
-        MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
-                                          lp, g, nl->flags, gate));
+        hipLaunchKernelGGL(k_cs_rank_fill<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
+                           lp.W, gate);
+        if (lp.pk)
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W, true>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
+                                              b, bins, lp, g, nl->flags, gate));
+        else
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W, false>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
+                                              b, bins, lp, g, nl->flags, gate));
     } else {
         hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
         hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
-        hipLaunchKernelGGL(k_cs_rank_fill<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, gate);
-        MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W>), dim3(rows_grid), dim3(kBlock), 0, s, pos, b, bins,
-                                          lp, g, nl->flags, gate));
+        hipLaunchKernelGGL(k_cs_rank_fill<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
+                           lp.W, gate);
+        if (lp.pk)
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W, true>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
+                                              b, bins, lp, g, nl->flags, gate));
+        else
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W, false>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
+                                              b, bins, lp, g, nl->flags, gate));
     }
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
@@ -2168,7 +2155,7 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
     StepArgs a;
     a.box = b;
-    a.lp = make_lp(nl, ctx->M_cap);
+    a.lp = make_lp(nl, ctx->M_cap, b, box->dim);
     a.gen[0] = caller_gen(nl);
     a.gen[1] = ListGen{ctx->g1_idx, ctx->g1_count, ctx->g1_pos_ref};
     a.bins[0] = ctx_bins(ctx, 0);
@@ -2227,7 +2214,7 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
     FireArgs a;
     a.box = b;
-    a.lp = make_lp(nl, ctx->M_cap);
+    a.lp = make_lp(nl, ctx->M_cap, b, box->dim);
     a.list = caller_gen(nl);
     a.flags = nl->flags;
     a.ctl = ctx->ctl;
