@@ -573,6 +573,15 @@ md_status md_rms_diff(md_ctx *ctx, const float *a, const float *b, int64_t n, do
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream);
 /* out[0] = 1/2 sum_i |v_i|^2 in double (device memory). */
 md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t dim, double *out, void *stream);
+/*
+ * md_kinetic_energy without a context, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): out[0] = 1/2 sum_i |v_i|^2 in double on the current HIP device.  Its 256 partial
+ * sums live in a 2 KiB array of the library's own device memory, one copy per GPU, held until the process ends;
+ * the call allocates nothing and needs no md_ctx.  Every call on one GPU shares that array, so calls that overlap
+ * on one GPU (different streams without ordering) race; calls ordered on one stream do not.  N dim above
+ * INT32_MAX returns MD_ERR_CAPACITY; NULL pointers, N < 0 or dim not in {2,3} return MD_ERR_ARG.
+ */
+md_status md_kinetic_energy_noalloc(const float *vel, int32_t N, int32_t dim, double *out, void *stream);
 /* Scale vel [N][dim] so that sum |v_i|^2 = dim (N - 1) T (unit mass, net momentum assumed zero): velocity
  * rescaling to a temperature, for preparing configurations at a given T.  No host synchronisation. */
 md_status md_rescale_velocities(md_ctx *ctx, float *vel, int32_t N, int32_t dim, double T, void *stream);

@@ -33,6 +33,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/md.h"
 #include "md_device.h"
 #include "md_host.h"
@@ -2286,6 +2288,45 @@ md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t di
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, (int64_t)N * dim, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+// Partial sums of md_kinetic_energy_noalloc: one double per reduction workgroup.  Every GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) double scratch[kRedBlocks];
+
+static constexpr int kMaxDevices = 64;
+static double *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device, looked up once per device.
+static md_status scratch_address(double **out)
+{
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return MD_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MD_ERR_HIP;
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return MD_OK;
+}
+
+md_status md_kinetic_energy_noalloc(const float *vel, int32_t N, int32_t dim, double *out, void *stream)
+{
+    if (!vel || !out || N < 0 || (dim != 2 && dim != 3)) return MD_ERR_ARG;
+    if ((int64_t)N * dim > (int64_t)INT32_MAX) return MD_ERR_CAPACITY;
+    double *partials = nullptr;
+    md_status st = scratch_address(&partials);
+    if (st != MD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // every partial is written before the final sum reads it, so nothing needs clearing between calls
+    hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, (int64_t)N * dim, partials);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, partials, kRedBlocks, out);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -141,6 +141,7 @@ _SIGNATURES = {
     "nn_cast_weights": [P, P, P, P, P],
     "md_sum": [P, P, ctypes.c_int64, P, P],
     "md_kinetic_energy": [P, P, ctypes.c_int32, ctypes.c_int32, P, P],
+    "md_kinetic_energy_noalloc": [P, ctypes.c_int32, ctypes.c_int32, P, P],
     "md_rescale_velocities": [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P],
     "md_kick_drift": [P, ctypes.POINTER(c_box), P, P, P, ctypes.c_int32, ctypes.POINTER(c_nlist), ctypes.c_float, P],
     "nl_update": [P, ctypes.POINTER(c_box), P, ctypes.c_int32, ctypes.POINTER(c_nlist), P],
@@ -749,6 +750,12 @@ def md_sum(ctx: Context, x: torch.Tensor, out: torch.Tensor):
 def kinetic_energy(ctx: Context, vel: torch.Tensor, out: torch.Tensor):
     _check("md_kinetic_energy", load().md_kinetic_energy(ctx.h, _ptr(vel), vel.shape[0], vel.shape[1], _ptr(out),
                                                          _stream()))
+
+
+def kinetic_energy_noalloc(vel: torch.Tensor, out: torch.Tensor):
+    """md_kinetic_energy_noalloc: no context, partial sums in the library's own per-GPU array."""
+    _check("md_kinetic_energy_noalloc", load().md_kinetic_energy_noalloc(_ptr(vel), vel.shape[0], vel.shape[1],
+                                                                         _ptr(out), _stream()))
 
 
 def fire_state_tensor(device=None) -> torch.Tensor:
