@@ -106,7 +106,10 @@ enum {
  * `lanes` (W = 1, 2, 4 or 8) interleaved sub-rows that W GPU lanes walk
  * together: entry t of sub-row l of particle i is idx[(t*N + i)*W + l], and
  * count[i*W + l] is that sub-row's length (at most capacity/W).  A build
- * numbers the accepted neighbors in a fixed order (stencil cell, then index)
+ * numbers the accepted neighbors in a fixed order (the particle's own cell
+ * first, then the other cells of its 27 (9 in 2D) cell stencil in stencil
+ * order, each cell's members in bin order: by index after nl_build, by their
+ * order in the previous bins after a rebuild inside verlet_step)
  * and deals them round-robin to the sub-rows: neighbor n goes to sub-row
  * n % W at position n / W, so sub-row lengths differ by at most one and a
  * build is deterministic.
@@ -189,8 +192,13 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
 /*
  * n_steps of velocity-Verlet NVE (Sec. 3.3.1), unit masses:
  *   v += dt/2 F;  r = shift(r, dt v);  F = F(r);  v += dt/2 F.
- * On entry `force` must hold F(pos).  The call first rebuilds nl for pos, then
- * enqueues one launch per step, in which nl->lanes lanes share a particle.  The list is kept valid on the device with no
+ * On entry `force` must hold F(pos).  The call keeps nl when the last call on ctx that
+ * built a list built this one (same arrays, sizes and box; nl_build, nl_update, fire_* or
+ * a verlet_step that ended with it), no build or run since found it incomplete, and on the
+ * device every particle is within skin/2 of nl->pos_ref by a margin of three steps of
+ * dt |v| + dt^2 |F|; otherwise it first rebuilds nl for pos.  Between calls the list arrays
+ * belong to the library: a caller that edits them must call nl_build before the next run.
+ * Then it enqueues one launch per step, in which nl->lanes lanes share a particle.  The list is kept valid on the device with no
  * host synchronisation: when a particle's displacement since the last build
  * plus twice its last step (and dt^2 |F|) would exceed nl->skin/2, the next
  * two launches rebuild it into a second generation while forces still use the

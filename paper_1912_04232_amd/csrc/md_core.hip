@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/md.h"
 #include "md_device.h"
@@ -89,6 +90,7 @@ struct ListParams {
     float rl2f_lo, rl2f_hi;  // float guard band around r_list^2
     double rl2;              // (double)r_list * (double)r_list
     float half_skin;         // skin / 2
+    uint32_t reach[3];       // skin / 2 with a margin, in torus units per axis (how far a particle can be from its record)
     float kappa;             // pipelined rebuild starts when disp + kappa * (last step + dt^2 |F|) > skin/2
 };
 
@@ -183,7 +185,7 @@ constexpr int kScanTile = 4096;  // cells per LDS tile (4 per thread)
 // zero for the next build.  The cells go through LDS in tiles of kScanTile: coalesced loads, each thread scans
 // 4 adjacent cells from LDS, the workgroup scans the thread sums, coalesced stores, and a carry between tiles.
 __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bins, int M, int32_t *flags,
-                                                   const int32_t *gate)
+                                                   int32_t *ok, const int32_t *gate)
 {
     constexpr int kPer = kScanTile / kScan;
     __shared__ int cnt[kScanTile];
@@ -251,6 +253,7 @@ __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bin
         if (lane == 0) {
             raise_max(&flags[MD_FLAG_MAXCELL], m2);
             if (m2 > M) flags[MD_FLAG_CELL_OVERFLOW] = 1;
+            *ok = m2 <= M ? 1 : 0;  // the bins are complete (the rows may still overflow)
             cs.cell_start[C] = carry;
         }
     }
@@ -345,9 +348,14 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
     const int sys = gc / b.C, c = gc - sys * b.C, cbase = sys * b.C;
     const int cx = c % b.nc[0], cy = (c / b.nc[0]) % b.nc[1], cz = D == 3 ? c / (b.nc[0] * b.nc[1]) : 0;
     const int nst = stencil_size<D>(b);
+    const int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1;
+    const int tc = -b.lo[0] + n0 * (-b.lo[1] + n1 * (D == 3 ? -b.lo[2] : 0));  // the cell itself in stencil order
+    // candidate order: the cell's own members first, then the other stencil cells in stencil order, each in bin
+    // order; entry u of the table is stencil cell tc for u = 0, else the (u-1)-th of the others
     int src = 0, m = 0;
     if (lane < nst) {
-        src = cbase + stencil_cell<D>(b, cx, cy, cz, lane);
+        const int t = lane == 0 ? tc : (lane - 1 < tc ? lane - 1 : lane);
+        src = cbase + stencil_cell<D>(b, cx, cy, cz, t);
         m = bins.cnt[src];
     }
     int incl = m;
@@ -358,9 +366,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
     }
     const int excl = incl - m;
     const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, nst - 1));
-    const int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1;
-    const int tc = -b.lo[0] + n0 * (-b.lo[1] + n1 * (D == 3 ? -b.lo[2] : 0));  // the cell itself in stencil order
-    const int mc = __builtin_amdgcn_readfirstlane(__shfl(m, tc));
+    const int mc = __builtin_amdgcn_readfirstlane(m);  // members of the cell itself (entry 0, lane 0)
     if (mc == 0) return 0;
     const uint32_t M = (uint32_t)lp.M;
     const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
@@ -370,35 +376,38 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
     const bool iso = b.iso != 0;
     const float s2 = b.s[0] * b.s[0];
     const float flo = iso ? lp.rl2f_lo / s2 : lp.rl2f_lo, fhi = iso ? lp.rl2f_hi / s2 : lp.rl2f_hi;
+    // record slot of candidate q (every lane runs it: a lane reads another lane's register through a shuffle only
+    // while that lane is active); slot 0, always mapped, past the last candidate
+    auto locate = [&](int q) -> uint32_t {
+        int t = 0;
+#pragma unroll
+        for (int st = 16; st > 0; st >>= 1) {
+            const int cand = t + st;
+            const int e = __shfl(excl, cand < nst ? cand : nst - 1);
+            if (cand < nst && e <= q) t = cand;
+        }
+        const int t_src = __shfl(src, t), t_ex = __shfl(excl, t);
+        return q < total ? (uint32_t)t_src * M + (uint32_t)(q - t_ex) : 0u;
+    };
+    // packed test: a lane whose spare 16-bit component holds -32768 has R16 >= 2^30, above pk_hi for every
+    // particle, so it never passes and never enters the uncertain band; it marks lanes past the last candidate and,
+    // while a particle is tested, the particle's own entry
+    constexpr uint32_t kMark = D == 3 ? 0x80000000u : 0x8000u;
     int longest = 0;
     for (int base = 0; base < total; base += NS * 64) {
         const bool last_batch = base + NS * 64 >= total;
         const int nslots = min(NS, (total - base + 63) >> 6);
-        uint32_t ca[NS], cb[NS], cc[NS], crec[NS];
+        uint32_t ca[NS], cb[NS], cc[NS];
         int cj[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int q = base + s * 64 + lane;
-            // stencil cell holding candidate q: the largest t with excl_t <= q
-            int t = 0;
-#pragma unroll
-            for (int st = 16; st > 0; st >>= 1) {
-                const int cand = t + st;
-                const int e = __shfl(excl, cand < nst ? cand : nst - 1);
-                if (cand < nst && e <= q) t = cand;
-            }
+            const uint4 r = rec16(bins.mem, locate(q));
             const bool ok = q < total;
-            // the shuffles run in every lane: a lane reads another lane's register only while that lane is active
-            const int t_src = __shfl(src, t), t_ex = __shfl(excl, t);
-            const uint32_t slot = ok ? (uint32_t)t_src * M + (uint32_t)(q - t_ex) : 0u;
-            const uint4 r = rec16(bins.mem, slot);  // slot 0 is always mapped
-            crec[s] = slot;
             cj[s] = ok ? (int)r.w : -1;
             if constexpr (PK) {
-                // a lane past the last candidate carries -32768 in a spare 16-bit component, so its R16 >= 2^30
-                // lies above pk_hi for every particle: it never passes and never enters the uncertain band
                 ca[s] = pack_hi16(r.x, r.y);
-                cb[s] = D == 3 ? (r.z >> 16) | (ok ? 0u : 0x80000000u) : (ok ? 0u : 0x8000u);
+                cb[s] = (D == 3 ? (r.z >> 16) : 0u) | (ok ? 0u : kMark);
                 cc[s] = 0u;
             } else {
                 ca[s] = r.x;
@@ -419,66 +428,78 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
             const uint32_t pxy = pack_hi16(ui[0], ui[1]), pz = D == 3 ? ui[2] >> 16 : 0u;
             const uint32_t iw4 = (uint32_t)i * W * 4u;
             int n = base > 0 ? __builtin_amdgcn_readfirstlane(ncnt[p]) : 0;
+            // the particle is candidate p (its cell comes first): with the packed test and p < 64 its own entry in
+            // slot 0 is marked while it is tested; otherwise the entries are compared with its index
+            auto test_slots = [&](auto marked) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (s >= nslots) break;
-                // lane masks straight from the compares (no per-lane booleans): acc = surely in the list and not the
-                // particle itself (the one candidate with its own index), band = undecided by the filter
-                uint64_t acc, band;
-                if constexpr (PK) {
-                    const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
-                    const uint64_t lo = __builtin_amdgcn_sicmp(r2, lp.pk_lo, kICmpSLT);
-                    const uint64_t hi = __builtin_amdgcn_sicmp(r2, lp.pk_hi, kICmpSLT);
-                    acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
-                    band = hi & ~lo;
-                } else {
-                    const uint32_t uj[3] = {ca[s], cb[s], cc[s]};
-                    float r2 = 0.0f;
-#pragma unroll
-                    for (int z = 0; z < D; ++z) {
-                        const float d = iso ? (float)(int32_t)(ui[z] - uj[z]) : tdisp(ui[z], uj[z], b.s[z]);
-                        r2 = __builtin_fmaf(d, d, r2);
-                    }
-                    const uint64_t ok = __builtin_amdgcn_sicmp(cj[s], 0, kICmpSGE);
-                    const uint64_t lo = __builtin_amdgcn_fcmpf(r2, flo, kFCmpOLT) & ok;
-                    const uint64_t hi = __builtin_amdgcn_fcmpf(r2, fhi, kFCmpOLE) & ok;
-                    acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
-                    band = hi & ~lo;
-                }
-                // candidates near r_list take the defining double expression (rare: the whole wave skips this)
-                if (band != 0) {
-                    bool take = false;
-                    if (__builtin_amdgcn_inverse_ballot_w64(band)) {
-                        uint32_t uj[3] = {ca[s], cb[s], cc[s]};
-                        if constexpr (PK) {
-                            // re-read the full record (the packed copy kept only 16 bits); the empty asm keeps the
-                            // compiler from holding every slot's full record in registers instead
-                            uint32_t slot = crec[s];
-                            asm volatile("" : "+v"(slot));
-                            const uint4 r = rec16(bins.mem, slot);
-                            uj[0] = r.x;
-                            uj[1] = r.y;
-                            uj[2] = r.z;
-                        }
-                        double r2d = 0.0;
+                for (int s = 0; s < NS; ++s) {
+                    if (s >= nslots) break;
+                    // lane masks straight from the compares: acc = surely in the list, band = undecided by the filter
+                    uint64_t acc, band;
+                    if constexpr (PK) {
+                        const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
+                        const uint64_t lo = __builtin_amdgcn_sicmp(r2, lp.pk_lo, kICmpSLT);
+                        const uint64_t hi = __builtin_amdgcn_sicmp(r2, lp.pk_hi, kICmpSLT);
+                        if constexpr (decltype(marked)::value) acc = lo;
+                        else acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                        band = hi & ~lo;
+                    } else {
+                        const uint32_t uj[3] = {ca[s], cb[s], cc[s]};
+                        float r2 = 0.0f;
 #pragma unroll
                         for (int z = 0; z < D; ++z) {
-                            const double d = tdisp_d(ui[z], uj[z], b.sd[z]);
-                            r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                            const float d = iso ? (float)(int32_t)(ui[z] - uj[z]) : tdisp(ui[z], uj[z], b.s[z]);
+                            r2 = __builtin_fmaf(d, d, r2);
                         }
-                        take = r2d < lp.rl2;
+                        const uint64_t ok = __builtin_amdgcn_sicmp(cj[s], 0, kICmpSGE);
+                        const uint64_t lo = __builtin_amdgcn_fcmpf(r2, flo, kFCmpOLT) & ok;
+                        const uint64_t hi = __builtin_amdgcn_fcmpf(r2, fhi, kFCmpOLE) & ok;
+                        acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                        band = hi & ~lo;
                     }
-                    acc |= __builtin_amdgcn_ballot_w64(take);
+                    // candidates near r_list take the defining double expression (rare: the whole wave skips this)
+                    if (band != 0) {
+                        band &= __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                        const uint32_t slot = locate(base + s * 64 + lane);  // the full record (PK kept 16 bits)
+                        bool take = false;
+                        if (__builtin_amdgcn_inverse_ballot_w64(band)) {
+                            uint32_t uj[3] = {ca[s], cb[s], cc[s]};
+                            if constexpr (PK) {
+                                const uint4 r = rec16(bins.mem, slot);
+                                uj[0] = r.x;
+                                uj[1] = r.y;
+                                uj[2] = r.z;
+                            }
+                            double r2d = 0.0;
+#pragma unroll
+                            for (int z = 0; z < D; ++z) {
+                                const double d = tdisp_d(ui[z], uj[z], b.sd[z]);
+                                r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                            }
+                            take = r2d < lp.rl2;
+                        }
+                        acc |= __builtin_amdgcn_ballot_w64(take);
+                    }
+                    if (__builtin_amdgcn_inverse_ballot_w64(acc)) {
+                        // entry k = n + (accepted lanes below this one) goes to sub-row k % W at position k / W:
+                        // (k / W) row_bytes + (k % W) 4 + 4 W i = (k / W) (row_bytes - 4 W) + 4 k + 4 W i
+                        const uint32_t k = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(acc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)acc, (uint32_t)n));
+                        const uint32_t k4 = (k << 2) + iw4;
+                        const uint32_t off = SMALL_ROWS ? __umul24(k / W, row_bytes - 4u * W) + k4
+                                                        : k / W * (row_bytes - 4u * W) + k4;
+                        __builtin_amdgcn_raw_buffer_store_b32(cj[s], ridx, off, 0, 0);
+                    }
+                    n += __popcll(acc);
                 }
-                if (__builtin_amdgcn_inverse_ballot_w64(acc)) {
-                    // entry k = n + (accepted lanes below this one) goes to sub-row k % W at position k / W
-                    const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(acc >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)acc, (uint32_t)n));
-                    const uint32_t lo4 = ((k << 2) & (uint32_t)(4 * W - 4)) | iw4;
-                    const uint32_t off = SMALL_ROWS ? __umul24(k / W, row_bytes) + lo4 : k / W * row_bytes + lo4;
-                    __builtin_amdgcn_raw_buffer_store_b32(cj[s], ridx, off, 0, 0);
-                }
-                n += __popcll(acc);
+            };
+            if (PK && base == 0 && p < 64) {
+                const uint32_t keep = cb[0];
+                cb[0] = lane == p ? keep | kMark : keep;
+                test_slots(std::integral_constant<bool, true>());
+                cb[0] = keep;
+            } else {
+                test_slots(std::integral_constant<bool, false>());
             }
             if (!last_batch) {
                 if (lane == 0) ncnt[p] = n;
@@ -496,7 +517,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
 template <int D, int W, bool PK, int NS>
 __device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bins, const ListParams &lp,
                                                  int32_t *__restrict__ idx, int32_t *__restrict__ count,
-                                                 int32_t *flags, int *ncnt_all, int *red)
+                                                 int32_t *flags, int32_t *ok, int *ncnt_all, int *red)
 {
     const int wave = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
     const int nwaves = gridDim.x * (kBlock / 64);
@@ -510,6 +531,7 @@ __device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bi
             longest = max(longest, build_cell<D, W, PK, NS, false>(gc, b, bins, lp, idx, count, ncnt));
     }
     wave_flag(longest > lp.cap, &flags[MD_FLAG_OVERFLOW]);
+    if (ok != nullptr && longest > lp.cap) *ok = 0;  // rare: only a wave with a row that did not fit stores
     longest = block_max(longest, red);
     if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCOUNT], (longest + W - 1) / W * W);
 }
@@ -517,12 +539,13 @@ __device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bi
 // Standalone build: rows of every particle from the bins, and pos_ref = the positions they were built from.
 template <int D, int W, bool PK>
 __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restrict__ pos, DevBox b, Bins bins,
-                                                       ListParams lp, ListGen g, int32_t *flags, const int32_t *gate)
+                                                       ListParams lp, ListGen g, int32_t *flags, int32_t *ok,
+                                                       const int32_t *gate)
 {
     __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     __shared__ int red[kBlock];
     if (gate_closed(gate)) return;
-    build_rows_cells<D, W, PK, PK ? 8 : 4>(b, bins, lp, g.idx, g.count, flags, ncnt, red);
+    build_rows_cells<D, W, PK, PK ? 8 : 4>(b, bins, lp, g.idx, g.count, flags, ok, ncnt, red);
     for (int q = blockIdx.x * kBlock + threadIdx.x; q < lp.N * D; q += gridDim.x * kBlock) g.pos_ref[q] = pos[q];
     if (threadIdx.x == 0 && blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
 }
@@ -530,63 +553,99 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restric
 // ------------------------------------------------------------------------------------------------
 // in-run bin refresh (no atomics): one wave per cell
 
-// Gather, from the previous bins of cell c's stencil, the members whose cell at the current positions
-// `pos` is c.  The stencil's candidates are numbered in stencil order, then previous bin order, and
-// handed out 64 at a time to the wave's lanes; ballot compaction keeps that order.
+// Gather, from the previous bins of cell c's stencil, the members whose cell at the current positions `pos` is c.
+// The stencil's candidates are numbered in stencil order, then previous bin order, and handed out 64 at a time to the
+// wave's lanes.  A previous member's record holds its position at the last build, and no particle is farther than
+// skin/2 from it (a step that finds one farther raises the stale flag, and the run stops), so along each axis it can
+// now be only in the cells of its recorded coordinate -+ reach (ListParams.reach: skin/2 with a margin, in torus
+// units).  Candidates that cannot be in c are dropped from their records alone; the rest are queued in LDS in
+// sequence order and tested against their current positions in one pass of independent loads (ballot compaction
+// keeps the order).  q is the wave's LDS queue of kMaxPerCellPad entries.
 template <int D>
-__device__ int bin_gather(const uint32_t *__restrict__ pos, const DevBox &b, const Bins &prev, const Bins &next,
-                          int M, int32_t *flags, int wave, int nwaves)
+__device__ int bin_gather(const uint32_t *__restrict__ pos, const DevBox &b, const ListParams &lp, const Bins &prev,
+                          const Bins &next, int32_t *flags, int wave, int nwaves, int *queue)
 {
-    int lane = threadIdx.x & 63;
-    int nst = stencil_size<D>(b);
+    const int lane = threadIdx.x & 63;
+    const int nst = stencil_size<D>(b);
+    const uint32_t M = (uint32_t)lp.M;
     int mymax = 0;
     for (int c = wave; c < b.C; c += nwaves) {
-        int cx = c % b.nc[0];
-        int cy = (c / b.nc[0]) % b.nc[1];
-        int cz = D == 3 ? c / (b.nc[0] * b.nc[1]) : 0;
+        const int cc[3] = {c % b.nc[0], (c / b.nc[0]) % b.nc[1], D == 3 ? c / (b.nc[0] * b.nc[1]) : 0};
         int src = 0, m = 0;
         if (lane < nst) {
-            src = stencil_cell<D>(b, cx, cy, cz, lane);
+            src = stencil_cell<D>(b, cc[0], cc[1], cc[2], lane);
             m = prev.cnt[src];
         }
         int incl = m;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
+        for (int o = 1; o < 32; o <<= 1) {
             int v = __shfl_up(incl, o);
             if (lane >= o) incl += v;
         }
-        int excl = incl - m;
-        int total = __shfl(incl, 63);
-        int cnt = 0;
-        for (int base = 0; base < total; base += 64) {
-            int q = base + lane;
-            // stencil cell holding candidate q: the largest t with excl_t <= q
-            int t = 0;
+        const int excl = incl - m;
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, nst - 1));
+        int cnt = 0, queued = 0;
+        // members of the queue: tested at their current positions and written in queue order
+        auto flush = [&]() {
+            for (int base = 0; base < queued; base += 64) {
+                const int e = base + lane;
+                bool take = false;
+                int j = 0;
+                uint32_t u[D];
+                if (e < queued) {
+                    j = queue[e];
+                    load_pos<D>(pos, j, u);
+                    take = cell_index<D>(u, b) == c;
+                }
+                const uint64_t mask = __ballot(take);
+                const int slot = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                if (take && slot < (int)M) store_rec<D>(next.mem, (uint32_t)(c * (int)M + slot), u, j);
+                cnt += __popcll(mask);
+            }
+            queued = 0;
+        };
+        // four batches of 64 candidates at a time: their record loads are issued together
+        for (int base = 0; base < total; base += 4 * 64) {
+            uint4 r[4];
 #pragma unroll
-            for (int step = 16; step > 0; step >>= 1) {
-                int cand = t + step;
-                int e = __shfl(excl, cand < nst ? cand : nst - 1);
-                if (cand < nst && e <= q) t = cand;
+            for (int h = 0; h < 4; ++h) {
+                const int q = base + h * 64 + lane;
+                // stencil cell holding candidate q: the largest t with excl_t <= q
+                int t = 0;
+#pragma unroll
+                for (int st = 16; st > 0; st >>= 1) {
+                    const int cand = t + st;
+                    const int e = __shfl(excl, cand < nst ? cand : nst - 1);
+                    if (cand < nst && e <= q) t = cand;
+                }
+                // the shuffles run in every lane: a lane reads another lane's register only while that lane is active
+                const int t_src = __shfl(src, t), t_ex = __shfl(excl, t);
+                r[h] = rec16(prev.mem, q < total ? (uint32_t)t_src * M + (uint32_t)(q - t_ex) : 0u);
             }
-            int s_src = __shfl(src, t);
-            int s_ex = __shfl(excl, t);
-            bool take = false;
-            int j = 0;
-            uint32_t u[D];
-            if (q < total) {
-                j = (int)prev.mem[((size_t)s_src * M + (q - s_ex)) * 4 + 3];
-                load_pos<D>(pos, j, u);
-                take = cell_index<D>(u, b) == c;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int q = base + h * 64 + lane;
+                bool may = q < total;
+                const uint32_t w[3] = {r[h].x, r[h].y, r[h].z};
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const int lo = cell_coord(w[k] - lp.reach[k], b.nc[k]);
+                    const int hi = cell_coord(w[k] + lp.reach[k], b.nc[k]);
+                    may = may && (lo == cc[k] || hi == cc[k]);
+                }
+                const uint64_t mask = __ballot(may);
+                if (may) queue[queued + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
+                    (int)r[h].w;
+                queued += __popcll(mask);
+                if (queued > kMaxPerCellPad - 64) flush();
             }
-            uint64_t mask = __ballot(take);
-            int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-            int slot = cnt + before;
-            if (take && slot < M) store_rec<D>(next.mem, (uint32_t)(c * M + slot), u, j);
-            cnt += __popcll(mask);
         }
+        flush();
         if (lane == 0) {
-            next.cnt[c] = min(cnt, M);
-            if (cnt > M) flags[MD_FLAG_CELL_OVERFLOW] = 1;  // one store per overflowing cell
+            next.cnt[c] = min(cnt, (int)M);
+            if (cnt > (int)M) flags[MD_FLAG_CELL_OVERFLOW] = 1;  // one store per overflowing cell
         }
         mymax = max(mymax, cnt);
     }
@@ -979,10 +1038,12 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
     step_control(a.ctl, a.flags, a.step, mode, gen);
     const ListParams &lp = a.lp;
     if (mode == M_BIN) {
-        // bins and reference positions of the other generation from r(s)
-        int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+        // bins and reference positions of the other generation from r(s); one XCD's workgroups take one contiguous
+        // range of cells, as in the build that reads these bins next
+        int wave = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
         int nwaves = (gridDim.x * kBlock) >> 6;
-        int occ = bin_gather<D>(a.pos_in, a.box, a.bins[gen], a.bins[gen ^ 1], lp.M, a.flags, wave, nwaves);
+        int *queue = ncnt + (threadIdx.x >> 6) * kMaxPerCellPad;
+        int occ = bin_gather<D>(a.pos_in, a.box, lp, a.bins[gen], a.bins[gen ^ 1], a.flags, wave, nwaves, queue);
         occ = block_max(occ, red);
         if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCELL], occ);
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < lp.N; i += gridDim.x * kBlock) {
@@ -994,9 +1055,11 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
         // rows of the other generation from those bins, one wave per cell
         const ListGen &g1 = a.gen[gen ^ 1];
         if (lp.pk)
-            build_rows_cells<D, W, true, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, ncnt, red);
+            build_rows_cells<D, W, true, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
+                                            red);
         else
-            build_rows_cells<D, W, false, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, ncnt, red);
+            build_rows_cells<D, W, false, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
+                                             red);
     }
     const ListGen &g = a.gen[gen];
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -1088,7 +1151,7 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 __global__ void k_ctl_init(int32_t *ctl)
 {
     int t = threadIdx.x;
-    if (t < kCtlWords) ctl[t] = 0;
+    if (t < kCtlWords && t != kListOkWord) ctl[t] = 0;
 }
 
 // After a run: if the list in use is the second generation, copy it into the caller's list.
@@ -1110,6 +1173,49 @@ __global__ __launch_bounds__(kBlock) void k_list_finalize(const int32_t *ctl, Li
 #pragma unroll
         for (int q = 0; q < D; ++q) dst.pos_ref[(size_t)i * D + q] = src.pos_ref[(size_t)i * D + q];
     }
+}
+
+// After a run: if the list in use is the second generation, its bins become generation 0 (the bins of the list
+// now in the caller's arrays), and the list is marked unusable by the next call when the run ended frozen.
+__global__ __launch_bounds__(kBlock) void k_bins_finalize(int32_t *ctl, const int32_t *flags, Bins dst, Bins src,
+                                                          int C, int M)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && frozen(flags)) ctl[kListOkWord] = 0;
+    if (ctl[kGenWord] == 0) return;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // record slot q = c * M + k
+    if (q >= (int64_t)C * M) return;
+    const int c = (int)(q / M), k = (int)(q - (int64_t)c * M);
+    const int n = src.cnt[c];
+    if (k == 0) dst.cnt[c] = n;
+    if (k < n) *(uint4 *)(dst.mem + (size_t)q * 4) = *(const uint4 *)(src.mem + (size_t)q * 4);
+}
+
+// Start of a verlet_step that may keep the caller's list: raises ctl[kTrigWord] (the gate of a full rebuild) unless
+// the list is complete and every particle is within skin/2 of its reference position by a margin of three steps
+// of dt |v| + dt^2 |F| (the longest a rebuild requested by the first step can take to replace it).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_verlet_check(const uint32_t *__restrict__ pos,
+                                                         const float *__restrict__ vel, const float *__restrict__ force,
+                                                         const uint32_t *__restrict__ pos_ref, DevBox b, int N,
+                                                         float dt, float half_skin, int32_t *ctl)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < N) {
+        uint32_t ui[D];
+        load_pos<D>(pos, i, ui);
+        float v2 = 0.0f, f2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const float v = vel[(size_t)i * D + q], f = force[(size_t)i * D + q];
+            v2 = __builtin_fmaf(v, v, v2);
+            f2 = __builtin_fmaf(f, f, f2);
+        }
+        const float ahead = dt * sqrtf(v2) + dt * dt * sqrtf(f2);
+        far = !(sqrtf(disp2<D>(ui, pos_ref, i, b)) + 3.0f * ahead <= half_skin);  // NaN counts as far
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl[kListOkWord] == 0) ctl[kTrigWord] = 1;
+    wave_flag(far, &ctl[kTrigWord]);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1769,6 +1875,10 @@ static ListParams make_lp(const md_nlist *nl, int M, const DevBox &b, int dim)
     v.rl2f_hi = rl2 * (1.0f + 1e-5f);
     v.rl2 = (double)nl->r_list * (double)nl->r_list;
     v.half_skin = 0.5f * nl->skin;
+    for (int q = 0; q < 3; ++q) {
+        const double r = b.s[q] > 0.0f ? 0.5 * (double)nl->skin * (1.0 + 1e-4) / (double)b.s[q] + 16.0 : 0.0;
+        v.reach[q] = (uint32_t)fmin(r, 2147483647.0);
+    }
     v.kappa = kKappa;
     v.pk = 0;
     v.pk_lo = v.pk_hi = 0;
@@ -1879,6 +1989,32 @@ static md_status check_list(md_ctx *ctx, const md_box *box, const md_nlist *nl, 
     return MD_OK;
 }
 
+static ListKey list_key(const md_nlist *nl, const DevBox &b, int dim, int M)
+{
+    ListKey k;
+    memset(&k, 0, sizeof(k));
+    k.idx = nl->idx;
+    k.count = nl->count;
+    k.pos_ref = nl->pos_ref;
+    k.N = nl->N;
+    k.dim = dim;
+    k.cap = nl->capacity;
+    k.W = nl->lanes;
+    k.M = M;
+    k.seg = nl->segment;
+    k.r_list = nl->r_list;
+    k.skin = nl->skin;
+    for (int q = 0; q < 3; ++q) k.L[q] = b.s[q];  // L / 2^32: the same box exactly when the same scales
+    return k;
+}
+
+static bool same_key(const ListKey &a, const ListKey &b)
+{
+    return a.idx == b.idx && a.count == b.count && a.pos_ref == b.pos_ref && a.N == b.N && a.dim == b.dim &&
+           a.cap == b.cap && a.W == b.W && a.M == b.M && a.seg == b.seg && a.r_list == b.r_list &&
+           a.skin == b.skin && a.L[0] == b.L[0] && a.L[1] == b.L[1] && a.L[2] == b.L[2];
+}
+
 // Counting-sort bins of generation 0 and rows of the caller's list; with a gate, every launch
 // returns at once unless *gate != 0 on the device.
 static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint32_t *pos, int32_t N,
@@ -1888,6 +2024,7 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     Bins bins = ctx_bins(ctx, 0);
     ListParams lp = make_lp(nl, ctx->M_cap, b, dim);
     ListGen g = caller_gen(nl);
+    int32_t *ok = ctx->ctl + kListOkWord;
     int C = lp.cells;  // cells over all systems of a segmented list
     // one wave per cell (four per workgroup); enough workgroups to copy the reference positions when cells are few
     int64_t want = ((int64_t)C + 3) / 4, copy = (int64_t)N * dim / (4 * kBlock);
@@ -1895,29 +2032,32 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     int rows_grid = (int)(want < 1 ? 1 : (want > kMaxBlocks ? kMaxBlocks : want));
     if (dim == 3) {
         hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, ok, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
         hipLaunchKernelGGL(k_cs_rank_fill<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
                            lp.W, gate);
         if (lp.pk)
             MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W, true>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
-                                              b, bins, lp, g, nl->flags, gate));
+                                              b, bins, lp, g, nl->flags, ok, gate));
         else
             MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<3, W, false>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
-                                              b, bins, lp, g, nl->flags, gate));
+                                              b, bins, lp, g, nl->flags, ok, gate));
     } else {
         hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
-        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, gate);
+        hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, ok, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
         hipLaunchKernelGGL(k_cs_rank_fill<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
                            lp.W, gate);
         if (lp.pk)
             MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W, true>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
-                                              b, bins, lp, g, nl->flags, gate));
+                                              b, bins, lp, g, nl->flags, ok, gate));
         else
             MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows<2, W, false>), dim3(rows_grid), dim3(kBlock), 0, s, pos,
-                                              b, bins, lp, g, nl->flags, gate));
+                                              b, bins, lp, g, nl->flags, ok, gate));
     }
+    // generation-0 bins now belong to nl (a gated build that did not run leaves both as they were)
+    ctx->bins_key = list_key(nl, b, dim, lp.M);
+    ctx->bins_key_set = true;
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
@@ -2007,6 +2147,7 @@ md_status md_ctx_reserve(md_ctx *ctx, int32_t N, int32_t dim, int32_t max_cells,
     int32_t M = max_per_cell > ctx->M_cap ? max_per_cell : ctx->M_cap;
     M = (M + 3) / 4 * 4;  // bins are read in chunks of four records
     free_scratch(ctx);
+    ctx->bins_key_set = false;
     ctx->N_cap = ctx->dim_cap = ctx->C_cap = ctx->cap_cap = ctx->W_cap = ctx->M_cap = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
     HIP_OK(hipMalloc(&ctx->pos_alt, sizeof(uint32_t) * nn * d));
@@ -2151,10 +2292,23 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
     if (N == 0 || n_steps == 0) return MD_OK;
     hipStream_t s = (hipStream_t)stream;
     bool multi = pot->n_species > 1;
-    // a fresh list (and generation-0 bins) for the input positions
-    st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
-    if (st != MD_OK) return st;
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
+    // The list the caller holds is used again when generation-0 bins belong to it and the device finds it complete
+    // and still valid for pos with room for the first steps; otherwise (or for any other list) a fresh list and
+    // generation-0 bins are built for the input positions.
+    const ListKey key = list_key(nl, b, box->dim, ctx->M_cap);
+    if (ctx->bins_key_set && same_key(key, ctx->bins_key)) {
+        if (box->dim == 3)
+            hipLaunchKernelGGL(k_verlet_check<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, nl->pos_ref, b,
+                               N, dt, 0.5f * nl->skin, ctx->ctl);
+        else
+            hipLaunchKernelGGL(k_verlet_check<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, vel, force, nl->pos_ref, b,
+                               N, dt, 0.5f * nl->skin, ctx->ctl);
+        st = launch_build(ctx, box->dim, b, pos, N, nl, s, ctx->ctl + kTrigWord);
+    } else {
+        st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
+    }
+    if (st != MD_OK) return st;
     StepArgs a;
     a.box = b;
     a.lp = make_lp(nl, ctx->M_cap, b, box->dim);
@@ -2197,6 +2351,8 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
         hipLaunchKernelGGL(k_list_finalize<3>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
     else
         hipLaunchKernelGGL(k_list_finalize<2>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
+    hipLaunchKernelGGL(k_bins_finalize, dim3(nblk((int64_t)b.C * a.lp.M)), dim3(kBlock), 0, s, ctx->ctl, nl->flags,
+                       a.bins[0], a.bins[1], b.C, a.lp.M);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -25,6 +25,18 @@ struct CountSort {
 // positions, and nl_update rebuilds (on the device) and clears it.
 constexpr int kCtlWords = 16;
 constexpr int kTrigWord = 10;
+// ctl[kListOkWord] is 1 while the list that generation-0 bins belong to is complete: a build sets it (0 when a cell
+// or a row did not fit) and a Verlet run clears it when it ends frozen (a list that overflowed or went stale).  It
+// survives k_ctl_init, so the next verlet_step can decide on the device whether that list can be used again.
+constexpr int kListOkWord = 12;
+
+// Identity of the list that generation-0 bins belong to (host side): the caller's list arrays, its sizes and the
+// box.  A verlet_step whose list has the same identity may use it again (the device confirms it is still valid).
+struct ListKey {
+    const void *idx, *count, *pos_ref;
+    int32_t N, dim, cap, W, M, seg;
+    float r_list, skin, L[3];
+};
 
 struct md_ctx {
     int device = 0;
@@ -40,6 +52,8 @@ struct md_ctx {
     int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
     int32_t *queue = nullptr;      // work counter of batched launches
     float *nn_partial = nullptr;   // partial weight gradients of the neural-potential training pass
+    ListKey bins_key = {};         // the list generation-0 bins were last built for (valid when bins_key_set)
+    bool bins_key_set = false;
 };
 
 // neural-potential training: parameter count and the number of partial gradients (one per wave)

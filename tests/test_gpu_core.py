@@ -177,7 +177,7 @@ def test_nl_boundary_pairs_bitexact(md, orc, dim, L, sites, lanes):
 
 
 def test_nl_rows_are_canonical(md):
-    """Two builds give identical rows (same order), and each row is ordered by stencil cell then index."""
+    """Two builds give identical rows (same order), dealt round-robin over the sub-rows."""
     cfg = lj_cfg(4000, 0.84, 3)
     s = make_system(md, cfg)
     s.build()

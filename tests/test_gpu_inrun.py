@@ -185,3 +185,44 @@ def test_kinetic_energy_and_sum_against_numpy(md):
         x = rng.standard_normal(n * dim)
         md.md_sum(ctx, torch.as_tensor(x, device=ctx.device), out)
         assert float(out.item()) == pytest.approx(math.fsum(x.tolist()), rel=1e-10, abs=1e-9)
+
+
+def test_verlet_step_keeps_a_valid_list_and_rebuilds_a_moved_or_overflowed_one(md, orc):
+    """verlet_step keeps the list the last build on the context made for the same arrays while the device finds it
+    valid for the positions (no build launch runs), rebuilds it when the positions have moved away from its reference
+    positions, and after a run whose list overflowed builds again instead of using the truncated rows, even when the
+    caller cleared the flags."""
+    import torch
+    N = 2000
+    L = inputs.box_for_density(N, 0.84)
+    u = inputs.random_insertion_torus(N, L, 3, 0.8, 91)
+    v = inputs.maxwell_velocities(N, 3, 1.0, 92)
+    s = lj_system(md, u, v, L)
+    s.build()
+    s.forces()
+    ref0 = md.from_device_u32(s.nl.pos_ref).copy()
+    # one step: no rebuild is due, and the list just built is kept (no build counted)
+    s.nl.clear_flags()
+    md.verlet_step(s.ctx, s.box, s.pot, s.pos, s.vel, s.force, s.species, s.nl, 0.005, 1)
+    f = s.nl.read_flags()
+    assert f[md.FLAG_REBUILDS] == 0 and f[md.FLAG_STALE] == 0, f
+    assert np.array_equal(md.from_device_u32(s.nl.pos_ref), ref0)
+    # positions moved by a uniform shift of 0.2 (more than skin/2): the call builds a list for them first
+    shifted = (md.from_device_u32(s.pos).astype(np.int64) + int(0.2 / L * 2 ** 32)) & 0xFFFFFFFF
+    s.pos.copy_(torch.as_tensor(shifted.astype(np.uint32).view(np.int32), device=s.pos.device).reshape(s.pos.shape))
+    s.forces()
+    s.nl.clear_flags()
+    md.verlet_step(s.ctx, s.box, s.pot, s.pos, s.vel, s.force, s.species, s.nl, 0.005, 1)
+    f = s.nl.read_flags()
+    assert f[md.FLAG_REBUILDS] >= 1 and f[md.FLAG_STALE] == 0, f
+    check_list_in_use(md, orc, s, L)
+    # a list too small for the rows: the run overflows; with the flags cleared and the same arrays, the next call
+    # builds again (and reports the overflow again) rather than stepping on truncated rows
+    small = md.NeighborList(N, 3, 24, s.nl.r_list, s.nl.skin, s.ctx.device, s.nl.max_per_cell, s.nl.lanes)
+    md.nl_build(s.ctx, s.box, s.pos, small)
+    assert small.read_flags()[md.FLAG_OVERFLOW] == 1
+    for _ in range(2):
+        small.clear_flags()
+        md.verlet_step(s.ctx, s.box, s.pot, s.pos, s.vel, s.force, s.species, small, 0.005, 1)
+        f = small.read_flags()
+        assert f[md.FLAG_OVERFLOW] == 1 and f[md.FLAG_REBUILDS] >= 1, f
