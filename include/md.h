@@ -310,6 +310,51 @@ md_status fire_batched(md_ctx *ctx, const md_batch *batch, const md_potential *p
 md_status envelope_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, double *g_sigma,
                         double *g_eps, double *energy, int32_t *status, void *stream);
 
+/* Parameter families for envelope_grad_wrt and md_diameter_grad. */
+enum {
+    MD_WRT_SIGMA = 0,          /* the S*S ordered entries of sigma (as g_sigma of envelope_grad) */
+    MD_WRT_EPSILON = 1,        /* the S*S ordered entries of epsilon */
+    MD_WRT_DIAMETER = 2,       /* per-species diameters d_s = sigma_ss, sigma_ab = (d_a + d_b)/2 (App. A): S values */
+    MD_WRT_EPSILON_COMMON = 3  /* one epsilon shared by every pair: 1 value */
+};
+/* How the box moves with the diameters. */
+enum {
+    MD_BOX_FIXED = 0,    /* positions and box fixed */
+    MD_BOX_PACKING = 1   /* 2D box edge at fixed packing fraction, L^2 proportional to sum_s n_s d_s^2 (n_s disks of
+                            species s in the replica), positions fractional (App. A's rescaled box) */
+};
+
+/*
+ * Derivative of each replica's energy U at the batch positions with respect to one parameter family (Sec. 4.2:
+ * at a converged FIRE minimum this is the derivative of the minimized energy E* by the envelope theorem; App. A differentiates with respect to the
+ * small-disk diameter with the box rescaled):
+ *   MD_WRT_SIGMA, MD_WRT_EPSILON: the ordered entries as envelope_grad computes them;
+ *   MD_WRT_EPSILON_COMMON: their sum over the entries of epsilon;
+ *   MD_WRT_DIAMETER: dU/dd_s = 1/2 sum_c (G_sc + G_cs), G_ab = dU/dsigma_ab; with MD_BOX_PACKING (soft spheres
+ *     only, whose u depends on r / sigma) plus (n_s d_s / sum_t n_t d_t^2) dU/dln L, dU/dln L = -sum_ab sigma_ab G_ab
+ *     (minus the virial).
+ * grad: device double [B][m] (m = S*S, S or 1 as above), or, when weights (device double [B]) is given, [m] holding
+ * sum_b weights[b] dU_b/dtheta, summed in a fixed order (the product a reverse pass needs).  energy [B] and status
+ * [B] as in envelope_grad, may be NULL.  MD_ERR_ARG: an unknown family or box, MD_WRT_DIAMETER with sigma not
+ * following the mixing rule (relative 1e-12), MD_BOX_PACKING with another family or potential.  MD_ERR_CAPACITY:
+ * B (2 S^2 + m) doubles above the context's reduction buffer (4 x 65536).  Pair arithmetic single precision, sums
+ * and the chain rule double.
+ */
+md_status envelope_grad_wrt(md_ctx *ctx, const md_batch *batch, const md_potential *pot, int32_t wrt, int32_t box,
+                            const double *weights, double *grad, double *energy, int32_t *status, void *stream);
+
+/*
+ * Per-species diameter derivatives out[b][s] (or, with weights [B], out[s] = sum_b weights[b] dU_b/dd_s) from
+ * dU/dsigma_ab g_sigma [B][S*S] computed elsewhere (e.g. dE_K/dsigma of fire_unrolled_grad), by the chain rule of
+ * envelope_grad_wrt's MD_WRT_DIAMETER: sigma_ab = (d_a + d_b)/2, d_s = sigma_ss of each replica's sigma matrix
+ * (sigma [B][S*S], device, or NULL for pot->sigma, which must then follow the mixing rule), and with MD_BOX_PACKING
+ * the box term (n_s d_s / sum_t n_t d_t^2) dln[b], dln [B] = dU/dln L at fixed fractional positions (e.g. g_lnc of
+ * fire_unrolled_grad), or NULL for soft spheres (minus the virial from g_sigma).  Every pointer is device memory.
+ */
+md_status md_diameter_grad(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const double *sigma,
+                           const double *g_sigma, const double *dln, int32_t box, const double *weights, double *out,
+                           void *stream);
+
 /*
  * Bytes of device workspace fire_unrolled_grad needs for B replicas holding
  * total_n particles in all and K steps: 40 K B bytes of step records
@@ -388,6 +433,10 @@ typedef struct {
 
 /* Number of network parameters (the length of theta). */
 int32_t nn_param_count(void);
+/* Descriptor normalisation of md_nn_params (m, s) from training descriptors G [N][K] (device float): mean[k] and
+ * the population standard deviation scale[k] over the N rows (1 where it is below 1e-8), in double and in a fixed
+ * order.  N >= 1. */
+md_status nn_descriptor_stats(md_ctx *ctx, const float *G, int32_t N, float *mean, float *scale, void *stream);
 /* G[i][k] (float [N][K]) over a neighbor list with r_list - skin >= r_c (3D; a segmented list gives each
  * system's; MD_ERR_ARG for a list that does not cover r_c). */
 md_status nn_descriptors(md_ctx *ctx, const md_box *box, const md_nn_params *nn, const uint32_t *pos, int32_t N,

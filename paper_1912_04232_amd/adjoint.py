@@ -9,7 +9,9 @@ R*: at a converged minimum F(R*) = 0, so by the envelope theorem
 
 which is the derivative the unrolled reverse pass converges to as max |F| -> 0.  Soft-sphere diameters
 enter through sigma_ab = (d_a + d_b) / 2 (App. A), so dE*/dd_s = 1/2 sum_b (G_sb + G_bs) with
-G_ab = dU/dsigma_ab per ordered species pair.  The box is held fixed while the diameters change.
+G_ab = dU/dsigma_ab per ordered species pair.  The box is held fixed while the diameters change.  Every step of
+this arithmetic (the chain rule, and the product with the upstream gradient in backward) runs in the library
+(envelope_grad_wrt, md_diameter_grad); this module only sequences the calls.
 
 ``rescaled_box_sweep`` is the experiment of Sec. 4.2 with the box of App. A: half the disks have diameter D and
 half diameter 1, and the box edge follows the packing fraction, L(D) ~ sqrt(D^2 + 1), so positions are fractional
@@ -64,14 +66,11 @@ class FireMinimizedEnergy(torch.autograd.Function):
     def backward(ctx, g_e):
         md_ctx, batch, pot, S = ctx.md
         batch.pos.copy_(ctx.pos_star)
-        gs, ge, _ = md.envelope_grad(md_ctx, batch, pot)
-        g = g_e.to(gs.device, torch.float64)
-        # dE_b/dd_s = 1/2 sum_c (G_sc + G_cs)
-        dEdd = 0.5 * (gs.sum(dim=2) + gs.sum(dim=1))          # [B][S]
-        dEde = ge.sum(dim=(1, 2))                              # [B]
-        grad_d = (g[:, None] * dEdd).sum(dim=0)
-        grad_e = (g * dEde).sum()
-        return grad_d.cpu(), grad_e.cpu(), None, None, None, None, None, None, None
+        # the library forms sum_b g_b dE_b/dd_s and sum_b g_b dE_b/deps (chain rule and weighted sum on the device)
+        w = g_e.to(batch.pos.device, torch.float64)
+        grad_d = md.envelope_grad_wrt(md_ctx, batch, pot, md.WRT_DIAMETER, md.BOX_FIXED, weights=w)
+        grad_e = md.envelope_grad_wrt(md_ctx, batch, pot, md.WRT_EPSILON_COMMON, md.BOX_FIXED, weights=w)
+        return grad_d.cpu(), grad_e[0].cpu(), None, None, None, None, None, None, None
 
 
 def minimized_energy(diameters: torch.Tensor, epsilon: torch.Tensor, batch: "md.Batch", batch_u: torch.Tensor,
@@ -80,15 +79,6 @@ def minimized_energy(diameters: torch.Tensor, epsilon: torch.Tensor, batch: "md.
     """E*_b for every replica, differentiable w.r.t. the species diameters and epsilon (box fixed)."""
     return FireMinimizedEnergy.apply(diameters, epsilon, batch_u, batch, fp or md.FireParams(), f_tol, max_steps,
                                      md_ctx or md.Context(), alpha)
-
-
-def rescaled_box_dEdD(G, D: float) -> np.ndarray:
-    """dU/dD at fixed fractional positions for every replica, from its dU/dsigma_ab G [B][2][2] at diameters (D, 1):
-    G_AA + (G_AB + G_BA)/2 - D/(D^2 + 1) W with W = sum_ab sigma_ab G_ab (harmonic soft spheres)."""
-    sig = sigma_from_diameters([D, 1.0])
-    dsig = np.array([[1.0, 0.5], [0.5, 0.0]])   # d sigma_ab / dD
-    W = (G * sig[None]).sum(axis=(1, 2))
-    return (G * dsig[None]).sum(axis=(1, 2)) - D / (D * D + 1.0) * W
 
 
 def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: "md.FireParams | None" = None,
@@ -113,9 +103,9 @@ def rescaled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, fp: 
         sig = sigma_from_diameters(d)
         pot = md.Potential("soft_sphere", sig, np.full((2, 2), float(epsilon)), alpha=alpha)
         e, fmax, steps, status = md.fire_batched(md_ctx, bt, pot, fp, max_steps, f_tol)
-        gs, _, _ = md.envelope_grad(md_ctx, bt, pot)
+        g = md.envelope_grad_wrt(md_ctx, bt, pot, md.WRT_DIAMETER, md.BOX_PACKING)   # [B][2]: species 0 has D
         out["energy"].append(e.cpu().numpy())
-        out["dEdD"].append(rescaled_box_dEdD(gs.cpu().numpy(), D))
+        out["dEdD"].append(g[:, 0].cpu().numpy())
         out["fmax"].append(fmax.cpu().numpy())
         out["steps"].append(steps.cpu().numpy())
         out["status"].append(status.cpu().numpy())
@@ -140,13 +130,11 @@ def unrolled_box_batch(diameters, starts, phi: float, epsilon: float = 1.0, alph
     return md.Batch(reps), pot, np.array(sig)
 
 
-def unrolled_box_grad(diameters, n_starts: int, res):
-    """dE_K/dD [len(D)][n_starts] from a fire_unrolled_grad result on an unrolled_box_batch."""
-    nD = len(diameters)
-    G = res["g_sigma"].cpu().numpy().reshape(nD, n_starts, 2, 2)
-    gl = res["g_lnc"].cpu().numpy().reshape(nD, n_starts)
-    Dv = np.asarray(diameters, dtype=np.float64)[:, None]
-    return G[..., 0, 0] + 0.5 * (G[..., 0, 1] + G[..., 1, 0]) + Dv / (Dv * Dv + 1.0) * gl
+def unrolled_box_grad(md_ctx: "md.Context", bt: "md.Batch", pot: "md.Potential", sig, diameters, n_starts: int, res):
+    """dE_K/dD [len(D)][n_starts] from a fire_unrolled_grad result on an unrolled_box_batch: the library's chain rule
+    (md_diameter_grad) with each replica's sigma and its box derivative g_lnc; D is species 0's diameter."""
+    g = md.diameter_grad(md_ctx, bt, pot, res["g_sigma"], dln=res["g_lnc"], box=md.BOX_PACKING, sigma=sig)
+    return g[:, 0].cpu().numpy().reshape(len(diameters), n_starts)
 
 
 def unrolled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, K: int = 300,
@@ -158,7 +146,8 @@ def unrolled_box_sweep(md_ctx: "md.Context", diameters, starts, phi: float, K: i
     bt, pot, sig = unrolled_box_batch(diameters, starts, phi, epsilon, alpha)
     res = md.fire_unrolled_grad(md_ctx, bt, pot, fp or md.FireParams(), K, workspace=workspace, sigma=sig)
     nD, ns = len(diameters), len(starts)
-    out = {"energy": res["energy"].cpu().numpy().reshape(nD, ns), "dEdD": unrolled_box_grad(diameters, ns, res),
+    out = {"energy": res["energy"].cpu().numpy().reshape(nD, ns),
+           "dEdD": unrolled_box_grad(md_ctx, bt, pot, sig, diameters, ns, res),
            "g_lnc": res["g_lnc"].cpu().numpy().reshape(nD, ns),
            "status": res["status"].cpu().numpy().reshape(nD, ns)}
     return out, res

@@ -465,6 +465,91 @@ __global__ __launch_bounds__(kRB) void k_param_grad(BatchArgs a, md_potential pi
     }
 }
 
+// Chain rule from the per-replica gradients to the requested parameters (one workgroup per replica):
+//   MD_WRT_SIGMA / MD_WRT_EPSILON: the S*S ordered entries as they are;
+//   MD_WRT_EPSILON_COMMON: sum over the entries (one epsilon shared by every pair);
+//   MD_WRT_DIAMETER: dU/dd_s = 1/2 sum_c (G_sc + G_cs) (sigma_ab = (d_a + d_b)/2, App. A), plus with a box that
+//   follows the packing fraction (L^2 proportional to sum_t n_t d_t^2 in 2D, positions fractional) the term
+//   (n_s d_s / sum_t n_t d_t^2) dU/dln L, with dU/dln L given per replica or, for soft spheres (u a function of
+//   r / sigma), equal to -sum_ab sigma_ab G_ab (minus the virial).
+struct ChainArgs {
+    int32_t B, S, wrt, box, m;     // m outputs per replica
+    const int32_t *offset;         // [B+1]
+    const int32_t *species;        // [total] or null
+    const double *G;               // [B][S*S] dU/dsigma_ab or dU/deps_ab
+    const double *rep_sigma;       // [B][S*S] or null (then sigma)
+    double sigma[64];              // the potential's sigma matrix
+    const double *dln;             // [B] dU/dln L, or null (minus the virial from G)
+    double *out;                   // [B][m]
+};
+
+__global__ __launch_bounds__(256) void k_chain(ChainArgs a)
+{
+    __shared__ double red[4];
+    __shared__ double cnt[kMaxS];
+    const int b = blockIdx.x;
+    const int S = a.S;
+    const double *G = a.G + (size_t)b * S * S;
+    double *out = a.out + (size_t)b * a.m;
+    if (a.wrt == MD_WRT_SIGMA || a.wrt == MD_WRT_EPSILON) {
+        for (int q = threadIdx.x; q < S * S; q += blockDim.x) out[q] = G[q];
+        return;
+    }
+    if (a.wrt == MD_WRT_EPSILON_COMMON) {
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < S * S; ++q) t += G[q];
+            out[0] = t;
+        }
+        return;
+    }
+    // species counts of the replica (needed for the packing box only)
+    if (a.box == MD_BOX_PACKING) {
+        const int lo = a.offset[b], hi = a.offset[b + 1];
+        for (int sp = 0; sp < S; ++sp) {
+            double c = 0.0;
+            for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) c += (a.species ? a.species[i] : 0) == sp ? 1.0 : 0.0;
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+            __syncthreads();
+            if (threadIdx.x == 0) cnt[sp] = red[0] + red[1] + red[2] + red[3];
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const double *sig = a.rep_sigma ? a.rep_sigma + (size_t)b * S * S : a.sigma;
+    double dln = 0.0, nd2 = 0.0;
+    if (a.box == MD_BOX_PACKING) {
+        if (a.dln) {
+            dln = a.dln[b];
+        } else {
+            for (int q = 0; q < S * S; ++q) dln -= sig[q] * G[q];
+        }
+        for (int t = 0; t < S; ++t) nd2 += cnt[t] * sig[t * S + t] * sig[t * S + t];
+    }
+    for (int sp = 0; sp < S; ++sp) {
+        double g = 0.0;
+        for (int c = 0; c < S; ++c) g += 0.5 * (G[sp * S + c] + G[c * S + sp]);
+        if (a.box == MD_BOX_PACKING && nd2 > 0.0) g += cnt[sp] * sig[sp * S + sp] / nd2 * dln;
+        out[sp] = g;
+    }
+}
+
+// out[k] = sum_b w[b] per[b][k] for k < m, summed in a fixed order by one workgroup (a vector-Jacobian product).
+__global__ __launch_bounds__(256) void k_weighted_sum(const double *per, const double *w, int B, int m, double *out)
+{
+    __shared__ double red[4];
+    for (int k = 0; k < m; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < B; b += blockDim.x) t += w[b] * per[(size_t)b * m + k];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) out[k] = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
+    }
+}
+
 __global__ void k_zero_queue(int32_t *q)
 {
     if (threadIdx.x == 0) q[0] = 0;
@@ -557,6 +642,88 @@ md_status envelope_grad(md_ctx *ctx, const md_batch *bt, const md_potential *pot
     else
         hipLaunchKernelGGL(k_param_grad<1>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, *pot, gp);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+
+// Outputs per replica for a derivative family.
+static int wrt_width(int wrt, int S)
+{
+    return wrt == MD_WRT_SIGMA || wrt == MD_WRT_EPSILON ? S * S : (wrt == MD_WRT_DIAMETER ? S : 1);
+}
+
+// The chain-rule launches shared by envelope_grad_wrt and md_diameter_grad: per-replica results into `per`
+// (scratch) or, without weights, straight into out.
+static md_status launch_chain(const md_batch *bt, const md_potential *pot, int wrt, int box, const double *G,
+                              const double *rep_sigma, const double *dln, const double *weights, double *per,
+                              double *out, hipStream_t s)
+{
+    ChainArgs c{};
+    c.B = bt->B;
+    c.S = pot->n_species;
+    c.wrt = wrt;
+    c.box = box;
+    c.m = wrt_width(wrt, c.S);
+    c.offset = bt->offset;
+    c.species = bt->species;
+    c.G = G;
+    c.rep_sigma = rep_sigma;
+    for (int q = 0; q < 64; ++q) c.sigma[q] = pot->sigma[q];
+    c.dln = dln;
+    c.out = weights ? per : out;
+    hipLaunchKernelGGL(k_chain, dim3(bt->B), dim3(256), 0, s, c);
+    if (weights) hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(256), 0, s, per, weights, bt->B, c.m, out);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+// The diameter derivative needs sigma_ab = (d_a + d_b)/2 with d_s = sigma_ss.
+static bool mixing_rule(const md_potential *pot)
+{
+    const int S = pot->n_species;
+    for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b) {
+            const double want = 0.5 * (pot->sigma[a * S + a] + pot->sigma[b * S + b]);
+            if (fabs(pot->sigma[a * S + b] - want) > 1e-12 * fabs(want)) return false;
+        }
+    return true;
+}
+
+md_status envelope_grad_wrt(md_ctx *ctx, const md_batch *bt, const md_potential *pot, int32_t wrt, int32_t box,
+                            const double *weights, double *grad, double *energy, int32_t *status, void *stream)
+{
+    DevPot p;
+    md_status st = batch_check(ctx, bt, pot, p);
+    if (st != MD_OK) return st;
+    if (!grad || pot->n_species > kMaxS || wrt < MD_WRT_SIGMA || wrt > MD_WRT_EPSILON_COMMON) return MD_ERR_ARG;
+    if (box != MD_BOX_FIXED && box != MD_BOX_PACKING) return MD_ERR_ARG;
+    if (wrt == MD_WRT_DIAMETER && !mixing_rule(pot)) return MD_ERR_ARG;
+    if (box == MD_BOX_PACKING && (wrt != MD_WRT_DIAMETER || pot->kind != MD_SOFT_SPHERE)) return MD_ERR_ARG;
+    if (bt->B == 0) return MD_OK;
+    const int S = pot->n_species, m = wrt_width(wrt, S);
+    // scratch: dU/dsigma and dU/deps per replica, then the per-replica results when they are weighted
+    if ((int64_t)bt->B * (2 * S * S + m) > (int64_t)4 * md_partials_blocks()) return MD_ERR_CAPACITY;
+    double *gs = ctx->partials, *ge = gs + (size_t)bt->B * S * S, *per = ge + (size_t)bt->B * S * S;
+    hipStream_t s = (hipStream_t)stream;
+    st = envelope_grad(ctx, bt, pot, gs, ge, energy, status, stream);
+    if (st != MD_OK) return st;
+    const bool eps = wrt == MD_WRT_EPSILON || wrt == MD_WRT_EPSILON_COMMON;
+    return launch_chain(bt, pot, wrt, box, eps ? ge : gs, nullptr, nullptr, weights, per, grad, s);
+}
+
+md_status md_diameter_grad(md_ctx *ctx, const md_batch *bt, const md_potential *pot, const double *sigma,
+                           const double *g_sigma, const double *dln, int32_t box, const double *weights, double *out,
+                           void *stream)
+{
+    if (!ctx || !bt || !pot || !g_sigma || !out || bt->B < 0 || pot->n_species < 1 || pot->n_species > kMaxS)
+        return MD_ERR_ARG;
+    if (box != MD_BOX_FIXED && box != MD_BOX_PACKING) return MD_ERR_ARG;
+    if (bt->B > 0 && (!bt->offset || (pot->n_species > 1 && !bt->species))) return MD_ERR_ARG;
+    if (!sigma && !mixing_rule(pot)) return MD_ERR_ARG;
+    if (box == MD_BOX_PACKING && (bt->dim != 2 || (!dln && pot->kind != MD_SOFT_SPHERE))) return MD_ERR_ARG;
+    if (bt->B == 0) return MD_OK;
+    const int S = pot->n_species;
+    if (weights && (int64_t)bt->B * S > (int64_t)4 * md_partials_blocks()) return MD_ERR_CAPACITY;
+    return launch_chain(bt, pot, MD_WRT_DIAMETER, box, g_sigma, sigma, dln, weights, ctx->partials, out,
+                        (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -34,7 +34,6 @@
 #include <string.h>
 
 #include <mutex>
-#include <type_traits>
 
 #include "../../include/md.h"
 #include "md_device.h"
@@ -390,8 +389,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
         return q < total ? (uint32_t)t_src * M + (uint32_t)(q - t_ex) : 0u;
     };
     // packed test: a lane whose spare 16-bit component holds -32768 has R16 >= 2^30, above pk_hi for every
-    // particle, so it never passes and never enters the uncertain band; it marks lanes past the last candidate and,
-    // while a particle is tested, the particle's own entry
+    // particle, so it never passes and never enters the uncertain band; it marks lanes past the last candidate
     constexpr uint32_t kMark = D == 3 ? 0x80000000u : 0x8000u;
     int longest = 0;
     for (int base = 0; base < total; base += NS * 64) {
@@ -428,9 +426,8 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
             const uint32_t pxy = pack_hi16(ui[0], ui[1]), pz = D == 3 ? ui[2] >> 16 : 0u;
             const uint32_t iw4 = (uint32_t)i * W * 4u;
             int n = base > 0 ? __builtin_amdgcn_readfirstlane(ncnt[p]) : 0;
-            // the particle is candidate p (its cell comes first): with the packed test and p < 64 its own entry in
-            // slot 0 is marked while it is tested; otherwise the entries are compared with its index
-            auto test_slots = [&](auto marked) {
+            // the particle itself is the one candidate with its own index
+            auto test_slots = [&]() {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (s >= nslots) break;
@@ -440,8 +437,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                         const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
                         const uint64_t lo = __builtin_amdgcn_sicmp(r2, lp.pk_lo, kICmpSLT);
                         const uint64_t hi = __builtin_amdgcn_sicmp(r2, lp.pk_hi, kICmpSLT);
-                        if constexpr (decltype(marked)::value) acc = lo;
-                        else acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                        acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
                         band = hi & ~lo;
                     } else {
                         const uint32_t uj[3] = {ca[s], cb[s], cc[s]};
@@ -493,14 +489,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                     n += __popcll(acc);
                 }
             };
-            if (PK && base == 0 && p < 64) {
-                const uint32_t keep = cb[0];
-                cb[0] = lane == p ? keep | kMark : keep;
-                test_slots(std::integral_constant<bool, true>());
-                cb[0] = keep;
-            } else {
-                test_slots(std::integral_constant<bool, false>());
-            }
+            test_slots();
             if (!last_batch) {
                 if (lane == 0) ncnt[p] = n;
             } else {

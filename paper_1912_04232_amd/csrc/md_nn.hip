@@ -732,15 +732,57 @@ __global__ __launch_bounds__(64) void k_nn_train(NNDev p, const float *__restric
     if (lane == 0) out[ob3] = gb3;
 }
 
-// grad[q] = sum over waves w (in order) of partial[w][q], in double.
-__global__ __launch_bounds__(kBlock) void k_nn_grad_reduce(const float *__restrict__ partial, int nw,
-                                                           float *__restrict__ grad)
+// grad[q] = sum over waves w of partial[w][q], in double and in a fixed order: a workgroup takes 64 parameters, its 16
+// waves sum the partials w = g, g + 16, ... (g = the wave) and the 16 sums are added in order of g.
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(64 * kRedGroups) void k_nn_grad_reduce(const float *__restrict__ partial, int nw,
+                                                                    float *__restrict__ grad)
 {
-    int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= kNP) return;
+    __shared__ double part[kRedGroups][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int q = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int w = 0; w < nw; ++w) acc += (double)partial[(size_t)w * kNP + q];
-    grad[q] = (float)acc;
+    if (q < kNP)
+        for (int w = g; w < nw; w += kRedGroups) acc += (double)partial[(size_t)w * kNP + q];
+    part[g][lane] = acc;
+    __syncthreads();
+    if (g == 0 && q < kNP) {
+        double t = 0.0;
+#pragma unroll
+        for (int h = 0; h < kRedGroups; ++h) t += part[h][lane];
+        grad[q] = (float)t;
+    }
+}
+
+// Per basis function k (one workgroup each) over the N descriptors G [N][K]: mean m[k] and population standard
+// deviation s[k] (1 where it is below 1e-8), in double and in a fixed order, two passes.
+__global__ __launch_bounds__(kBlock) void k_nn_desc_stats(const float *__restrict__ G, int N, float *m, float *sd)
+{
+    __shared__ double red[kBlock / 64];
+    const int k = blockIdx.x;
+    auto block_sum = [&](double v) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+        __syncthreads();
+        return t;
+    };
+    double sum = 0.0;
+    for (int i = threadIdx.x; i < N; i += kBlock) sum += (double)G[(size_t)i * kK + k];
+    const double mean = block_sum(sum) / (double)(N > 0 ? N : 1);
+    double var = 0.0;
+    for (int i = threadIdx.x; i < N; i += kBlock) {
+        const double d = (double)G[(size_t)i * kK + k] - mean;
+        var += d * d;
+    }
+    const double sdev = sqrt(block_sum(var) / (double)(N > 0 ? N : 1));
+    if (threadIdx.x == 0) {
+        m[k] = (float)mean;
+        sd[k] = sdev > 1e-8 ? (float)sdev : 1.0f;
+    }
 }
 
 // One workgroup per system s of `seg` atoms: E_s (double, fixed order), gE[s] and the system's part of the
@@ -957,7 +999,7 @@ md_status nn_mlp_grad(md_ctx *ctx, const md_nn_params *q, const float *G, int32_
     int nw = ntiles < kTrainWaves ? ntiles : kTrainWaves;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_nn_train, dim3(nw), dim3(64), 0, s, p, G, N, segment, gE, ebar, ctx->nn_partial);
-    hipLaunchKernelGGL(k_nn_grad_reduce, dim3((kNP + kBlock - 1) / kBlock), dim3(kBlock), 0, s, ctx->nn_partial, nw,
+    hipLaunchKernelGGL(k_nn_grad_reduce, dim3((kNP + 63) / 64), dim3(64 * kRedGroups), 0, s, ctx->nn_partial, nw,
                        grad);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
@@ -969,6 +1011,13 @@ md_status nn_adam(md_ctx *ctx, float *theta, float *m, float *v, const float *gr
     float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_nn_adam, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, (hipStream_t)stream, theta, m, v,
                        grad, n, lr, beta1, beta2, eps, c1, c2, W1, W2);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status nn_descriptor_stats(md_ctx *ctx, const float *G, int32_t N, float *mean, float *scale, void *stream)
+{
+    if (!ctx || !G || !mean || !scale || N < 1) return MD_ERR_ARG;
+    hipLaunchKernelGGL(k_nn_desc_stats, dim3(kK), dim3(kBlock), 0, (hipStream_t)stream, G, N, mean, scale);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

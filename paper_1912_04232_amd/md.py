@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(HERE, "libmdcore.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
 
 MD_LJ, MD_SOFT_SPHERE, MD_MORSE = 0, 1, 2
+WRT_SIGMA, WRT_EPSILON, WRT_DIAMETER, WRT_EPSILON_COMMON = 0, 1, 2, 3
+BOX_FIXED, BOX_PACKING = 0, 1
 FLAG_OVERFLOW, FLAG_MAXCOUNT, FLAG_NONFINITE, FLAG_REBUILDS = 0, 1, 2, 3
 FLAG_CELL_OVERFLOW, FLAG_STALE, FLAG_MAXCELL, FLAG_STEPS, NFLAGS = 4, 5, 6, 7, 8
 
@@ -123,6 +125,10 @@ _SIGNATURES = {
     "fire_batched": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
                      ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
     "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
+    "envelope_grad_wrt": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.c_int32, ctypes.c_int32, P,
+                          P, P, P, P],
+    "md_diameter_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, ctypes.c_int32, P, P, P],
+    "nn_descriptor_stats": [P, P, ctypes.c_int32, P, P, P],
     "fire_unrolled_workspace_bytes": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32],
     "fire_unrolled_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, ctypes.POINTER(c_fire_params),
                            ctypes.c_int32, P, ctypes.c_uint64, P, P, P, P, P, P, P, P],
@@ -637,6 +643,37 @@ def envelope_grad(ctx: Context, batch: Batch, pot: Potential):
     return gs[: batch.B], ge[: batch.B], e[: batch.B]
 
 
+def envelope_grad_wrt(ctx: Context, batch: Batch, pot: Potential, wrt: int, box: int = BOX_FIXED, weights=None):
+    """dU_b/dtheta for one parameter family (WRT_*) at the batch positions: [B][m] (m = S*S, S or 1), or with
+    weights [B] (float64 device tensor) the weighted sum over replicas [m]."""
+    dev = batch.pos.device
+    S = pot.n_species
+    m = S * S if wrt in (WRT_SIGMA, WRT_EPSILON) else (S if wrt == WRT_DIAMETER else 1)
+    out = torch.zeros((m,) if weights is not None else (max(batch.B, 1), m), dtype=torch.float64, device=dev)
+    b, p = batch.c(pot.cutoff()), pot.c()
+    w = None if weights is None else weights.to(dev, torch.float64).contiguous()
+    _check("envelope_grad_wrt", load().envelope_grad_wrt(ctx.h, ctypes.byref(b), ctypes.byref(p), int(wrt), int(box),
+                                                         _ptr(w), _ptr(out), None, None, _stream()))
+    return out if weights is not None else out[: batch.B]
+
+
+def diameter_grad(ctx: Context, batch: Batch, pot: Potential, g_sigma: torch.Tensor, dln=None, box: int = BOX_FIXED,
+                  sigma=None, weights=None):
+    """md_diameter_grad: per-species diameter derivatives [B][S] (or weighted [S]) from dU/dsigma_ab g_sigma
+    [B][S][S] (float64 device), with per-replica sigma [B][S][S] or the potential's, and for BOX_PACKING the box
+    derivative dln [B] (or minus the virial for soft spheres when None)."""
+    dev = batch.pos.device
+    S = pot.n_species
+    out = torch.zeros((S,) if weights is not None else (max(batch.B, 1), S), dtype=torch.float64, device=dev)
+    b, p = batch.c(pot.cutoff()), pot.c()
+    sg = None if sigma is None else torch.as_tensor(sigma, dtype=torch.float64, device=dev).contiguous()
+    w = None if weights is None else weights.to(dev, torch.float64).contiguous()
+    _check("md_diameter_grad", load().md_diameter_grad(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(sg),
+                                                       _ptr(g_sigma.contiguous()), _ptr(dln), int(box), _ptr(w),
+                                                       _ptr(out), _stream()))
+    return out if weights is not None else out[: batch.B]
+
+
 def fire_unrolled_grad(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, K: int, rbar0: bool = False,
                        mixed: bool = False, workspace=None, sigma=None):
     """K FIRE steps on every replica, then dE_K/dtheta by reverse mode through the steps (one launch).
@@ -715,6 +752,12 @@ class NNParams:
                     b1=self.b1.cpu().numpy().astype(np.float64), b2=self.b2.cpu().numpy().astype(np.float64),
                     w3=self.w3.cpu().numpy().astype(np.float64), b3=float(self.b3.cpu()[0]),
                     m=self.m.cpu().numpy().astype(np.float64), s=self.s.cpu().numpy().astype(np.float64))
+
+
+def nn_descriptor_stats(ctx: Context, G: torch.Tensor, mean: torch.Tensor, scale: torch.Tensor):
+    """Per-basis mean and population standard deviation of G [N][K] (float32 device) into mean, scale [K]."""
+    _check("nn_descriptor_stats", load().nn_descriptor_stats(ctx.h, _ptr(G), G.shape[0], _ptr(mean), _ptr(scale),
+                                                             _stream()))
 
 
 def nn_descriptors(ctx: Context, box: Box, nn: NNParams, pos: torch.Tensor, nl: NeighborList) -> torch.Tensor:

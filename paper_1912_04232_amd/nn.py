@@ -43,8 +43,9 @@ class Network:
         self.v_adam = torch.zeros(P, dtype=torch.float32, device=dev)
         self.W1 = torch.zeros(H * K, dtype=torch.int16, device=dev)
         self.W2 = torch.zeros(H * H, dtype=torch.int16, device=dev)
-        self.m = torch.as_tensor(np.asarray(m, np.float32), device=dev).contiguous()
-        self.s = torch.as_tensor(np.asarray(s, np.float32), device=dev).contiguous()
+        as_dev = lambda x: (x.to(dev, torch.float32) if isinstance(x, torch.Tensor)
+                            else torch.as_tensor(np.asarray(x, np.float32), device=dev)).contiguous()
+        self.m, self.s = as_dev(m), as_dev(s)
         self.mu0, self.mu1, self.r_c = float(mu0), float(mu1), float(r_c)
         self.step = 0
         md._check("nn_cast_weights", md.load().nn_cast_weights(ctx.h, md._ptr(self.theta),
@@ -195,12 +196,13 @@ def generate_lj_data(ctx: md.Context, n_runs=20, per_run=100, equilibrate=2000, 
     return box, torch.stack(P), torch.cat(E), torch.stack(F), np.array(T)
 
 
-def descriptor_scale(G: torch.Tensor):
-    """Per-basis mean and standard deviation of the training descriptors (host numpy, set-up only)."""
-    g = G.cpu().numpy().astype(np.float64)
-    m = g.mean(axis=0)
-    s = g.std(axis=0)
-    return m, np.where(s > 1e-8, s, 1.0)
+def descriptor_scale(ctx, G: torch.Tensor):
+    """Per-basis mean and standard deviation of the training descriptors (nn_descriptor_stats, on the device)."""
+    K = G.shape[1]
+    m = torch.zeros(K, dtype=torch.float32, device=G.device)
+    s = torch.ones(K, dtype=torch.float32, device=G.device)
+    md.nn_descriptor_stats(ctx, G.contiguous(), m, s)
+    return m, s
 
 
 def make_batches(ctx, box, net, P, E, F, idx, per_batch, r_list=2.5):
@@ -373,7 +375,7 @@ def train_network(ctx: md.Context, n_runs=20, per_run=100, steps=20000, per_batc
     w = inputs.nn_init(seed)
     probe = Network(ctx, w, np.zeros(K), np.ones(K))
     G = torch.cat([b.G for b in make_batches(ctx, box, probe, P, E, F, train_idx, per_batch)])
-    m, s = descriptor_scale(G)
+    m, s = descriptor_scale(ctx, G)
     del G
     net = Network(ctx, w, m, s)
     train = make_batches(ctx, box, net, P, E, F, train_idx, per_batch)

@@ -55,7 +55,7 @@ def run_unrolled(ctx, K: int = 300, phi: float = 1.0, n_starts: int = 100, launc
     bt, pot, sig = adjoint.unrolled_box_batch(Ds, starts, phi)
     u0 = bt.pos.clone()
     res = md.fire_unrolled_grad(ctx, bt, pot, md.FireParams(), K, sigma=sig)
-    G = adjoint.unrolled_box_grad(Ds, n_starts, res)
+    G = adjoint.unrolled_box_grad(ctx, bt, pot, sig, Ds, n_starts, res)
     E = res["energy"].cpu().numpy().reshape(len(Ds), n_starts)
     done = int((res["status"].cpu().numpy() == 1).sum())
     t = None

@@ -105,14 +105,27 @@ def test_envelope_grad_matches_oracle_at_same_positions(md, orc):
     ctx = md.Context()
     bt = md.Batch(reps)
     d = np.array([1.0, 1.4])
-    gs, ge, e = (t.cpu().numpy() for t in md.envelope_grad(ctx, bt, ss_pot(md, d)))
+    import torch
+    pot = ss_pot(md, d)
+    gs, ge, e = (t.cpu().numpy() for t in md.envelope_grad(ctx, bt, pot))
+    # the library's chain rule: per-species diameters (sigma_ab = (d_a + d_b)/2) and one shared epsilon
+    gd = md.envelope_grad_wrt(ctx, bt, pot, md.WRT_DIAMETER).cpu().numpy()
+    gE = md.envelope_grad_wrt(ctx, bt, pot, md.WRT_EPSILON_COMMON).cpu().numpy()[:, 0]
+    w = torch.tensor([0.5, -1.0, 2.0, 0.25][: len(reps)], dtype=torch.float64, device=bt.pos.device)
+    gdw = md.envelope_grad_wrt(ctx, bt, pot, md.WRT_DIAMETER, weights=w).cpu().numpy()
+    g_all = []
     for b, r in enumerate(reps):
         x = orc.decode(r["u"], r["L"][:2])
         g_orc = orc.diameter_grad(x, r["L"][:2], d, 1.0, r["species"])
+        g_all.append(g_orc)
         g_gpu = 0.5 * (gs[b].sum(1) + gs[b].sum(0))
         assert np.allclose(g_gpu, g_orc, rtol=1e-5, atol=1e-9 * np.abs(g_orc).max()), (b, g_gpu, g_orc)
+        assert np.allclose(gd[b], g_orc, rtol=1e-5, atol=1e-9 * np.abs(g_orc).max()), (b, gd[b], g_orc)
         # dE/deps = E/eps at any positions
         assert ge[b].sum() == pytest.approx(e[b], rel=1e-6)
+        assert gE[b] == pytest.approx(e[b], rel=1e-6)
+    want = (w.cpu().numpy()[:, None] * np.array(g_all)).sum(0)
+    assert np.allclose(gdw, want, rtol=1e-5, atol=1e-9 * np.abs(want).max())
 
 
 def test_adjoint_autograd_matches_finite_differences(md):
@@ -209,9 +222,9 @@ def fig3_starts(n, count, seed):
 
 
 def test_rescaled_box_grad_matches_oracle(md, orc):
-    """dU/dD with the box rescaled with D (App. A) at fixed fractional positions, from the GPU's parameter-gradient
-    sums, against the FP64 oracle at the same seeded positions, for several D around the disorder maximum."""
-    from paper_1912_04232_amd import adjoint
+    """dU/dD with the box rescaled with D (App. A) at fixed fractional positions (envelope_grad_wrt, diameter of
+    species 0, packing box), against the FP64 oracle at the same seeded positions, for several D around the
+    disorder maximum."""
     ctx = md.Context()
     starts = fig3_starts(64, 4, 5101)
     sp = inputs.bidisperse_species(64)
@@ -220,8 +233,8 @@ def test_rescaled_box_grad_matches_oracle(md, orc):
         reps = [dict(N=64, L=[L, L, 0.0], u=u, species=sp) for u in starts]
         bt = md.Batch(reps)
         pot = ss_pot(md, (D, 1.0))
-        gs, _, e = md.envelope_grad(ctx, bt, pot)
-        g = adjoint.rescaled_box_dEdD(gs.cpu().numpy(), D)
+        _, _, e = md.envelope_grad(ctx, bt, pot)
+        g = md.envelope_grad_wrt(ctx, bt, pot, md.WRT_DIAMETER, md.BOX_PACKING)[:, 0].cpu().numpy()
         e = e.cpu().numpy()
         for b, u in enumerate(starts):
             U, go = orc.rescaled_box_grad(u, float(np.float32(L)), D, sp)

@@ -81,12 +81,25 @@ def test_morse_verlet_steps_and_conservation(md, orc):
         say("verlet", n, np.abs(d).max(), rel_l2(s.vel.cpu().numpy(), xv))
         assert np.abs(d).max() < 1e-5 and rel_l2(s.vel.cpu().numpy(), xv) < 1e-5
         assert rel_l2(s.force.cpu().numpy(), F) < 1e-4
-    E = []
-    for _ in range(10):
-        update(200)
-        E.append(s.potential_energy() + 0.5 * float((s.vel.double() ** 2).sum()))
-    say("total energy", E[0], "drift", max(E) - min(E))
-    assert max(E) - min(E) < 2e-3 * s.N
+    # the total energy over 8 time units at dt = 0.004 and, from the same state, at dt = 0.002: the spread of the
+    # velocity-Verlet energy error shrinks with dt^2 (a force inconsistent with the energy, or a missing pair, would
+    # leave an error that does not), and stays below 3e-3 per particle at this stiff, hot state (alpha = 5)
+    import torch
+    state = [t.clone() for t in (s.pos, s.vel, s.force)]
+    spread = {}
+    for dt, n in ((0.004, 200), (0.002, 400)):
+        for t, v0 in zip((s.pos, s.vel, s.force), state):
+            t.copy_(v0)
+        s.build()
+        init, update = md.nve(s, dt)
+        E = []
+        for _ in range(10):
+            update(n)
+            E.append(s.potential_energy() + 0.5 * float((s.vel.double() ** 2).sum()))
+        spread[dt] = max(E) - min(E)
+        say("dt", dt, "total energy", E[0], "spread", spread[dt])
+    assert spread[0.004] < 3e-3 * s.N
+    assert spread[0.004] / spread[0.002] > 2.5, spread
 
 
 def test_replica_paths_refuse_morse(md):

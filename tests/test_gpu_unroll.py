@@ -247,6 +247,14 @@ def test_unrolled_rescaled_box_derivative(md, orc, un):
     out = run(md, [dict(N=N, L=np.array([L, L, 0.0]), u=u, species=sp)], mpot, K)
     gs = out["g_sigma"][0]
     g = gs[0, 0] + 0.5 * (gs[0, 1] + gs[1, 0]) + D / (D * D + 1.0) * out["g_lnc"][0]
+    # the library's chain rule (md_diameter_grad with the packing box) gives the same number from the same sums
+    import torch
+    ctx = md.Context()
+    bt = md.Batch([dict(N=N, L=np.array([L, L, 0.0]), u=u, species=sp)])
+    dev = bt.pos.device
+    glib = md.diameter_grad(ctx, bt, mpot, torch.as_tensor(out["g_sigma"], device=dev),
+                            dln=torch.as_tensor(out["g_lnc"], device=dev), box=md.BOX_PACKING)
+    assert float(glib[0, 0]) == pytest.approx(g, rel=1e-12, abs=1e-15)
     R0 = un.torus_to_frac(u)
     h = 1e-6
 
