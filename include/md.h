@@ -281,6 +281,14 @@ typedef struct {
     const int32_t *species;  /* [offset[B]] or NULL when the potential has one species */
 } md_batch;
 
+/* Launch shape of fire_batched, chosen by the caller (e.g. by timing trial launches): threads per replica
+ * workgroup (512: 8 particles per thread, or 1024: 4) and the cell edge as a multiple (1 to 4) of the
+ * interaction range (larger cells: fewer cells to sort, more candidates per particle). */
+typedef struct {
+    int32_t threads;
+    float cell_factor;
+} md_batch_config;
+
 /*
  * FIRE (same rules as fire_step, v = 0 and dt_start / alpha_start at the
  * start) on every replica of the batch in one launch: one workgroup per
@@ -290,11 +298,14 @@ typedef struct {
  * (double), max_i |F_i|, steps taken, status (1 converged, 0 not converged
  * within max_steps, -1 replica too large).  All outputs are device arrays of
  * length B.  Calls that share a ctx must not overlap (the work queue lives in
- * the ctx).
+ * the ctx).  cfg may be NULL (512 threads, cells of the interaction range);
+ * MD_ERR_ARG for another thread count or a cell factor outside [1, 4].  Both
+ * change only the order of floating-point sums (a particle's pair terms, the
+ * workgroup reductions), not the method.
  */
 md_status fire_batched(md_ctx *ctx, const md_batch *batch, const md_potential *pot, const md_fire_params *fp,
-                       int32_t max_steps, double f_tol, double *energy, double *fmax, int32_t *steps,
-                       int32_t *status, void *stream);
+                       const md_batch_config *cfg, int32_t max_steps, double f_tol, double *energy, double *fmax,
+                       int32_t *steps, int32_t *status, void *stream);
 
 /*
  * Gradient of each replica's energy U = 1/2 sum_{i != j} u(r_ij) with respect

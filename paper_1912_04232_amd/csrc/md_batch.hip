@@ -28,11 +28,10 @@ using namespace md;
 
 namespace {
 
-constexpr int kRB = 512;          // threads per replica workgroup
-constexpr int kPerThread = 8;     // particles per thread
-constexpr int kMaxRepN = kRB * kPerThread;
+constexpr int kRB = 512;          // threads per replica workgroup of the gradient kernel (FIRE: 512 or 1024)
+constexpr int kMaxRepN = 4096;    // particles per replica (kMaxRepN / RB per thread)
 constexpr int kMaxRepCells = 3072;
-constexpr int kWaves = kRB / 64;
+constexpr int kWaves = 1024 / 64;  // LDS slots for the largest workgroup's waves
 constexpr int kMaxS = 8;          // species handled by the gradient kernel
 
 struct RepGeom {
@@ -92,29 +91,32 @@ __device__ __forceinline__ int rep_cell(const uint32_t *u, const RepGeom &g)
 }
 
 // Workgroup-wide sum / max of one double per thread; every thread gets the same value.
+template <int RB>
 __device__ __forceinline__ double wg_sum(double v, Lds &s)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0.0;
-    for (int w = 0; w < kWaves; ++w) r += s.red[w];
+    for (int w = 0; w < RB / 64; ++w) r += s.red[w];
     __syncthreads();
     return r;
 }
 
+template <int RB>
 __device__ __forceinline__ double wg_max(double v, Lds &s)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0.0;
-    for (int w = 0; w < kWaves; ++w) r = fmax(r, s.red[w]);
+    for (int w = 0; w < RB / 64; ++w) r = fmax(r, s.red[w]);
     __syncthreads();
     return r;
 }
 
 // Exclusive scan of one int per thread over the workgroup (shuffles + LDS, no atomics).
+template <int RB>
 __device__ __forceinline__ int wg_excl_scan(int v, Lds &s, int &total)
 {
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -127,7 +129,7 @@ __device__ __forceinline__ int wg_excl_scan(int v, Lds &s, int &total)
     __syncthreads();
     int off = 0;
     total = 0;
-    for (int q = 0; q < kWaves; ++q) {
+    for (int q = 0; q < RB / 64; ++q) {
         if (q < w) off += s.wtot[q];
         total += s.wtot[q];
     }
@@ -137,15 +139,17 @@ __device__ __forceinline__ int wg_excl_scan(int v, Lds &s, int &total)
 
 // Cell list of the replica's LDS positions: counts (LDS integer atomics), exclusive scan,
 // placement, then each cell's members ordered by index.
+template <int RB>
 __device__ void rep_cells(Lds &s, int n, const RepGeom &g)
 {
+    constexpr int PT = kMaxRepN / RB;
     int t = threadIdx.x;
-    for (int c = t; c < g.C; c += kRB) s.start[c] = 0;
+    for (int c = t; c < g.C; c += RB) s.start[c] = 0;
     __syncthreads();
-    int cell[kPerThread], slot[kPerThread];
+    int cell[PT], slot[PT];
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        int i = t + k * kRB;
+    for (int k = 0; k < PT; ++k) {
+        int i = t + k * RB;
         cell[k] = 0;
         slot[k] = 0;
         if (i < n) {
@@ -154,12 +158,12 @@ __device__ void rep_cells(Lds &s, int n, const RepGeom &g)
         }
     }
     __syncthreads();
-    int chunk = (g.C + kRB - 1) / kRB;
+    int chunk = (g.C + RB - 1) / RB;
     int lo = min(g.C, t * chunk), hi = min(g.C, lo + chunk);
     int local = 0;
     for (int c = lo; c < hi; ++c) local += s.start[c];
     int total;
-    int run = wg_excl_scan(local, s, total);
+    int run = wg_excl_scan<RB>(local, s, total);
     for (int c = lo; c < hi; ++c) {
         int v = s.start[c];
         s.start[c] = run;
@@ -168,12 +172,12 @@ __device__ void rep_cells(Lds &s, int n, const RepGeom &g)
     if (t == 0) s.start[g.C] = n;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        int i = t + k * kRB;
+    for (int k = 0; k < PT; ++k) {
+        int i = t + k * RB;
         if (i < n) s.sorted[s.start[cell[k]] + slot[k]] = (int16_t)i;
     }
     __syncthreads();
-    for (int c = t; c < g.C; c += kRB) {
+    for (int c = t; c < g.C; c += RB) {
         int a0 = s.start[c], a1 = s.start[c + 1];
         for (int a = a0 + 1; a < a1; ++a) {
             int16_t key = s.sorted[a];
@@ -209,12 +213,13 @@ __device__ __forceinline__ void rep_pairs(const Lds &s, const RepGeom &g, int i,
     }
 }
 
-template <int KIND>
+template <int KIND, int RB>
 __device__ __forceinline__ void rep_forces(const Lds &s, const RepGeom &g, const DevPot &p, int n, float (*F)[2])
 {
+    constexpr int PT = kMaxRepN / RB;
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        int i = threadIdx.x + k * kRB;
+    for (int k = 0; k < PT; ++k) {
+        int i = threadIdx.x + k * RB;
         float fx = 0.0f, fy = 0.0f;
         if (i < n) {
             rep_pairs(s, g, i, p.S, [&](int, const uint32_t *ui, const uint32_t *uj, int pt) {
@@ -229,13 +234,14 @@ __device__ __forceinline__ void rep_forces(const Lds &s, const RepGeom &g, const
     }
 }
 
+template <int RB>
 __device__ bool rep_load(Lds &s, const BatchArgs &a, int b, float range, int &n, int &off, RepGeom &g)
 {
     off = a.offset[b];
     n = a.offset[b + 1] - off;
     g = rep_geom(a.box[2 * b], a.box[2 * b + 1], range);
     if (n < 0 || n > kMaxRepN || g.C > kMaxRepCells) return false;
-    for (int i = threadIdx.x; i < n; i += kRB) {
+    for (int i = threadIdx.x; i < n; i += RB) {
         s.pos[2 * i] = a.pos[2 * (size_t)(off + i)];
         s.pos[2 * i + 1] = a.pos[2 * (size_t)(off + i) + 1];
         s.spec[i] = a.species ? (int8_t)a.species[off + i] : (int8_t)0;
@@ -262,9 +268,10 @@ struct FireBatchParams {
     double f_tol;
 };
 
-template <int KIND>
-__global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, FireBatchParams fp)
+template <int KIND, int RB>
+__global__ __launch_bounds__(RB) void k_fire_batched(BatchArgs a, DevPot pin, FireBatchParams fp)
 {
+    constexpr int PT = kMaxRepN / RB;
     __shared__ Lds s;
     if (threadIdx.x == 0) s.pot = pin;
     __syncthreads();
@@ -272,28 +279,28 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
     for (int b = next_replica(s, a.queue); b < a.B; b = next_replica(s, a.queue)) {
         int n, off;
         RepGeom g;
-        if (!rep_load(s, a, b, fp.range, n, off, g)) {
+        if (!rep_load<RB>(s, a, b, fp.range, n, off, g)) {
             if (threadIdx.x == 0) fp.status[b] = -1;
             continue;
         }
-        float v[kPerThread][2], F[kPerThread][2], Fn[kPerThread][2];
+        float v[PT][2], F[PT][2], Fn[PT][2];
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) v[k][0] = v[k][1] = 0.0f;
-        rep_cells(s, n, g);
-        rep_forces<KIND>(s, g, p, n, F);
+        for (int k = 0; k < PT; ++k) v[k][0] = v[k][1] = 0.0f;
+        rep_cells<RB>(s, n, g);
+        rep_forces<KIND, RB>(s, g, p, n, F);
         double fm = 0.0;
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k)
+        for (int k = 0; k < PT; ++k)
             fm = fmax(fm, (double)F[k][0] * F[k][0] + (double)F[k][1] * F[k][1]);
-        fm = wg_max(fm, s);
+        fm = wg_max<RB>(fm, s);
         double dt = fp.dt_start, alpha = fp.alpha_start, mix_v = 1.0, mix_f = 0.0;
         int n_pos = 0, steps = 0;
         bool conv = sqrt(fm) < fp.f_tol;
         while (!conv && steps < fp.max_steps) {
             // velocity mixing decided by the previous step, then r += dt v + dt^2/2 F
 #pragma unroll
-            for (int k = 0; k < kPerThread; ++k) {
-                int i = threadIdx.x + k * kRB;
+            for (int k = 0; k < PT; ++k) {
+                int i = threadIdx.x + k * RB;
                 if (i < n) {
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
@@ -304,13 +311,13 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
                 }
             }
             __syncthreads();
-            rep_cells(s, n, g);
-            rep_forces<KIND>(s, g, p, n, Fn);
+            rep_cells<RB>(s, n, g);
+            rep_forces<KIND, RB>(s, g, p, n, Fn);
             double P = 0.0, vv = 0.0, ff = 0.0;
             fm = 0.0;
 #pragma unroll
-            for (int k = 0; k < kPerThread; ++k) {
-                int i = threadIdx.x + k * kRB;
+            for (int k = 0; k < PT; ++k) {
+                int i = threadIdx.x + k * RB;
                 if (i < n) {
                     double f2 = 0.0;
 #pragma unroll
@@ -325,10 +332,10 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
                     fm = fmax(fm, f2);
                 }
             }
-            P = wg_sum(P, s);
-            vv = wg_sum(vv, s);
-            ff = wg_sum(ff, s);
-            fm = wg_max(fm, s);
+            P = wg_sum<RB>(P, s);
+            vv = wg_sum<RB>(vv, s);
+            ff = wg_sum<RB>(ff, s);
+            fm = wg_max<RB>(fm, s);
             ++steps;
             if (sqrt(fm) < fp.f_tol) {
                 conv = true;
@@ -353,8 +360,8 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
         // energy at the final positions, written back with them
         double e = 0.0;
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            int i = threadIdx.x + k * kRB;
+        for (int k = 0; k < PT; ++k) {
+            int i = threadIdx.x + k * RB;
             if (i < n) {
                 rep_pairs(s, g, i, p.S, [&](int, const uint32_t *ui, const uint32_t *uj, int pt) {
                     float d[2], r2, u = 0.0f;
@@ -363,8 +370,8 @@ __global__ __launch_bounds__(kRB) void k_fire_batched(BatchArgs a, DevPot pin, F
                 });
             }
         }
-        e = 0.5 * wg_sum(e, s);
-        for (int i = threadIdx.x; i < n; i += kRB) {
+        e = 0.5 * wg_sum<RB>(e, s);
+        for (int i = threadIdx.x; i < n; i += RB) {
             a.pos[2 * (size_t)(off + i)] = s.pos[2 * i];
             a.pos[2 * (size_t)(off + i) + 1] = s.pos[2 * i + 1];
         }
@@ -432,11 +439,11 @@ __global__ __launch_bounds__(kRB) void k_param_grad(BatchArgs a, md_potential pi
     for (int b = next_replica(s, a.queue); b < a.B; b = next_replica(s, a.queue)) {
         int n, off;
         RepGeom g;
-        if (!rep_load(s, a, b, gp.range, n, off, g)) {
+        if (!rep_load<kRB>(s, a, b, gp.range, n, off, g)) {
             if (threadIdx.x == 0 && gp.status) gp.status[b] = -1;
             continue;
         }
-        rep_cells(s, n, g);
+        rep_cells<kRB>(s, n, g);
         // one pass per pair type keeps the accumulators in two registers
         for (int q = 0; q < S * S; ++q) {
             double gs = 0.0, ge = 0.0, e = 0.0;
@@ -452,9 +459,9 @@ __global__ __launch_bounds__(kRB) void k_param_grad(BatchArgs a, md_potential pi
                     e += (double)u;
                 });
             }
-            gs = 0.5 * wg_sum(gs, s);
-            ge = 0.5 * wg_sum(ge, s);
-            e = 0.5 * wg_sum(e, s);
+            gs = 0.5 * wg_sum<kRB>(gs, s);
+            ge = 0.5 * wg_sum<kRB>(ge, s);
+            e = 0.5 * wg_sum<kRB>(e, s);
             if (threadIdx.x == 0) {
                 gp.g_sigma[(size_t)b * S * S + q] = gs;
                 gp.g_eps[(size_t)b * S * S + q] = ge;
@@ -587,13 +594,16 @@ int batch_grid(int B)
 extern "C" {
 
 md_status fire_batched(md_ctx *ctx, const md_batch *bt, const md_potential *pot, const md_fire_params *fp,
-                       int32_t max_steps, double f_tol, double *energy, double *fmax, int32_t *steps,
-                       int32_t *status, void *stream)
+                       const md_batch_config *cfg, int32_t max_steps, double f_tol, double *energy, double *fmax,
+                       int32_t *steps, int32_t *status, void *stream)
 {
     DevPot p;
     md_status st = batch_check(ctx, bt, pot, p);
     if (st != MD_OK) return st;
     if (!fp || !energy || !fmax || !steps || !status || max_steps < 0) return MD_ERR_ARG;
+    const int threads = cfg ? cfg->threads : 512;
+    const float cell_factor = cfg ? cfg->cell_factor : 1.0f;
+    if ((threads != 512 && threads != 1024) || !(cell_factor >= 1.0f && cell_factor <= 4.0f)) return MD_ERR_ARG;
     if (bt->B == 0) return MD_OK;
     hipStream_t s = (hipStream_t)stream;
     BatchArgs a = batch_args(ctx, bt);
@@ -608,15 +618,18 @@ md_status fire_batched(md_ctx *ctx, const md_batch *bt, const md_potential *pot,
     q.f_dec = fp->f_dec;
     q.alpha_start = fp->alpha_start;
     q.f_alpha = fp->f_alpha;
-    q.range = md_max_cutoff(pot);
+    q.range = md_max_cutoff(pot) * cell_factor;  // cells of edge >= this; pairs still stop at the potential's range
     q.n_min = fp->n_min;
     q.max_steps = max_steps;
     q.f_tol = f_tol;
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, ctx->queue);
-    if (pot->kind == MD_LJ)
-        hipLaunchKernelGGL(k_fire_batched<0>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, p, q);
-    else
-        hipLaunchKernelGGL(k_fire_batched<1>, dim3(batch_grid(bt->B)), dim3(kRB), 0, s, a, p, q);
+    if (pot->kind == MD_LJ) {
+        if (threads == 1024) hipLaunchKernelGGL((k_fire_batched<0, 1024>), dim3(batch_grid(bt->B)), dim3(1024), 0, s, a, p, q);
+        else hipLaunchKernelGGL((k_fire_batched<0, 512>), dim3(batch_grid(bt->B)), dim3(512), 0, s, a, p, q);
+    } else {
+        if (threads == 1024) hipLaunchKernelGGL((k_fire_batched<1, 1024>), dim3(batch_grid(bt->B)), dim3(1024), 0, s, a, p, q);
+        else hipLaunchKernelGGL((k_fire_batched<1, 512>), dim3(batch_grid(bt->B)), dim3(512), 0, s, a, p, q);
+    }
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

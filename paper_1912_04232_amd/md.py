@@ -75,6 +75,10 @@ class c_nhc_state(ctypes.Structure):
                 ("kT", ctypes.c_double), ("scale", ctypes.c_double), ("M", ctypes.c_int32), ("n_dof", ctypes.c_int32)]
 
 
+class c_batch_config(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("cell_factor", ctypes.c_float)]
+
+
 class c_batch(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int32), ("dim", ctypes.c_int32), ("max_n", ctypes.c_int32),
                 ("max_cells", ctypes.c_int32), ("offset", ctypes.c_void_p), ("box", ctypes.c_void_p),
@@ -123,7 +127,7 @@ _SIGNATURES = {
     "fire_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
                   ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_int32, ctypes.c_double, P],
     "fire_batched": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.POINTER(c_fire_params),
-                     ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
+                     ctypes.POINTER(c_batch_config), ctypes.c_int32, ctypes.c_double, P, P, P, P, P],
     "envelope_grad": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), P, P, P, P, P],
     "envelope_grad_wrt": [P, ctypes.POINTER(c_batch), ctypes.POINTER(c_potential), ctypes.c_int32, ctypes.c_int32, P,
                           P, P, P, P],
@@ -616,18 +620,56 @@ class Batch:
         return from_device_u32(self.pos)[off[b]:off[b + 1]]
 
 
-def fire_batched(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, max_steps: int, f_tol: float):
-    """FIRE on every replica in one launch.  Returns (energy[B] f64, fmax[B] f64, steps[B] i32, status[B] i32)."""
+def fire_batched(ctx: Context, batch: Batch, pot: Potential, fp: FireParams, max_steps: int, f_tol: float,
+                 config: tuple | None = None):
+    """FIRE on every replica in one launch.  Returns (energy[B] f64, fmax[B] f64, steps[B] i32, status[B] i32).
+    config: (threads per replica workgroup, cell factor), e.g. from autotune_fire_batched; None for the default."""
     dev = batch.pos.device
     e = torch.zeros(max(batch.B, 1), dtype=torch.float64, device=dev)
     fm = torch.zeros_like(e)
     st = torch.zeros(max(batch.B, 1), dtype=torch.int32, device=dev)
     status = torch.zeros_like(st)
     b, p, f = batch.c(pot.cutoff()), pot.c(), fp.c()
+    cfg = None
+    if config is not None:
+        cfg = c_batch_config()
+        cfg.threads, cfg.cell_factor = int(config[0]), float(config[1])
     _check("fire_batched", load().fire_batched(ctx.h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(f),
-                                               int(max_steps), ctypes.c_double(f_tol), _ptr(e), _ptr(fm), _ptr(st),
-                                               _ptr(status), _stream()))
+                                               None if cfg is None else ctypes.byref(cfg), int(max_steps),
+                                               ctypes.c_double(f_tol), _ptr(e), _ptr(fm), _ptr(st), _ptr(status),
+                                               _stream()))
     return e[: batch.B], fm[: batch.B], st[: batch.B], status[: batch.B]
+
+
+BATCH_CONFIGS = ((512, 1.0), (512, 1.25), (512, 1.5), (1024, 1.0), (1024, 1.25), (1024, 1.5))
+
+
+def autotune_fire_batched(ctx: Context, batch: Batch, pot: Potential, fp: FireParams | None = None,
+                          trial_steps: int = 200, candidates=BATCH_CONFIGS, repeats: int = 2) -> dict:
+    """Launch shape for fire_batched on this batch: each candidate (threads per replica workgroup, cell factor) runs
+    `trial_steps` FIRE steps on every replica (f_tol 0, from the batch's current positions, restored afterwards),
+    timed with HIP events on the launch stream; the fastest (best of `repeats`) is returned with every timing.
+    Trials take the same steps as a real run, so the time per step they measure is the one that matters."""
+    fp = fp or FireParams()
+    saved = batch.pos.clone()
+    stream = torch.cuda.current_stream()
+    times = {}
+    for cfg in candidates:
+        best = None
+        for _ in range(repeats):
+            batch.pos.copy_(saved)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fire_batched(ctx, batch, pot, fp, trial_steps, 0.0, config=cfg)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        times[cfg] = best
+    batch.pos.copy_(saved)
+    choice = min(times, key=times.get)
+    return {"config": choice, "ms_per_trial": {f"{t}x{c}": v for (t, c), v in times.items()},
+            "trial_steps": trial_steps}
 
 
 def envelope_grad(ctx: Context, batch: Batch, pot: Potential):

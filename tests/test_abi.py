@@ -32,6 +32,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(md.c_fire_state) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(md.c_flock_params) == 10 * 4 + 2 * 4 + 16 * 3 * 4
     assert ctypes.sizeof(md.c_flock_predators) == 6 * 4 + 2 * 8
+    assert ctypes.sizeof(md.c_batch_config) == 8
 
 
 def test_host_side_helpers_without_gpu():

@@ -24,6 +24,12 @@ def md():
     return m
 
 
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
 def replicas(B, seed, n_lo=256, n_hi=700):
     return inputs.ss_batch(B=B, seed=seed, n_lo=n_lo, n_hi=n_hi)
 
@@ -83,6 +89,38 @@ def test_batched_fire_matches_oracle_fire_from_same_start(md, orc):
         say("N", r["N"], "E* gpu", e[b], "oracle", Eo, "fmax", fmax[b], "steps", steps[b], o["steps"])
         assert status[b] == 1
         assert abs(e[b] - Eo) <= 1e-6 * abs(Eo) + 1e-12
+
+
+@pytest.mark.parametrize("K", [1, 5])
+def test_batched_fire_first_steps_match_oracle_at_workload_sizes(md, orc, K):
+    """K FIRE steps (f_tol 0) of fire_batched against the oracle's FIRE from the same seeded starts, at the replica
+    sizes of the batched workload (N = 1024 and 4096, which fill the 512-thread workgroup and its LDS cell list, and
+    a ragged 1538), at packing fractions 0.84 and 0.92: the displacements from the start agree to 1e-4 (rel-L2) and
+    the energies after K steps to 1e-6."""
+    reps = []
+    for N, phi, seed in ((1024, 0.84, 4501), (4096, 0.92, 4502), (1538, 0.88, 4503)):
+        L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], phi, 2)
+        reps.append(dict(N=N, L=np.array([L, L, 0.0]), u=inputs.uniform_torus(N, 2, seed),
+                         species=inputs.bidisperse_species(N)))
+    ctx = md.Context()
+    bt = md.Batch(reps)
+    e, fmax, steps, status = (t.cpu().numpy() for t in
+                              md.fire_batched(ctx, bt, ss_pot(md), md.FireParams(), K, 0.0))
+    op = orc_pot(orc)
+    for b, r in enumerate(reps):
+        L = r["L"][:2]
+        x0 = orc.decode(r["u"], L)
+        o = orc.fire(x0, L, op, r["species"], max_steps=K, f_tol=0.0)
+        xg = orc.decode(bt.replica_positions(b), L)
+        dg = xg - x0
+        dg -= np.asarray(L) * np.rint(dg / np.asarray(L))
+        do = o["x"] - x0
+        do -= np.asarray(L) * np.rint(do / np.asarray(L))
+        Eo = orc.energy(o["x"], L, op, r["species"])
+        say("K", K, "N", r["N"], "displacement rel-L2", rel_l2(dg, do), "E", e[b], Eo)
+        assert steps[b] == K and status[b] == 0
+        assert rel_l2(dg, do) < 1e-4
+        assert abs(e[b] - Eo) <= 1e-6 * abs(Eo)
 
 
 def test_batched_replicas_are_independent(md):
@@ -201,8 +239,9 @@ def test_adjoint_same_start_small_packing(md, orc):
     assert np.allclose(grad, fd, rtol=1e-3, atol=1e-8)
 
 
-def test_batch_of_uneven_sizes_full_range(md):
-    """The C4 shape: 64 packings with N from 256 to 4096 in one launch all reach max |F| < 1e-6."""
+def test_batch_of_uneven_sizes_full_range(md, orc):
+    """The C4 shape: 64 packings with N from 256 to 4096 in one launch all reach max |F| < 1e-6, confirmed by the
+    oracle's forces and energies at the returned positions."""
     reps = inputs.ss_batch()
     ctx = md.Context()
     bt = md.Batch(reps)
@@ -212,6 +251,94 @@ def test_batch_of_uneven_sizes_full_range(md):
         "converged", int((status == 1).sum()))
     assert (status == 1).all()
     assert (fmax < 1e-6).all()
+    # the FP64 oracle, as the checker of these results: every replica's forces at the returned positions are
+    # below 2e-6 (the single-precision force floor adds ~1e-9) and its energy is the returned one
+    op = orc_pot(orc)
+    for b, r in enumerate(reps):
+        L = r["L"][:2]
+        x = orc.decode(bt.replica_positions(b), L)
+        F, ei, _ = orc.pair_rows(x, L, op, r["species"])
+        Eo = math.fsum(ei)
+        assert np.sqrt((F ** 2).sum(1)).max() < 2e-6, (b, np.sqrt((F ** 2).sum(1)).max())
+        assert abs(e[b] - Eo) <= 1e-6 * math.fsum(np.abs(ei)) + 1e-12, (b, e[b], Eo)
+
+
+def test_adjoint_matches_oracle_fd_at_workload_size(md, orc):
+    """The C4 check at replica size N = 256: for seeded packings where the GPU's and the oracle's FIRE from the same
+    start reach the same minimum (the same E* to 1e-6; float32 and float64 runs can part at a P > 0 decision), the
+    GPU adjoint (envelope_grad_wrt through the autograd function) equals central differences (h = 1e-4) of the
+    oracle's minimized energy, each E*(d +- h) minimized by the oracle from the oracle's own minimum at d so that it
+    follows that basin.  Two packings (phi 0.84 and 0.88) are required."""
+    import torch
+
+    from paper_1912_04232_amd.adjoint import minimized_energy
+    ctx = md.Context()
+    op = orc_pot(orc)
+    done = 0
+    for phi, seed in ((0.84, 4601), (0.84, 4602), (0.88, 4603), (0.88, 4604), (0.84, 4605), (0.88, 4606)):
+        if done >= 2:
+            break
+        N = 256
+        L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], phi, 2)
+        u = inputs.uniform_torus(N, 2, seed)
+        sp = inputs.bidisperse_species(N)
+        bt = md.Batch([dict(N=N, L=np.array([L, L, 0.0]), u=u, species=sp)])
+        u0 = bt.pos.clone()
+        d = torch.tensor([1.0, 1.4], dtype=torch.float64, requires_grad=True)
+        E = minimized_energy(d, torch.tensor(1.0, dtype=torch.float64), bt, u0, f_tol=1e-7, md_ctx=ctx)
+        E.sum().backward()
+        grad = d.grad.numpy()
+        o = orc.fire(orc.decode(u, [L, L]), [L, L], op, sp, f_tol=1e-11, max_steps=400000)
+        assert o["converged"]
+        Eo = orc.energy(o["x"], [L, L], op, sp)
+        if abs(float(E[0]) - Eo) > 1e-6 * abs(Eo):
+            say("phi", phi, "seed", seed, "different minima", float(E[0]), Eo)
+            continue
+        h = 1e-4
+        fd = []
+        for sidx in range(2):
+            vals = []
+            for sgn in (1, -1):
+                dd = np.array([1.0, 1.4])
+                dd[sidx] += sgn * h
+                r = orc.fire(o["x"], [L, L], orc_pot(orc, dd), sp, f_tol=1e-11, max_steps=400000)
+                assert r["converged"]
+                vals.append(orc.energy(r["x"], [L, L], orc_pot(orc, dd), sp))
+            fd.append((vals[0] - vals[1]) / (2 * h))
+        say("phi", phi, "seed", seed, "E*", Eo, "adjoint", grad, "oracle fd", fd)
+        assert np.allclose(grad, fd, rtol=1e-4, atol=1e-7)
+        done += 1
+    assert done >= 2, done
+
+
+def test_autotuned_launch_shapes_give_the_same_minima(md, orc):
+    """autotune_fire_batched times every launch shape on the batch and returns one of them; every shape minimizes
+    small packings (unique basins) to the oracle's minimized energies."""
+    reps = []
+    for N, phi, seed in ((40, 0.9, 4111), (48, 0.88, 4112), (64, 0.85, 4113)):
+        L = inputs.box_for_packing([1.0, 1.4], [N // 2, N // 2], phi, 2)
+        reps.append(dict(N=N, L=np.array([L, L, 0.0]), u=inputs.uniform_torus(N, 2, seed),
+                         species=inputs.bidisperse_species(N)))
+    ctx = md.Context()
+    bt = md.Batch(reps)
+    u0 = bt.pos.clone()
+    tune = md.autotune_fire_batched(ctx, bt, ss_pot(md), trial_steps=50)
+    say("autotune", tune)
+    assert tune["config"] in md.BATCH_CONFIGS and len(tune["ms_per_trial"]) == len(md.BATCH_CONFIGS)
+    assert np.array_equal(bt.pos.cpu().numpy(), u0.cpu().numpy())   # the trials leave the batch where it was
+    op = orc_pot(orc)
+    want = []
+    for r in reps:
+        L = r["L"][:2]
+        o = orc.fire(orc.decode(r["u"], L), L, op, r["species"], f_tol=1e-11, max_steps=400000)
+        want.append(orc.energy(o["x"], L, op, r["species"]))
+    for cfg in md.BATCH_CONFIGS:
+        bt.pos.copy_(u0)
+        e, fmax, steps, status = (t.cpu().numpy() for t in
+                                  md.fire_batched(ctx, bt, ss_pot(md), md.FireParams(), 400000, 1e-7, config=cfg))
+        assert (status == 1).all(), cfg
+        for b in range(len(reps)):
+            assert abs(e[b] - want[b]) <= 1e-6 * abs(want[b]) + 1e-12, (cfg, b, e[b], want[b])
 
 
 # ------------------------------------------------------------ box rescaled with the small-disk diameter

@@ -578,7 +578,7 @@ def test_fire_graph_replay_matches_eager(md):
 
 def test_fire_full_size_packing(md):
     """The C2 workload itself: 65536 bidisperse harmonic disks at phi = 0.90 from uniform positions reach
-    max |F| < 1e-6 (graph-replayed chunks)."""
+    max |F| < 1e-6 (graph-replayed chunks), confirmed by the oracle on sampled disks."""
     import time
     import torch
     cfg = inputs.ss_fire()
@@ -594,6 +594,18 @@ def test_fire_full_size_packing(md):
     dt = time.perf_counter() - t0
     say("C2 fire steps", st["steps"], "fmax", st["fmax"], "s", dt, "us/step", 1e6 * dt / max(st["steps"], 1))
     assert st["converged"] and st["fmax"] < 1e-6
+    # the FP64 oracle as the checker, on 4096 sampled disks: forces at the returned positions below 2e-6 and the
+    # per-disk energies those of the GPU's energy pass (1e-6 of their absolute sum)
+    import oracle as orc
+    e, _ = s.forces(energy=True)
+    rows = np.sort(np.random.default_rng(2002).choice(s.N, 4096, replace=False))
+    L = c["L"][:2]
+    x = orc.decode(md.from_device_u32(s.pos), L)
+    op = orc.Potential("soft_sphere", np.array(c["sigma"]), np.array(c["epsilon"]), alpha=2.0)
+    Fo, eo, _ = orc.pair_rows(x, L, op, c["species"], rows=rows)
+    assert np.sqrt((Fo ** 2).sum(1)).max() < 2e-6
+    eg = e.cpu().numpy()[rows]
+    assert np.abs(eg - eo).sum() <= 1e-6 * np.abs(eo).sum()
 
 
 # --------------------------------------------------------------- full-size sample
