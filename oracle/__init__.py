@@ -44,7 +44,8 @@ def build(force: bool = False) -> str:
 class _Pot(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32),
                 ("sigma", ctypes.c_double * 64), ("epsilon", ctypes.c_double * 64),
-                ("alpha", ctypes.c_double), ("r_cut", ctypes.c_double), ("shift", ctypes.c_int32)]
+                ("alpha", ctypes.c_double), ("r_cut", ctypes.c_double), ("shift", ctypes.c_int32),
+                ("coef", ctypes.c_double * 64)]
 
 
 class _FireParams(ctypes.Structure):
@@ -85,23 +86,26 @@ def default_threads() -> int:
 @dataclass
 class Potential:
     """Pair potential parameters (paper Sec. 3.3.2; species matrices as App. A)."""
-    kind: str = "lj"                      # "lj", "soft_sphere" or "morse"
+    kind: str = "lj"                      # "lj", "soft_sphere", "morse" or "buckingham"
     sigma: np.ndarray = field(default_factory=lambda: np.ones((1, 1)))
     epsilon: np.ndarray = field(default_factory=lambda: np.ones((1, 1)))
     alpha: float = 2.0
     r_cut: float = 2.5
     shift: bool = True
+    coef: np.ndarray | None = None        # Buckingham: dispersion coefficients C_ab (S x S)
 
     def _c(self) -> _Pot:
         s = np.atleast_2d(np.asarray(self.sigma, dtype=np.float64))
         e = np.atleast_2d(np.asarray(self.epsilon, dtype=np.float64))
         S = s.shape[0]
         p = _Pot()
-        p.kind = {"lj": 0, "soft_sphere": 1, "morse": 2}[self.kind]
+        p.kind = {"lj": 0, "soft_sphere": 1, "morse": 2, "buckingham": 3}[self.kind]
         p.n_species = S
+        c = np.zeros((S, S)) if self.coef is None else np.atleast_2d(np.asarray(self.coef, dtype=np.float64))
         for q in range(S * S):
             p.sigma[q] = float(s.reshape(-1)[q])
             p.epsilon[q] = float(e.reshape(-1)[q])
+            p.coef[q] = float(c.reshape(-1)[q])
         p.alpha = float(self.alpha)
         p.r_cut = float(self.r_cut)
         p.shift = 1 if self.shift else 0

@@ -22,6 +22,9 @@
  *                    cutoff function (App. B, eq. "cutoff")
  *     Morse          u = eps [(1 - exp(-alpha (r - s)))^2 - 1] (- u(r_c) if
  *                    shifted), 0 for r >= r_c: well depth eps at r = s
+ *     Buckingham     u = eps exp(-r/s) - c / r^6 (- u(r_c) if shifted), 0 for
+ *                    r >= r_c: exponential repulsion of strength eps and range
+ *                    s, dispersion coefficient c (a third S x S matrix)
  *   species mixing : s_ab, eps_ab given as S x S matrices (App. A builds
  *                    s_ab = (d_a + d_b)/2)
  *   neighbor set   : all ordered pairs with r^2 < r_list^2 (Sec. 3.2.3)
@@ -36,13 +39,14 @@
 #include <string.h>
 
 typedef struct {
-    int32_t kind;        /* 0 = Lennard-Jones, 1 = soft sphere, 2 = Morse */
+    int32_t kind;        /* 0 = Lennard-Jones, 1 = soft sphere, 2 = Morse, 3 = Buckingham */
     int32_t n_species;   /* S, 1..8 */
     double sigma[64];    /* S x S, row-major */
     double epsilon[64];  /* S x S, row-major */
     double alpha;        /* soft-sphere exponent; Morse range parameter */
-    double r_cut;        /* Lennard-Jones / Morse cutoff distance */
-    int32_t shift;       /* Lennard-Jones / Morse: subtract u(r_cut) from the energy */
+    double r_cut;        /* Lennard-Jones / Morse / Buckingham cutoff distance */
+    int32_t shift;       /* Lennard-Jones / Morse / Buckingham: subtract u(r_cut) from the energy */
+    double coef[64];     /* Buckingham: the dispersion coefficient C_ab, S x S */
 } orc_pot;
 
 typedef struct {
@@ -77,8 +81,8 @@ static double norm2(int dim, const double *d)
 
 /* ------------------------------------------------------------ potentials */
 
-/* u(r) and f(r) = -du/dr for one pair with parameters (s, e). */
-static void pair_u(const orc_pot *p, double r, double s, double e, double *u, double *f)
+/* u(r) and f(r) = -du/dr for one pair with parameters (s, e) and, for Buckingham, c. */
+static void pair_u(const orc_pot *p, double r, double s, double e, double c, double *u, double *f)
 {
     *u = 0.0;
     *f = 0.0;
@@ -102,6 +106,13 @@ static void pair_u(const orc_pot *p, double r, double s, double e, double *u, do
             *u -= e * ((1.0 - xc) * (1.0 - xc) - 1.0);
         }
         *f = -2.0 * p->alpha * e * x * (1.0 - x);
+    } else if (p->kind == 3) {
+        /* Buckingham (the exponential-six form named in Sec. 3.3.2): u = e exp(-r/s) - c / r^6, e the
+           repulsion strength, s its range, c the dispersion coefficient */
+        if (r >= p->r_cut) return;
+        *u = e * exp(-r / s) - c / pow(r, 6.0);
+        if (p->shift) *u -= e * exp(-p->r_cut / s) - c / pow(p->r_cut, 6.0);
+        *f = e / s * exp(-r / s) - 6.0 * c / pow(r, 7.0);
     } else {
         if (r >= s) return;
         double t = 1.0 - r / s;
@@ -200,7 +211,8 @@ static void pair_rows_body(void *vctx, int64_t lo, int64_t hi)
             displacement(dim, c->L, c->x + i * dim, c->x + j * dim, d);
             double r = sqrt(norm2(dim, d));
             double u, f;
-            pair_u(c->pot, r, c->pot->sigma[si * S + sj], c->pot->epsilon[si * S + sj], &u, &f);
+            pair_u(c->pot, r, c->pot->sigma[si * S + sj], c->pot->epsilon[si * S + sj], c->pot->coef[si * S + sj], &u,
+                   &f);
             if (u == 0.0 && f == 0.0) continue;
             for (int k = 0; k < dim; ++k) Fi[k] += f * d[k] / r;
             ei += 0.5 * u;
@@ -427,7 +439,7 @@ int orc_fire(int dim, const double *L, int64_t N, double *x, double *v, double *
 int orc_param_grad(int dim, const double *L, int64_t N, const double *x, const int32_t *species,
                    const orc_pot *pot, double *g_sigma, double *g_eps)
 {
-    if (pot->kind == 2) return -3; /* parameter derivatives are written for Lennard-Jones and soft spheres */
+    if (pot->kind == 2 || pot->kind == 3) return -3; /* parameter derivatives: Lennard-Jones and soft spheres */
     int S = pot->n_species;
     for (int q = 0; q < S * S; ++q) {
         g_sigma[q] = 0.0;

@@ -586,3 +586,69 @@ def test_morse_forces_are_minus_energy_gradient(orc):
     h = 1e-6
     fd = -(orc.energy(x + h * z, L, pot, sp) - orc.energy(x - h * z, L, pot, sp)) / (2 * h)
     assert (F * z).sum() == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+# ------------------------------------------------------------------- Buckingham
+
+def buck_pot(orc, A=((2.6e5, 2.0e5), (2.0e5, 1.6e5)), rho=((0.08, 0.085), (0.085, 0.09)),
+             C=((1.0, 1.2), (1.2, 1.4)), shift=True, r_cut=2.8):
+    return orc.Potential("buckingham", np.array(rho), np.array(A), r_cut=r_cut, shift=shift, coef=np.array(C))
+
+
+def dimer_energy_force(orc, pot, r, sp=(0, 1)):
+    L = [30.0, 30.0, 30.0]
+    x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+    F, e, _ = orc.pair_rows(x, L, pot, list(sp))
+    return float(e.sum()), float(F[1, 0])     # energy and the force on the second particle along +x
+
+
+def test_buckingham_exponential_and_dispersion_laws(orc):
+    """The two parts of the (0, 1) pair separately, unshifted: with the dispersion off, the energy falls by e over
+    one range rho_01 = 0.085 and the force is u / rho; with the repulsion off, doubling r divides u by 64 and
+    r f = 6 u (an attraction: u < 0, f < 0).  Both parts use the (0, 1) entries of their matrices."""
+    rep = buck_pot(orc, C=((0.0, 0.0), (0.0, 0.0)), shift=False)
+    for r in (0.9, 1.3):
+        u1, f1 = dimer_energy_force(orc, rep, r)
+        u2, _ = dimer_energy_force(orc, rep, r + 0.085)
+        assert math.isclose(u2 / u1, math.exp(-1.0), rel_tol=1e-13)
+        assert math.isclose(f1, u1 / 0.085, rel_tol=1e-13)
+    disp = buck_pot(orc, A=((0.0, 0.0), (0.0, 0.0)), shift=False)
+    for r in (0.9, 1.2):
+        u1, f1 = dimer_energy_force(orc, disp, r)
+        u2, _ = dimer_energy_force(orc, disp, 2 * r)
+        assert math.isclose(u2 / u1, 1.0 / 64.0, rel_tol=1e-13) and u1 < 0
+        assert math.isclose(r * f1, 6.0 * u1, rel_tol=1e-13) and f1 < 0
+    # beyond the cutoff nothing; with the shift the energy is continuous at the cutoff, without it is not
+    assert dimer_energy_force(orc, buck_pot(orc), 2.8001) == (0.0, 0.0)
+    assert abs(dimer_energy_force(orc, buck_pot(orc), 2.8 - 1e-9)[0]) < 1e-9
+    assert abs(dimer_energy_force(orc, buck_pot(orc, shift=False), 2.8 - 1e-9)[0]) > 1e-3
+
+
+def test_buckingham_force_vanishes_at_the_energy_minimum(orc):
+    """The (0, 0) dimer's energy minimum located from energies alone (bounded scalar minimization) is where the
+    oracle's force vanishes."""
+    from scipy.optimize import minimize_scalar
+    pot = buck_pot(orc, shift=False)
+    res = minimize_scalar(lambda r: dimer_energy_force(orc, pot, r, (0, 0))[0], bounds=(0.8, 2.5), method="bounded",
+                          options={"xatol": 1e-10})
+    r0 = res.x
+    u0, f0 = dimer_energy_force(orc, pot, r0, (0, 0))
+    assert u0 < 0 and 0.9 < r0 < 2.0
+    _, f_near = dimer_energy_force(orc, pot, r0 - 0.05, (0, 0))
+    assert abs(f0) < 1e-6 * abs(f_near)
+
+
+def test_buckingham_forces_are_minus_energy_gradient(orc):
+    N = 60
+    L = [5.5, 5.0, 4.8]
+    x = inputs.random_insertion_torus(N, 5.0, 3, 0.85, 23).astype(np.float64) * (5.0 / 2.0 ** 32)
+    L = [5.0, 5.0, 5.0]
+    sp = np.arange(N) % 2
+    pot = buck_pot(orc, r_cut=2.4)
+    F, _, _ = orc.pair_rows(x, L, pot, sp)
+    assert abs(F.sum(0)).max() < 1e-10 * abs(F).max()
+    rng = np.random.default_rng(3)
+    z = rng.standard_normal(x.shape)
+    h = 1e-6
+    fd = -(orc.energy(x + h * z, L, pot, sp) - orc.energy(x - h * z, L, pot, sp)) / (2 * h)
+    assert (F * z).sum() == pytest.approx(fd, rel=1e-7, abs=1e-9)
