@@ -63,7 +63,7 @@ typedef struct {
     float L[3];    /* edge lengths; L[2] ignored when dim == 2 */
 } md_box;
 
-enum { MD_LJ = 0, MD_SOFT_SPHERE = 1, MD_MORSE = 2 };
+enum { MD_LJ = 0, MD_SOFT_SPHERE = 1, MD_MORSE = 2, MD_BUCKINGHAM = 3 };
 
 /*
  * Pair potential with S species (Sec. 3.3.2; species matrices as in App. A).
@@ -72,19 +72,23 @@ enum { MD_LJ = 0, MD_SOFT_SPHERE = 1, MD_MORSE = 2 };
  *   MD_SOFT_SPHERE u = eps_ab/alpha (1 - r/sigma_ab)^alpha for r < sigma_ab, else 0.
  *   MD_MORSE       u = eps_ab [(1 - exp(-alpha (r - sigma_ab)))^2 - 1] for r < r_cut (well depth eps_ab at
  *                  r = sigma_ab, range alpha > 0), minus u(r_cut) when shift != 0; 0 beyond r_cut.
- *                  Accepted by the list, dense and step entry points; the replica entry points
- *                  (fire_batched, envelope_grad, fire_unrolled_grad) take MD_LJ and MD_SOFT_SPHERE only.
- * sigma and epsilon are S x S row-major (entry a*S+b), symmetric, S <= 8.
+ *   MD_BUCKINGHAM  u = eps_ab exp(-r/sigma_ab) - coef_ab / r^6 for r < r_cut (exponential repulsion of
+ *                  strength eps_ab and range sigma_ab > 0, dispersion coefficient coef_ab), minus u(r_cut) when
+ *                  shift != 0; 0 beyond r_cut.
+ *                  MD_MORSE and MD_BUCKINGHAM are accepted by the list, dense and step entry points; the replica
+ *                  entry points (fire_batched, envelope_grad, fire_unrolled_grad) take MD_LJ and MD_SOFT_SPHERE only.
+ * sigma, epsilon and coef are S x S row-major (entry a*S+b), symmetric, S <= 8; coef is read for MD_BUCKINGHAM only.
  */
 typedef struct {
     int32_t kind;
     int32_t n_species;
     double sigma[64];
     double epsilon[64];
-    float alpha;      /* soft-sphere exponent, >= 1 (2 = harmonic) */
-    float r_cut;      /* Lennard-Jones cutoff distance (absolute) */
-    int32_t shift;    /* Lennard-Jones energy shift on/off */
+    float alpha;      /* soft-sphere exponent, >= 1 (2 = harmonic); Morse range */
+    float r_cut;      /* Lennard-Jones / Morse / Buckingham cutoff distance (absolute) */
+    int32_t shift;    /* energy shift at the cutoff on/off */
     int32_t reserved;
+    double coef[64];  /* Buckingham dispersion coefficients */
 } md_potential;
 
 /* Device flag words in md_nlist.flags (int32 each). */

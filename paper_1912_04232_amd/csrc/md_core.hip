@@ -1775,7 +1775,9 @@ static bool make_box(const md_box *box, float r_list, DevBox &b)
 
 bool md_make_pot(const md_potential *pot, DevPot &p)
 {
-    if (!pot || (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE && pot->kind != MD_MORSE)) return false;
+    if (!pot || (pot->kind != MD_LJ && pot->kind != MD_SOFT_SPHERE && pot->kind != MD_MORSE &&
+                 pot->kind != MD_BUCKINGHAM))
+        return false;
     int S = pot->n_species;
     if (S < 1 || S > kMaxSpecies) return false;
     memset(&p, 0, sizeof(p));
@@ -1787,6 +1789,7 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
     if (pot->kind == MD_SOFT_SPHERE && !(pot->alpha >= 1.0f)) return false;
     if (pot->kind == MD_LJ && !(pot->r_cut > 0.0f)) return false;
     if (pot->kind == MD_MORSE && !(pot->r_cut > 0.0f && pot->alpha > 0.0f)) return false;
+    if (pot->kind == MD_BUCKINGHAM && !(pot->r_cut > 0.0f)) return false;
     p.mk = (float)((double)pot->alpha * 1.4426950408889634);  // alpha log2(e)
     for (int a = 0; a < S; ++a)
         for (int c = 0; c < S; ++c) {
@@ -1812,6 +1815,16 @@ bool md_make_pot(const md_potential *pot, DevPot &p)
                 p.c12[q] = (float)e;
                 p.ushift[q] = pot->shift ? (float)(e * xc * (xc - 2.0)) : 0.0f;
             }
+            if (pot->kind == MD_BUCKINGHAM) {
+                const double c = pot->coef[q];
+                if (!isfinite(c)) return false;
+                p.a12[q] = (float)(e / s);
+                p.a6[q] = (float)(6.0 * c);
+                p.c12[q] = (float)e;
+                p.c6[q] = (float)c;
+                p.inv_sig[q] = (float)(1.4426950408889634 / s);  // log2(e) / rho
+                p.ushift[q] = pot->shift ? (float)(e * exp(-rc / s) - c / pow(rc, 6.0)) : 0.0f;
+            }
         }
     return true;
 }
@@ -1823,7 +1836,7 @@ int md_partials_blocks()
 
 float md_max_cutoff(const md_potential *pot)
 {
-    if (pot->kind == MD_LJ || pot->kind == MD_MORSE) return pot->r_cut;
+    if (pot->kind == MD_LJ || pot->kind == MD_MORSE || pot->kind == MD_BUCKINGHAM) return pot->r_cut;
     float m = 0.0f;
     for (int q = 0; q < pot->n_species * pot->n_species; ++q) m = fmaxf(m, (float)pot->sigma[q]);
     return m;
@@ -1903,6 +1916,10 @@ static inline int nblk(int64_t n)
                 constexpr int KIND = 2;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
                 else { constexpr bool MULTI = false; __VA_ARGS__; }          \
+            } else if (KIND_ == 3) {                                         \
+                constexpr int KIND = 3;                                      \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \
                 constexpr int KIND = 1;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
@@ -1916,6 +1933,10 @@ static inline int nblk(int64_t n)
                 else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else if (KIND_ == 2) {                                         \
                 constexpr int KIND = 2;                                      \
+                if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
+                else { constexpr bool MULTI = false; __VA_ARGS__; }          \
+            } else if (KIND_ == 3) {                                         \
+                constexpr int KIND = 3;                                      \
                 if (MULTI_) { constexpr bool MULTI = true; __VA_ARGS__; }    \
                 else { constexpr bool MULTI = false; __VA_ARGS__; }          \
             } else {                                                         \

@@ -29,13 +29,14 @@ struct DevBox {
 // For soft spheres: f/r = (eps/sig) t^(alpha-1) / r, u = eps/alpha t^alpha,
 // t = 1 - r/sig.
 struct DevPot {
-    int kind;          // 0 LJ, 1 soft sphere, 2 Morse
+    int kind;          // 0 LJ, 1 soft sphere, 2 Morse, 3 Buckingham
     int S;
     float rc2;         // LJ / Morse cutoff squared
     float alpha;
     int alpha_is_2;
     float mk;          // Morse: alpha log2(e)
-    float a12[64], a6[64], c12[64], c6[64], ushift[64];  // LJ; Morse keeps 2 alpha eps in a12, eps in c12
+    float a12[64], a6[64], c12[64], c6[64], ushift[64];  // LJ; Morse keeps 2 alpha eps in a12, eps in c12;
+                                                         // Buckingham A/rho in a12, 6 C in a6, A in c12, C in c6
     float sig[64], inv_sig[64], eps_over_sig[64], eps_over_alpha[64];  // soft sphere
     double sigd[64];                                                    // sigma in double (overlap)
 };
@@ -93,6 +94,23 @@ __device__ __forceinline__ float morse_fs(float r2, float rc2, float r0, float m
     return in ? fs : 0.0f;
 }
 
+// Buckingham, u = A exp(-r/rho) - C / r^6: returns f/r = (A/rho) exp(-r/rho) / r - 6 C / r^8 (0 beyond the cutoff);
+// u - u(r_c) when WANT_U.  kr = log2(e) / rho, so exp(-r/rho) = exp2(-kr r).
+template <bool WANT_U>
+__device__ __forceinline__ float buck_fs(float r2, float rc2, float kr, float a_over_rho, float six_c, float a, float c,
+                                         float ushift, float &u)
+{
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float r = r2 * ri;
+    float x = __builtin_exp2f(-kr * r);
+    float r2i = ri * ri;
+    float r6i = r2i * r2i * r2i;
+    float fs = a_over_rho * x * ri - six_c * r6i * r2i;
+    bool in = r2 < rc2;
+    if (WANT_U) u = in ? a * x - c * r6i - ushift : 0.0f;
+    return in ? fs : 0.0f;
+}
+
 template <int KIND, bool MULTI, bool WANT_U>
 __device__ __forceinline__ float pair_fs(const DevPot &p, int pt, float r2, float &u)
 {
@@ -102,6 +120,9 @@ __device__ __forceinline__ float pair_fs(const DevPot &p, int pt, float r2, floa
     } else if (KIND == 2) {
         int q = MULTI ? pt : 0;
         return morse_fs<WANT_U>(r2, p.rc2, p.sig[q], p.mk, p.c12[q], p.a12[q], p.ushift[q], u);
+    } else if (KIND == 3) {
+        int q = MULTI ? pt : 0;
+        return buck_fs<WANT_U>(r2, p.rc2, p.inv_sig[q], p.a12[q], p.a6[q], p.c12[q], p.c6[q], p.ushift[q], u);
     } else {
         int q = MULTI ? pt : 0;
         return ss_fs<WANT_U>(r2, p.sig[q], p.inv_sig[q], p.eps_over_sig[q], p.eps_over_alpha[q], p.alpha,

@@ -150,10 +150,12 @@ md_status pair_force_half(md_ctx *ctx, const md_box *box, const md_potential *po
     if (box->dim == 3) {
         if (K == MD_LJ) { if (multi) HALF(3, 0, true); else HALF(3, 0, false); }
         else if (K == MD_MORSE) { if (multi) HALF(3, 2, true); else HALF(3, 2, false); }
+        else if (K == MD_BUCKINGHAM) { if (multi) HALF(3, 3, true); else HALF(3, 3, false); }
         else { if (multi) HALF(3, 1, true); else HALF(3, 1, false); }
     } else {
         if (K == MD_LJ) { if (multi) HALF(2, 0, true); else HALF(2, 0, false); }
         else if (K == MD_MORSE) { if (multi) HALF(2, 2, true); else HALF(2, 2, false); }
+        else if (K == MD_BUCKINGHAM) { if (multi) HALF(2, 3, true); else HALF(2, 3, false); }
         else { if (multi) HALF(2, 1, true); else HALF(2, 1, false); }
     }
 #undef HALF

@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmdcore.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
 
-MD_LJ, MD_SOFT_SPHERE, MD_MORSE = 0, 1, 2
+MD_LJ, MD_SOFT_SPHERE, MD_MORSE, MD_BUCKINGHAM = 0, 1, 2, 3
 WRT_SIGMA, WRT_EPSILON, WRT_DIAMETER, WRT_EPSILON_COMMON = 0, 1, 2, 3
 BOX_FIXED, BOX_PACKING = 0, 1
 FLAG_OVERFLOW, FLAG_MAXCOUNT, FLAG_NONFINITE, FLAG_REBUILDS = 0, 1, 2, 3
@@ -48,7 +48,7 @@ class c_box(ctypes.Structure):
 class c_potential(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32), ("sigma", ctypes.c_double * 64),
                 ("epsilon", ctypes.c_double * 64), ("alpha", ctypes.c_float), ("r_cut", ctypes.c_float),
-                ("shift", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("shift", ctypes.c_int32), ("reserved", ctypes.c_int32), ("coef", ctypes.c_double * 64)]
 
 
 class c_nlist(ctypes.Structure):
@@ -241,21 +241,23 @@ class Box:
 
 @dataclass
 class Potential:
-    """Pair potential (paper Sec. 3.3.2): kind 'lj', 'soft_sphere' or 'morse', S x S sigma / epsilon (Morse: sigma
-    is the minimum position, epsilon the well depth, alpha the range)."""
+    """Pair potential (paper Sec. 3.3.2): kind 'lj', 'soft_sphere', 'morse' or 'buckingham', S x S sigma / epsilon
+    (Morse: sigma is the minimum position, epsilon the well depth, alpha the range; Buckingham: epsilon the
+    repulsion strength A, sigma its range rho, coef the dispersion coefficient C)."""
     kind: str = "lj"
     sigma: object = ((1.0,),)
     epsilon: object = ((1.0,),)
     alpha: float = 2.0
     r_cut: float = 2.5
     shift: bool = True
+    coef: object = None
 
     @property
     def n_species(self) -> int:
         return int(np.atleast_2d(np.asarray(self.sigma)).shape[0])
 
     def cutoff(self) -> float:
-        if self.kind in ("lj", "morse"):
+        if self.kind in ("lj", "morse", "buckingham"):
             return float(self.r_cut)
         return float(np.max(np.asarray(self.sigma, dtype=np.float64)))
 
@@ -266,11 +268,14 @@ class Potential:
         if e.shape != (S, S) or S > 8:
             raise ValueError("sigma / epsilon must be S x S with S <= 8")
         p = c_potential()
-        p.kind = {"lj": MD_LJ, "soft_sphere": MD_SOFT_SPHERE, "morse": MD_MORSE}[self.kind]
+        p.kind = {"lj": MD_LJ, "soft_sphere": MD_SOFT_SPHERE, "morse": MD_MORSE,
+                  "buckingham": MD_BUCKINGHAM}[self.kind]
         p.n_species = S
+        c = np.zeros((S, S)) if self.coef is None else np.atleast_2d(np.asarray(self.coef, dtype=np.float64))
         for q in range(S * S):
             p.sigma[q] = float(s.reshape(-1)[q])
             p.epsilon[q] = float(e.reshape(-1)[q])
+            p.coef[q] = float(c.reshape(-1)[q])
         p.alpha = float(self.alpha)
         p.r_cut = float(self.r_cut)
         p.shift = 1 if self.shift else 0

@@ -26,7 +26,7 @@ def test_library_exports_every_header_symbol():
 def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/md.h (natural alignment, x86-64)
     assert ctypes.sizeof(md.c_box) == 16
-    assert ctypes.sizeof(md.c_potential) == 4 * 2 + 8 * 64 * 2 + 4 * 4
+    assert ctypes.sizeof(md.c_potential) == 4 * 2 + 8 * 64 * 2 + 4 * 4 + 8 * 64
     assert ctypes.sizeof(md.c_nlist) == 24 + 4 * 8
     assert ctypes.sizeof(md.c_fire_params) == 32
     assert ctypes.sizeof(md.c_fire_state) == 6 * 8 + 8 + 8
