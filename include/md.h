@@ -202,12 +202,12 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
  * device every particle is within skin/2 of nl->pos_ref by a margin of three steps of
  * dt |v| + dt^2 |F|; otherwise it first rebuilds nl for pos.  Between calls the list arrays
  * belong to the library: a caller that edits them must call nl_build before the next run.
- * Then it enqueues one launch per step, in which nl->lanes lanes share a particle.  The list is kept valid on the device with no
- * host synchronisation: when a particle's displacement since the last build
- * plus twice its last step (and dt^2 |F|) would exceed nl->skin/2, the next
- * two launches rebuild it into a second generation while forces still use the
- * current one, and the launch after that switches (Sec. 3.1: the list is
- * rebuilt when particles have moved too far for the halo).  Every step checks
+ * Then it enqueues one launch per step, in which nl->lanes lanes share a particle.  The list is kept valid on the
+ * device with no host synchronisation: when a particle's displacement from the reference positions of the list the
+ * next step uses (after a build step, the new list's) plus twice its last step (and dt^2 |F|) would exceed
+ * nl->skin/2, the next two launches rebuild it into a second generation while forces still use the current one,
+ * and the launch after that switches (Sec. 3.1: the list is rebuilt when particles have moved too far for the
+ * halo).  Every step checks
  * that the list it uses is within skin/2 of the positions and raises
  * MD_FLAG_STALE otherwise.  On return pos, vel, force and nl hold the state
  * after n_steps.  If a build overflows (MD_FLAG_OVERFLOW / _CELL_OVERFLOW) or

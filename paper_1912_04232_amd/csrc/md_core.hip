@@ -1069,6 +1069,9 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
 #pragma unroll
     for (int q = 0; q < D; ++q) bad = bad || !isfinite(F[q]);
     wave_flag(live && bad, &a.flags[MD_FLAG_NONFINITE]);
+    // The rebuild lookahead measures r(s+1) against the reference positions of the list step s+1 will use: the
+    // current one, or after a build step the new one, so that a new rebuild can start right after a switch.
+    const uint32_t *ref_next = mode == M_BUILD ? a.gen[gen ^ 1].pos_ref : g.pos_ref;
     if constexpr (W >= D) {
         // every lane of the particle holds the summed force: lane q < D updates coordinate q
         if (!live) return;
@@ -1089,13 +1092,13 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
                 const float dx = a.dt * v;
                 const uint32_t un = shift_coord(uq, dx, isq);
                 a.pos_out[at] = un;
-                const float d = tdisp(un, g.pos_ref[at], sq);
+                const float d = tdisp(un, ref_next[at], sq);
                 dq2 = d * d;
                 st2 = dx * dx;
                 f2q = Fq * Fq;
             }
         }
-        if (a.last || mode != M_IDLE) return;
+        if (a.last || mode == M_BIN) return;
         // |r(s+1) - r_ref|^2, |step|^2 and |F|^2 summed over the particle's lanes
 #pragma unroll
         for (int o = 1; o < W; o <<= 1) {
@@ -1130,8 +1133,8 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
         f2 = __builtin_fmaf(F[q], F[q], f2);
     }
     store_pos<D>(a.pos_out, i, un);
-    if (mode == M_IDLE) {
-        float d = sqrtf(disp2<D>(un, g.pos_ref, i, a.box));
+    if (mode != M_BIN) {
+        float d = sqrtf(disp2<D>(un, ref_next, i, a.box));
         float ahead = sqrtf(step2) + a.dt * a.dt * sqrtf(f2);
         if (d + lp.kappa * ahead > lp.half_skin) a.ctl[6 + (a.step + 1) % 3] = 1;
     }

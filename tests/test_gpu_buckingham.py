@@ -36,9 +36,9 @@ def rel_l2(a, b):
 
 
 def case(md, orc, N=1500, seed=171, shift=True, T=0.5):
-    """Random insertion at density 0.8 with no pair closer than 0.95 (the repulsive wall), Maxwell velocities."""
+    """Random insertion at density 0.8 with no pair closer than 0.9 (the repulsive wall), Maxwell velocities."""
     L = inputs.box_for_density(N, 0.8)
-    u = inputs.random_insertion_torus(N, L, 3, 0.95, seed)
+    u = inputs.random_insertion_torus(N, L, 3, 0.9, seed)
     v = inputs.maxwell_velocities(N, 3, T, seed + 1)
     sp = (np.arange(N) % 2).astype(np.int32)
     mpot = md.Potential("buckingham", RHO, A, r_cut=R_CUT, shift=shift, coef=C)
