@@ -307,17 +307,35 @@ def integrators(ctx, progress, steps: int = 1000):
 
 
 def surrogate(progress, nn_steps: int, md_steps: int):
-    """The learned part against the plain method on the same GPU: a network trained on plain-engine LJ data
-    (2000 snapshots of N = 4000 over T in [0.5, 1.5]), then NVE at N = 65536 with network forces (a HIP graph
-    per 20 steps) and with plain LJ; the LJ forces of the final configuration judge the network's RMSE."""
+    """The learned part against the plain method on the same GPU.  Networks with Gaussians of four widths (the
+    default 1/(2 Delta^2) = 38.9 for the 16 centres on [0.8, 2.5], and the narrower 80, 160 and 320) are trained on
+    the same plain-engine LJ data (2000 snapshots of N = 4000 over T in [0.5, 1.5]); the best held-out force RMSE is
+    deployed in NVE at N = 65536 under the real judge (plain LJ forces every 100 steps, fallback above 1e-2), which
+    reports how many steps ran on the network.  The network's own throughput (judge off) and plain LJ's are timed
+    on the same system."""
     import torch
 
     from paper_1912_04232_amd import inputs, md, nn
     ctx = md.Context()
-    net, box4k, test, rec = nn.train_network(ctx, steps=nn_steps, progress=progress)
-    progress(f"network trained: held-out force RMSE {rec['force_rmse']:.4g} (untrained {rec['force_rmse_untrained']:.4g})")
+    t0 = time.perf_counter()
+    data = nn.generate_lj_data(ctx, progress=progress)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sweep, best = {}, None
+    for eta in (0.0, 80.0, 160.0, 320.0):
+        net, box4k, test, rec = nn.train_network(ctx, steps=nn_steps, eta=eta, data=data)
+        sweep[f"{rec['eta']:.1f}"] = {"force_rmse": rec["force_rmse"], "energy_rmse_per_atom": rec["energy_rmse_per_atom"],
+                                      "train_ms_per_step": rec["train_ms_per_step"]}
+        progress(f"eta {rec['eta']:.1f}: held-out force RMSE {rec['force_rmse']:.4g}")
+        if best is None or rec["force_rmse"] < best[3]["force_rmse"]:
+            best = (net, box4k, test, rec)
+    net, box4k, test, rec = best
     d = inputs.lj_nn_deploy()
     box = md.Box(tuple(d["L"]), 3)
+    # deployment under the judge the method states (force RMSE 1e-2 against plain LJ)
+    judged = nn.NNMD(ctx, net, box, d["u"], d["v"], dt=d["dt"], skin=d["skin"], max_rmse=1e-2, check_every=100)
+    on_network = judged.run(md_steps)
+    # throughput of the network step itself (judge off) and of plain LJ, same system
     sim = nn.NNMD(ctx, net, box, d["u"], d["v"], dt=d["dt"], skin=d["skin"], max_rmse=float("inf"),
                   check_every=md_steps)
     sim.run(100)
@@ -338,13 +356,18 @@ def surrogate(progress, nn_steps: int, md_steps: int):
     torch.cuda.synchronize()
     t_lj = time.perf_counter() - t0
     return {"N": d["N"], "workload": "3D LJ rho=0.84 BCC 32^3 start, T=1, dt=0.005, skin 0.3",
-            "nn_steps_per_s": md_steps / t_nn, "plain_steps_per_s": md_steps / t_lj,
+            "width_sweep": sweep, "eta_deployed": rec["eta"],
+            "judged_run": {"max_rmse": 1e-2, "check_every": 100, "steps_requested": md_steps,
+                           "steps_on_network": int(on_network), "fell_back_to_plain": bool(judged.fallback),
+                           "judge_rmse_log": judged.rmse_log[:10]},
+            "nn_steps_per_s_judge_off": md_steps / t_nn, "plain_steps_per_s": md_steps / t_lj,
             "nn_over_plain": (md_steps / t_nn) / (md_steps / t_lj),
             "nn_force_rmse_heldout": rec["force_rmse"], "nn_energy_rmse_per_atom_heldout": rec["energy_rmse_per_atom"],
             "untrained_force_rmse_heldout": rec["force_rmse_untrained"],
             "judge_force_rmse_after_md": judge, "force_rmse_target": 1e-2,
             "target_met": bool(rec["force_rmse"] <= 1e-2), "list_overflow": bool(flags[md.FLAG_OVERFLOW]),
-            "training": {k: rec[k] for k in ("snapshots", "steps", "per_batch", "train_ms_per_step", "data_s")}}
+            "training": {"snapshots": rec["snapshots"], "steps": rec["steps"], "per_batch": rec["per_batch"],
+                         "train_ms_per_step": rec["train_ms_per_step"], "data_s": t_data}}
 
 
 def main():

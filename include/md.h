@@ -427,7 +427,7 @@ md_status fire_unrolled_grad(md_ctx *ctx, const md_batch *batch, const md_potent
  * Neural pair potential (Sec. 3.2.4 featurizations, Sec. 4.1 per-atom networks, forces as -grad E by
  * Sec. 3.3.2): K = 16 radial basis functions
  *   G_i^k = sum_{j != i, r_ij < r_c} exp(-eta (r_ij - mu_k)^2) (cos(pi r_ij / r_c) + 1)/2,
- *   mu_k = mu0 + k (mu1 - mu0)/(K-1), eta = 1/(2 ((mu1 - mu0)/(K-1))^2),
+ *   mu_k = mu0 + k (mu1 - mu0)/(K-1), eta given, or 1/(2 ((mu1 - mu0)/(K-1))^2) when 0,
  * and an MLP with H = 64: x = (G - m)/s, E_i = w3 . sp(W2 sp(W1 x + b1) + b2) + b3, sp = softplus.
  * W1, W2 are BF16 (the MFMA operands, the model's own values), everything else float.  All pointers are
  * device memory.  The network's parameters as one float vector theta (nn_param_count() = 5313 entries):
@@ -437,7 +437,7 @@ typedef struct {
     int32_t K;              /* 16 */
     int32_t H;              /* 64 */
     float mu0, mu1, r_c;    /* basis centres and cutoff */
-    int32_t reserved;
+    float eta;              /* Gaussian width parameter (> 0), or 0 for 1/(2 Delta^2), Delta the centre spacing */
     const uint16_t *W1;     /* bf16 [H][K] */
     const uint16_t *W2;     /* bf16 [H][H] */
     const float *b1, *b2;   /* [H] */

@@ -35,6 +35,7 @@ class NNSpec:
     r_c: float = 2.5
     H: int = 64
     act: str = "softplus"   # "softplus" or "linear" (a linear network reduces the model to a pair potential)
+    width: float = 0.0      # eta when > 0; else 1/(2 Delta^2) with Delta the centre spacing
 
     @property
     def mu(self) -> np.ndarray:
@@ -42,6 +43,8 @@ class NNSpec:
 
     @property
     def eta(self) -> float:
+        if self.width > 0.0:
+            return float(self.width)
         delta = (self.mu1 - self.mu0) / (self.K - 1)
         return 1.0 / (2.0 * delta * delta)
 

@@ -867,7 +867,8 @@ static bool make_nn(const md_nn_params *q, NNDev &p)
     p.mu0 = q->mu0;
     p.dmu = (q->mu1 - q->mu0) / (kK - 1);
     p.r_c = q->r_c;
-    p.eta = 1.0f / (2.0f * p.dmu * p.dmu);
+    if (!(q->eta >= 0.0f) || !isfinite(q->eta)) return false;
+    p.eta = q->eta > 0.0f ? q->eta : 1.0f / (2.0f * p.dmu * p.dmu);
     p.W1 = q->W1;
     p.W2 = q->W2;
     p.b1 = q->b1;

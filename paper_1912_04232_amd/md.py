@@ -87,7 +87,7 @@ class c_batch(ctypes.Structure):
 
 class c_nn_params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("H", ctypes.c_int32), ("mu0", ctypes.c_float), ("mu1", ctypes.c_float),
-                ("r_c", ctypes.c_float), ("reserved", ctypes.c_int32), ("W1", ctypes.c_void_p),
+                ("r_c", ctypes.c_float), ("eta", ctypes.c_float), ("W1", ctypes.c_void_p),
                 ("W2", ctypes.c_void_p), ("b1", ctypes.c_void_p), ("b2", ctypes.c_void_p), ("w3", ctypes.c_void_p),
                 ("b3", ctypes.c_void_p), ("m", ctypes.c_void_p), ("s", ctypes.c_void_p)]
 
@@ -771,7 +771,7 @@ def fire_unrolled_grad(ctx: Context, batch: Batch, pot: Potential, fp: FireParam
 class NNParams:
     """Device copy of the neural pair potential: BF16 W1 [H][K], W2 [H][H]; float b1, b2, w3 [H], b3; m, s [K]."""
 
-    def __init__(self, W1, b1, W2, b2, w3, b3, m, s, mu0=0.8, mu1=2.5, r_c=2.5, device=None):
+    def __init__(self, W1, b1, W2, b2, w3, b3, m, s, mu0=0.8, mu1=2.5, r_c=2.5, device=None, eta=0.0):
         dev = device or _dev()
 
         def f32(a):
@@ -781,12 +781,12 @@ class NNParams:
         self.W2 = f32(W2).to(torch.bfloat16).contiguous()
         self.b1, self.b2, self.w3, self.m, self.s = f32(b1), f32(b2), f32(w3), f32(m), f32(s)
         self.b3 = f32([b3])
-        self.mu0, self.mu1, self.r_c = float(mu0), float(mu1), float(r_c)
+        self.mu0, self.mu1, self.r_c, self.eta = float(mu0), float(mu1), float(r_c), float(eta)
         self.K, self.H = int(self.W1.shape[1]), int(self.W1.shape[0])
 
     def c(self) -> c_nn_params:
         q = c_nn_params()
-        q.K, q.H, q.mu0, q.mu1, q.r_c = self.K, self.H, self.mu0, self.mu1, self.r_c
+        q.K, q.H, q.mu0, q.mu1, q.r_c, q.eta = self.K, self.H, self.mu0, self.mu1, self.r_c, self.eta
         q.W1, q.W2 = self.W1.data_ptr(), self.W2.data_ptr()
         q.b1, q.b2, q.w3, q.b3, q.m, q.s = (t.data_ptr() for t in (self.b1, self.b2, self.w3, self.b3, self.m,
                                                                    self.s))

@@ -29,7 +29,7 @@ K, H = 16, 64
 class Network:
     """Parameters on the device.  theta: float32 [P]; W1, W2: BF16 copies; m, s: descriptor shift / scale."""
 
-    def __init__(self, ctx: md.Context, weights: dict, m, s, mu0=0.8, mu1=2.5, r_c=2.5):
+    def __init__(self, ctx: md.Context, weights: dict, m, s, mu0=0.8, mu1=2.5, r_c=2.5, eta=0.0):
         dev = ctx.device
         P = int(md.load().nn_param_count())
         th = np.concatenate([np.asarray(weights["W1"], np.float64).ravel(), np.asarray(weights["b1"]).ravel(),
@@ -47,13 +47,14 @@ class Network:
                             else torch.as_tensor(np.asarray(x, np.float32), device=dev)).contiguous()
         self.m, self.s = as_dev(m), as_dev(s)
         self.mu0, self.mu1, self.r_c = float(mu0), float(mu1), float(r_c)
+        self.eta = float(eta)   # 0: the default width 1/(2 Delta^2) of the basis
         self.step = 0
         md._check("nn_cast_weights", md.load().nn_cast_weights(ctx.h, md._ptr(self.theta),
                                                                  md._ptr(self.W1), md._ptr(self.W2), md._stream()))
 
     def c(self) -> md.c_nn_params:
         q = md.c_nn_params()
-        q.K, q.H, q.mu0, q.mu1, q.r_c = K, H, self.mu0, self.mu1, self.r_c
+        q.K, q.H, q.mu0, q.mu1, q.r_c, q.eta = K, H, self.mu0, self.mu1, self.r_c, self.eta
         base = self.theta.data_ptr()
         o_b1, o_W2 = H * K, H * K + H
         o_b2 = o_W2 + H * H
@@ -358,14 +359,15 @@ class NNMD:
 
 
 def train_network(ctx: md.Context, n_runs=20, per_run=100, steps=20000, per_batch=16, lr=3e-3, lr_end=3e-5,
-                  lam_F=1.0, seed=1, progress=None):
+                  lam_F=1.0, seed=1, progress=None, eta=0.0, data=None):
     """The learned part end to end: plain-engine LJ data (n_runs x per_run snapshots of N = 4000), 10% held out,
     descriptor scale from the training set, `steps` Adam steps on minibatches of `per_batch` snapshots with an
     exponential learning-rate decay from lr to lr_end.  Returns the network, the held-out batches and a record
     (force / energy RMSE of the untrained and trained network on the held-out set, timings)."""
     import time
     t0 = time.perf_counter()
-    box, P, E, F, T = generate_lj_data(ctx, n_runs=n_runs, per_run=per_run, progress=progress)
+    box, P, E, F, T = data if data is not None else generate_lj_data(ctx, n_runs=n_runs, per_run=per_run,
+                                                                      progress=progress)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     S = P.shape[0]
@@ -373,11 +375,11 @@ def train_network(ctx: md.Context, n_runs=20, per_run=100, steps=20000, per_batc
     ntest = max(1, S // 10)
     test_idx, train_idx = perm[:ntest], perm[ntest:]
     w = inputs.nn_init(seed)
-    probe = Network(ctx, w, np.zeros(K), np.ones(K))
+    probe = Network(ctx, w, np.zeros(K), np.ones(K), eta=eta)
     G = torch.cat([b.G for b in make_batches(ctx, box, probe, P, E, F, train_idx, per_batch)])
     m, s = descriptor_scale(ctx, G)
     del G
-    net = Network(ctx, w, m, s)
+    net = Network(ctx, w, m, s, eta=eta)
     train = make_batches(ctx, box, net, P, E, F, train_idx, per_batch)
     test = make_batches(ctx, box, net, P, E, F, test_idx, per_batch)
     f0, e0 = evaluate(ctx, box, net, test)
@@ -394,7 +396,8 @@ def train_network(ctx: md.Context, n_runs=20, per_run=100, steps=20000, per_batc
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     f1, e1 = evaluate(ctx, box, net, test)
-    rec = dict(snapshots=int(S), atoms_per_snapshot=int(P.shape[1]), test_snapshots=int(ntest), steps=steps,
+    eta_used = eta if eta > 0 else 1.0 / (2.0 * ((net.mu1 - net.mu0) / (K - 1)) ** 2)
+    rec = dict(eta=eta_used, snapshots=int(S), atoms_per_snapshot=int(P.shape[1]), test_snapshots=int(ntest), steps=steps,
                per_batch=per_batch, force_rmse_untrained=f0, energy_rmse_untrained=e0, force_rmse=f1,
                energy_rmse_per_atom=e1, data_s=t_data, train_s=t_train, train_ms_per_step=1e3 * t_train / steps,
                force_rms_reference=float(F.pow(2).mean().sqrt()))

@@ -82,6 +82,28 @@ def test_descriptors_match_oracle(md):
     assert rel_l2(G, Go) < 1e-5
 
 
+@pytest.mark.parametrize("eta", [15.0, 120.0])
+def test_descriptors_and_forces_at_other_widths_match_oracle(md, eta):
+    """A width parameter eta given in the parameter block (here wider and narrower Gaussians than the default
+    1/(2 Delta^2) = 38.9) gives the oracle's descriptors, and the network forces through it the oracle's."""
+    from oracle import nn_oracle
+    import oracle as orc
+    s, nn, Q, spec, x, L = setup(md, nn_oracle, orc)
+    nn.eta = eta
+    spec = nn_oracle.NNSpec(width=eta)
+    G = md.nn_descriptors(s.ctx, s.box, nn, s.pos, s.nl)
+    Go, _ = nn_oracle.descriptors(x, L, spec)
+    say("eta", eta, "G rel-L2", rel_l2(G.cpu().numpy(), Go))
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+    import torch
+    _, e = md.nn_mlp(s.ctx, nn, G)
+    F = torch.zeros_like(s.force)
+    md.nn_forces(s.ctx, s.box, nn, s.pos, s.nl, e, F)
+    _, _, Fo, _, _ = nn_oracle.energy_forces(x, L, Q, spec)
+    say("eta", eta, "F rel-L2", rel_l2(F.cpu().numpy(), Fo))
+    assert rel_l2(F.cpu().numpy(), Fo) < 1e-4
+
+
 def test_mlp_matches_oracle(md):
     from oracle import nn_oracle
     import oracle as orc
