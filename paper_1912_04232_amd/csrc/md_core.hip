@@ -394,7 +394,6 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
     int longest = 0;
     for (int base = 0; base < total; base += NS * 64) {
         const bool last_batch = base + NS * 64 >= total;
-        const int nslots = min(NS, (total - base + 63) >> 6);
         uint32_t ca[NS], cb[NS], cc[NS];
         int cj[NS];
 #pragma unroll
@@ -426,19 +425,23 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
             const uint32_t pxy = pack_hi16(ui[0], ui[1]), pz = D == 3 ? ui[2] >> 16 : 0u;
             const uint32_t iw4 = (uint32_t)i * W * 4u;
             int n = base > 0 ? __builtin_amdgcn_readfirstlane(ncnt[p]) : 0;
-            // the particle itself is the one candidate with its own index
+            // the particle itself is the one candidate with its own index.  The slots are tested in three passes so
+            // that the filter of every slot is one straight run of independent instructions: the filter (lane masks
+            // of every slot), then the double-precision recheck of the rare undecided candidates, then the stores in
+            // sequence order.  Slots past the last candidate hold no accepted and no undecided lane.
             auto test_slots = [&]() {
+                uint64_t acc[NS], band[NS];
+                uint64_t any_band = 0;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    if (s >= nslots) break;
                     // lane masks straight from the compares: acc = surely in the list, band = undecided by the filter
-                    uint64_t acc, band;
                     if constexpr (PK) {
                         const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
                         const uint64_t lo = __builtin_amdgcn_sicmp(r2, lp.pk_lo, kICmpSLT);
                         const uint64_t hi = __builtin_amdgcn_sicmp(r2, lp.pk_hi, kICmpSLT);
-                        acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
-                        band = hi & ~lo;
+                        const uint64_t other = __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                        acc[s] = lo & other;
+                        band[s] = hi & ~lo & other;
                     } else {
                         const uint32_t uj[3] = {ca[s], cb[s], cc[s]};
                         float r2 = 0.0f;
@@ -447,18 +450,23 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                             const float d = iso ? (float)(int32_t)(ui[z] - uj[z]) : tdisp(ui[z], uj[z], b.s[z]);
                             r2 = __builtin_fmaf(d, d, r2);
                         }
-                        const uint64_t ok = __builtin_amdgcn_sicmp(cj[s], 0, kICmpSGE);
+                        const uint64_t ok = __builtin_amdgcn_sicmp(cj[s], 0, kICmpSGE) &
+                                            __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
                         const uint64_t lo = __builtin_amdgcn_fcmpf(r2, flo, kFCmpOLT) & ok;
                         const uint64_t hi = __builtin_amdgcn_fcmpf(r2, fhi, kFCmpOLE) & ok;
-                        acc = lo & __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
-                        band = hi & ~lo;
+                        acc[s] = lo;
+                        band[s] = hi & ~lo;
                     }
-                    // candidates near r_list take the defining double expression (rare: the whole wave skips this)
-                    if (band != 0) {
-                        band &= __builtin_amdgcn_sicmp(cj[s], i, kICmpNE);
+                    any_band |= band[s];
+                }
+                // candidates near r_list take the defining double expression (rare: the whole wave skips this)
+                if (any_band != 0) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        if (band[s] == 0) continue;
                         const uint32_t slot = locate(base + s * 64 + lane);  // the full record (PK kept 16 bits)
                         bool take = false;
-                        if (__builtin_amdgcn_inverse_ballot_w64(band)) {
+                        if (__builtin_amdgcn_inverse_ballot_w64(band[s])) {
                             uint32_t uj[3] = {ca[s], cb[s], cc[s]};
                             if constexpr (PK) {
                                 const uint4 r = rec16(bins.mem, slot);
@@ -474,19 +482,22 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                             }
                             take = r2d < lp.rl2;
                         }
-                        acc |= __builtin_amdgcn_ballot_w64(take);
+                        acc[s] |= __builtin_amdgcn_ballot_w64(take);
                     }
-                    if (__builtin_amdgcn_inverse_ballot_w64(acc)) {
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(acc[s])) {
                         // entry k = n + (accepted lanes below this one) goes to sub-row k % W at position k / W:
                         // (k / W) row_bytes + (k % W) 4 + 4 W i = (k / W) (row_bytes - 4 W) + 4 k + 4 W i
                         const uint32_t k = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(acc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)acc, (uint32_t)n));
+                            (uint32_t)(acc[s] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)acc[s], (uint32_t)n));
                         const uint32_t k4 = (k << 2) + iw4;
                         const uint32_t off = SMALL_ROWS ? __umul24(k / W, row_bytes - 4u * W) + k4
                                                         : k / W * (row_bytes - 4u * W) + k4;
                         __builtin_amdgcn_raw_buffer_store_b32(cj[s], ridx, off, 0, 0);
                     }
-                    n += __popcll(acc);
+                    n += __popcll(acc[s]);
                 }
             };
             test_slots();
