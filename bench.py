@@ -76,6 +76,68 @@ def cpu_baseline(cfg, seconds: float):
                       f"scaled by N/{m} to one step"}
 
 
+def cpu_per_config(seconds: float):
+    """The oracle as it stands, timed on bounded samples of the secondary configurations (each about `seconds`):
+    NVE steps of the N = 1000 LJ system; one FIRE force evaluation of the 65536-disk packing from sampled rows;
+    FIRE steps of the first replicas of the 64-packing batch; the neural potential's energies and forces (numpy)
+    on a 3456-atom LJ configuration at the training density."""
+    import numpy as np
+
+    import oracle
+    from oracle import nn_oracle
+    from paper_1912_04232_amd import inputs
+    threads = oracle.default_threads()
+    out = {}
+
+    def timed(fn, n0=1):
+        n = n0
+        while True:
+            t0 = time.perf_counter()
+            fn(n)
+            t = time.perf_counter() - t0
+            if t > seconds / 3 or n >= 1 << 20:
+                return n, t
+            n = int(n * max(2.0, seconds / max(t, 1e-3) / 2))
+
+    c = inputs.lj_small()
+    x = oracle.decode(c["u"], c["L"])
+    pot = oracle.Potential("lj", np.ones((1, 1)), np.ones((1, 1)), r_cut=c["r_cut"])
+    F, _, _ = oracle.pair_rows(x, c["L"], pot, nthreads=threads)
+    n, t = timed(lambda k: oracle.verlet(x, c["v"], F, c["L"], pot, c["dt"], k, nthreads=threads))
+    out["lj_small_N1000"] = {"nve_steps_per_s": n / t, "cores": threads,
+                             "sample": f"{n} brute-force FP64 velocity-Verlet steps in {t:.2f} s"}
+    c = inputs.ss_fire()
+    x = oracle.decode(c["u"], c["L"][:2])
+    pot = oracle.Potential("soft_sphere", np.array(c["sigma"]), np.array(c["epsilon"]), alpha=2.0)
+    N = c["N"]
+    rng = np.random.default_rng(0)
+    m, t = timed(lambda k: oracle.pair_rows(x, c["L"][:2], pot, c["species"], rows=rng.choice(N, min(k, N), replace=False),
+                                            nthreads=threads), n0=256)
+    m = min(m, N)
+    out["fire_ss_N65536"] = {"steps_per_s": m / (t * N), "cores": threads,
+                             "sample": f"brute-force FP64 forces of {m} of {N} disks in {t:.2f} s, scaled by N/{m} "
+                                       f"to one FIRE step (the force evaluation is the step's cost)"}
+    reps = inputs.ss_batch()
+    d = np.array([1.0, 1.4])
+    spot = oracle.Potential("soft_sphere", 0.5 * (d[:, None] + d[None, :]), np.ones((2, 2)), alpha=2.0)
+    r0 = reps[0]
+    xb = oracle.decode(r0["u"], r0["L"][:2])
+    k, t = timed(lambda k: oracle.fire(xb, r0["L"][:2], spot, r0["species"], max_steps=k, f_tol=0.0,
+                                       nthreads=threads), n0=10)
+    out["batched_fire_64"] = {"particle_steps_per_s": k * r0["N"] / t, "cores": threads,
+                              "sample": f"{k} FP64 FIRE steps of replica 0 (N = {r0['N']}) in {t:.2f} s"}
+    n_cells = 12
+    Ln = inputs.box_for_density(2 * n_cells ** 3, 0.84)
+    xn = oracle.decode(inputs.bcc_torus(n_cells, Ln), [Ln] * 3)
+    spec = nn_oracle.NNSpec()
+    P = nn_oracle.init_params(spec, 1)
+    k, t = timed(lambda k: [nn_oracle.energy_forces(xn, [Ln] * 3, P, spec) for _ in range(k)])
+    out["nn_energy_forces"] = {"atom_evals_per_s": k * xn.shape[0] / t, "cores": 1,
+                               "sample": f"{k} numpy FP64 energy+force evaluations of {xn.shape[0]} atoms in {t:.2f} s "
+                                         f"(numpy, one thread apart from its BLAS calls)"}
+    return out
+
+
 def traffic_from(fetch_dir: str, write_dir: str):
     """HBM bytes per k_md_step launch from two rocprofv3 counter runs of `bench.py --copy-calibration` (one with
     --pmc FETCH_SIZE, one with --pmc WRITE_SIZE; counters in KiB per dispatch), each scaled by what the same
@@ -116,16 +178,11 @@ def traffic_from(fetch_dir: str, write_dir: str):
     print(json.dumps(rec))
 
 
-def secondary(progress):
-    """Per-config secondary numbers: the small LJ system (list and dense force evaluations), FIRE on 65536 soft
-    disks, and the 64-replica batched minimizer with its adjoint."""
-    import numpy as np
+def lj_small(ctx, progress):
+    """3D LJ N=1000: 100 NVE steps over the list, and the list and dense force evaluations."""
     import torch
 
     from paper_1912_04232_amd import inputs, md
-    out = {}
-    ctx = md.Context()
-    # C1: 3D LJ N=1000, 100 NVE steps over the list; dense and list force evaluations
     c = inputs.lj_small()
     box = md.Box(tuple(c["L"]), 3)
     pot = md.Potential("lj", [[1.0]], [[1.0]], r_cut=c["r_cut"])
@@ -154,34 +211,54 @@ def secondary(progress):
     torch.cuda.synchronize()
     t_dense = (time.perf_counter() - t0) / reps
     n_mean = float(s.nl.lengths().mean())
-    out["lj_small_N1000"] = {"nve_steps_per_s": c["steps"] / t_nve, "list_force_evals_per_s": 1.0 / t_nl,
-                             "dense_force_evals_per_s": 1.0 / t_dense,
-                             "list_pair_evals_per_s": n_mean * c["N"] / t_nl,
-                             "dense_pair_evals_per_s": c["N"] * (c["N"] - 1) / t_dense}
     progress("small LJ done")
-    # C2: FIRE on 65536 bidisperse harmonic disks at phi 0.90
+    return {"nve_steps_per_s": c["steps"] / t_nve, "list_force_evals_per_s": 1.0 / t_nl,
+            "dense_force_evals_per_s": 1.0 / t_dense, "list_pair_evals_per_s": n_mean * c["N"] / t_nl,
+            "dense_pair_evals_per_s": c["N"] * (c["N"] - 1) / t_dense}
+
+
+def fire_ss(ctx, progress):
+    """FIRE on 65536 bidisperse harmonic disks at phi 0.90 to max |F| < 1e-6 (HIP graphs of 500 steps)."""
+    import torch
+
+    from paper_1912_04232_amd import inputs, md
     c = inputs.ss_fire()
     box = md.Box(tuple(c["L"][:2]), 2)
     pot = md.Potential("soft_sphere", c["sigma"], c["epsilon"], alpha=2.0)
     s = md.System(box, pot, c["u"], None, c["species"], skin=c["skin"], ctx=ctx)
     init, step, minimize = md.fire_descent(s, f_tol=1e-6)
     init()
+    s.nl.clear_flags()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = minimize(400000, chunk=500, graph=True)
     torch.cuda.synchronize()
     t_fire = time.perf_counter() - t0
-    out["fire_ss_N65536"] = {"converged": bool(st["converged"]), "steps": int(st["steps"]), "fmax": st["fmax"],
-                             "seconds": t_fire, "steps_per_s": st["steps"] / t_fire}
+    f = s.nl.read_flags()
     progress("FIRE done")
-    # C4: 64 packings of uneven N in one launch, then the adjoint at the minima
+    return {"converged": bool(st["converged"]), "steps": int(st["steps"]), "fmax": st["fmax"],
+            "seconds": t_fire, "steps_per_s": st["steps"] / t_fire, "rebuilds": int(f[md.FLAG_REBUILDS]),
+            "launches_per_step": "drift, five device-gated rebuild kernels, force, reduction"}
+
+
+def batched_fire(ctx, progress):
+    """64 packings of uneven N (256 to 4096) minimized in one launch, with the launch shape chosen by the batched
+    autotuner (200 trial steps per candidate), then the adjoint at the minima."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04232_amd import inputs, md
     reps = inputs.ss_batch()
     bt = md.Batch(reps)
     d = np.array([1.0, 1.4])
     spot = md.Potential("soft_sphere", 0.5 * (d[:, None] + d[None, :]), np.ones((2, 2)), alpha=2.0)
+    t0 = time.perf_counter()
+    tune = md.autotune_fire_batched(ctx, bt, spot)
+    t_tune = time.perf_counter() - t0
+    progress(f"batched FIRE launch shape {tune['config']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e, fmax, steps, status = md.fire_batched(ctx, bt, spot, md.FireParams(), 400000, 1e-6)
+    e, fmax, steps, status = md.fire_batched(ctx, bt, spot, md.FireParams(), 400000, 1e-6, config=tune["config"])
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -190,25 +267,51 @@ def secondary(progress):
     t_g = time.perf_counter() - t0
     steps = steps.cpu().numpy()
     sizes = np.asarray(bt.sizes)
-    out["batched_fire_64"] = {"replicas": len(reps), "N_range": [int(sizes.min()), int(sizes.max())],
-                              "converged": int((status.cpu().numpy() == 1).sum()), "seconds": t_b,
-                              "max_steps": int(steps.max()),
-                              "particle_steps_per_s": float((steps * sizes).sum()) / t_b,
-                              "adjoint_seconds": t_g}
     progress("batched FIRE done")
-    # Sec. 4.2 with the box of App. A: 128 disks, half of diameter D and half 1, box rescaled with D at packing
-    # fraction 1, 100 random starts per D; dE*/dD at minima (batched FIRE + envelope_grad), then the way App. A
-    # computes it: 300 FIRE steps and dE_300/dD by reverse mode through the steps, all 1500 replicas in one launch
+    return {"replicas": len(reps), "N_range": [int(sizes.min()), int(sizes.max())],
+            "converged": int((status.cpu().numpy() == 1).sum()), "seconds": t_b, "max_steps": int(steps.max()),
+            "particle_steps_per_s": float((steps * sizes).sum()) / t_b, "adjoint_seconds": t_g,
+            "launch_shape": {"threads": tune["config"][0], "cell_factor": tune["config"][1],
+                             "trial_ms": tune["ms_per_trial"], "autotune_seconds": t_tune}}
+
+
+def rescaled_box_sweep(ctx, progress):
+    """Sec. 4.2 with the box of App. A: 128 disks, half of diameter D and half 1, box rescaled with D at packing
+    fraction 1, 100 random starts per D; dE*/dD at minima (batched FIRE + envelope gradient)."""
     from paper_1912_04232_amd import sweep
-    out["rescaled_box_sweep"] = sweep.run_envelope(ctx)
+    out = sweep.run_envelope(ctx)
     progress("rescaled-box sweep done")
-    out["unrolled_box_sweep"] = sweep.run_unrolled(ctx)
-    progress("unrolled sweep done")
-    out["integrators_lj256k"] = integrators(ctx, progress)
-    out["morse_nve_256k"] = morse_nve(ctx, progress)
-    out["half_vs_full_list_256k"] = half_vs_full(ctx, progress)
-    out["flocking_65536"] = flocking(ctx, progress)
     return out
+
+
+def unrolled_box_sweep(ctx, progress):
+    """The same sweep the way App. A computes it: 300 FIRE steps and dE_300/dD by reverse mode through the steps,
+    all 1500 replicas in one launch."""
+    from paper_1912_04232_amd import sweep
+    out = sweep.run_unrolled(ctx)
+    progress("unrolled sweep done")
+    return out
+
+
+# secondary configurations in the order the default run takes them; `--only` names any of them (and "surrogate")
+SECTIONS = {
+    "lj_small_N1000": lj_small,
+    "fire_ss_N65536": fire_ss,
+    "batched_fire_64": batched_fire,
+    "rescaled_box_sweep": rescaled_box_sweep,
+    "unrolled_box_sweep": unrolled_box_sweep,
+    "integrators_lj256k": lambda ctx, progress: integrators(ctx, progress),
+    "morse_nve_256k": lambda ctx, progress: morse_nve(ctx, progress),
+    "half_vs_full_list_256k": lambda ctx, progress: half_vs_full(ctx, progress),
+    "flocking_65536": lambda ctx, progress: flocking(ctx, progress),
+}
+
+
+def secondary(progress, names=None):
+    """Per-config secondary numbers (every section, or the named ones), on one context."""
+    from paper_1912_04232_amd import md
+    ctx = md.Context()
+    return {k: f(ctx, progress) for k, f in SECTIONS.items() if names is None or k in names}
 
 
 def flocking(ctx, progress, steps: int = 2000):
@@ -381,6 +484,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the neural-potential comparison")
     ap.add_argument("--no-secondary", action="store_true", help="skip the small LJ / FIRE / batched numbers")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated secondary sections (or 'surrogate') to run alone, printing one JSON object")
     ap.add_argument("--nn-train-steps", type=int, default=20000)
     ap.add_argument("--nn-md-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -406,6 +511,16 @@ def main():
     from paper_1912_04232_amd import inputs, md
 
     torch.cuda.set_device(0)
+    if args.only:
+        names = args.only.split(",")
+        unknown = [n for n in names if n not in SECTIONS and n != "surrogate"]
+        if unknown:
+            raise SystemExit(f"unknown sections {unknown}; choose from {list(SECTIONS)} or surrogate")
+        res = secondary(progress, names)
+        if "surrogate" in names:
+            res["surrogate_vs_plain"] = surrogate(progress, args.nn_train_steps, args.nn_md_steps)
+        print(json.dumps(res), flush=True)
+        return
     progress("generating the FCC workload")
     cfg = inputs.lj_large(n_cells=args.n_cells)
     N = cfg["N"]
@@ -509,6 +624,9 @@ def main():
     if not args.no_cpu_baseline:
         progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        if not args.no_secondary:
+            progress("timing the oracle on the secondary configurations")
+            out["cpu_baseline"]["per_config"] = cpu_per_config(args.cpu_seconds / 3)
     print(json.dumps(out), flush=True)
 
 

@@ -56,6 +56,7 @@ struct Lds {
     int8_t spec[kMaxRepN];
     int32_t wtot[kWaves];
     double red[kWaves];
+    double red4[4][kWaves];
     int32_t rep;
     DevPot pot;       // pair coefficients, indexed by pair type from LDS (not from kernel arguments)
     md_potential raw; // the caller's parameters, for the gradient kernel
@@ -113,6 +114,39 @@ __device__ __forceinline__ double wg_max(double v, Lds &s)
     for (int w = 0; w < RB / 64; ++w) r = fmax(r, s.red[w]);
     __syncthreads();
     return r;
+}
+
+// Three sums and one maximum over the workgroup in a single exchange; each is combined in the order wg_sum and
+// wg_max use (lanes by the xor tree, then the waves in order), so the results are theirs bit for bit.
+template <int RB>
+__device__ __forceinline__ void wg_sum3_max(double &a, double &b, double &c, double &m, Lds &s)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+        m = fmax(m, __shfl_xor(m, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s.red4[0][w] = a;
+        s.red4[1][w] = b;
+        s.red4[2][w] = c;
+        s.red4[3][w] = m;
+    }
+    __syncthreads();
+    double ra = 0.0, rb = 0.0, rc = 0.0, rm = 0.0;
+    for (int q = 0; q < RB / 64; ++q) {
+        ra += s.red4[0][q];
+        rb += s.red4[1][q];
+        rc += s.red4[2][q];
+        rm = fmax(rm, s.red4[3][q]);
+    }
+    __syncthreads();
+    a = ra;
+    b = rb;
+    c = rc;
+    m = rm;
 }
 
 // Exclusive scan of one int per thread over the workgroup (shuffles + LDS, no atomics).
@@ -332,10 +366,7 @@ __global__ __launch_bounds__(RB) void k_fire_batched(BatchArgs a, DevPot pin, Fi
                     fm = fmax(fm, f2);
                 }
             }
-            P = wg_sum<RB>(P, s);
-            vv = wg_sum<RB>(vv, s);
-            ff = wg_sum<RB>(ff, s);
-            fm = wg_max<RB>(fm, s);
+            wg_sum3_max<RB>(P, vv, ff, fm, s);
             ++steps;
             if (sqrt(fm) < fp.f_tol) {
                 conv = true;

@@ -518,6 +518,29 @@ def test_fire_one_step_vs_oracle(md, orc):
     assert st["dt"] == pytest.approx(res["dt"]) and st["n_pos"] == res["n_pos"] and st["steps"] == 1
 
 
+@pytest.mark.parametrize("K", [10, 30])
+def test_fire_steps_vs_oracle(md, orc, K):
+    """K FIRE steps from the same start (each step the drift launch, the device-gated rebuild, the force launch and
+    the one-workgroup reduction that applies the FIRE rules): positions, mixed velocities and the FIRE scalars follow
+    the FP64 oracle's."""
+    cfg = ss_cfg(1000, 0.9, 81)
+    s = make_system(md, cfg)
+    init, step, _ = md.fire_descent(s, f_tol=1e-30)
+    init()
+    st = step(K)
+    p = orc_pot(orc, cfg)
+    L = np.asarray(cfg["L"][:2], dtype=np.float64)
+    res = orc.fire(orc.decode(cfg["u"], L), L, p, cfg["species"], max_steps=K, f_tol=0.0)
+    dx = orc.decode(s.pos.cpu().numpy(), L) - res["x"]
+    dx -= L * np.round(dx / L)
+    v = st["mix_v"] * s.vel.cpu().numpy().astype(np.float64) + st["mix_f"] * s.force.cpu().numpy()
+    say("K", K, "position rms", np.sqrt((dx ** 2).sum(1).mean()), "v rel-L2", rel_l2(v, res["v"]))
+    assert np.sqrt((dx ** 2).sum(1).mean()) < 1e-4
+    assert rel_l2(v, res["v"]) < 1e-3
+    assert rel_l2(s.force.cpu().numpy(), res["F"]) < 1e-3
+    assert st["dt"] == pytest.approx(res["dt"]) and st["n_pos"] == res["n_pos"] and st["steps"] == K
+
+
 def test_fire_lattice_reaches_closed_form(md):
     """A jittered compressed triangular lattice relaxes to E/N = 3/2 (1 - a)^2 with max |F| < 1e-6."""
     a = 0.98
