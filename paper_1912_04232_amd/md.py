@@ -1182,12 +1182,16 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         """Run FIRE until converged or max_steps.  With graph=True the launches of `chunk` steps are captured
         once in a HIP graph and replayed (a step's launches are all device-gated, so replays need no host
         decisions); the flags are read after every chunk and a chunk that reports a problem is re-run eagerly
-        from its saved state."""
+        from its saved state.  The returned state also holds "rebuilds": list builds run over the call (one at
+        the start of every chunk, plus the device-gated ones)."""
         st = fire_state_read(state)
+        rebuilds = 0
         while not st["converged"] and st["steps"] < max_steps:
             k = min(chunk, max_steps - st["steps"])
             if not graph or k != chunk:
+                system.nl.clear_flags()
                 st = step_fn(k)
+                rebuilds += int(system.nl.read_flags()[FLAG_REBUILDS])
                 continue
             tensors = (system.pos, system.vel, system.force, state)
             saved = tuple(t.clone() for t in tensors)
@@ -1205,9 +1209,13 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
                 for t, v in zip(tensors, saved):
                     t.copy_(v)
                 graphs.clear()  # the list may be regrown (new buffers): capture again afterwards
+                system.nl.clear_flags()
                 st = step_fn(chunk)
+                rebuilds += int(system.nl.read_flags()[FLAG_REBUILDS])
                 continue
+            rebuilds += int(f[FLAG_REBUILDS])
             st = fire_state_read(state)
+        st["rebuilds"] = rebuilds
         return st
 
     return init_fn, step_fn, minimize
