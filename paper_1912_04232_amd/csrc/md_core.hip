@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/md.h"
 #include "md_device.h"
@@ -339,7 +340,7 @@ __device__ __forceinline__ int sub_count(int n, int l)
 // Rows of every particle of cell gc (a global cell number: system gc / C of a segmented list, cell gc % C in it)
 // from the bins, by the calling wave.  ncnt is the wave's LDS array of running row lengths (used when the stencil
 // holds more candidates than the wave's slots).  Returns the longest row of the cell.
-template <int D, int W, bool PK, int NS, bool SMALL_ROWS>
+template <int D, int W, bool PK, int NS, bool SMALL_ROWS, bool SPARSE>
 __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListParams &lp, int32_t *__restrict__ idx,
                           int32_t *__restrict__ count, int *ncnt)
 {
@@ -394,12 +395,15 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
     int longest = 0;
     for (int base = 0; base < total; base += NS * 64) {
         const bool last_batch = base + NS * 64 >= total;
+        // slots that hold candidates (a sparse system fills one or two of them): the rest are neither loaded nor tested
+        const int nslots = min(NS, (total - base + 63) >> 6);
         uint32_t ca[NS], cb[NS], cc[NS];
         int cj[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int q = base + s * 64 + lane;
-            const uint4 r = rec16(bins.mem, locate(q));
+            const uint4 r = !SPARSE || nslots == NS || s < nslots ? rec16(bins.mem, locate(q))
+                                                                 : make_uint4(0u, 0u, 0u, 0u);
             const bool ok = q < total;
             cj[s] = ok ? (int)r.w : -1;
             if constexpr (PK) {
@@ -428,12 +432,19 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
             // the particle itself is the one candidate with its own index.  The slots are tested in three passes so
             // that the filter of every slot is one straight run of independent instructions: the filter (lane masks
             // of every slot), then the double-precision recheck of the rare undecided candidates, then the stores in
-            // sequence order.  Slots past the last candidate hold no accepted and no undecided lane.
-            auto test_slots = [&]() {
+            // sequence order.  FULL: every slot is tested, with no slot-count branches (a slot or lane past the last
+            // candidate holds no accepted and no undecided candidate).  Otherwise (SPARSE builds with a partly used
+            // batch) only the used slots are loaded and tested: the standalone build serves sparse systems (2D
+            // packings, boids) with one or two of its eight slots in use, while the step kernel's dense cells fill
+            // its four.
+            auto test_slots = [&](auto full_tag) {
+                constexpr bool FULL = decltype(full_tag)::value;
                 uint64_t acc[NS], band[NS];
                 uint64_t any_band = 0;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
+                    acc[s] = band[s] = 0;
+                    if (!FULL && s >= nslots) break;
                     // lane masks straight from the compares: acc = surely in the list, band = undecided by the filter
                     if constexpr (PK) {
                         const int r2 = r2_packed(ca[s], cb[s], pxy, pz);
@@ -463,6 +474,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                 if (any_band != 0) {
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
+                        if (!FULL && s >= nslots) break;
                         if (band[s] == 0) continue;
                         const uint32_t slot = locate(base + s * 64 + lane);  // the full record (PK kept 16 bits)
                         bool take = false;
@@ -487,6 +499,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
+                    if (!FULL && s >= nslots) break;
                     if (__builtin_amdgcn_inverse_ballot_w64(acc[s])) {
                         // entry k = n + (accepted lanes below this one) goes to sub-row k % W at position k / W:
                         // (k / W) row_bytes + (k % W) 4 + 4 W i = (k / W) (row_bytes - 4 W) + 4 k + 4 W i
@@ -500,7 +513,10 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
                     n += __popcll(acc[s]);
                 }
             };
-            test_slots();
+            if (!SPARSE || nslots == NS)
+                test_slots(std::integral_constant<bool, true>());
+            else
+                test_slots(std::integral_constant<bool, false>());
             if (!last_batch) {
                 if (lane == 0) ncnt[p] = n;
             } else {
@@ -514,7 +530,7 @@ __device__ int build_cell(int gc, const DevBox &b, const Bins &bins, const ListP
 
 // Cells of the list handed to the waves of a launch: wave w (blocks remapped so that one XCD's workgroups are one
 // contiguous range) takes cells w, w + nwaves, ...  The longest row and the overflow flag go to flags.
-template <int D, int W, bool PK, int NS>
+template <int D, int W, bool PK, int NS, bool SPARSE>
 __device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bins, const ListParams &lp,
                                                  int32_t *__restrict__ idx, int32_t *__restrict__ count,
                                                  int32_t *flags, int32_t *ok, int *ncnt_all, int *red)
@@ -525,10 +541,10 @@ __device__ __forceinline__ void build_rows_cells(const DevBox &b, const Bins &bi
     int longest = 0;
     if ((uint64_t)lp.N * W * 4u < (1u << 24)) {  // row stride fits the 24-bit multiplier
         for (int gc = wave; gc < lp.cells; gc += nwaves)
-            longest = max(longest, build_cell<D, W, PK, NS, true>(gc, b, bins, lp, idx, count, ncnt));
+            longest = max(longest, build_cell<D, W, PK, NS, true, SPARSE>(gc, b, bins, lp, idx, count, ncnt));
     } else {
         for (int gc = wave; gc < lp.cells; gc += nwaves)
-            longest = max(longest, build_cell<D, W, PK, NS, false>(gc, b, bins, lp, idx, count, ncnt));
+            longest = max(longest, build_cell<D, W, PK, NS, false, SPARSE>(gc, b, bins, lp, idx, count, ncnt));
     }
     wave_flag(longest > lp.cap, &flags[MD_FLAG_OVERFLOW]);
     if (ok != nullptr && longest > lp.cap) *ok = 0;  // rare: only a wave with a row that did not fit stores
@@ -545,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restric
     __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     __shared__ int red[kBlock];
     if (gate_closed(gate)) return;
-    build_rows_cells<D, W, PK, PK ? 8 : 4>(b, bins, lp, g.idx, g.count, flags, ok, ncnt, red);
+    build_rows_cells<D, W, PK, PK ? 8 : 4, true>(b, bins, lp, g.idx, g.count, flags, ok, ncnt, red);
     for (int q = blockIdx.x * kBlock + threadIdx.x; q < lp.N * D; q += gridDim.x * kBlock) g.pos_ref[q] = pos[q];
     if (threadIdx.x == 0 && blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
 }
@@ -1055,10 +1071,10 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
         // rows of the other generation from those bins, one wave per cell
         const ListGen &g1 = a.gen[gen ^ 1];
         if (lp.pk)
-            build_rows_cells<D, W, true, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
+            build_rows_cells<D, W, true, 4, false>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
                                             red);
         else
-            build_rows_cells<D, W, false, 4>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
+            build_rows_cells<D, W, false, 4, false>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
                                              red);
     }
     const ListGen &g = a.gen[gen];
