@@ -30,6 +30,12 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *    Calls enqueue work and return without waiting, except md_flags_read
  *    and md_ctx_* which synchronise as documented.
+ *  - An empty system (N = 0) is valid for nl_build, nl_update,
+ *    pair_energy_force, verlet_step, fire_init, fire_step, md_kick_drift,
+ *    md_kick, md_kinetic_energy and md_sum (and flock_step): nothing is
+ *    computed on particles, and the particle arrays (positions, velocities,
+ *    forces, species, the list's idx / count / pos_ref) may be NULL.  fire_init
+ *    of an empty system reports max |F| = 0 and converged.
  *  - Errors the host can see are returned at once and nothing is enqueued:
  *    NULL pointers, dim not in {2,3}, N < 0, sizes above what md_ctx_reserve
  *    provided (MD_ERR_CAPACITY), r_list >= L_k/2 (MD_ERR_BOX).  Conditions

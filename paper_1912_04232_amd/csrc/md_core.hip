@@ -1628,6 +1628,14 @@ __global__ void k_fire_state_init(md_fire_state *st, double dt, double alpha)
     st->converged = 0;
 }
 
+// An empty system is at its minimum: max |F| = 0 passes any positive tolerance.
+__global__ void k_fire_state_empty(md_fire_state *st, double f_tol)
+{
+    st->fmax = 0.0;
+    st->power = 0.0;
+    st->converged = 0.0 < f_tol ? 1 : 0;
+}
+
 // ------------------------------------------------------------------------------------------------
 // small kernels: conversions, reductions, flags
 
@@ -1993,11 +2001,18 @@ static bool lanes_ok(int W)
     return W == 1 || W == 2 || W == 4 || W == 8;
 }
 
+// Particle arrays of an empty system (N = 0) may be NULL: nothing reads them.
+static bool given(const void *ptr, int64_t n)
+{
+    return ptr != nullptr || n == 0;
+}
+
 static bool nl_ok(const md_nlist *nl, int N)
 {
     if (nl && (nl->segment < 0 || (nl->segment > 0 && N % nl->segment != 0))) return false;
     return nl && nl->N == N && lanes_ok(nl->lanes) && nl->capacity >= nl->lanes && nl->capacity % nl->lanes == 0 &&
-           nl->idx && nl->count && nl->pos_ref && nl->flags && nl->r_list > 0.0f && nl->skin >= 0.0f;
+           given(nl->idx, N) && given(nl->count, N) && given(nl->pos_ref, N) && nl->flags && nl->r_list > 0.0f &&
+           nl->skin >= 0.0f;
 }
 
 static ListGen caller_gen(const md_nlist *nl)
@@ -2248,7 +2263,7 @@ md_status nl_build(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t 
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!pos) return MD_ERR_ARG;
+    if (!given(pos, N)) return MD_ERR_ARG;
     DevBox b;
     st = check_list(ctx, box, nl, N, b);
     if (st != MD_OK) return st;
@@ -2263,9 +2278,9 @@ md_status pair_energy_force(md_ctx *ctx, const md_box *box, const md_potential *
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
     DevPot p;
-    if (!pos || !md_make_pot(pot, p)) return MD_ERR_ARG;
+    if (!given(pos, N) || !md_make_pot(pot, p)) return MD_ERR_ARG;
     bool multi = pot->n_species > 1;
-    if (multi && !species) return MD_ERR_ARG;
+    if (multi && !given(species, N)) return MD_ERR_ARG;
     if (nl && !nl_ok(nl, N)) return MD_ERR_ARG;
     if (nl && !md_list_covers(nl, md_max_cutoff(pot))) return MD_ERR_ARG;
     if (!box_ok(box, nl ? nl->r_list : md_max_cutoff(pot))) return MD_ERR_BOX;
@@ -2312,7 +2327,7 @@ static md_status run_checks(md_ctx *ctx, const md_box *box, const md_potential *
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
     if (!md_make_pot(pot, p)) return MD_ERR_ARG;
-    if (pot->n_species > 1 && !species) return MD_ERR_ARG;
+    if (pot->n_species > 1 && !given(species, N)) return MD_ERR_ARG;
     st = check_list(ctx, box, nl, N, b);
     if (st != MD_OK) return st;
     if (!md_list_covers(nl, md_max_cutoff(pot))) return MD_ERR_ARG;
@@ -2326,7 +2341,8 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
 {
     DevBox b;
     DevPot p;
-    if (!pos || !vel || !force || n_steps < 0 || !isfinite(dt) || (nl && nl->segment != 0)) return MD_ERR_ARG;
+    if (!given(pos, N) || !given(vel, N) || !given(force, N) || n_steps < 0 || !isfinite(dt) || (nl && nl->segment != 0))
+        return MD_ERR_ARG;
     md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
     if (st != MD_OK) return st;
     if (N == 0 || n_steps == 0) return MD_OK;
@@ -2402,10 +2418,14 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
 {
     DevBox b;
     DevPot p;
-    if (!pos || !vel || !force || !fst || !fp || n_steps < 0 || (nl && nl->segment != 0)) return MD_ERR_ARG;
+    if (!given(pos, N) || !given(vel, N) || !given(force, N) || !fst || !fp || n_steps < 0 || (nl && nl->segment != 0))
+        return MD_ERR_ARG;
     md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
     if (st != MD_OK) return st;
-    if (N == 0) return MD_OK;
+    if (N == 0) {
+        if (init) hipLaunchKernelGGL(k_fire_state_empty, dim3(1), dim3(1), 0, s, fst, f_tol);
+        return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+    }
     bool multi = pot->n_species > 1;
     st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
     if (st != MD_OK) return st;
@@ -2471,7 +2491,7 @@ md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uin
 
 md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *stream)
 {
-    if (!ctx || !x || !out || n < 0) return MD_ERR_ARG;
+    if (!ctx || !given(x, n) || !out || n < 0) return MD_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_sum_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, x, n, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
@@ -2480,7 +2500,7 @@ md_status md_sum(md_ctx *ctx, const double *x, int64_t n, double *out, void *str
 
 md_status md_kinetic_energy(md_ctx *ctx, const float *vel, int32_t N, int32_t dim, double *out, void *stream)
 {
-    if (!ctx || !vel || !out || N < 0 || (dim != 2 && dim != 3)) return MD_ERR_ARG;
+    if (!ctx || !given(vel, N) || !out || N < 0 || (dim != 2 && dim != 3)) return MD_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ke_partial, dim3(kRedBlocks), dim3(kBlock), 0, s, vel, (int64_t)N * dim, ctx->partials);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, ctx->partials, kRedBlocks, out);
@@ -2531,7 +2551,8 @@ md_status md_kick_drift(md_ctx *ctx, const md_box *box, uint32_t *pos, float *ve
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!pos || !vel || !force || !nl_ok(nl, N) || !isfinite(dt) || nl->segment != 0) return MD_ERR_ARG;
+    if (!given(pos, N) || !given(vel, N) || !given(force, N) || !nl_ok(nl, N) || !isfinite(dt) || nl->segment != 0)
+        return MD_ERR_ARG;
     DevBox b;
     if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
     if (N == 0) return MD_OK;
@@ -2550,7 +2571,7 @@ static md_status step_common(md_ctx *ctx, const md_box *box, const uint32_t *pos
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!pos || !force || !nl_ok(nl, N) || nl->segment != 0) return MD_ERR_ARG;
+    if (!given(pos, N) || !given(force, N) || !nl_ok(nl, N) || nl->segment != 0) return MD_ERR_ARG;
     if (!make_box(box, 0.0f, b)) return MD_ERR_ARG;
     return MD_OK;
 }
@@ -2638,7 +2659,7 @@ md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t
 {
     md_status st = check_common(ctx, box, N);
     if (st != MD_OK) return st;
-    if (!pos || (nl && nl->segment != 0)) return MD_ERR_ARG;
+    if (!given(pos, N) || (nl && nl->segment != 0)) return MD_ERR_ARG;
     DevBox b;
     st = check_list(ctx, box, nl, N, b);
     if (st != MD_OK) return st;
@@ -2652,7 +2673,7 @@ md_status nl_update(md_ctx *ctx, const md_box *box, const uint32_t *pos, int32_t
 
 md_status md_kick(md_ctx *ctx, float *vel, const float *force, int32_t N, int32_t dim, float h, void *stream)
 {
-    if (!ctx || !vel || !force || N < 0 || (dim != 2 && dim != 3) || !isfinite(h)) return MD_ERR_ARG;
+    if (!ctx || !given(vel, N) || !given(force, N) || N < 0 || (dim != 2 && dim != 3) || !isfinite(h)) return MD_ERR_ARG;
     int64_t n = (int64_t)N * dim;
     if (n == 0) return MD_OK;
     hipLaunchKernelGGL(k_kick, dim3(nblk(n)), dim3(kBlock), 0, (hipStream_t)stream, vel, force, n, h);

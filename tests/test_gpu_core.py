@@ -669,3 +669,82 @@ def test_min_distance_and_rms_diff(md, orc):
     b = torch.cos(a * 3)
     want = float(np.sqrt(np.mean((a.cpu().numpy().astype(np.float64) - b.cpu().numpy().astype(np.float64)) ** 2)))
     assert float(md.rms_diff(s.ctx, a, b)) == pytest.approx(want, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------- degenerate sizes
+
+def test_empty_and_tiny_systems(md, orc):
+    """The degenerate sizes of the path.  N = 0: list build, forces, Verlet steps, FIRE, the kinetic energy and the
+    energy sum accept the empty system (FIRE reports it converged).  N = 1: no neighbors, zero force, and Verlet
+    moves the particle as the oracle does.  N = 2: an LJ dimer's rows, forces and 50 Verlet steps against the
+    oracle; two overlapping soft disks relax to contact under FIRE."""
+    import torch
+    for dim in (2, 3):
+        box = md.Box((6.0,) * dim, dim)
+        s = md.System(box, md.Potential("lj", [[1.0]], [[1.0]], r_cut=2.5), np.zeros((0, dim), np.uint32),
+                      np.zeros((0, dim), np.float32), skin=0.3)
+        s.build()
+        s.forces()
+        init, update = md.nve(s, 0.005)
+        init()
+        update(5)
+        f = s.nl.read_flags()
+        assert not (f[md.FLAG_OVERFLOW] or f[md.FLAG_NONFINITE] or f[md.FLAG_STALE]), f
+        assert s.kinetic_energy() == 0.0 and s.potential_energy() == 0.0
+        d = md.System(box, md.Potential("soft_sphere", [[1.0]], [[1.0]], alpha=2.0), np.zeros((0, dim), np.uint32),
+                      None, skin=0.3)
+        fi, _, fmin = md.fire_descent(d, f_tol=1e-6)
+        fi()
+        st = fmin(100)
+        assert st["converged"] and st["fmax"] == 0.0, st
+
+    # one particle in a 3D box: no neighbors, ballistic motion
+    L = [6.0, 6.0, 6.0]
+    x0 = np.array([[1.0, 2.0, 3.0]])
+    v0 = np.array([[0.3, -0.2, 0.1]])
+    s = md.System(md.Box(tuple(L), 3), md.Potential("lj", [[1.0]], [[1.0]], r_cut=2.5), inputs.to_torus(x0, L),
+                  v0.astype(np.float32), skin=0.3)
+    init, update = md.nve(s, 0.005)
+    init()
+    update(40)
+    p = orc.Potential("lj", np.ones((1, 1)), np.ones((1, 1)), r_cut=2.5)
+    xo, vo, Fo = orc.verlet(orc.decode(inputs.to_torus(x0, L), L), v0, np.zeros((1, 3)), L, p, 0.005, 40)
+    dx = torus_x(s.pos.cpu().numpy(), L) - xo
+    dx -= np.asarray(L) * np.round(dx / np.asarray(L))
+    say("N = 1: position error", np.abs(dx).max(), "force", s.force.cpu().numpy())
+    assert np.abs(dx).max() < 1e-6 and not s.force.cpu().numpy().any()
+    assert s.nl.lengths().tolist() == [0]
+
+    # an LJ dimer at r = 1.1 in a 3D box
+    L = [8.0, 8.0, 8.0]
+    u = inputs.to_torus(np.array([[1.0, 1.0, 1.0], [2.1, 1.0, 1.0]]), L)
+    s = md.System(md.Box(tuple(L), 3), md.Potential("lj", [[1.0]], [[1.0]], r_cut=2.5), u,
+                  np.zeros((2, 3), np.float32), skin=0.3)
+    s.build()
+    assert [sorted(r.tolist()) for r in s.nl.rows()] == [[1], [0]]
+    init, update = md.nve(s, 0.005)
+    init()
+    x = orc.decode(u, L)
+    Fo, _, _ = orc.pair_rows(x, L, p)
+    assert rel_l2(s.force.cpu().numpy(), Fo) < F_TOL
+    update(50)
+    xo, vo, Fo = orc.verlet(x, np.zeros((2, 3)), Fo, L, p, 0.005, 50)
+    dx = torus_x(s.pos.cpu().numpy(), L) - xo
+    dx -= np.asarray(L) * np.round(dx / np.asarray(L))
+    say("dimer: position error", np.abs(dx).max(), "velocity rel-L2", rel_l2(s.vel.cpu().numpy(), vo))
+    assert np.abs(dx).max() < 1e-5
+    assert rel_l2(s.vel.cpu().numpy(), vo) < 1e-4
+
+    # two overlapping soft disks relax to contact
+    L = [8.0, 8.0]
+    u = inputs.to_torus(np.array([[3.0, 4.0], [3.7, 4.0]]), L)
+    d = md.System(md.Box(tuple(L), 2), md.Potential("soft_sphere", [[1.0]], [[1.0]], alpha=2.0), u, None, skin=0.3)
+    fi, _, fmin = md.fire_descent(d, f_tol=1e-6)
+    fi()
+    st = fmin(20000)
+    xd = torus_x(d.pos.cpu().numpy(), L)
+    r = xd[1] - xd[0]
+    r -= np.asarray(L) * np.round(r / np.asarray(L))
+    say("two disks: steps", st["steps"], "fmax", st["fmax"], "r", np.linalg.norm(r))
+    assert st["converged"] and st["fmax"] < 1e-6
+    assert 1.0 - 2e-6 < np.linalg.norm(r) < 1.05
