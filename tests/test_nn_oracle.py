@@ -32,6 +32,25 @@ def params(nn, spec, seed=5):
     return P
 
 
+@pytest.mark.parametrize("width", [0.0, 15.0, 120.0])
+def test_descriptor_width_from_a_dimer(nn, width):
+    """A dimer at r = mu_5 (a basis centre): G^5 = f_c(r) of each atom, the neighbors G^4 = G^6 by symmetry, and
+    -ln(G^6 / G^5) / Delta^2 recovers the width eta (the default 1/(2 Delta^2) when width is 0).  A wrong width, a
+    sign or a missing square in the Gaussian fails one of these."""
+    spec = nn.NNSpec(width=width)
+    delta = (spec.mu1 - spec.mu0) / (spec.K - 1)
+    eta = width if width > 0 else 1.0 / (2.0 * delta * delta)
+    r = spec.mu[5]
+    L = [10.0, 10.0, 10.0]
+    x = np.array([[1.0, 2.0, 3.0], [1.0 + r, 2.0, 3.0]])
+    G, _ = nn.descriptors(x, L, spec)
+    fc = 0.5 * (math.cos(math.pi * r / spec.r_c) + 1.0)
+    assert np.allclose(G[0], G[1], rtol=0, atol=1e-15)
+    assert math.isclose(G[0, 5], fc, rel_tol=1e-12)
+    assert math.isclose(G[0, 4], G[0, 6], rel_tol=1e-9)
+    assert math.isclose(-math.log(G[0, 6] / G[0, 5]) / delta ** 2, eta, rel_tol=1e-9)
+
+
 def test_basis_constants(nn):
     spec = nn.NNSpec()
     assert np.allclose(spec.mu[[0, -1]], [0.8, 2.5])
