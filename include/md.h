@@ -552,6 +552,20 @@ md_status pair_force_half(md_ctx *ctx, const md_box *box, const md_potential *po
 md_status md_langevin_baoa(md_ctx *ctx, const md_box *box, uint32_t *pos, float *vel, const float *force, int32_t N,
                            const md_nlist *nl, float dt, float gamma, float kT, uint64_t seed, uint64_t *step,
                            void *stream);
+/*
+ * Langevin (BAOAB) fused like verlet_step: n_steps steps of
+ *   v += dt/2 F; x += dt/2 v; v = c1 v + c2 xi; x += dt/2 v; F = F(x); v += dt/2 F
+ * in one launch per step, with the list rebuilt on the device inside the run exactly as in verlet_step (same list
+ * arguments, flags and reuse rules), c1 = exp(-gamma dt), c2 = sqrt((1 - c1^2) kT).  The normals of particle i at
+ * noise step t are those md_langevin_baoa draws (Philox4x64-10 at counter (i, t, 0, 0), key (seed, 0)); the steps
+ * use t = step[0], step[0] + 1, ... and step[0] (device memory, required) advances by n_steps.  On entry force
+ * holds F(x); on return pos, vel, force are the state after the last step.  The arithmetic of a coordinate is that
+ * of md_langevin_baoa -> forces -> md_kick; forces summed over a list rebuilt at other steps may differ in the last
+ * bits.  Errors as verlet_step; also gamma < 0, kT < 0 or a NULL step.
+ */
+md_status langevin_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                       float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, float gamma, float kT,
+                       uint64_t seed, uint64_t *step, int32_t n_steps, void *stream);
 /* Brownian dynamics (overdamped Langevin, Euler-Maruyama): x += (dt/gamma) F + sqrt(2 kT dt / gamma) xi, then
  * nl_update and new forces.  gamma > 0; with kT = 0 no noise is drawn and step may be NULL. */
 md_status md_brownian_step(md_ctx *ctx, const md_box *box, uint32_t *pos, const float *force, int32_t N,

@@ -971,6 +971,44 @@ __device__ __forceinline__ float disp2(const uint32_t *a, const uint32_t *__rest
     return r2;
 }
 
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): the counter c is replaced by the output block.
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(m0, c[0]), lo0 = m0 * c[0];
+        uint64_t hi1 = __umul64hi(m1, c[2]), lo1 = m1 * c[2];
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += w0;
+        k1 += w1;
+    }
+}
+
+// Four standard normals of particle i at step s: the top 24 bits of each Philox word plus half a unit give a
+// uniform in (0, 1), exact in float; Box-Muller turns (u0, u1) and (u2, u3) into normals.
+__device__ __forceinline__ void normals4(uint64_t i, uint64_t s, uint64_t seed, float z[4])
+{
+    uint64_t c[4] = {i, s, 0, 0};
+    philox4x64(c, seed, 0);
+    float u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = ((float)(uint32_t)(c[q] >> 40) + 0.5f) * (1.0f / 16777216.0f);
+    float r0 = sqrtf(-2.0f * logf(u[0])), r1 = sqrtf(-2.0f * logf(u[2]));
+    float s0, c0, s1, c1;
+    sincospif(2.0f * u[1], &s0, &c0);
+    sincospif(2.0f * u[3], &s1, &c1);
+    z[0] = r0 * c0;
+    z[1] = r0 * s0;
+    z[2] = r1 * c1;
+    z[3] = r1 * s1;
+}
+
 struct StepArgs {
     DevBox box;
     ListParams lp;
@@ -986,7 +1024,25 @@ struct StepArgs {
     float dt;
     int32_t step;  // s >= 1
     int32_t last;  // 1: kick dt/2, store F, no drift
+    // Langevin (BAOAB) instead of velocity Verlet when langevin != 0: the drift of a step becomes x += dt/2 v,
+    // v = c1 v + c2 xi, x += dt/2 v, with xi the normals of particle i at noise step noise_step[0] + s
+    int32_t langevin;
+    float c1, c2;
+    uint64_t seed;
+    const uint64_t *noise_step;
 };
+
+// The BAOAB update of one coordinate after the force F of this step: the closing half kick of the last step and
+// the opening half kick of this one (two roundings, as the kick and the BAOA launches of the composed step do), the
+// friction and noise, and the displacement dt/2 (v_b + v').  Returns the new velocity; dx receives the displacement.
+__device__ __forceinline__ float baoab_coord(float v, float F, float dt, float c1, float c2, float z, float &dx)
+{
+    const float vh = __builtin_fmaf(0.5f * dt, F, v);
+    const float vb = __builtin_fmaf(0.5f * dt, F, vh);
+    const float vo = __builtin_fmaf(c1, vb, c2 * z);
+    dx = 0.5f * dt * (vb + vo);
+    return vo;
+}
 
 // Control state of step s: {mode, gen} from the previous step's workgroup 0, upgraded to BIN when a
 // rebuild was requested.  Workgroup 0 publishes step s+1's words and clears the request slot of s+2.
@@ -1023,12 +1079,19 @@ __global__ __launch_bounds__(kBlock) void k_verlet_begin(StepArgs a)
         uint32_t ui[D], un[D];
         float step2 = 0.0f, f2 = 0.0f;
         load_pos<D>(a.pos_in, i, ui);
+        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (a.langevin) normals4((uint64_t)i, a.noise_step[0], a.seed, z);
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             float f = a.force[(size_t)i * D + q];
             float v = __builtin_fmaf(0.5f * a.dt, f, a.vel[(size_t)i * D + q]);
-            a.vel[(size_t)i * D + q] = v;
             float dx = a.dt * v;
+            if (a.langevin) {
+                const float vo = __builtin_fmaf(a.c1, v, a.c2 * z[q]);
+                dx = 0.5f * a.dt * (v + vo);
+                v = vo;
+            }
+            a.vel[(size_t)i * D + q] = v;
             un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
             step2 = __builtin_fmaf(dx, dx, step2);
             f2 = __builtin_fmaf(f, f, f2);
@@ -1114,9 +1177,16 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
                 a.vel[at] = __builtin_fmaf(0.5f * a.dt, Fq, a.vel[at]);
                 a.force[at] = Fq;
             } else {
-                const float v = __builtin_fmaf(a.dt, Fq, a.vel[at]);
+                float v, dx;
+                if (a.langevin) {
+                    float z[4];
+                    normals4((uint64_t)i, a.noise_step[0] + (uint64_t)a.step, a.seed, z);
+                    v = baoab_coord(a.vel[at], Fq, a.dt, a.c1, a.c2, pick<D>(q, z[0], z[1], z[2]), dx);
+                } else {
+                    v = __builtin_fmaf(a.dt, Fq, a.vel[at]);
+                    dx = a.dt * v;
+                }
                 a.vel[at] = v;
-                const float dx = a.dt * v;
                 const uint32_t un = shift_coord(uq, dx, isq);
                 a.pos_out[at] = un;
                 const float d = tdisp(un, ref_next[at], sq);
@@ -1150,11 +1220,18 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
     }
     uint32_t un[D];
     float step2 = 0.0f, f2 = 0.0f;
+    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.langevin) normals4((uint64_t)i, a.noise_step[0] + (uint64_t)a.step, a.seed, z);
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-        float v = __builtin_fmaf(a.dt, F[q], a.vel[(size_t)i * D + q]);
+        float v, dx;
+        if (a.langevin) {
+            v = baoab_coord(a.vel[(size_t)i * D + q], F[q], a.dt, a.c1, a.c2, z[q], dx);
+        } else {
+            v = __builtin_fmaf(a.dt, F[q], a.vel[(size_t)i * D + q]);
+            dx = a.dt * v;
+        }
         a.vel[(size_t)i * D + q] = v;
-        float dx = a.dt * v;
         un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
         step2 = __builtin_fmaf(dx, dx, step2);
         f2 = __builtin_fmaf(F[q], F[q], f2);
@@ -1457,44 +1534,6 @@ __global__ __launch_bounds__(kBlock) void k_force_lanes(DevBox b, DevPot p, cons
 // ------------------------------------------------------------------------------------------------
 // constant-temperature steps and gradient descent (the caller computes forces between launches)
 
-// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): the counter c is replaced by the output block.
-__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
-{
-    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
-    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t hi0 = __umul64hi(m0, c[0]), lo0 = m0 * c[0];
-        uint64_t hi1 = __umul64hi(m1, c[2]), lo1 = m1 * c[2];
-        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += w0;
-        k1 += w1;
-    }
-}
-
-// Four standard normals of particle i at step s: the top 24 bits of each Philox word plus half a unit give a
-// uniform in (0, 1), exact in float; Box-Muller turns (u0, u1) and (u2, u3) into normals.
-__device__ __forceinline__ void normals4(uint64_t i, uint64_t s, uint64_t seed, float z[4])
-{
-    uint64_t c[4] = {i, s, 0, 0};
-    philox4x64(c, seed, 0);
-    float u[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = ((float)(uint32_t)(c[q] >> 40) + 0.5f) * (1.0f / 16777216.0f);
-    float r0 = sqrtf(-2.0f * logf(u[0])), r1 = sqrtf(-2.0f * logf(u[2]));
-    float s0, c0, s1, c1;
-    sincospif(2.0f * u[1], &s0, &c0);
-    sincospif(2.0f * u[3], &s1, &c1);
-    z[0] = r0 * c0;
-    z[1] = r0 * s0;
-    z[2] = r1 * c1;
-    z[3] = r1 * s1;
-}
-
 // BAOA of a BAOAB Langevin step (Leimkuhler and Matthews): v += dt/2 F, x += dt/2 v, v = c1 v + c2 xi,
 // x += dt/2 v (both drifts applied as one shift), and the rebuild trigger of k_kick_drift.
 template <int D>
@@ -1551,6 +1590,11 @@ __global__ __launch_bounds__(kBlock) void k_overdamped(uint32_t *pos, const floa
 __global__ void k_step_advance(uint64_t *step)
 {
     if (threadIdx.x == 0) step[0] += 1;
+}
+
+__global__ void k_step_advance_by(uint64_t *step, int32_t n)
+{
+    if (threadIdx.x == 0) step[0] += (uint64_t)n;
 }
 
 // Half step of a Nose-Hoover chain over time h (Martyna, Tuckerman, Tobias and Klein 1996, one stage): 2K from
@@ -2335,9 +2379,16 @@ static md_status run_checks(md_ctx *ctx, const md_box *box, const md_potential *
     return MD_OK;
 }
 
-md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
-                      float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, int32_t n_steps,
-                      void *stream)
+// Langevin parameters of a fused run (langevin_run); NULL for velocity Verlet.
+struct LangevinCfg {
+    float c1, c2;
+    uint64_t seed;
+    uint64_t *step;
+};
+
+static md_status md_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                        float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, int32_t n_steps,
+                        void *stream, const LangevinCfg *lv)
 {
     DevBox b;
     DevPot p;
@@ -2345,8 +2396,12 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
         return MD_ERR_ARG;
     md_status st = run_checks(ctx, box, pot, nl, N, species, b, p);
     if (st != MD_OK) return st;
-    if (N == 0 || n_steps == 0) return MD_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (N == 0 || n_steps == 0) {
+        // an empty system still uses up its noise steps, as the composed Langevin step does
+        if (lv && n_steps > 0) hipLaunchKernelGGL(k_step_advance_by, dim3(1), dim3(64), 0, s, lv->step, n_steps);
+        return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+    }
     bool multi = pot->n_species > 1;
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctx->ctl);
     // The list the caller holds is used again when generation-0 bins belong to it and the device finds it complete
@@ -2383,6 +2438,11 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
     a.pos_out = buf[1];
     a.step = 0;
     a.last = 0;
+    a.langevin = lv != nullptr;
+    a.c1 = lv ? lv->c1 : 0.0f;
+    a.c2 = lv ? lv->c2 : 0.0f;
+    a.seed = lv ? lv->seed : 0;
+    a.noise_step = lv ? lv->step : nullptr;
     if (box->dim == 3)
         hipLaunchKernelGGL(k_verlet_begin<3>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
     else
@@ -2409,7 +2469,25 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
         hipLaunchKernelGGL(k_list_finalize<2>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
     hipLaunchKernelGGL(k_bins_finalize, dim3(nblk((int64_t)b.C * a.lp.M)), dim3(kBlock), 0, s, ctx->ctl, nl->flags,
                        a.bins[0], a.bins[1], b.C, a.lp.M);
+    if (lv) hipLaunchKernelGGL(k_step_advance_by, dim3(1), dim3(64), 0, s, lv->step, n_steps);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                      float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, int32_t n_steps,
+                      void *stream)
+{
+    return md_run(ctx, box, pot, pos, vel, force, species, N, nl, dt, n_steps, stream, nullptr);
+}
+
+md_status langevin_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
+                       float *force, const int32_t *species, int32_t N, md_nlist *nl, float dt, float gamma, float kT,
+                       uint64_t seed, uint64_t *step, int32_t n_steps, void *stream)
+{
+    if (!step || !(gamma >= 0.0f) || !(kT >= 0.0f) || !isfinite(gamma) || !isfinite(kT)) return MD_ERR_ARG;
+    const double c1 = exp(-(double)gamma * (double)dt);
+    LangevinCfg lv{(float)c1, (float)sqrt((1.0 - c1 * c1) * (double)kT), seed, step};
+    return md_run(ctx, box, pot, pos, vel, force, species, N, nl, dt, n_steps, stream, &lv);
 }
 
 static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,

@@ -122,6 +122,9 @@ _SIGNATURES = {
                           ctypes.POINTER(c_nlist), P, P, P, P],
     "verlet_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
                     ctypes.POINTER(c_nlist), ctypes.c_float, ctypes.c_int32, P],
+    "langevin_run": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
+                     ctypes.POINTER(c_nlist), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P,
+                     ctypes.c_int32, P],
     "fire_init": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
                   ctypes.POINTER(c_nlist), ctypes.POINTER(c_fire_params), P, ctypes.c_double, P],
     "fire_step": [P, ctypes.POINTER(c_box), ctypes.POINTER(c_potential), P, P, P, P, ctypes.c_int32,
@@ -559,6 +562,17 @@ def verlet_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species
     _check("verlet_step", load().verlet_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                              _ptr(force), _ptr(species), N, ctypes.byref(n),
                                              ctypes.c_float(dt), int(n_steps), _stream()))
+
+
+def langevin_run(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList, dt: float,
+                 gamma: float, kT: float, seed: int, step: torch.Tensor, n_steps: int):
+    N = pos.shape[0]
+    _reserve_for(ctx, box, N, nl)
+    b, p, n = box.c(), pot.c(), nl.c()
+    _check("langevin_run", load().langevin_run(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
+                                               _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.c_float(dt),
+                                               ctypes.c_float(gamma), ctypes.c_float(kT), ctypes.c_uint64(seed),
+                                               _ptr(step), int(n_steps), _stream()))
 
 
 def fire_init(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
@@ -1064,10 +1078,26 @@ def _init_forces(system: System):
     return init_fn
 
 
-def nvt_langevin(system: System, dt: float, gamma: float, kT: float, seed: int = 0):
+def nvt_langevin(system: System, dt: float, gamma: float, kT: float, seed: int = 0, fused: bool = False):
     """init_fn / update_fn for Langevin dynamics at temperature kT (Sec. 3.3.1 ``simulate.nvt_langevin``; BAOAB
-    with friction gamma, unit masses).  The step counter that indexes the noise lives on the device."""
+    with friction gamma, unit masses).  The step counter that indexes the noise lives on the device.  fused=True
+    runs the steps like ``nve`` (langevin_run: one launch per step, the list rebuilt inside the run); otherwise a
+    step is the BAOA launch, the device-gated rebuild, the force pass and the closing kick."""
     step = torch.zeros(1, dtype=torch.int64, device=system.ctx.device)
+    if fused:
+        def update_fn(n_steps: int = 1, graph: bool = False):
+            tensors = (system.pos, system.vel, system.force, step)
+            saved = (tensors, tuple(t.clone() for t in tensors))
+
+            def call(n):
+                langevin_run(system.ctx, system.box, system.pot, system.pos, system.vel, system.force,
+                             system.species, system.nl, dt, gamma, kT, seed, step, n)
+
+            system.last_flags = _run_checked(system, saved, call, n_steps)
+            return system
+
+        update_fn.step = step
+        return _init_forces(system), update_fn
 
     def once():
         langevin_baoa(system.ctx, system.box, system.pos, system.vel, system.force, system.nl, dt, gamma, kT, seed,

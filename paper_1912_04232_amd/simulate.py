@@ -1,14 +1,15 @@
 """Constant-temperature dynamics, gradient descent and flocking, as a command.
 
-    python -m paper_1912_04232_amd.simulate [--method langevin|nose_hoover|brownian|gradient_descent|all|flocking]
+    python -m paper_1912_04232_amd.simulate [--method langevin|langevin_fused|nose_hoover|brownian|gradient_descent|all|
+                                             flocking]
                                             [--steps 1000] [--n-cells 40] [--boids 65536]
 
 The integrators run on 3D Lennard-Jones, 4 n^3 particles on an FCC lattice at density 0.84 (N = 256000 for
 n = 40), Maxwell velocities at T = 1, cutoff 2.5, skin 0.3.  Flocking (Sec. 4.3, App. B) runs the boid model with
 its default parameters: boids uniform in a square box at density 0.25 with 16 disk obstacles, skin 0.5, and
 optionally predators (App. B's two-player extension).  Each run
-takes 100 steps (graph capture and warm-up), then `steps` timed steps replayed from HIP graphs of 20 steps; one
-JSON line per run.
+takes 100 steps (graph capture and warm-up), then `steps` timed steps replayed from HIP graphs of 20 steps (the
+fused Langevin run, like NVE, is one launch per step with the list rebuilt inside the run); one JSON line per run.
 """
 from __future__ import annotations
 
@@ -24,6 +25,8 @@ from . import inputs, md
 
 METHODS = {
     "langevin": ("BAOAB, gamma 1, kT 1, dt 0.005", lambda s, c: md.nvt_langevin(s, c["dt"], 1.0, 1.0, 1)),
+    "langevin_fused": ("BAOAB fused into the step kernel, gamma 1, kT 1, dt 0.005",
+                       lambda s, c: md.nvt_langevin(s, c["dt"], 1.0, 1.0, 1, fused=True)),
     "nose_hoover": ("chain Q = (100, 10), kT 1, dt 0.005",
                     lambda s, c: md.nvt_nose_hoover(s, c["dt"], 1.0, (100.0, 10.0))[:2]),
     "brownian": ("gamma 1, kT 1, dt 1e-4", lambda s, c: md.brownian(s, 1e-4, 1.0, 1.0, 1)),
@@ -45,7 +48,7 @@ def run(ctx, method: str, steps: int = 1000, n_cells: int = 40) -> dict:
     update(steps, graph=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    inertial = method in ("langevin", "nose_hoover")
+    inertial = method in ("langevin", "langevin_fused", "nose_hoover")
     return {"method": method, "scheme": what, "N": s.N, "steps": steps, "steps_per_s": steps / t,
             "us_per_step": 1e6 * t / steps,
             "kinetic_T": float((s.vel.double() ** 2).sum()) / (3 * s.N) if inertial else None}

@@ -87,6 +87,56 @@ def test_langevin_steps_match_oracle(md, orc, th, case):
         assert dx < 1e-5 and ev < 1e-5 and ef < 1e-4
 
 
+@pytest.mark.parametrize("case", ["soft2d", "lj3d"])
+def test_fused_langevin_steps_match_oracle(md, orc, th, case):
+    """langevin_run (the Verlet step kernel with the BAOAB drift, the list rebuilt inside the run) against the
+    oracle's BAOAB from the same seeded state and noise: 1, then 4, then 10 more steps."""
+    s, opot, u, v, sp, L = (soft_case if case == "soft2d" else lj_case)(md, orc)
+    dt, gamma, kT, seed = (0.01, 1.0, 0.3, 5) if case == "soft2d" else (0.004, 2.0, 1.2, 6)
+    init, update = md.nvt_langevin(s, dt, gamma, kT, seed, fused=True)
+    init()
+    x = torus_x(u, L)
+    F, _, _ = orc.pair_rows(x, L, opot, sp)
+    xv = v.astype(np.float64)
+    done = 0
+    for n in (1, 4, 10):
+        update(n)
+        x, xv, F = th.langevin_baoab(x, xv, F, L, opot, sp, dt, gamma, kT, seed, done, n)
+        done += n
+        dx = max_image_diff(torus_x(md.from_device_u32(s.pos), L), x, L)
+        ev, ef = rel_l2(s.vel.cpu().numpy(), xv), rel_l2(s.force.cpu().numpy(), F)
+        say(case, "fused steps", done, "dx", dx, "v", ev, "F", ef, "noise step", int(update.step.item()))
+        assert int(update.step.item()) == done
+        assert dx < 1e-5 and ev < 1e-5 and ef < 1e-4
+
+
+def test_fused_langevin_equals_composed_steps(md, orc):
+    """The fused run and the composed step (BAOA launch, gated rebuild, force pass, closing kick) do the same
+    arithmetic per coordinate: from the same state and noise, while neither has rebuilt its list, the two states are
+    identical bit for bit; over 300 steps with rebuilds they agree to float rounding of the force sums for the first
+    steps and keep the same temperature."""
+    import torch
+    a, _, _, _, _, L = lj_case(md, orc, N=1500, seed=72)
+    b, _, _, _, _, _ = lj_case(md, orc, N=1500, seed=72)
+    dt, gamma, kT, seed = 0.004, 2.0, 1.2, 11
+    ia, ua = md.nvt_langevin(a, dt, gamma, kT, seed, fused=True)
+    ib, ub = md.nvt_langevin(b, dt, gamma, kT, seed)
+    ia()
+    ib()
+    ua(2)
+    ub(2)
+    fa, fb = a.nl.read_flags(), b.nl.read_flags()
+    say("rebuilds in the first 2 steps: fused", int(fa[md.FLAG_REBUILDS]), "composed", int(fb[md.FLAG_REBUILDS]))
+    if fa[md.FLAG_REBUILDS] == 0 and fb[md.FLAG_REBUILDS] == 0:
+        assert torch.equal(a.pos, b.pos) and torch.equal(a.vel, b.vel) and torch.equal(a.force, b.force)
+    ua(298)
+    ub(298)
+    Ta = a.kinetic_energy() * 2.0 / (3 * a.N)
+    Tb = b.kinetic_energy() * 2.0 / (3 * b.N)
+    say("kinetic T after 300 steps: fused", Ta, "composed", Tb)
+    assert abs(Ta - kT) < 0.1 * kT and abs(Tb - kT) < 0.1 * kT
+
+
 def test_noise_matches_oracle_generator(md, orc, th):
     """A force-free Brownian step moves each particle by sqrt(2 kT dt / gamma) xi: the displacements give back the
     GPU's normals, which match the oracle's Philox4x64 + Box-Muller values to float32 rounding."""
