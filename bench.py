@@ -236,7 +236,9 @@ def fire_ss(ctx, progress):
     progress("FIRE done")
     return {"converged": bool(st["converged"]), "steps": int(st["steps"]), "fmax": st["fmax"],
             "seconds": t_fire, "steps_per_s": st["steps"] / t_fire, "rebuilds": int(st["rebuilds"]),
-            "launches_per_step": "drift, five device-gated rebuild kernels, force, reduction"}
+            "chunks_of_500": st["chunks"],
+            "launches_per_step": "2: FIRE rules, mixing and drift; forces (with the list pipeline's bin or "
+                                 "row work when a rebuild is under way)"}
 
 
 def batched_fire(ctx, progress):

@@ -229,7 +229,8 @@ md_status verlet_step(md_ctx *ctx, const md_box *box, const md_potential *pot, u
 typedef struct {
     float dt_start, dt_max, f_inc, f_dec, alpha_start, f_alpha;
     int32_t n_min;
-    int32_t reserved;
+    int32_t sync_rebuild;  /* fire_step's list upkeep: 0 pipelined, 1 before each force evaluation (see fire_step);
+                              the batched and unrolled minimizers ignore it */
 } md_fire_params;
 
 /* FIRE scalars, kept in DEVICE memory by the caller (one struct). */
@@ -261,11 +262,28 @@ md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, con
  *   else : dt *= f_dec, v = 0, a = alpha_start, n_pos = 0.
  * Steps after convergence do nothing, so the call can be enqueued in fixed
  * chunks; st->converged / st->steps tell the caller where it stopped.  The
- * call rebuilds nl for pos first; before each force evaluation a rebuild runs
- * on the device when a particle has moved more than skin/2 since the last
- * one (its launches return at once otherwise).  The velocity mixing decided by a step is applied at the start
- * of the next one (st->mix_v, st->mix_f).  Global sums are double and summed
- * in a fixed order by one workgroup.
+ * call rebuilds nl for pos first.  Each step starts with a launch that
+ * applies the rules of the previous step, the velocity mixing and the drift,
+ * and ends with the force launch.  The list is kept up on the device in one
+ * of two ways (fp->sync_rebuild):
+ *   0  pipelined, two launches per step, as in verlet_step: a particle that
+ *      comes within 3 steps of its current displacement of skin/2 from the
+ *      list's reference positions starts a rebuild whose bins and rows are
+ *      made inside the next two force launches, into the context's second
+ *      list.  A step that moves a particle farther than that margin allows
+ *      (the large early steps from an overlapping start) leaves the list
+ *      stale: MD_FLAG_STALE is set and the call freezes.
+ *   1  before each force evaluation a full rebuild runs when a particle is
+ *      farther than skin/2 from the reference positions (five more launches
+ *      per step, which return at once when no rebuild is due); never stale.
+ * At the end of the call nl holds the list in use.  A list that went stale
+ * or overflowed sets its flag and freezes the call; st is then left as it
+ * was at the start.  The velocity mixing decided by a step is applied at
+ * the start of the next one (st->mix_v, st->mix_f).  Global sums are double
+ * and summed in a fixed order: every workgroup of the mixing launch sums the
+ * force launch's per-workgroup partials itself and gets the same values.
+ * Scratch: the context's partials, control words, second list and two state
+ * slots (calls on one context are serialized by its stream).
  */
 md_status fire_step(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                     float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,

@@ -1046,7 +1046,8 @@ __device__ __forceinline__ float baoab_coord(float v, float F, float dt, float c
 
 // Control state of step s: {mode, gen} from the previous step's workgroup 0, upgraded to BIN when a
 // rebuild was requested.  Workgroup 0 publishes step s+1's words and clears the request slot of s+2.
-__device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s, int &mode, int &gen)
+__device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s, int &mode, int &gen,
+                                             bool count_steps = true)
 {
     int r = s % 3;
     mode = ctl[2 * r];
@@ -1059,7 +1060,7 @@ __device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s
         ctl[2 * ((s + 1) % 3) + 1] = ng;
         ctl[6 + (s + 2) % 3] = 0;
         ctl[kGenWord] = ng;
-        flags[MD_FLAG_STEPS] = s;
+        if (count_steps) flags[MD_FLAG_STEPS] = s;
         if (mode == M_BUILD) flags[MD_FLAG_REBUILDS] += 1;
     }
 }
@@ -1067,6 +1068,35 @@ __device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s
 __device__ __forceinline__ bool frozen(const int32_t *flags)
 {
     return flags[MD_FLAG_OVERFLOW] | flags[MD_FLAG_CELL_OVERFLOW] | flags[MD_FLAG_STALE];
+}
+
+// The rebuild work a step does for the list generation not in use: gather the bins and reference positions of
+// the other generation from the positions of this step (BIN), or build its rows from those bins, one wave per cell
+// (BUILD).  One XCD's workgroups take one contiguous range of cells in both, so the build finds the bins in its L2.
+template <int D, int W>
+__device__ __forceinline__ void list_phase(int mode, int gen, const DevBox &box, const ListParams &lp,
+                                           const Bins *bins, const ListGen *gens, const uint32_t *pos,
+                                           int32_t *flags, int *red, int *ncnt)
+{
+    if (mode == M_BIN) {
+        int wave = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+        int nwaves = (gridDim.x * kBlock) >> 6;
+        int *queue = ncnt + (threadIdx.x >> 6) * kMaxPerCellPad;
+        int occ = bin_gather<D>(pos, box, lp, bins[gen], bins[gen ^ 1], flags, wave, nwaves, queue);
+        occ = block_max(occ, red);
+        if (threadIdx.x == 0) raise_max(&flags[MD_FLAG_MAXCELL], occ);
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < lp.N; i += gridDim.x * kBlock) {
+            uint32_t ui[D];
+            load_pos<D>(pos, i, ui);
+            store_pos<D>(gens[gen ^ 1].pos_ref, i, ui);
+        }
+    } else if (mode == M_BUILD) {
+        const ListGen &g1 = gens[gen ^ 1];
+        if (lp.pk)
+            build_rows_cells<D, W, true, 4, false>(box, bins[gen ^ 1], lp, g1.idx, g1.count, flags, nullptr, ncnt, red);
+        else
+            build_rows_cells<D, W, false, 4, false>(box, bins[gen ^ 1], lp, g1.idx, g1.count, flags, nullptr, ncnt, red);
+    }
 }
 
 // First half kick and drift of a verlet_step call: v += dt/2 F; r(1) = r(0) + dt v; rebuild request for step 1.
@@ -1116,30 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_md_step(StepArgs a, DevPot p)
     int mode, gen;
     step_control(a.ctl, a.flags, a.step, mode, gen);
     const ListParams &lp = a.lp;
-    if (mode == M_BIN) {
-        // bins and reference positions of the other generation from r(s); one XCD's workgroups take one contiguous
-        // range of cells, as in the build that reads these bins next
-        int wave = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
-        int nwaves = (gridDim.x * kBlock) >> 6;
-        int *queue = ncnt + (threadIdx.x >> 6) * kMaxPerCellPad;
-        int occ = bin_gather<D>(a.pos_in, a.box, lp, a.bins[gen], a.bins[gen ^ 1], a.flags, wave, nwaves, queue);
-        occ = block_max(occ, red);
-        if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCELL], occ);
-        for (int i = blockIdx.x * kBlock + threadIdx.x; i < lp.N; i += gridDim.x * kBlock) {
-            uint32_t ui[D];
-            load_pos<D>(a.pos_in, i, ui);
-            store_pos<D>(a.gen[gen ^ 1].pos_ref, i, ui);
-        }
-    } else if (mode == M_BUILD) {
-        // rows of the other generation from those bins, one wave per cell
-        const ListGen &g1 = a.gen[gen ^ 1];
-        if (lp.pk)
-            build_rows_cells<D, W, true, 4, false>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
-                                            red);
-        else
-            build_rows_cells<D, W, false, 4, false>(a.box, a.bins[gen ^ 1], lp, g1.idx, g1.count, a.flags, nullptr, ncnt,
-                                             red);
-    }
+    list_phase<D, W>(mode, gen, a.box, lp, a.bins, a.gen, a.pos_in, a.flags, red, ncnt);
     const ListGen &g = a.gen[gen];
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int i = gt / W, l = gt % W;
@@ -1320,70 +1327,128 @@ __global__ __launch_bounds__(kBlock) void k_verlet_check(const uint32_t *__restr
 struct FireArgs {
     DevBox box;
     ListParams lp;
-    ListGen list;
+    ListGen list;    // the caller's list (the first force evaluation of fire_init)
+    ListGen gen[2];  // list generations of the step pipeline: the caller's and the context's
+    Bins bins[2];
     int32_t *flags;
     int32_t *ctl;
     uint32_t *pos;
     float *vel;
     float *force;
     const int32_t *species;
-    md_fire_state *st;
-    double *partials;  // [4 * blocks]
+    const md_fire_state *st_in;  // the state a launch starts from
+    md_fire_state *st_out;       // where the state after the rules goes (workgroup 0)
+    double *partials;            // [4 * nparts]: F.v, v.v, F.F and max |F_i|^2 of each force workgroup
+    int32_t nparts;
+    int32_t apply;  // mixing launch: 1 = apply the rules to the partials first; 0 = st_in is the state of the step
+    int32_t step;   // step of the call, >= 1
+    int32_t sync;   // 1: a full rebuild gated on ctl[kTrigWord] runs between the two launches of a step
+    float kappa;    // rebuild lookahead of the pipeline, in steps of the current displacement
     double f_tol;
     float dt_max, f_inc, f_dec, alpha_start, f_alpha;
     int32_t n_min;
 };
 
-// Velocity mixing decided by the previous step, then r += dt v + dt^2/2 F; requests a rebuild
-// (ctl[kTrigWord]) when a particle is now farther than skin/2 from its position at the last build.
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_fire_drift(FireArgs a)
+// Three sums and a maximum over the workgroup: lanes by an xor tree, then the four waves in order.  Every thread
+// gets the results, and every workgroup that reduces the same values gets them bit for bit.
+__device__ __forceinline__ void block_sum3_max(double &x, double &y, double &z, double &m, double (*red4)[kBlock / 64])
 {
-    if (frozen(a.flags) || a.st->converged) return;
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    bool far = false;
-    if (i < a.lp.N) {
-        double dt = a.st->dt, mv = a.st->mix_v, mf = a.st->mix_f;
-        uint32_t ui[D], un[D];
-        load_pos<D>(a.pos, i, ui);
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            float f = a.force[(size_t)i * D + q];
-            float v = (float)(mv * (double)a.vel[(size_t)i * D + q] + mf * (double)f);
-            a.vel[(size_t)i * D + q] = v;
-            float dx = (float)(dt * (double)v + 0.5 * dt * dt * (double)f);
-            un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
-        }
-        store_pos<D>(a.pos, i, un);
-        far = disp2<D>(un, a.list.pos_ref, i, a.box) > a.lp.half_skin * a.lp.half_skin;
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o);
+        y += __shfl_xor(y, o);
+        z += __shfl_xor(z, o);
+        m = fmax(m, __shfl_xor(m, o));
     }
-    wave_flag(far, &a.ctl[kTrigWord]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red4[0][w] = x;
+        red4[1][w] = y;
+        red4[2][w] = z;
+        red4[3][w] = m;
+    }
+    __syncthreads();
+    x = y = z = m = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+        x += red4[0][q];
+        y += red4[1][q];
+        z += red4[2][q];
+        m = fmax(m, red4[3][q]);
+    }
+    __syncthreads();
 }
 
-// F' = F(r) over the list by W lanes per particle; v += dt/2 (F + F'); workgroup partials of
-// F.v, v.v, F.F and max |F_i|^2 in double.
-template <int D, int KIND, bool MULTI, int W>
-__global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p, int init)
+// The global P = F.v, |v|^2, |F|^2 and max |F_i|^2 of a step from its force workgroups' partials, in a fixed order.
+__device__ __forceinline__ void fire_totals(const double *part, int n, double &P, double &vv, double &ff, double &fm,
+                                            double (*red4)[kBlock / 64])
 {
-    __shared__ double red[kBlock];
-    if (frozen(a.flags) || a.st->converged) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[kTrigWord] = 0;  // the gated rebuild of this step is done
+    P = vv = ff = fm = 0.0;
+    for (int b = threadIdx.x; b < n; b += kBlock) {
+        P += part[4 * b + 0];
+        vv += part[4 * b + 1];
+        ff += part[4 * b + 2];
+        fm = fmax(fm, part[4 * b + 3]);
+    }
+    block_sum3_max(P, vv, ff, fm, red4);
+}
+
+// The FIRE rules after the forces of a step (Sec. 3.3.1, after Bitzek et al. 2006): stop once max |F_i| < f_tol;
+// otherwise decide the velocity mixing of the next drift and that step's dt and alpha from the sign of P.
+__device__ __forceinline__ void fire_rules(md_fire_state &s, double P, double vv, double ff, double fm,
+                                           const FireArgs &a, int init)
+{
+    s.fmax = sqrt(fm);
+    s.power = P;
+    if (!init) s.steps += 1;
+    if (s.fmax < a.f_tol) {
+        s.converged = 1;
+        return;
+    }
+    if (init) {
+        s.mix_v = 1.0;
+        s.mix_f = 0.0;
+        return;
+    }
+    const double al = s.alpha, fn = sqrt(ff), vn = sqrt(vv);
+    if (P > 0.0) {
+        s.mix_v = 1.0 - al;
+        s.mix_f = fn > 0.0 ? al * vn / fn : 0.0;
+        s.n_pos += 1;
+        if (s.n_pos > a.n_min) {
+            s.dt = fmin(s.dt * (double)a.f_inc, (double)a.dt_max);
+            s.alpha = al * (double)a.f_alpha;
+        }
+    } else {
+        s.mix_v = 0.0;
+        s.mix_f = 0.0;
+        s.dt = s.dt * (double)a.f_dec;
+        s.alpha = (double)a.alpha_start;
+        s.n_pos = 0;
+    }
+}
+
+// F' = F(r) over the list by W lanes per particle; v += dt/2 (F + F') (v = 0 for the first evaluation); workgroup
+// partials of F.v, v.v, F.F and max |F_i|^2 in double.  The step's state is st_in.
+template <int D, int KIND, bool MULTI, int W>
+__device__ __forceinline__ void fire_force_pass(const FireArgs &a, const DevPot &p, const ListGen &g, int init,
+                                                double (*red4)[kBlock / 64])
+{
     const ListParams &lp = a.lp;
-    double dt = a.st->dt;
+    const double dt = a.st_in->dt;
     int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int i = gt / W, l = gt % W;
     bool live = i < lp.N;
     int ii = live ? i : lp.N - 1;
     uint32_t ui[D];
     load_pos<D>(a.pos, ii, ui);
-    bool stale = live && l == 0 && disp2<D>(ui, a.list.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
+    bool stale = live && l == 0 && disp2<D>(ui, g.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
     wave_flag(stale, &a.flags[MD_FLAG_STALE]);
     int si = MULTI ? a.species[ii] : 0;
     float F[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) F[q] = 0.0f;
-    int n = live ? min(a.list.count[(size_t)ii * W + l], lp.capW) : 0;
-    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, lp.capW, a.list.idx, n, ii, l, ui, si, F);
+    int n = live ? min(g.count[(size_t)ii * W + l], lp.capW) : 0;
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, lp.capW, g.idx, n, ii, l, ui, si, F);
     double P = 0.0, vv = 0.0, ff = 0.0;
     bool bad = false;
     if (live && l == 0) {
@@ -1402,10 +1467,7 @@ __global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p, int
     }
     wave_flag(bad, &a.flags[MD_FLAG_NONFINITE]);
     double fm = ff;
-    P = block_sum(P, red);
-    vv = block_sum(vv, red);
-    ff = block_sum(ff, red);
-    fm = block_max(fm, red);
+    block_sum3_max(P, vv, ff, fm, red4);
     if (threadIdx.x == 0) {
         a.partials[4 * blockIdx.x + 0] = P;
         a.partials[4 * blockIdx.x + 1] = vv;
@@ -1414,55 +1476,97 @@ __global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p, int
     }
 }
 
-// One workgroup: global sums in a fixed order, convergence test and the FIRE rules.
-__global__ __launch_bounds__(kBlock) void k_fire_reduce(FireArgs a, int nblocks, int init)
+// The first force evaluation of fire_init, over the caller's list.
+template <int D, int KIND, bool MULTI, int W>
+__global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p)
 {
-    __shared__ double red[kBlock];
+    __shared__ double red4[4][kBlock / 64];
     if (frozen(a.flags)) return;
-    md_fire_state *st = a.st;
-    if (st->converged) return;
-    double sP = 0.0, svv = 0.0, sff = 0.0, sfm = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
-        sP += a.partials[4 * b + 0];
-        svv += a.partials[4 * b + 1];
-        sff += a.partials[4 * b + 2];
-        sfm = fmax(sfm, a.partials[4 * b + 3]);
-    }
-    sP = block_sum(sP, red);
-    svv = block_sum(svv, red);
-    sff = block_sum(sff, red);
-    sfm = block_max(sfm, red);
-    if (threadIdx.x != 0) return;
-    st->fmax = sqrt(sfm);
-    st->power = sP;
-    if (!init) st->steps += 1;
-    a.flags[MD_FLAG_STEPS] = (int32_t)st->steps;
-    if (st->fmax < a.f_tol) {
-        st->converged = 1;
-        return;
-    }
-    if (init) {
-        st->mix_v = 1.0;
-        st->mix_f = 0.0;
-        return;
-    }
-    double al = st->alpha;
-    double fn = sqrt(sff), vn = sqrt(svv);
-    if (sP > 0.0) {
-        st->mix_v = 1.0 - al;
-        st->mix_f = fn > 0.0 ? al * vn / fn : 0.0;
-        st->n_pos += 1;
-        if (st->n_pos > a.n_min) {
-            st->dt = fmin(st->dt * (double)a.f_inc, (double)a.dt_max);
-            st->alpha = al * (double)a.f_alpha;
-        }
+    fire_force_pass<D, KIND, MULTI, W>(a, p, a.list, 1, red4);
+}
+
+// One FIRE step's force launch.  Pipelined: the list pipeline's rebuild work when a rebuild is under way (bins one
+// step, rows the next, as in the Verlet step kernel), then the forces over the list in use.  Synchronous: the
+// gated rebuild before this launch has brought the caller's list up to date; clear its trigger, then the forces.
+template <int D, int KIND, bool MULTI, int W>
+__global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
+{
+    __shared__ int red[kBlock];
+    __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
+    __shared__ double red4[4][kBlock / 64];
+    if (frozen(a.flags) || a.st_in->converged) return;
+    int gen = 0;
+    if (a.sync) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[kTrigWord] = 0;
     } else {
-        st->mix_v = 0.0;
-        st->mix_f = 0.0;
-        st->dt = st->dt * (double)a.f_dec;
-        st->alpha = (double)a.alpha_start;
-        st->n_pos = 0;
+        int mode;
+        step_control(a.ctl, a.flags, a.step, mode, gen, false);
+        list_phase<D, W>(mode, gen, a.box, a.lp, a.bins, a.gen, a.pos, a.flags, red, ncnt);
     }
+    fire_force_pass<D, KIND, MULTI, W>(a, p, a.gen[gen], 0, red4);
+}
+
+// One FIRE step's mixing launch.  Each workgroup sums the previous step's partials (the same values in every
+// workgroup) and applies the rules to st_in; workgroup 0 stores the resulting state in st_out, which the force
+// launch of this step reads.  Then v = mix_v v + mix_f F and r += dt v + dt^2/2 F.  Pipelined, a rebuild is
+// requested for this step when a particle is within kappa steps of the current displacement of skin/2 from the
+// reference positions of the list this step uses; synchronous, the gated rebuild is triggered when a particle is
+// farther than skin/2 from the caller's list's reference positions.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_fire_mix_drift(FireArgs a)
+{
+    __shared__ double red4[4][kBlock / 64];
+    if (frozen(a.flags)) return;
+    md_fire_state s = *a.st_in;
+    if (!s.converged && a.apply) {
+        double P, vv, ff, fm;
+        fire_totals(a.partials, a.nparts, P, vv, ff, fm, red4);
+        fire_rules(s, P, vv, ff, fm, a, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[MD_FLAG_STEPS] = (int32_t)s.steps;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.st_out != a.st_in) *a.st_out = s;
+    if (s.converged) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool req = false;
+    if (i < a.lp.N) {
+        const double dt = s.dt, mv = s.mix_v, mf = s.mix_f;
+        const int gen = a.ctl[2 * (a.step % 3) + 1];  // the list generation of this step, published by the last one
+        uint32_t ui[D], un[D];
+        load_pos<D>(a.pos, i, ui);
+        float step2 = 0.0f, f2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            float f = a.force[(size_t)i * D + q];
+            float v = (float)(mv * (double)a.vel[(size_t)i * D + q] + mf * (double)f);
+            a.vel[(size_t)i * D + q] = v;
+            float dx = (float)(dt * (double)v + 0.5 * dt * dt * (double)f);
+            un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
+            step2 = __builtin_fmaf(dx, dx, step2);
+            f2 = __builtin_fmaf(f, f, f2);
+        }
+        store_pos<D>(a.pos, i, un);
+        const float d = sqrtf(disp2<D>(un, a.gen[a.sync ? 0 : gen].pos_ref, i, a.box));
+        const float ahead = a.sync ? 0.0f : sqrtf(step2) + (float)(dt * dt) * sqrtf(f2);
+        req = !(d + a.kappa * ahead <= a.lp.half_skin);  // NaN requests a rebuild
+    }
+    wave_flag(req, a.sync ? &a.ctl[kTrigWord] : &a.ctl[6 + a.step % 3]);
+}
+
+// One workgroup: the rules after the forces of a step in a fixed order (the first evaluation of fire_init, or
+// the last step of a fire_step call), from st_in into st_out.
+__global__ __launch_bounds__(kBlock) void k_fire_reduce(FireArgs a, int init)
+{
+    __shared__ double red4[4][kBlock / 64];
+    if (frozen(a.flags)) return;
+    md_fire_state s = *a.st_in;
+    if (!s.converged) {
+        double P, vv, ff, fm;
+        fire_totals(a.partials, a.nparts, P, vv, ff, fm, red4);
+        fire_rules(s, P, vv, ff, fm, a, init);
+    }
+    if (threadIdx.x != 0) return;
+    *a.st_out = s;
+    a.flags[MD_FLAG_STEPS] = (int32_t)s.steps;
 }
 
 constexpr int kRedBlocks = 256;  // workgroups of the two-pass reductions
@@ -1823,6 +1927,7 @@ static constexpr int kMaxBlocks = 1 << 16;
 static constexpr int kMaxPerCell = 252;                 // bin occupancy fits the 8-bit field of a stencil entry
 static constexpr int64_t kMaxBytes = (int64_t)1 << 32;  // list and bin arrays stay below 4 GiB
 static constexpr float kKappa = 2.0f;
+static constexpr float kFireKappa = 3.0f;  // FIRE speeds up (dt grows, v mixes toward F): a wider margin
 
 static bool make_box(const md_box *box, float r_list, DevBox &b)
 {
@@ -2179,6 +2284,7 @@ md_status md_ctx_create(int device, md_ctx **out)
         hipMalloc(&c->ctl, sizeof(int32_t) * kCtlWords) != hipSuccess ||
         hipMalloc(&c->queue, sizeof(int32_t) * 4) != hipSuccess ||
         hipMalloc(&c->nn_partial, sizeof(float) * (size_t)kNNTrainWaves * kNNParams) != hipSuccess ||
+        hipMalloc(&c->fire_slots, sizeof(md_fire_state) * 2) != hipSuccess ||
         hipMemset(c->own_flags, 0, sizeof(int32_t) * MD_NFLAGS) != hipSuccess ||
         hipMemset(c->ctl, 0, sizeof(int32_t) * kCtlWords) != hipSuccess) {
         (void)hipFree(c->partials);
@@ -2186,6 +2292,7 @@ md_status md_ctx_create(int device, md_ctx **out)
         (void)hipFree(c->ctl);
         (void)hipFree(c->queue);
         (void)hipFree(c->nn_partial);
+        (void)hipFree(c->fire_slots);
         delete c;
         return MD_ERR_HIP;
     }
@@ -2220,6 +2327,7 @@ md_status md_ctx_destroy(md_ctx *ctx)
     (void)hipFree(ctx->ctl);
     (void)hipFree(ctx->queue);
     (void)hipFree(ctx->nn_partial);
+    (void)hipFree(ctx->fire_slots);
     delete ctx;
     return MD_OK;
 }
@@ -2490,6 +2598,12 @@ md_status langevin_run(md_ctx *ctx, const md_box *box, const md_potential *pot, 
     return md_run(ctx, box, pot, pos, vel, force, species, N, nl, dt, n_steps, stream, &lv);
 }
 
+// FIRE steps.  A call builds the list for pos, then runs each step as two launches: the mixing launch (the rules
+// of the previous step, the velocity mixing and the drift, and the rebuild request) and the force launch (the
+// rebuild work of the two-generation list pipeline when a rebuild is under way, then the forces); with
+// sync_rebuild, the device-gated full rebuild runs between the two instead of the pipeline.  The state of
+// step q lives in the caller's struct for q = 1 and in the context's two slots after that; a last one-workgroup
+// launch applies the rules of the last step into the caller's struct.  fire_init evaluates the first forces.
 static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *pot, uint32_t *pos, float *vel,
                           float *force, const int32_t *species, int32_t N, md_nlist *nl, const md_fire_params *fp,
                           md_fire_state *fst, int32_t n_steps, double f_tol, int init, hipStream_t s)
@@ -2504,6 +2618,7 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
         if (init) hipLaunchKernelGGL(k_fire_state_empty, dim3(1), dim3(1), 0, s, fst, f_tol);
         return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
     }
+    if (!init && n_steps == 0) return MD_OK;
     bool multi = pot->n_species > 1;
     st = launch_build(ctx, box->dim, b, pos, N, nl, s, nullptr);
     if (st != MD_OK) return st;
@@ -2512,14 +2627,23 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
     a.box = b;
     a.lp = make_lp(nl, ctx->M_cap, b, box->dim);
     a.list = caller_gen(nl);
+    a.gen[0] = a.list;
+    a.gen[1] = ListGen{ctx->g1_idx, ctx->g1_count, ctx->g1_pos_ref};
+    a.bins[0] = ctx_bins(ctx, 0);
+    a.bins[1] = ctx_bins(ctx, 1);
     a.flags = nl->flags;
     a.ctl = ctx->ctl;
     a.pos = pos;
     a.vel = vel;
     a.force = force;
     a.species = species;
-    a.st = fst;
+    a.st_in = fst;
+    a.st_out = fst;
     a.partials = ctx->partials;
+    a.apply = 0;
+    a.step = 0;
+    a.sync = fp->sync_rebuild != 0;
+    a.kappa = kFireKappa;
     a.f_tol = f_tol;
     a.dt_max = fp->dt_max;
     a.f_inc = fp->f_inc;
@@ -2527,23 +2651,43 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
     a.alpha_start = fp->alpha_start;
     a.f_alpha = fp->f_alpha;
     a.n_min = fp->n_min;
-    int grid = nblk((int64_t)N * a.lp.W);
-    const int32_t *gate = ctx->ctl + kTrigWord;
-    int n = init ? 1 : n_steps;
-    for (int q = 0; q < n; ++q) {
-        if (!init) {
-            if (box->dim == 3)
-                hipLaunchKernelGGL(k_fire_drift<3>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_fire_drift<2>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
-            st = launch_build(ctx, box->dim, b, pos, N, nl, s, gate);
+    const int grid = nblk((int64_t)N * a.lp.W);
+    a.nparts = grid;
+    if (init) {
+        MD_DISPATCH(box->dim, pot->kind, multi,
+                    MD_LANES(a.lp.W, hipLaunchKernelGGL((k_fire_force<D, KIND, MULTI, W>), dim3(grid), dim3(kBlock),
+                                                        0, s, a, p)));
+        hipLaunchKernelGGL(k_fire_reduce, dim3(1), dim3(kBlock), 0, s, a, 1);
+        return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+    }
+    md_fire_state *slot = ctx->fire_slots;
+    for (int32_t q = 1; q <= n_steps; ++q) {
+        a.step = q;
+        a.apply = q >= 2;
+        a.st_in = q <= 2 ? fst : slot + ((q - 1) & 1);
+        a.st_out = q == 1 ? fst : slot + (q & 1);
+        if (box->dim == 3)
+            hipLaunchKernelGGL(k_fire_mix_drift<3>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_fire_mix_drift<2>, dim3(nblk(N)), dim3(kBlock), 0, s, a);
+        a.st_in = a.st_out;
+        if (a.sync) {
+            st = launch_build(ctx, box->dim, b, pos, N, nl, s, ctx->ctl + kTrigWord);
             if (st != MD_OK) return st;
         }
         MD_DISPATCH(box->dim, pot->kind, multi,
-                    MD_LANES(a.lp.W, hipLaunchKernelGGL((k_fire_force<D, KIND, MULTI, W>), dim3(grid), dim3(kBlock),
-                                                        0, s, a, p, init)));
-        hipLaunchKernelGGL(k_fire_reduce, dim3(1), dim3(kBlock), 0, s, a, grid, init);
+                    MD_LANES(a.lp.W, hipLaunchKernelGGL((k_fire_step<D, KIND, MULTI, W>), dim3(grid), dim3(kBlock),
+                                                        0, s, a, p)));
     }
+    a.st_out = fst;
+    hipLaunchKernelGGL(k_fire_reduce, dim3(1), dim3(kBlock), 0, s, a, 0);
+    HIP_OK(hipGetLastError());
+    if (box->dim == 3)
+        hipLaunchKernelGGL(k_list_finalize<3>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
+    else
+        hipLaunchKernelGGL(k_list_finalize<2>, dim3(grid), dim3(kBlock), 0, s, ctx->ctl, a.gen[0], a.gen[1], a.lp);
+    hipLaunchKernelGGL(k_bins_finalize, dim3(nblk((int64_t)b.C * a.lp.M)), dim3(kBlock), 0, s, ctx->ctl, nl->flags,
+                       a.bins[0], a.bins[1], b.C, a.lp.M);
     return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 

@@ -49,6 +49,7 @@ struct md_ctx {
     uint32_t *g1_pos_ref = nullptr;
     int32_t *ctl = nullptr;        // kCtlWords
     double *partials = nullptr;    // 4 * kMaxBlocks doubles
+    md_fire_state *fire_slots = nullptr;  // two FIRE states a fire_step call alternates between
     int32_t *own_flags = nullptr;  // MD_NFLAGS words for calls made without a neighbor list
     int32_t *queue = nullptr;      // work counter of batched launches
     float *nn_partial = nullptr;   // partial weight gradients of the neural-potential training pass

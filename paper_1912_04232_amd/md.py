@@ -61,7 +61,7 @@ class c_nlist(ctypes.Structure):
 class c_fire_params(ctypes.Structure):
     _fields_ = [("dt_start", ctypes.c_float), ("dt_max", ctypes.c_float), ("f_inc", ctypes.c_float),
                 ("f_dec", ctypes.c_float), ("alpha_start", ctypes.c_float), ("f_alpha", ctypes.c_float),
-                ("n_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_min", ctypes.c_int32), ("sync_rebuild", ctypes.c_int32)]
 
 
 class c_fire_state(ctypes.Structure):
@@ -296,9 +296,9 @@ class FireParams:
     alpha_start: float = 0.1
     f_alpha: float = 0.99
 
-    def c(self) -> c_fire_params:
+    def c(self, sync_rebuild: bool = False) -> c_fire_params:
         return c_fire_params(self.dt_start, self.dt_max, self.f_inc, self.f_dec, self.alpha_start, self.f_alpha,
-                             self.n_min, 0)
+                             self.n_min, int(sync_rebuild))
 
 
 class Context:
@@ -586,10 +586,12 @@ def fire_init(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, 
 
 
 def fire_step(ctx: Context, box: Box, pot: Potential, pos, vel, force, species, nl: NeighborList,
-              fp: FireParams, state: torch.Tensor, n_steps: int, f_tol: float):
+              fp: FireParams, state: torch.Tensor, n_steps: int, f_tol: float, sync_rebuild: bool = False):
+    """n_steps FIRE steps; sync_rebuild selects the list upkeep (pipelined, or a full rebuild before each force
+    evaluation that needs one)."""
     N = pos.shape[0]
     _reserve_for(ctx, box, N, nl)
-    b, p, n, f = box.c(), pot.c(), nl.c(), fp.c()
+    b, p, n, f = box.c(), pot.c(), nl.c(), fp.c(sync_rebuild)
     _check("fire_step", load().fire_step(ctx.h, ctypes.byref(b), ctypes.byref(p), _ptr(pos), _ptr(vel),
                                          _ptr(force), _ptr(species), N, ctypes.byref(n), ctypes.byref(f),
                                          _ptr(state), int(n_steps), ctypes.c_double(f_tol), _stream()))
@@ -969,10 +971,11 @@ class System:
         return float(out.item())
 
 
-def _run_checked(system: System, saved, call, n_steps: int):
+def _run_checked(system: System, saved, call, n_steps: int, on_stale=None):
     """Run call(n) and re-run from `saved` when the device reported a list that did not fit (grow it) or went
-    stale (run again in shorter pieces, each starting from a fresh list; a piece of one step cannot go stale
-    unless a single step moves a particle more than skin/2)."""
+    stale: with `on_stale`, run the same steps through it (a call whose list cannot go stale); otherwise in
+    shorter pieces, each starting from a fresh list (a piece of one step cannot go stale unless a single step
+    moves a particle more than skin/2)."""
     for _ in range(6):
         system.nl.clear_flags()
         call(n_steps)
@@ -983,6 +986,9 @@ def _run_checked(system: System, saved, call, n_steps: int):
             return f
         for t, v in zip(saved[0], saved[1]):
             t.copy_(v)
+        if f[FLAG_STALE] and on_stale is not None:
+            call, on_stale = on_stale, None
+            continue
         if f[FLAG_STALE]:
             if n_steps == 1:
                 raise RuntimeError(f"a single step left the list stale: flags {f.tolist()}")
@@ -1195,57 +1201,66 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
                   system.nl, fp, state, f_tol)
         return state
 
-    def step_fn(n_steps: int = 1):
+    def call(n: int, sync: bool):
+        fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
+                  system.nl, fp, state, n, f_tol, sync)
+
+    def step_fn(n_steps: int = 1, sync: bool = False):
+        """n_steps FIRE steps in one call: the list pipeline (sync=False) or a full rebuild before each force
+        evaluation that needs one (sync=True).  A pipelined run whose list went stale (a step too long for the
+        pipeline's lookahead, as in the first steps from an overlapping start) is run again synchronously."""
         tensors = (system.pos, system.vel, system.force, state)
         saved = (tensors, tuple(t.clone() for t in tensors))
-
-        def call(n):
-            fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force, system.species,
-                      system.nl, fp, state, n, f_tol)
-
-        _run_checked(system, saved, call, n_steps)
+        _run_checked(system, saved, lambda n: call(n, sync), n_steps, on_stale=lambda n: call(n, True))
         return fire_state_read(state)
 
     graphs = {}
 
     def minimize(max_steps: int = 100000, chunk: int = 200, graph: bool = False):
-        """Run FIRE until converged or max_steps.  With graph=True the launches of `chunk` steps are captured
-        once in a HIP graph and replayed (a step's launches are all device-gated, so replays need no host
-        decisions); the flags are read after every chunk and a chunk that reports a problem is re-run eagerly
-        from its saved state.  The returned state also holds "rebuilds": list builds run over the call (one at
-        the start of every chunk, plus the device-gated ones)."""
+        """Run FIRE until converged or max_steps, in fire_step calls of `chunk` steps.  With graph=True the
+        launches of a chunk are captured once in a HIP graph and replayed (a step's launches are all device-gated,
+        so replays need no host decisions).  The flags are read after every chunk; a chunk that reports a problem
+        is re-run eagerly from its saved state.  Chunks use the list pipeline; one whose list went stale is re-run
+        with a full rebuild before each force evaluation that needs one, and so are the chunks after it until a
+        chunk needs no more than one rebuild per 8 steps.  The returned state also holds "rebuilds" (list builds
+        over the call: one at the start of every chunk, plus the device's) and "chunks" (how many ran each way)."""
         st = fire_state_read(state)
         rebuilds = 0
+        chunks = {"pipelined": 0, "synchronous": 0, "stale_reruns": 0}
+        sync = False
         while not st["converged"] and st["steps"] < max_steps:
             k = min(chunk, max_steps - st["steps"])
-            if not graph or k != chunk:
-                system.nl.clear_flags()
-                st = step_fn(k)
-                rebuilds += int(system.nl.read_flags()[FLAG_REBUILDS])
-                continue
             tensors = (system.pos, system.vel, system.force, state)
             saved = tuple(t.clone() for t in tensors)
-            g = graphs.get(chunk)
-            if g is None:
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
-                    fire_step(system.ctx, system.box, system.pot, system.pos, system.vel, system.force,
-                              system.species, system.nl, fp, state, chunk, f_tol)
-                graphs[chunk] = g
             system.nl.clear_flags()
-            g.replay()
+            if graph and k == chunk:
+                g = graphs.get((chunk, sync))
+                if g is None:
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
+                        call(chunk, sync)
+                    graphs[(chunk, sync)] = g
+                g.replay()
+            else:
+                call(k, sync)
             f = system.nl.read_flags()
             if f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW] or f[FLAG_STALE] or f[FLAG_NONFINITE]:
                 for t, v in zip(tensors, saved):
                     t.copy_(v)
-                graphs.clear()  # the list may be regrown (new buffers): capture again afterwards
-                system.nl.clear_flags()
-                st = step_fn(chunk)
-                rebuilds += int(system.nl.read_flags()[FLAG_REBUILDS])
-                continue
+                if f[FLAG_OVERFLOW] or f[FLAG_CELL_OVERFLOW]:
+                    graphs.clear()  # the list will be regrown (new buffers): capture again afterwards
+                if f[FLAG_STALE]:
+                    chunks["stale_reruns"] += 1
+                    sync = True
+                step_fn(k, sync)
+                f = system.nl.read_flags()
             rebuilds += int(f[FLAG_REBUILDS])
+            chunks["synchronous" if sync else "pipelined"] += 1
+            if sync and 8 * int(f[FLAG_REBUILDS]) <= k:
+                sync = False
             st = fire_state_read(state)
         st["rebuilds"] = rebuilds
+        st["chunks"] = chunks
         return st
 
     return init_fn, step_fn, minimize

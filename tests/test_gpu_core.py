@@ -518,16 +518,20 @@ def test_fire_one_step_vs_oracle(md, orc):
     assert st["dt"] == pytest.approx(res["dt"]) and st["n_pos"] == res["n_pos"] and st["steps"] == 1
 
 
-@pytest.mark.parametrize("K", [10, 30])
-def test_fire_steps_vs_oracle(md, orc, K):
-    """K FIRE steps from the same start (each step the drift launch, the device-gated rebuild, the force launch and
-    the one-workgroup reduction that applies the FIRE rules): positions, mixed velocities and the FIRE scalars follow
-    the FP64 oracle's."""
-    cfg = ss_cfg(1000, 0.9, 81)
+@pytest.mark.parametrize("K,skin", [(10, 0.3), (30, 0.3), (30, 0.05)])
+def test_fire_steps_vs_oracle(md, orc, K, skin):
+    """K FIRE steps from the same start in one fire_step call (each step the mixing launch, which applies the FIRE
+    rules of the previous step, and the force launch): positions, mixed velocities and the FIRE scalars follow the
+    FP64 oracle's.  With skin 0.05 the list is rebuilt inside the call several times."""
+    cfg = ss_cfg(1000, 0.9, 81, skin=skin)
     s = make_system(md, cfg)
     init, step, _ = md.fire_descent(s, f_tol=1e-30)
     init()
     st = step(K)
+    builds = int(s.nl.read_flags()[md.FLAG_REBUILDS])
+    say("K", K, "skin", skin, "list builds", builds)
+    if skin < 0.1:
+        assert builds >= 3
     p = orc_pot(orc, cfg)
     L = np.asarray(cfg["L"][:2], dtype=np.float64)
     res = orc.fire(orc.decode(cfg["u"], L), L, p, cfg["species"], max_steps=K, f_tol=0.0)

@@ -226,3 +226,58 @@ def test_verlet_step_keeps_a_valid_list_and_rebuilds_a_moved_or_overflowed_one(m
         md.verlet_step(s.ctx, s.box, s.pot, s.pos, s.vel, s.force, s.species, small, 0.005, 1)
         f = small.read_flags()
         assert f[md.FLAG_OVERFLOW] == 1 and f[md.FLAG_REBUILDS] >= 1, f
+
+
+def disks(md, N, phi, seed, skin, lanes=None):
+    L = inputs.box_for_packing([1.0, 1.4], [N // 2, N - N // 2], phi, 2)
+    d = np.array([1.0, 1.4])
+    sig = 0.5 * (d[:, None] + d[None, :])
+    box = md.Box((L, L), 2)
+    pot = md.Potential("soft_sphere", sig, np.ones((2, 2)), alpha=2.0)
+    sp = inputs.bidisperse_species(N)
+    return md.System(box, pot, inputs.uniform_torus(N, 2, seed), None, sp, skin=skin, lanes=lanes), L, sig, sp
+
+
+@pytest.mark.parametrize("case", ["disks2000", "disks3001_ragged"])
+def test_fire_inrun_rebuilt_rows_and_forces_match_oracle(md, orc, case):
+    """FIRE's step pipeline rebuilds the list inside a fire_step call (bins in one force launch, rows in the next).
+    Bidisperse harmonic disks at phi = 0.9 from uniform random positions, skin 0.3 as in the 65536-disk workload:
+    300 synchronous steps take the packing past its first, long steps (the pipeline needs about three steps from a
+    request to the new list, so it cannot follow steps that need a list every two or three); then four pipelined
+    calls of 40 steps run with no list going stale, and
+    after each the rows of the list in use are the brute-force r_list sets at its reference positions bit for bit
+    and the forces at the final positions are the oracle's (rel-L2 <= 1e-5).  The ragged case (uneven cells) runs
+    4 lanes per disk."""
+    N, seed, lanes = (2000, 4401, None) if case == "disks2000" else (3001, 4402, 4)
+    s, L, sig, sp = disks(md, N, 0.9, seed, 0.3, lanes)
+    op = orc.Potential("soft_sphere", sig, np.ones((2, 2)), alpha=2.0)
+    fp = md.FireParams()
+    init, step, _ = md.fire_descent(s, fp, f_tol=1e-30)
+    state = init()
+    step(300, sync=True)
+    inrun = rebuilds = 0
+    seen = {md.from_device_u32(s.nl.pos_ref).tobytes()}
+    for c in range(4):
+        start = md.from_device_u32(s.pos).tobytes()
+        s.nl.clear_flags()
+        md.fire_step(s.ctx, s.box, s.pot, s.pos, s.vel, s.force, s.species, s.nl, fp, state, 40, 1e-30,
+                     sync_rebuild=False)
+        f = s.nl.read_flags()
+        assert not (f[md.FLAG_STALE] or f[md.FLAG_OVERFLOW] or f[md.FLAG_CELL_OVERFLOW]), f.tolist()
+        rebuilds += int(f[md.FLAG_REBUILDS]) - 1  # less the build at the start of the call
+        ref = md.from_device_u32(s.nl.pos_ref)
+        got = s.nl.rows()
+        want = orc.neighbors(ref, [L, L], s.nl.r_list)
+        for i in range(N):
+            assert np.array_equal(np.sort(got[i]), want[i]), (c, i)
+        key = ref.tobytes()
+        if key != start and key not in seen:
+            inrun += 1
+        seen.add(key)
+        u = md.from_device_u32(s.pos)
+        Fo, _, _ = orc.pair_rows(orc.decode(u, [L, L]), [L, L], op, sp)
+        err = rel_l2(s.force.cpu().numpy(), Fo)
+        say(f"FIRE call {c}: in-run builds {int(f[md.FLAG_REBUILDS]) - 1}, in-run lists checked {inrun}, "
+            f"force rel-L2 {err:.2e}")
+        assert err <= F_TOL, err
+    assert inrun >= 2 and rebuilds >= 4, (inrun, rebuilds)
