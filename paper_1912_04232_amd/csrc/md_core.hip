@@ -707,15 +707,13 @@ __device__ __forceinline__ int ld_species(const __amdgpu_buffer_rsrc_t &rs, int 
 // ISO (LJ in a box with one scale s along every axis) the displacement stays in integer units: r^2 is their
 // squared sum times s^2, and the caller multiplies the summed force by s once.
 template <int D, int KIND, bool MULTI, bool MASK, bool ISO>
-__device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, const __amdgpu_buffer_rsrc_t &rs,
-                                           int si, const uint32_t *ui, const int *jc, const uint32_t (*pc)[D],
-                                           int t0, int n, float s2, float *F)
+__device__ __forceinline__ void quad_force(const DevBox &b, const DevPot &p, int si, const uint32_t *ui,
+                                           const int *sc, const uint32_t (*pc)[D], int t0, int n, float s2, float *F)
 {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         float d[D], r2, u, fs;
-        // species of a slot past the row's end come through the range-checked load like its position
-        int pt = MULTI ? si * p.S + ld_species(rs, jc[a]) : 0;
+        int pt = MULTI ? si * p.S + sc[a] : 0;
         if constexpr (ISO) {
             float r2u = 0.0f;
 #pragma unroll
@@ -756,29 +754,35 @@ __device__ __forceinline__ void lane_force_rows(const DevBox &b, const DevPot &p
     };
     int jA[4], jB[4];
     uint32_t pA[4][D], pB[4][D];
+    int sA[4] = {0, 0, 0, 0}, sB[4] = {0, 0, 0, 0};  // species, loaded with the positions (two or more species)
+    // a neighbor's position and species; a slot past the row's end comes through the range-checked loads
+    auto ld_nb = [&](int j, uint32_t *pj, int &sj) {
+        ld_pos<D>(rp, j, pj);
+        if constexpr (MULTI) sj = ld_species(rs, j);
+    };
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         jA[a] = ldj(a);
         jB[a] = ldj(4 + a);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jA[a], pA[a]);
+    for (int a = 0; a < 4; ++a) ld_nb(jA[a], pA[a], sA[a]);
     int t = 0;
     // full pairs of groups: A holds group t/4 (positions loaded), B the next group's indices
     for (; t + 8 <= n; t += 8) {
         int jC[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jB[a], pB[a]);
+        for (int a = 0; a < 4; ++a) ld_nb(jB[a], pB[a], sB[a]);
 #pragma unroll
         for (int a = 0; a < 4; ++a) jC[a] = ldj(t + 8 + a);
         asm volatile("" ::: "memory");  // keep the loads above ahead of the arithmetic below
-        quad_force<D, KIND, MULTI, false, ISO>(b, p, rs, si, ui, jA, pA, t, n, s2, F);
+        quad_force<D, KIND, MULTI, false, ISO>(b, p, si, ui, sA, pA, t, n, s2, F);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jC[a], pA[a]);
+        for (int a = 0; a < 4; ++a) ld_nb(jC[a], pA[a], sA[a]);
 #pragma unroll
         for (int a = 0; a < 4; ++a) jA[a] = ldj(t + 12 + a);
         asm volatile("" ::: "memory");
-        quad_force<D, KIND, MULTI, false, ISO>(b, p, rs, si, ui, jB, pB, t + 4, n, s2, F);
+        quad_force<D, KIND, MULTI, false, ISO>(b, p, si, ui, sB, pB, t + 4, n, s2, F);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             int x = jA[a];
@@ -789,9 +793,9 @@ __device__ __forceinline__ void lane_force_rows(const DevBox &b, const DevPot &p
     // at most two groups remain: A (positions loaded) and B (indices loaded)
     if (t < n) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ld_pos<D>(rp, jB[a], pB[a]);
-        quad_force<D, KIND, MULTI, true, ISO>(b, p, rs, si, ui, jA, pA, t, n, s2, F);
-        if (t + 4 < n) quad_force<D, KIND, MULTI, true, ISO>(b, p, rs, si, ui, jB, pB, t + 4, n, s2, F);
+        for (int a = 0; a < 4; ++a) ld_nb(jB[a], pB[a], sB[a]);
+        quad_force<D, KIND, MULTI, true, ISO>(b, p, si, ui, sA, pA, t, n, s2, F);
+        if (t + 4 < n) quad_force<D, KIND, MULTI, true, ISO>(b, p, si, ui, sB, pB, t + 4, n, s2, F);
     }
     if constexpr (ISO) {
 #pragma unroll
@@ -1046,8 +1050,7 @@ __device__ __forceinline__ float baoab_coord(float v, float F, float dt, float c
 
 // Control state of step s: {mode, gen} from the previous step's workgroup 0, upgraded to BIN when a
 // rebuild was requested.  Workgroup 0 publishes step s+1's words and clears the request slot of s+2.
-__device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s, int &mode, int &gen,
-                                             bool count_steps = true)
+__device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s, int &mode, int &gen)
 {
     int r = s % 3;
     mode = ctl[2 * r];
@@ -1060,7 +1063,7 @@ __device__ __forceinline__ void step_control(int32_t *ctl, int32_t *flags, int s
         ctl[2 * ((s + 1) % 3) + 1] = ng;
         ctl[6 + (s + 2) % 3] = 0;
         ctl[kGenWord] = ng;
-        if (count_steps) flags[MD_FLAG_STEPS] = s;
+        flags[MD_FLAG_STEPS] = s;
         if (mode == M_BUILD) flags[MD_FLAG_REBUILDS] += 1;
     }
 }
@@ -1378,16 +1381,32 @@ __device__ __forceinline__ void block_sum3_max(double &x, double &y, double &z, 
     __syncthreads();
 }
 
-// The global P = F.v, |v|^2, |F|^2 and max |F_i|^2 of a step from its force workgroups' partials, in a fixed order.
+// The global P = F.v, |v|^2, |F|^2 and max |F_i|^2 of a step from its force workgroups' partials, in a fixed order:
+// thread t adds partials t, t + kBlock, ... from zero, then the workgroup's threads are combined.  fire_part_first
+// loads the first of them (issued early by the mixing launch), fire_totals the rest and the combination.
+__device__ __forceinline__ void fire_part_first(const double *part, int n, double &P, double &vv, double &ff,
+                                                double &fm)
+{
+    P = vv = ff = fm = 0.0;
+    const int b = threadIdx.x;
+    if (b < n) {
+        const double4 q = *(const double4 *)(part + 4 * b);
+        P += q.x;
+        vv += q.y;
+        ff += q.z;
+        fm = fmax(fm, q.w);
+    }
+}
+
 __device__ __forceinline__ void fire_totals(const double *part, int n, double &P, double &vv, double &ff, double &fm,
                                             double (*red4)[kBlock / 64])
 {
-    P = vv = ff = fm = 0.0;
-    for (int b = threadIdx.x; b < n; b += kBlock) {
-        P += part[4 * b + 0];
-        vv += part[4 * b + 1];
-        ff += part[4 * b + 2];
-        fm = fmax(fm, part[4 * b + 3]);
+    for (int b = threadIdx.x + kBlock; b < n; b += kBlock) {
+        const double4 q = *(const double4 *)(part + 4 * b);
+        P += q.x;
+        vv += q.y;
+        ff += q.z;
+        fm = fmax(fm, q.w);
     }
     block_sum3_max(P, vv, ff, fm, red4);
 }
@@ -1427,37 +1446,55 @@ __device__ __forceinline__ void fire_rules(md_fire_state &s, double P, double vv
     }
 }
 
+// The particle a FIRE force-launch thread works on (W lanes per particle) and that particle's own state, loaded
+// before the launch's first decision so that these loads and the control words' are waited on together.
+template <int D, int W>
+struct FireOwn {
+    int i, l, ii;
+    bool live;
+    uint32_t u[D];
+    float v[D], f[D];
+    __device__ __forceinline__ void load(const FireArgs &a)
+    {
+        const int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+        i = gt / W;
+        l = gt % W;
+        live = i < a.lp.N;
+        ii = live ? i : a.lp.N - 1;  // dead lanes shadow the last particle so the lane reduction stays uniform
+        load_pos<D>(a.pos, ii, u);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            v[q] = a.vel[(size_t)ii * D + q];
+            f[q] = a.force[(size_t)ii * D + q];
+        }
+    }
+};
+
 // F' = F(r) over the list by W lanes per particle; v += dt/2 (F + F') (v = 0 for the first evaluation); workgroup
-// partials of F.v, v.v, F.F and max |F_i|^2 in double.  The step's state is st_in.
+// partials of F.v, v.v, F.F and max |F_i|^2 in double.
 template <int D, int KIND, bool MULTI, int W>
-__device__ __forceinline__ void fire_force_pass(const FireArgs &a, const DevPot &p, const ListGen &g, int init,
+__device__ __forceinline__ void fire_force_pass(const FireArgs &a, const DevPot &p, const ListGen &g,
+                                                const FireOwn<D, W> &o, double dt, int init,
                                                 double (*red4)[kBlock / 64])
 {
     const ListParams &lp = a.lp;
-    const double dt = a.st_in->dt;
-    int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    int i = gt / W, l = gt % W;
-    bool live = i < lp.N;
-    int ii = live ? i : lp.N - 1;
-    uint32_t ui[D];
-    load_pos<D>(a.pos, ii, ui);
-    bool stale = live && l == 0 && disp2<D>(ui, g.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
+    const int i = o.i, l = o.l, ii = o.ii;
+    const bool live = o.live;
+    bool stale = live && l == 0 && disp2<D>(o.u, g.pos_ref, ii, a.box) > lp.half_skin * lp.half_skin;
     wave_flag(stale, &a.flags[MD_FLAG_STALE]);
     int si = MULTI ? a.species[ii] : 0;
     float F[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) F[q] = 0.0f;
     int n = live ? min(g.count[(size_t)ii * W + l], lp.capW) : 0;
-    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, lp.capW, g.idx, n, ii, l, ui, si, F);
+    lane_force<D, KIND, MULTI, W>(a.box, p, a.pos, a.species, lp.N, lp.capW, g.idx, n, ii, l, o.u, si, F);
     double P = 0.0, vv = 0.0, ff = 0.0;
     bool bad = false;
     if (live && l == 0) {
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             bad = bad || !isfinite(F[q]);
-            float v = init ? 0.0f
-                           : (float)((double)a.vel[(size_t)i * D + q] +
-                                     0.5 * dt * ((double)a.force[(size_t)i * D + q] + (double)F[q]));
+            float v = init ? 0.0f : (float)((double)o.v[q] + 0.5 * dt * ((double)o.f[q] + (double)F[q]));
             a.vel[(size_t)i * D + q] = v;
             a.force[(size_t)i * D + q] = F[q];
             P += (double)F[q] * (double)v;
@@ -1482,28 +1519,51 @@ __global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p)
 {
     __shared__ double red4[4][kBlock / 64];
     if (frozen(a.flags)) return;
-    fire_force_pass<D, KIND, MULTI, W>(a, p, a.list, 1, red4);
+    FireOwn<D, W> o;
+    o.load(a);
+    fire_force_pass<D, KIND, MULTI, W>(a, p, a.list, o, a.st_in->dt, 1, red4);
 }
 
 // One FIRE step's force launch.  Pipelined: the list pipeline's rebuild work when a rebuild is under way (bins one
 // step, rows the next, as in the Verlet step kernel), then the forces over the list in use.  Synchronous: the
 // gated rebuild before this launch has brought the caller's list up to date; clear its trigger, then the forces.
+// The flags, the state, the step's control words and the particle's own state are loaded first and waited on
+// together (a chain of dependent loads is what a launch of a small system spends its time on).
 template <int D, int KIND, bool MULTI, int W>
 __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
 {
     __shared__ int red[kBlock];
     __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     __shared__ double red4[4][kBlock / 64];
-    if (frozen(a.flags) || a.st_in->converged) return;
+    const int r = a.step % 3;
+    const int32_t halt = a.flags[MD_FLAG_OVERFLOW] | a.flags[MD_FLAG_CELL_OVERFLOW] | a.flags[MD_FLAG_STALE] |
+                         a.st_in->converged;
+    const double dt = a.st_in->dt;
+    const int32_t c_mode = a.ctl[2 * r], c_gen = a.ctl[2 * r + 1], c_req = a.ctl[6 + r];
+    FireOwn<D, W> o;
+    o.load(a);
+    asm volatile("" ::"v"(c_mode), "v"(c_gen), "v"(c_req), "v"(dt), "v"(o.u[0]), "v"(o.v[0]), "v"(o.f[0]));
+    if (halt) return;
     int gen = 0;
     if (a.sync) {
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[kTrigWord] = 0;
     } else {
-        int mode;
-        step_control(a.ctl, a.flags, a.step, mode, gen, false);
+        // the step's mode and list generation; workgroup 0 publishes the next step's and clears the request slot
+        // of the step after it
+        int mode = c_mode;
+        gen = c_gen;
+        if (mode == M_IDLE && c_req) mode = M_BIN;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int ng = mode == M_BUILD ? gen ^ 1 : gen;
+            a.ctl[2 * ((a.step + 1) % 3)] = mode == M_BIN ? M_BUILD : M_IDLE;
+            a.ctl[2 * ((a.step + 1) % 3) + 1] = ng;
+            a.ctl[6 + (a.step + 2) % 3] = 0;
+            a.ctl[kGenWord] = ng;
+            if (mode == M_BUILD) a.flags[MD_FLAG_REBUILDS] += 1;
+        }
         list_phase<D, W>(mode, gen, a.box, a.lp, a.bins, a.gen, a.pos, a.flags, red, ncnt);
     }
-    fire_force_pass<D, KIND, MULTI, W>(a, p, a.gen[gen], 0, red4);
+    fire_force_pass<D, KIND, MULTI, W>(a, p, a.gen[gen], o, dt, 0, red4);
 }
 
 // One FIRE step's mixing launch.  Each workgroup sums the previous step's partials (the same values in every
@@ -1511,43 +1571,61 @@ __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
 // launch of this step reads.  Then v = mix_v v + mix_f F and r += dt v + dt^2/2 F.  Pipelined, a rebuild is
 // requested for this step when a particle is within kappa steps of the current displacement of skin/2 from the
 // reference positions of the list this step uses; synchronous, the gated rebuild is triggered when a particle is
-// farther than skin/2 from the caller's list's reference positions.
+// farther than skin/2 from the caller's list's reference positions.  The particle's state, the first partial of
+// each thread and the list generation are loaded before the first decision, as in the force launch.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_fire_mix_drift(FireArgs a)
 {
     __shared__ double red4[4][kBlock / 64];
-    if (frozen(a.flags)) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < a.lp.N;
+    const int ii = live ? i : a.lp.N - 1;
+    const int32_t halt = a.flags[MD_FLAG_OVERFLOW] | a.flags[MD_FLAG_CELL_OVERFLOW] | a.flags[MD_FLAG_STALE];
     md_fire_state s = *a.st_in;
+    const int gen = a.sync ? 0 : a.ctl[2 * (a.step % 3) + 1];  // the list generation of this step
+    uint32_t ui[D];
+    float f[D], v[D];
+    load_pos<D>(a.pos, ii, ui);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        f[q] = a.force[(size_t)ii * D + q];
+        v[q] = a.vel[(size_t)ii * D + q];
+    }
+    double P, vv, ff, fm;
+    fire_part_first(a.partials, a.apply ? a.nparts : 0, P, vv, ff, fm);
+    uint32_t ref[D];
+    load_pos<D>(a.gen[gen].pos_ref, ii, ref);
+    if (halt) return;
     if (!s.converged && a.apply) {
-        double P, vv, ff, fm;
         fire_totals(a.partials, a.nparts, P, vv, ff, fm, red4);
         fire_rules(s, P, vv, ff, fm, a, 0);
         if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[MD_FLAG_STEPS] = (int32_t)s.steps;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.st_out != a.st_in) *a.st_out = s;
     if (s.converged) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     bool req = false;
-    if (i < a.lp.N) {
+    if (live) {
         const double dt = s.dt, mv = s.mix_v, mf = s.mix_f;
-        const int gen = a.ctl[2 * (a.step % 3) + 1];  // the list generation of this step, published by the last one
-        uint32_t ui[D], un[D];
-        load_pos<D>(a.pos, i, ui);
+        uint32_t un[D];
         float step2 = 0.0f, f2 = 0.0f;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-            float f = a.force[(size_t)i * D + q];
-            float v = (float)(mv * (double)a.vel[(size_t)i * D + q] + mf * (double)f);
-            a.vel[(size_t)i * D + q] = v;
-            float dx = (float)(dt * (double)v + 0.5 * dt * dt * (double)f);
+            const float vq = (float)(mv * (double)v[q] + mf * (double)f[q]);
+            a.vel[(size_t)i * D + q] = vq;
+            const float dx = (float)(dt * (double)vq + 0.5 * dt * dt * (double)f[q]);
             un[q] = shift_coord(ui[q], dx, a.box.inv_s[q]);
             step2 = __builtin_fmaf(dx, dx, step2);
-            f2 = __builtin_fmaf(f, f, f2);
+            f2 = __builtin_fmaf(f[q], f[q], f2);
         }
         store_pos<D>(a.pos, i, un);
-        const float d = sqrtf(disp2<D>(un, a.gen[a.sync ? 0 : gen].pos_ref, i, a.box));
+        float d2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const float dq = tdisp(un[q], ref[q], a.box.s[q]);
+            d2 = __builtin_fmaf(dq, dq, d2);
+        }
         const float ahead = a.sync ? 0.0f : sqrtf(step2) + (float)(dt * dt) * sqrtf(f2);
-        req = !(d + a.kappa * ahead <= a.lp.half_skin);  // NaN requests a rebuild
+        req = !(sqrtf(d2) + a.kappa * ahead <= a.lp.half_skin);  // NaN requests a rebuild
     }
     wave_flag(req, a.sync ? &a.ctl[kTrigWord] : &a.ctl[6 + a.step % 3]);
 }
@@ -1561,6 +1639,7 @@ __global__ __launch_bounds__(kBlock) void k_fire_reduce(FireArgs a, int init)
     md_fire_state s = *a.st_in;
     if (!s.converged) {
         double P, vv, ff, fm;
+        fire_part_first(a.partials, a.nparts, P, vv, ff, fm);
         fire_totals(a.partials, a.nparts, P, vv, ff, fm, red4);
         fire_rules(s, P, vv, ff, fm, a, init);
     }

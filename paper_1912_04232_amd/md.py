@@ -1220,14 +1220,15 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         """Run FIRE until converged or max_steps, in fire_step calls of `chunk` steps.  With graph=True the
         launches of a chunk are captured once in a HIP graph and replayed (a step's launches are all device-gated,
         so replays need no host decisions).  The flags are read after every chunk; a chunk that reports a problem
-        is re-run eagerly from its saved state.  Chunks use the list pipeline; one whose list went stale is re-run
-        with a full rebuild before each force evaluation that needs one, and so are the chunks after it until a
-        chunk needs no more than one rebuild per 8 steps.  The returned state also holds "rebuilds" (list builds
+        is re-run eagerly from its saved state.  The first chunk runs with a full rebuild before each force
+        evaluation that needs one (the first steps from an overlapping start are too long for the list pipeline),
+        and so do the chunks after it until a chunk needs no more than one rebuild per 8 steps; then chunks use the
+        pipeline, and one whose list went stale is re-run synchronously and the rule starts over.  The returned state also holds "rebuilds" (list builds
         over the call: one at the start of every chunk, plus the device's) and "chunks" (how many ran each way)."""
         st = fire_state_read(state)
         rebuilds = 0
         chunks = {"pipelined": 0, "synchronous": 0, "stale_reruns": 0}
-        sync = False
+        sync = True
         while not st["converged"] and st["steps"] < max_steps:
             k = min(chunk, max_steps - st["steps"])
             tensors = (system.pos, system.vel, system.force, state)
