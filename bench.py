@@ -236,7 +236,7 @@ def fire_ss(ctx, progress):
     progress("FIRE done")
     return {"converged": bool(st["converged"]), "steps": int(st["steps"]), "fmax": st["fmax"],
             "seconds": t_fire, "steps_per_s": st["steps"] / t_fire, "rebuilds": int(st["rebuilds"]),
-            "chunks_of_500": st["chunks"],
+            "chunks": st["chunks"], "chunk_steps": {"pipelined": 500, "synchronous": 100},
             "launches_per_step": "2: FIRE rules, mixing and drift; forces (with the list pipeline's bin or "
                                  "row work when a rebuild is under way)"}
 

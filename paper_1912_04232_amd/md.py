@@ -1223,24 +1223,27 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         is re-run eagerly from its saved state.  The first chunk runs with a full rebuild before each force
         evaluation that needs one (the first steps from an overlapping start are too long for the list pipeline),
         and so do the chunks after it until a chunk needs no more than one rebuild per 8 steps; then chunks use the
-        pipeline, and one whose list went stale is re-run synchronously and the rule starts over.  The returned state also holds "rebuilds" (list builds
+        pipeline, and one whose list went stale is re-run synchronously and the rule starts over.  Synchronous
+        chunks are a fifth as long (at least 20 steps), so that the switch comes soon after the steps have
+        shortened.  The returned state also holds "rebuilds" (list builds
         over the call: one at the start of every chunk, plus the device's) and "chunks" (how many ran each way)."""
         st = fire_state_read(state)
         rebuilds = 0
         chunks = {"pipelined": 0, "synchronous": 0, "stale_reruns": 0}
         sync = True
         while not st["converged"] and st["steps"] < max_steps:
-            k = min(chunk, max_steps - st["steps"])
+            size = max(20, chunk // 5) if sync else chunk
+            k = min(size, max_steps - st["steps"])
             tensors = (system.pos, system.vel, system.force, state)
             saved = tuple(t.clone() for t in tensors)
             system.nl.clear_flags()
-            if graph and k == chunk:
-                g = graphs.get((chunk, sync))
+            if graph and k == size:
+                g = graphs.get((size, sync))
                 if g is None:
                     g = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(g):  # records the launches; nothing runs until a replay
-                        call(chunk, sync)
-                    graphs[(chunk, sync)] = g
+                        call(size, sync)
+                    graphs[(size, sync)] = g
                 g.replay()
             else:
                 call(k, sync)
