@@ -567,6 +567,287 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(const uint32_t *__restric
 }
 
 // ------------------------------------------------------------------------------------------------
+// standalone build for sparsely filled cells: one particle per W lanes
+//
+// With a few particles per cell (a 2D packing or a flock, two to three per cell), a wave per cell holds one slot of
+// candidates and walks two or three particles, so the cell's set-up and its chain of loads are the whole cost.
+// Giving every particle its own W lanes keeps the machine full instead.
+
+// Stencil table of particle i at reference position ui: the stencil cells that can hold a neighbor, in stencil
+// order, packed as (cell << 8) | count at tab[e * ts].  A cell is left out when its slab distance from the particle
+// (the distance to the faces it lies beyond) already exceeds r_list, or when it is empty.  Every lane of the
+// particle computes the table; only lanes with `write` store it.  Returns the number of entries; `chunks` receives
+// the number of 4-record chunks they hold.
+template <int D>
+__device__ __forceinline__ int stencil_table(int i, const uint32_t *ui, const DevBox &b, const Bins &bins,
+                                             const ListParams &lp, uint32_t *tab, int ts, bool write, int &chunks)
+{
+    constexpr int NST = D == 3 ? 27 : 9;
+    int cc[3][3];
+    float lo2[3], hi2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        cc[q][0] = cc[q][1] = cc[q][2] = 0;
+        lo2[q] = hi2[q] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const uint64_t pr = (uint64_t)ui[q] * (uint64_t)b.nc[q];
+        const int c = (int)(pr >> 32);
+        const float f = (float)(uint32_t)pr * 2.3283064365386963e-10f;  // position within the cell, [0, 1)
+        const float dl = f * b.cw[q], dh = (1.0f - f) * b.cw[q];
+        lo2[q] = dl * dl;
+        hi2[q] = dh * dh;
+        cc[q][0] = wrapc(c - 1, b.nc[q]);
+        cc[q][1] = c;
+        cc[q][2] = wrapc(c + 1, b.nc[q]);
+    }
+    const int cbase = lp.seg > 0 ? (i / lp.seg) * b.C : 0;  // first cell of the particle's system
+    // a cell whose slab distance exceeds r_list (with the float guard band above it) holds no neighbor
+    const float cull2 = lp.rl2f_hi;
+    int cell[NST], m[NST];
+#pragma unroll
+    for (int t = 0; t < NST; ++t) {
+        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = D == 3 ? t / 9 - 1 : 0;
+        bool use = ox >= b.lo[0] && ox <= b.hi[0] && oy >= b.lo[1] && oy <= b.hi[1];
+        if (D == 3) use = use && oz >= b.lo[2] && oz <= b.hi[2];
+        const float g = (ox < 0 ? lo2[0] : ox > 0 ? hi2[0] : 0.0f) + (oy < 0 ? lo2[1] : oy > 0 ? hi2[1] : 0.0f) +
+                        (oz < 0 ? lo2[2] : oz > 0 ? hi2[2] : 0.0f);
+        use = use && g <= cull2;
+        cell[t] = cbase + cc[0][ox + 1] + b.nc[0] * (cc[1][oy + 1] + b.nc[1] * cc[2][oz + 1]);
+        m[t] = use ? bins.cnt[cell[t]] : 0;
+    }
+    int ne = 0;
+    chunks = 0;
+#pragma unroll
+    for (int t = 0; t < NST; ++t) {
+        if (m[t] > 0) {
+            if (write) tab[ne * ts] = ((uint32_t)cell[t] << 8) | (uint32_t)m[t];
+            ++ne;
+            chunks += (m[t] + 3) >> 2;
+        }
+    }
+    return ne;
+}
+
+// Inclusive prefix sum of x over the W lanes of a particle (W <= 8: the groups lie within DPP rows of 16 lanes),
+// by DPP row shifts; tot = the group's sum.  Every lane of a group is active together.
+template <int W>
+__device__ __forceinline__ int group_scan(int x, int l, int &tot)
+{
+    int incl = x;
+    if constexpr (W >= 2) {
+        const int v = __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);  // row_shr:1
+        incl += l >= 1 ? v : 0;
+    }
+    if constexpr (W >= 4) {
+        const int v = __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);  // row_shr:2
+        incl += l >= 2 ? v : 0;
+    }
+    if constexpr (W >= 8) {
+        const int v = __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);  // row_shr:4
+        incl += l >= 4 ? v : 0;
+    }
+    if constexpr (W == 1) tot = incl;
+    else if constexpr (W == 2) tot = __builtin_amdgcn_update_dpp(0, incl, 0xF5, 0xf, 0xf, false);  // quad_perm 1,1,3,3
+    else if constexpr (W == 4) tot = __builtin_amdgcn_update_dpp(0, incl, 0xFF, 0xf, 0xf, false);  // quad_perm 3,3,3,3
+    else tot = __shfl(incl, W - 1, W);
+    return incl;
+}
+
+// A lane's place in the stencil table's chunk sequence: entry e, chunk c within it, the entry's first slot cb and
+// member count mc; `have` is false past the last chunk.
+struct ChunkCursor {
+    int e, c, mc;
+    uint32_t cb;
+    bool have;
+};
+
+// The four records of a chunk as separate registers.
+struct Chunk4 {
+    uint32_t x[4], y[4], z[4], j[4];
+};
+
+// The cursor's chunk, W chunks on (entries of the table are ts words apart).
+template <int W>
+__device__ __forceinline__ ChunkCursor chunk_next(ChunkCursor k, const uint32_t *tab, int ts, int ne, uint32_t M)
+{
+    k.c += W;
+    if (k.have) {
+        while (true) {
+            const int nch = (k.mc + 3) >> 2;
+            if (k.c < nch) break;
+            k.c -= nch;
+            ++k.e;
+            if (k.e >= ne) {
+                k.have = false;
+                break;
+            }
+            const uint32_t en = tab[k.e * ts];
+            k.mc = (int)(en & 255u);
+            k.cb = (en >> 8) * M;
+        }
+    }
+    return k;
+}
+
+// Loads the cursor's chunk (a cursor past the end reads slot 0, always mapped).
+__device__ __forceinline__ void chunk_load(const ChunkCursor &k, const uint32_t *mem, Chunk4 &r)
+{
+    const uint4 *p = (const uint4 *)mem + (k.have ? k.cb + 4u * (uint32_t)k.c : 0u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 v = p[q];
+        r.x[q] = v.x;
+        r.y[q] = v.y;
+        r.z[q] = v.z;
+        r.j[q] = v.w;
+    }
+}
+
+// Row of particle i (Sec. 3.2.3) built by its W lanes from its stencil table.  The listed cells' records form one
+// sequence of 4-record chunks; lane l tests chunks l, l + W, ..., loading its next chunk while it tests the current
+// one.  Candidates are tested in float against a guard band around r_list^2; those inside the band take the double
+// expression that defines the list.  Accepted neighbors are numbered in sequence order (a prefix sum over the W
+// lanes after each round) and dealt round-robin to the interleaved sub-rows.  Returns the row length (the same in
+// every lane of the particle; it may exceed the capacity, and only the first `cap` entries are stored).
+template <int D, int W>
+__device__ __forceinline__ int build_row(int i, int l, const uint32_t *ui, const DevBox &b, const Bins &bins,
+                                         const ListParams &lp, int32_t *__restrict__ idx, const uint32_t *tab, int ts,
+                                         int ne, int chunks)
+{
+    const uint32_t M = (uint32_t)lp.M;
+    const uint32_t row_bytes = (uint32_t)lp.N * W * 4u;  // bytes between positions t and t+1 of a sub-row
+    const bool iso = b.iso != 0;
+    const float s2 = b.s[0] * b.s[0];
+    const float lo = iso ? lp.rl2f_lo / s2 : lp.rl2f_lo, hi = iso ? lp.rl2f_hi / s2 : lp.rl2f_hi;
+    ChunkCursor ka{0, l, 0, 0u, false};
+    while (ka.e < ne) {
+        const uint32_t en = tab[ka.e * ts];
+        ka.mc = (int)(en & 255u);
+        const int nch = (ka.mc + 3) >> 2;
+        if (ka.c < nch) {
+            ka.cb = (en >> 8) * M;
+            ka.have = true;
+            break;
+        }
+        ka.c -= nch;
+        ++ka.e;
+    }
+    int n = 0;
+    auto test = [&](const Chunk4 &r, const ChunkCursor &k) {
+        int bits = 0, band = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
+            float r2 = 0.0f;
+            if (iso) {
+#pragma unroll
+                for (int z = 0; z < D; ++z) {
+                    const float d = (float)(int32_t)(ui[z] - uj[z]);
+                    r2 = __builtin_fmaf(d, d, r2);
+                }
+            } else {
+#pragma unroll
+                for (int z = 0; z < D; ++z) {
+                    const float d = tdisp(ui[z], uj[z], b.s[z]);
+                    r2 = __builtin_fmaf(d, d, r2);
+                }
+            }
+            bits |= r2 < lo ? 1 << q : 0;
+            band |= r2 >= lo && r2 <= hi ? 1 << q : 0;
+        }
+        // candidates within the guard band (rare) take the defining double expression; the branch is taken by the
+        // whole wave or not at all
+        if (__ballot(band != 0) != 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (band & (1 << q)) {
+                    const uint32_t uj[3] = {r.x[q], r.y[q], r.z[q]};
+                    double r2d = 0.0;
+#pragma unroll
+                    for (int z = 0; z < D; ++z) {
+                        const double d = tdisp_d(ui[z], uj[z], b.sd[z]);
+                        r2d = __dadd_rn(r2d, __dmul_rn(d, d));
+                    }
+                    bits |= r2d < lp.rl2 ? 1 << q : 0;
+                }
+            }
+        }
+        // records of the chunk that are members (a cell's last chunk may be partial), other than i itself
+        const int left = k.have ? k.mc - 4 * k.c : 0;
+        bits &= left >= 4 ? 15 : (1 << max(left, 0)) - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bits &= (int)r.j[q] != i ? 15 : ~(1 << q);
+        const int a = __popc(bits);
+        int tot;
+        const int incl = group_scan<W>(a, l, tot);
+        uint32_t slot = (uint32_t)(n + incl - a);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (bits & (1 << q)) {
+                if (slot < (uint32_t)lp.cap) {
+                    // byte offset of entry slot (below 4 GiB, checked on the host)
+                    const uint32_t off = slot / W * row_bytes + ((uint32_t)i * W + slot % W) * 4u;
+                    *(int32_t *)((char *)idx + off) = (int)r.j[q];
+                }
+                ++slot;
+            }
+        }
+        n += tot;
+    };
+    const int iters = (chunks + W - 1) / W;  // the same in every lane of the particle
+    Chunk4 A, B;
+    chunk_load(ka, bins.mem, A);
+    int it = 0;
+    for (; it + 2 <= iters; it += 2) {
+        const ChunkCursor kb = chunk_next<W>(ka, tab, ts, ne, M);
+        chunk_load(kb, bins.mem, B);
+        test(A, ka);
+        ka = chunk_next<W>(kb, tab, ts, ne, M);
+        chunk_load(ka, bins.mem, A);
+        test(B, kb);
+    }
+    if (it < iters) test(A, ka);
+    return n;
+}
+
+// Standalone build for sparse cells: rows of every particle from the bins, W lanes per particle, and pos_ref = the
+// positions the rows were built from.
+template <int D, int W>
+__global__ __launch_bounds__(kBlock) void k_build_rows_pp(const uint32_t *__restrict__ pos, DevBox b, Bins bins,
+                                                          ListParams lp, ListGen g, int32_t *flags, int32_t *ok,
+                                                          const int32_t *gate)
+{
+    constexpr int TS = kBlock / W;
+    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * TS];
+    __shared__ int red[kBlock];
+    if (gate_closed(gate)) return;
+    const int gt = blockIdx.x * kBlock + threadIdx.x;
+    const int i = gt / W, l = gt % W;
+    const bool live = i < lp.N;
+    uint32_t ui[D];
+    int ne = 0, chunks = 0, n = 0;
+    if (live) {
+        load_pos<D>(pos, i, ui);
+        ne = stencil_table<D>(i, ui, b, bins, lp, tab + threadIdx.x / W, TS, l == 0, chunks);
+    }
+    __syncthreads();
+    if (live) {
+        n = build_row<D, W>(i, l, ui, b, bins, lp, g.idx, tab + threadIdx.x / W, TS, ne, chunks);
+        g.count[(size_t)i * W + l] = sub_count<W>(n, l);
+        if (l == 0) store_pos<D>(g.pos_ref, i, ui);
+    }
+    wave_flag(n > lp.cap, &flags[MD_FLAG_OVERFLOW]);
+    if (ok != nullptr && n > lp.cap) *ok = 0;  // rare: only a particle whose row did not fit stores
+    n = block_max(n, red);
+    if (threadIdx.x == 0) {
+        raise_max(&flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
+        if (blockIdx.x == 0) flags[MD_FLAG_REBUILDS] += 1;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // in-run bin refresh (no atomics): one wave per cell
 
 // Gather, from the previous bins of cell c's stencil, the members whose cell at the current positions `pos` is c.
@@ -2006,6 +2287,7 @@ static constexpr int kMaxBlocks = 1 << 16;
 static constexpr int kMaxPerCell = 252;                 // bin occupancy fits the 8-bit field of a stencil entry
 static constexpr int64_t kMaxBytes = (int64_t)1 << 32;  // list and bin arrays stay below 4 GiB
 static constexpr float kKappa = 2.0f;
+static constexpr int kSparseCell = 8;  // below this mean cell occupancy the standalone build goes per particle
 static constexpr float kFireKappa = 3.0f;  // FIRE speeds up (dt grows, v mixes toward F): a wider margin
 
 static bool make_box(const md_box *box, float r_list, DevBox &b)
@@ -2313,7 +2595,29 @@ static md_status launch_build(md_ctx *ctx, int dim, const DevBox &b, const uint3
     int64_t want = ((int64_t)C + 3) / 4, copy = (int64_t)N * dim / (4 * kBlock);
     if (copy > want) want = copy;
     int rows_grid = (int)(want < 1 ? 1 : (want > kMaxBlocks ? kMaxBlocks : want));
-    if (dim == 3) {
+    // sparsely filled cells (fewer than kSparseCell particles per cell on average) are built one particle per W
+    // lanes; denser ones one wave per cell
+    const bool sparse = (int64_t)N < (int64_t)kSparseCell * C;
+    const int pp_grid = nblk((int64_t)N * lp.W);
+    if (sparse) {
+        if (dim == 3) {
+            hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
+            hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, ok, gate);
+            hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
+            hipLaunchKernelGGL(k_cs_rank_fill<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
+                               lp.W, gate);
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows_pp<3, W>), dim3(pp_grid), dim3(kBlock), 0, s, pos, b, bins,
+                                              lp, g, nl->flags, ok, gate));
+        } else {
+            hipLaunchKernelGGL(k_cs_count<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
+            hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, ok, gate);
+            hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);
+            hipLaunchKernelGGL(k_cs_rank_fill<2>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, cs, bins, lp.M, g.count,
+                               lp.W, gate);
+            MD_LANES(lp.W, hipLaunchKernelGGL((k_build_rows_pp<2, W>), dim3(pp_grid), dim3(kBlock), 0, s, pos, b, bins,
+                                              lp, g, nl->flags, ok, gate));
+        }
+    } else if (dim == 3) {
         hipLaunchKernelGGL(k_cs_count<3>, dim3(nblk(N)), dim3(kBlock), 0, s, pos, N, lp.seg, b, cs, gate);
         hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kScan), 0, s, cs, C, bins, lp.M, nl->flags, ok, gate);
         hipLaunchKernelGGL(k_cs_place, dim3(nblk(N)), dim3(kBlock), 0, s, cs, N, gate);

@@ -103,9 +103,12 @@ def check_rows(orc, sysm, cfg, rows=None):
 
 # ------------------------------------------------------------------ neighbor list
 
-@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "lj_blocks6", "lj_blocks7", "ss2d", "tiny_box", "two",
-                                  "one"])
+@pytest.mark.parametrize("case", ["lj1000", "lj_ragged", "lj_blocks6", "lj_blocks7", "ss2d", "lj_dilute", "tiny_box",
+                                  "two", "one"])
 def test_nl_build_bitexact(md, orc, case):
+    """Rows against the brute-force sets.  Dense cells (LJ at density 0.84, about 18 per cell) are built one wave per
+    cell; sparse ones (the 2D packing and the dilute gas, about 2 per cell, and the few-particle boxes) one particle
+    per W lanes."""
     say("nl_build", case)
     if case == "lj1000":
         cfg = inputs.lj_small()
@@ -117,6 +120,8 @@ def test_nl_build_bitexact(md, orc, case):
         cfg = lj_cfg(8000, 0.84, 79)                 # 7 cells a side: a ragged last cell block
     elif case == "ss2d":
         cfg = ss_cfg(5000, 0.9, 21)
+    elif case == "lj_dilute":
+        cfg = lj_cfg(3000, 0.1, 80)                  # about 2.2 particles per cell
     elif case == "tiny_box":
         cfg = lj_cfg(40, 0.12, 5, rmin=0.9)         # L = 6.93 < 3 r_list: whole-box scan
     elif case == "two":
