@@ -177,70 +177,110 @@ __global__ void k_cs_count(const uint32_t *__restrict__ pos, int N, int seg, Dev
     cs.slot[i] = atomicAdd(&cs.cell_count[c], 1);  // integer counts: the totals do not depend on order
 }
 
-constexpr int kScan = 1024;      // threads of the one-workgroup scan
-constexpr int kScanTile = 4096;  // cells per LDS tile (4 per thread)
+constexpr int kScan = 1024;                 // threads of the one-workgroup scan
+constexpr int kScanPer = 16;                // consecutive cells per thread and tile, held in registers
+constexpr int kScanTile = kScan * kScanPer;  // cells per tile
 
-// Exclusive scan of cell_count into cell_start[0..C] by one workgroup (wave shuffles and LDS, no atomics);
-// also the bin counts min(count, M), the cell-overflow flag and the largest occupancy.  It leaves the counts at
-// zero for the next build.  The cells go through LDS in tiles of kScanTile: coalesced loads, each thread scans
-// 4 adjacent cells from LDS, the workgroup scans the thread sums, coalesced stores, and a carry between tiles.
+// Counts of the kScanPer cells of thread t in the tile at base (zero past C): four 16-byte loads when the thread's
+// cells are all below C.
+__device__ __forceinline__ void scan_load(const int32_t *cnt, int base, int C, int t, int *v)
+{
+    const int c0 = base + t * kScanPer;
+    if (c0 + kScanPer <= C) {
+        const int4 *p = (const int4 *)(cnt + c0);
+#pragma unroll
+        for (int q = 0; q < kScanPer / 4; ++q) {
+            const int4 x = p[q];
+            v[4 * q] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) v[k] = c0 + k < C ? cnt[c0 + k] : 0;
+    }
+}
+
+// Exclusive scan of cell_count into cell_start[0..C] by one workgroup (wave shuffles and LDS, no atomics); also the
+// bin counts min(count, M), the cell-overflow flag and the largest occupancy.  It leaves the counts at zero for the
+// next build.  Each thread holds kScanPer adjacent cells of a tile in registers and scans them, the workgroup scans
+// the thread sums, and a carry joins the tiles; the next tile's counts are loaded while a tile is scanned.
 __global__ __launch_bounds__(kScan) void k_cs_scan(CountSort cs, int C, Bins bins, int M, int32_t *flags,
                                                    int32_t *ok, const int32_t *gate)
 {
-    constexpr int kPer = kScanTile / kScan;
-    __shared__ int cnt[kScanTile];
-    __shared__ int start[kScanTile];
     __shared__ int wsum[kScan / 64];
     __shared__ int wmax[kScan / 64];
-    __shared__ int tile_end;
+    __shared__ int tile_total;
     if (gate_closed(gate)) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int carry = 0, mx = 0;
+    int cur[kScanPer];
+    scan_load(cs.cell_count, 0, C, t, cur);
     for (int base = 0; base < C; base += kScanTile) {
-        const int n = min(kScanTile, C - base);
-        for (int k = t; k < kScanTile; k += kScan) cnt[k] = k < n ? cs.cell_count[base + k] : 0;
-        __syncthreads();
+        int nxt[kScanPer];
+        if (base + kScanTile < C) {
+            scan_load(cs.cell_count, base + kScanTile, C, t, nxt);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) nxt[k] = 0;
+        }
         int local = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            int v = cnt[t * kPer + k];
-            local += v;
-            mx = max(mx, v);
+        for (int k = 0; k < kScanPer; ++k) {
+            local += cur[k];
+            mx = max(mx, cur[k]);
         }
         int incl = local;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            int v = __shfl_up(incl, o);
+            const int v = __shfl_up(incl, o);
             if (lane >= o) incl += v;
         }
         if (lane == 63) wsum[w] = incl;
         __syncthreads();
         if (w == 0) {
-            int x = lane < kScan / 64 ? wsum[lane] : 0;
+            const int x = lane < kScan / 64 ? wsum[lane] : 0;
             int xi = x;
 #pragma unroll
             for (int o = 1; o < kScan / 64; o <<= 1) {
-                int v = __shfl_up(xi, o);
+                const int v = __shfl_up(xi, o);
                 if (lane >= o) xi += v;
             }
             if (lane < kScan / 64) wsum[lane] = xi - x;
+            if (lane == kScan / 64 - 1) tile_total = xi;
         }
         __syncthreads();
         int run = carry + incl - local + wsum[w];
+        const int c0 = base + t * kScanPer;
+        int st[kScanPer], bc[kScanPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            start[t * kPer + k] = run;
-            run += cnt[t * kPer + k];
+        for (int k = 0; k < kScanPer; ++k) {
+            st[k] = run;
+            bc[k] = min(cur[k], M);
+            run += cur[k];
         }
-        if (t == kScan - 1) tile_end = run;
-        __syncthreads();
-        for (int k = t; k < n; k += kScan) {
-            cs.cell_start[base + k] = start[k];
-            cs.cell_count[base + k] = 0;  // ready for the next build (the counts start zeroed at allocation)
-            bins.cnt[base + k] = min(cnt[k], M);
+        if (c0 + kScanPer <= C) {
+#pragma unroll
+            for (int q = 0; q < kScanPer / 4; ++q) {
+                ((int4 *)(cs.cell_start + c0))[q] = make_int4(st[4 * q], st[4 * q + 1], st[4 * q + 2], st[4 * q + 3]);
+                ((int4 *)(cs.cell_count + c0))[q] = make_int4(0, 0, 0, 0);  // ready for the next build
+                ((int4 *)(bins.cnt + c0))[q] = make_int4(bc[4 * q], bc[4 * q + 1], bc[4 * q + 2], bc[4 * q + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) {
+                if (c0 + k < C) {
+                    cs.cell_start[c0 + k] = st[k];
+                    cs.cell_count[c0 + k] = 0;
+                    bins.cnt[c0 + k] = bc[k];
+                }
+            }
         }
-        carry = tile_end;
-        __syncthreads();  // the next tile overwrites cnt, start and tile_end
+        carry += tile_total;
+        __syncthreads();  // the next tile overwrites wsum and tile_total
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) cur[k] = nxt[k];
     }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o));
