@@ -1667,6 +1667,7 @@ struct FireArgs {
     int32_t apply;  // mixing launch: 1 = apply the rules to the partials first; 0 = st_in is the state of the step
     int32_t step;   // step of the call, >= 1
     int32_t sync;   // 1: a full rebuild gated on ctl[kTrigWord] runs between the two launches of a step
+    int32_t pp;     // 1: sparse cells; the pipeline's rows are built one particle per W lanes
     float kappa;    // rebuild lookahead of the pipeline, in steps of the current displacement
     double f_tol;
     float dt_max, f_inc, f_dec, alpha_start, f_alpha;
@@ -1850,12 +1851,41 @@ __global__ __launch_bounds__(kBlock) void k_fire_force(FireArgs a, DevPot p)
 // gated rebuild before this launch has brought the caller's list up to date; clear its trigger, then the forces.
 // The flags, the state, the step's control words and the particle's own state are loaded first and waited on
 // together (a chain of dependent loads is what a launch of a small system spends its time on).
+// The pipeline's rows for sparse cells: the rows of generation gen1 from its bins, one particle per W lanes (the
+// particles' reference positions are those the bins were gathered at).
+template <int D, int W>
+__device__ __forceinline__ void fire_build_pp(const FireArgs &a, int gen1, int *red, uint32_t *tab)
+{
+    constexpr int TS = kBlock / W;
+    const ListParams &lp = a.lp;
+    const ListGen &g1 = a.gen[gen1];
+    const Bins &bn = a.bins[gen1];
+    const int gt = blockIdx.x * kBlock + threadIdx.x;
+    const int i = gt / W, l = gt % W;
+    const bool live = i < lp.N;
+    uint32_t ur[D];
+    int ne = 0, chunks = 0, n = 0;
+    if (live) {
+        load_pos<D>(g1.pos_ref, i, ur);
+        ne = stencil_table<D>(i, ur, a.box, bn, lp, tab + threadIdx.x / W, TS, l == 0, chunks);
+    }
+    __syncthreads();
+    if (live) {
+        n = build_row<D, W>(i, l, ur, a.box, bn, lp, g1.idx, tab + threadIdx.x / W, TS, ne, chunks);
+        g1.count[(size_t)i * W + l] = sub_count<W>(n, l);
+    }
+    wave_flag(n > lp.cap, &a.flags[MD_FLAG_OVERFLOW]);
+    n = block_max(n, red);
+    if (threadIdx.x == 0) raise_max(&a.flags[MD_FLAG_MAXCOUNT], (n + W - 1) / W * W);
+}
+
 template <int D, int KIND, bool MULTI, int W>
 __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
 {
     __shared__ int red[kBlock];
     __shared__ int ncnt[(kBlock / 64) * kMaxPerCellPad];
     __shared__ double red4[4][kBlock / 64];
+    __shared__ uint32_t tab[(D == 3 ? 27 : 9) * (kBlock / W)];
     const int r = a.step % 3;
     const int32_t halt = a.flags[MD_FLAG_OVERFLOW] | a.flags[MD_FLAG_CELL_OVERFLOW] | a.flags[MD_FLAG_STALE] |
                          a.st_in->converged;
@@ -1882,7 +1912,10 @@ __global__ __launch_bounds__(kBlock) void k_fire_step(FireArgs a, DevPot p)
             a.ctl[kGenWord] = ng;
             if (mode == M_BUILD) a.flags[MD_FLAG_REBUILDS] += 1;
         }
-        list_phase<D, W>(mode, gen, a.box, a.lp, a.bins, a.gen, a.pos, a.flags, red, ncnt);
+        if (mode == M_BUILD && a.pp)
+            fire_build_pp<D, W>(a, gen ^ 1, red, tab);
+        else
+            list_phase<D, W>(mode, gen, a.box, a.lp, a.bins, a.gen, a.pos, a.flags, red, ncnt);
     }
     fire_force_pass<D, KIND, MULTI, W>(a, p, a.gen[gen], o, dt, 0, red4);
 }
@@ -3066,6 +3099,7 @@ static md_status fire_run(md_ctx *ctx, const md_box *box, const md_potential *po
     a.apply = 0;
     a.step = 0;
     a.sync = fp->sync_rebuild != 0;
+    a.pp = (int64_t)N < (int64_t)kSparseCell * a.lp.cells;  // the standalone build's choice
     a.kappa = kFireKappa;
     a.f_tol = f_tol;
     a.dt_max = fp->dt_max;
