@@ -281,3 +281,31 @@ def test_fire_inrun_rebuilt_rows_and_forces_match_oracle(md, orc, case):
             f"force rel-L2 {err:.2e}")
         assert err <= F_TOL, err
     assert inrun >= 2 and rebuilds >= 4, (inrun, rebuilds)
+
+
+def test_fire_pipelined_and_synchronous_agree_while_no_rebuild_runs(md):
+    """The two ways fire_step keeps the list share their arithmetic: the mixing launch (rules, mixing, drift) and the
+    force pass.  From a packing relaxed far enough that 40 steps move no disk near skin/2, neither rebuilds inside
+    the call, and the positions, velocities, forces and FIRE state after 40 steps agree bit for bit."""
+    import torch
+    s0, L, sig, sp = disks(md, 3000, 0.9, 4501, 0.3)
+    fp = md.FireParams()
+    init, step, minimize = md.fire_descent(s0, fp, f_tol=1e-30)
+    state = init()
+    minimize(3000, chunk=500)
+    saved = (s0.pos.clone(), s0.vel.clone(), s0.force.clone(), state.clone())
+    out = {}
+    for sync in (False, True):
+        for t, v in zip((s0.pos, s0.vel, s0.force, state), saved):
+            t.copy_(v)
+        s0.build()
+        s0.nl.clear_flags()
+        md.fire_step(s0.ctx, s0.box, s0.pot, s0.pos, s0.vel, s0.force, s0.species, s0.nl, fp, state, 40, 1e-30,
+                     sync_rebuild=sync)
+        f = s0.nl.read_flags()
+        say(f"sync {sync}: list builds {int(f[md.FLAG_REBUILDS])}, flags {f.tolist()}")
+        assert int(f[md.FLAG_REBUILDS]) == 1  # the build at the start of the call only
+        assert not (f[md.FLAG_STALE] or f[md.FLAG_OVERFLOW] or f[md.FLAG_NONFINITE])
+        out[sync] = (s0.pos.clone(), s0.vel.clone(), s0.force.clone(), state.clone())
+    for a, b in zip(out[False], out[True]):
+        assert torch.equal(a, b)
