@@ -173,7 +173,11 @@ md_status md_positions_to_float(const md_box *box, const uint32_t *pos, float *x
  * Build the neighbor list of `pos` (Sec. 3.2.3): counting-sort cell binning
  * with cells of edge >= r_list (27 or 9 stencil cells; a dimension with fewer
  * than 3 cells is scanned whole) into bins of max_per_cell members (more
- * raises MD_FLAG_CELL_OVERFLOW), then one candidate scan per particle.  The
+ * raises MD_FLAG_CELL_OVERFLOW), then one candidate scan per particle: by
+ * one wave per cell (the cell's stencil candidates in its lanes) when cells
+ * hold 8 or more particles on average, else by the W lanes of each particle
+ * over the stencil cells its slab distances allow.  Either way the set of
+ * each row is the same.  The
  * predicate is r2 < r_list^2 with r2 evaluated in IEEE double as
  * d_0*d_0 + d_1*d_1 (+ d_2*d_2), d_k = (double)wrap32(pos_ik - pos_jk) *
  * (L_k / 2^32): a single-precision filter decides pairs far from the
@@ -270,7 +274,8 @@ md_status fire_init(md_ctx *ctx, const md_box *box, const md_potential *pot, con
  *      comes within 3 steps of its current displacement of skin/2 from the
  *      list's reference positions starts a rebuild whose bins and rows are
  *      made inside the next two force launches, into the context's second
- *      list.  A step that moves a particle farther than that margin allows
+ *      list (rows one particle per W lanes when cells are sparse, as in
+ *      nl_build).  A step that moves a particle farther than that margin allows
  *      (the large early steps from an overlapping start) leaves the list
  *      stale: MD_FLAG_STALE is set and the call freezes.
  *   1  before each force evaluation a full rebuild runs when a particle is
