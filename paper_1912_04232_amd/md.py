@@ -1222,7 +1222,7 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
         so replays need no host decisions).  The flags are read after every chunk; a chunk that reports a problem
         is re-run eagerly from its saved state.  The first chunk runs with a full rebuild before each force
         evaluation that needs one (the first steps from an overlapping start are too long for the list pipeline),
-        and so do the chunks after it until a chunk needs no more than one rebuild per 8 steps; then chunks use the
+        and so do the chunks after it until a chunk needs no more than one rebuild per 6 steps; then chunks use the
         pipeline, and one whose list went stale is re-run synchronously and the rule starts over.  Synchronous
         chunks are a fifth as long (at least 20 steps), so that the switch comes soon after the steps have
         shortened.  The returned state also holds "rebuilds" (list builds
@@ -1260,7 +1260,7 @@ def fire_descent(system: System, fp: FireParams | None = None, f_tol: float = 1e
                 f = system.nl.read_flags()
             rebuilds += int(f[FLAG_REBUILDS])
             chunks["synchronous" if sync else "pipelined"] += 1
-            if sync and 8 * int(f[FLAG_REBUILDS]) <= k:
+            if sync and 6 * int(f[FLAG_REBUILDS]) <= k:
                 sync = False
             st = fire_state_read(state)
         st["rebuilds"] = rebuilds
